@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Walker-step throughput of the phaseless-AFQMC hot path on one MI355X.
+
+One step = afqmc_propagate (overlap/LU, force bias, V_HS, B1 T6(sqrt(dt) V_HS) B1,
+weight update) + afqmc_local_energy (overlap/LU, Coulomb, one-body, exchange,
+estimator), with afqmc_reorthogonalize every 5th step, for every walker of the
+headline workload (M=400 orbitals, 40+40 electrons, 1600 Cholesky vectors,
+256 walkers, dt=0.005; seeded synthetic Hamiltonian, trial and fields).
+
+Prints ONE JSON line with walker-steps/s, the roofline position of the
+dominant kernel (exchange) measured with the library's HIP-event phase timers
+inside the timed region, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "walker-steps/s (propagate+energy) at M=400,N=40; speed-up vs FP64 at 0.1 mHa"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
+    ap.add_argument("--phases", action="store_true", help="print the per-phase table to stderr")
+    return ap.parse_args(argv)
+
+
+def exchange_flops(M, na, nb, G, W):
+    """Algorithmic flops of one exchange launch: T = Ltilde Theta (real x complex,
+    4 flops per (i, j, q)) and the trace sum_ij T_ij T_ji (8 flops per (i, j))."""
+    n2 = na * na + nb * nb
+    return float(W) * (4.0 * n2 * M * G + 8.0 * n2 * G)
+
+
+def step_flops(M, na, nb, G):
+    """Algorithmic flops of one walker-step (both spins, real L and trial,
+    complex walkers): exchange + trace + V_HS + Taylor(6) + B1 (twice) +
+    force bias and Coulomb (twice) + overlaps and solves."""
+    n2 = na * na + nb * nb
+    nt = na + nb
+    return (4.0 * n2 * M * G + 8.0 * n2 * G + 4.0 * G * M * M + 6 * 8.0 * M * M * nt + 2 * 4.0 * M * M * nt
+            + 2 * 4.0 * G * M * nt + 2 * 16.0 * M * n2)
+
+
+def cpu_baseline(spec, n_walkers, n_steps):
+    """The CPU oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    import afqmc_inputs as gi
+    from oracle import afqmc_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        cores = int(blas[0]["num_threads"]) if blas else 1
+    except Exception:
+        cores = len(os.sched_getaffinity(0))
+    s = spec.system
+    h1, chol, ecore, trial = gi.make_system(s)
+    ham = O.build(h1, chol, ecore, trial, s.nalpha, s.nbeta, spec.dt)
+    phis = gi.initial_walkers(trial, n_walkers)
+    fields = gi.FieldStream(spec.field_seed, n_walkers, s.nchol)
+    w = np.ones(n_walkers)
+    logo = O.initial_logo(ham, phis)
+    t0 = time.perf_counter()
+    for k in range(1, n_steps + 1):
+        phis, w, logo, _ = O.propagate(ham, phis, w, logo, fields.next())
+        if k % spec.reortho_every == 0:
+            phis, logo = O.reorthogonalize(ham, phis, logo)
+        O.local_energies(ham, phis)
+    dt = time.perf_counter() - t0
+    return {"value": n_walkers * n_steps / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_walkers} walkers x {n_steps} steps (propagate + local energy) of {spec.name}, "
+                      f"{dt:.1f} s on the host CPU, numpy complex128"}
+
+
+def main(argv=None):
+    args = parse_args(argv)
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures the walker step on one GPU only; multi-GPU runs are not part of this "
+              "build (walkers shard across GPUs with a 16-byte all-reduce per step).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import afqmc_inputs as gi
+    from paper_2406_16238_amd import afqmc as A
+
+    spec = {"headline": gi.HEADLINE, "medium": gi.MEDIUM, "small": gi.SMALL}[args.workload]
+    s = spec.system
+    W, G, M = spec.nwalkers, s.nchol, s.nbasis
+    h1, chol, ecore, trial = gi.make_system(s)
+    ctx = A.setup_hamiltonian(A.SystemInput(h1, chol, ecore, trial, s.nalpha, s.nbeta, W, spec.dt))
+    del chol
+    walkers = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
+    A.overlap(ctx, walkers)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(spec.field_seed)
+    nsteps = args.warmup + args.steps
+    xs = torch.randn((nsteps, W, G), dtype=torch.float64, device="cuda", generator=gen)
+    e_out = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+    est = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+
+    def step(k):
+        A.propagate(ctx, walkers, xs[k])
+        if (k + 1) % spec.reortho_every == 0:
+            A.reorthogonalize(ctx, walkers)
+        A.local_energy(ctx, walkers, e_out, est)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    A.set_timing(ctx, True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for k in range(args.warmup, nsteps):
+        step(k)
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    phases = A.get_timings(ctx)
+    A.set_timing(ctx, False)
+    est_h = est.cpu().numpy()[0]
+    flags = walkers.flags.cpu().numpy()
+    energy = est_h[0] / est_h[1] if est_h[1] > 0 else float("nan")
+
+    ms_per_step = total_ms / args.steps
+    value = W * args.steps / (total_ms * 1e-3)
+    ex_ms, ex_n = phases["exchange"]
+    ex_flops = exchange_flops(M, s.nalpha, s.nbeta, G, W)
+    achieved = ex_flops / (ex_ms / ex_n * 1e-3) / 1e12 if ex_n else 0.0
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None,
+                "kernel": "exchange (k_exchange_v1)", "avg_launch_ms": round(ex_ms / max(ex_n, 1), 4),
+                "flops_per_launch": ex_flops}
+    step_tf = step_flops(M, s.nalpha, s.nbeta, G) * W / (ms_per_step * 1e-3) / 1e12
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded generator: random symmetric h and Cholesky vectors scaled by "
+                   "exp(-g/tau)/M, trial = lowest orbitals of a Fock-like matrix, N(0,1) fields)",
+           "config": {"workload": spec.name, "nbasis": M, "nalpha": s.nalpha, "nbeta": s.nbeta, "nchol": G,
+                      "nwalkers": W, "dt": spec.dt, "reortho_every": spec.reortho_every,
+                      "precision": "fp64", "taylor_order": 6},
+           "roofline": roofline,
+           "step_algorithmic_tflops": round(step_tf, 3),
+           "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
+           "mixed_energy": round(float(energy), 8), "walkers_flagged": int((flags != 0).sum())}
+    if args.phases:
+        for k, (ms, n) in phases.items():
+            print(f"{k:12s} {ms / args.steps:9.3f} ms/step  {n:6d} launches", file=sys.stderr)
+    ctx.close()
+    del xs, walkers
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_walkers, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

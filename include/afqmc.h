@@ -1,0 +1,215 @@
+/*
+ * afqmc.h -- C ABI of the MI355X phaseless-AFQMC walker step (libafqmc.so).
+ *
+ * The library implements one time step of phaseless auxiliary-field quantum
+ * Monte Carlo for an ab-initio Hamiltonian whose two-electron integrals are
+ * given as Cholesky vectors (arXiv:2406.16238, Sec. 2, eqs. qcham and
+ * chol_decomp), with a single Slater-determinant trial (Sec. 3.3, the
+ * single-determinant trial object) and unrestricted walkers.  Every step of the
+ * path runs in the library's own HIP kernels on the caller's stream.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * Sizes: M = nbasis, Na = nalpha, Nb = nbeta, Nt = Na + Nb, G = nchol,
+ *        W = nwalkers (fixed per system at set-up).
+ * Complex numbers are interleaved (re, im) pairs of doubles ("double2").
+ * All matrices are row-major.
+ * Walker slab phi: device double2 [W][M][Nt]; columns 0..Na-1 are the alpha
+ *   orbitals, Na..Nt-1 the beta orbitals (the trial's hstack([orbs_a, orbs_b])
+ *   layout).
+ * Ownership: the caller allocates and owns every walker, field and output
+ *   buffer; the context owns everything derived from the Hamiltonian and its
+ *   own workspaces, and frees them in afqmc_destroy.  No call keeps a caller
+ *   pointer after it returns.
+ * Streams: every call except afqmc_setup_hamiltonian enqueues its kernels on
+ *   `hip_stream` (a hipStream_t, NULL = the default stream) and returns
+ *   without synchronising.  The returned status covers argument validation and
+ *   launch errors only; numerical trouble is reported per walker in the flag
+ *   word.  Calls that share a context must not overlap in time (they share the
+ *   context's workspaces): issue them on one stream, or synchronise.
+ * Errors: no call aborts or throws.  On a non-OK status the outputs are
+ *   unspecified, the context stays valid, and afqmc_last_error() returns a
+ *   message for the calling thread.
+ */
+#ifndef AFQMC_H
+#define AFQMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct afqmc_ctx afqmc_ctx;
+
+typedef enum {
+  AFQMC_OK = 0,
+  AFQMC_ERR_ARG = 1,          /* invalid argument; nothing was launched       */
+  AFQMC_ERR_OOM = 2,          /* device memory (or mem_limit_bytes) exhausted */
+  AFQMC_ERR_HIP = 3,          /* a HIP runtime call or launch failed          */
+  AFQMC_ERR_UNSUPPORTED = 4   /* valid but outside what this build supports   */
+} afqmc_status;
+
+/* Precision of the force-bias and exchange contractions (overlap LU,
+ * determinant ratios, re-orthogonalisation and weights are always FP64). */
+enum { AFQMC_FP64 = 0, AFQMC_FP32_CONTRACT = 1, AFQMC_BF16X3_CONTRACT = 2 };
+
+/* Per-walker flag bits, OR-ed into afqmc_walkers.flags by the library. */
+enum {
+  AFQMC_W_SINGULAR = 1u,   /* <Psi_T|phi> is exactly zero or not finite: weight set to 0 */
+  AFQMC_W_NONFINITE = 2u,  /* the walker's fields x contained NaN/Inf: weight set to 0  */
+  AFQMC_W_DEAD = 4u        /* cos(theta) <= 0 this step: weight set to 0 (phaseless)     */
+};
+
+/* One Cholesky-factorised system (Sec. 3.2, the generic Hamiltonian object
+ * built from h1e, chol, ecore; Sec. 3.3, the single-determinant trial). */
+typedef struct {
+  int32_t nbasis, nalpha, nbeta, nchol, nwalkers;
+  const double *h1;     /* host [M][M], real symmetric one-body integrals h_pq      */
+  const double *chol;   /* host [G][M][M], real symmetric Cholesky vectors L^g_pq,
+                           (ps|qr) = sum_g L^g_ps L^g_qr (eq. chol_decomp)         */
+  double ecore;         /* constant energy (nuclear repulsion)                      */
+  const double *trial;  /* host [M][Nt] real, orthonormal columns per spin block    */
+  double dt;            /* imaginary time step (eq. afqmc), > 0                     */
+} afqmc_system_desc;
+
+/* Options (zero-initialise, then call afqmc_default_options). */
+typedef struct {
+  int32_t precision;        /* AFQMC_FP64 (default) or a *_CONTRACT form          */
+  int32_t taylor_order;     /* order of exp(sqrt(dt) V_HS); default 6, 1..16       */
+  double fb_cap;            /* force-bias modulus cap; default 1.0, <= 0 disables  */
+  double e_shift;           /* energy shift E_T; NaN (default) = the trial's E_HF  */
+  uint64_t mem_limit_bytes; /* refuse set-up needing more device memory; 0 = none  */
+  int32_t reserved[8];
+} afqmc_options;
+
+/* Walker state of one system; every pointer is device memory owned by the caller. */
+typedef struct {
+  void *phi;          /* double2 [W][M][Nt] orbitals, updated in place            */
+  double *weight;     /* [W] real weights                                           */
+  void *log_ovlp;     /* double2 [W]: log <Psi_T|phi>, imaginary part in (-pi, pi] */
+  uint32_t *flags;    /* [W] AFQMC_W_* bits, OR-ed in by the library               */
+} afqmc_walkers;
+
+/* Scalars derived at set-up, for reporting and tests. */
+typedef struct {
+  double e_hf;        /* trial energy <Psi_T|H|Psi_T> (also the default E_T)   */
+  double e_shift;     /* E_T in use                                            */
+  double const_c;     /* ecore - 1/2 sum_g l_g^2 (mean-field constant)         */
+  uint64_t device_bytes; /* device memory held by this system                 */
+} afqmc_info;
+
+/* Fills `opt` with the defaults listed above.  Returns AFQMC_ERR_ARG on NULL. */
+afqmc_status afqmc_default_options(afqmc_options *opt);
+
+/*
+ * Builds a context for `nsys` >= 1 independent systems (nsys > 1 is the
+ * batching form; walkers, fields and outputs of the other calls are then
+ * arrays of length nsys).  Copies h1, chol and trial to the device and derives
+ * (Sec. 2, the equations after eq. chol_decomp; eq. fb; eq. Bprop):
+ *   v0 = h - 1/2 sum_g L^g L^g, l_g = sum_s Tr(L^g Psi_s Psi_s^T),
+ *   H1 = v0 + sum_g l_g L^g, C = ecore - 1/2 sum_g l_g^2, B1 = exp(-dt/2 H1),
+ *   the half-rotated Ltilde^{g s} = Psi_s^T L^g and htilde_s = Psi_s^T h, and
+ *   E_HF, the trial's local energy.
+ * Synchronous: returns after all set-up work on `hip_stream` has finished.
+ * Errors: AFQMC_ERR_ARG (NULL pointer, non-positive size, N_s > M, dt <= 0),
+ * AFQMC_ERR_UNSUPPORTED (a spin block wider than 64 orbitals),
+ * AFQMC_ERR_OOM (allocation failure or over mem_limit_bytes; nothing is left
+ * allocated), AFQMC_ERR_HIP.
+ */
+afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
+                                     const afqmc_options *opt, void *hip_stream,
+                                     afqmc_ctx **out);
+
+/*
+ * One phaseless time step for every walker (Sec. 2, eqs. propagate,
+ * weight_update, fb, ovlp_ratio and the hybrid importance function):
+ *   Theta = phi (Psi^T phi)^-1 per spin; vbias_g = sum_s Tr(Ltilde^{g s} Theta_s);
+ *   xbar = i sqrt(dt) (vbias - l), each |xbar_g| capped at fb_cap; y = x - xbar;
+ *   phi <- B1 T(sqrt(dt) V_HS) B1 phi with V_HS = -i sum_g y_g L^g and T the
+ *   Taylor series of the exponential;
+ *   S = <Psi_T|phi'>/<Psi_T|phi> exp(i sqrt(dt) y.l), I = S exp(x.xbar - xbar.xbar/2),
+ *   w <- w |I| max(0, cos arg S) exp(-dt (C - E_T)), log_ovlp <- log<Psi_T|phi'>.
+ * `x`: array of nsys device pointers, each [W][G] standard-normal fields.
+ * Errors: AFQMC_ERR_ARG on NULL pointers; AFQMC_ERR_HIP on launch failure.
+ */
+afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w,
+                             const double *const *x, void *hip_stream);
+
+/*
+ * Local energy E_loc = <Psi_T|H|phi>/<Psi_T|phi> of every walker (eq. Eloc)
+ * by Wick's theorem with the Cholesky integrals:
+ *   E1 = ecore + sum_s Tr(htilde_s Theta_s),
+ *   E2 = 1/2 sum_g vbias_g^2 - 1/2 sum_g sum_s Tr(T^{g s} T^{g s}),
+ *   T^{g s} = Ltilde^{g s} Theta_s (exchange; never stored).
+ * `e_out`: array of nsys device pointers, each double2 [W][3] = (E, E1, E2).
+ * `est_out`: NULL or device double [nsys][4] = (ENumer, EDenom, E1Body, E2Body)
+ *   = (sum w Re E, sum w, sum w Re E1, sum w Re E2) over walkers with w > 0
+ *   (the estimator record of Sec. 3.5).  Reductions are deterministic.
+ */
+afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w,
+                                void *const *e_out, double *est_out, void *hip_stream);
+
+/*
+ * Re-orthogonalisation (the stabilisation of Sec. 3.1): modified Gram-Schmidt
+ * on each spin block, phi_s = Q_s R_s with real R_ii > 0, phi_s <- Q_s and
+ * log_ovlp -= sum_s sum_i log R_ii.  Weights and energies are unchanged.
+ */
+afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream);
+
+/*
+ * Trial-object operations of Sec. 3.3 (calc_overlap, calc_greens_function,
+ * calc_force_bias) exposed on their own, for initialisation and tests.
+ * afqmc_overlap: writes log_ovlp = log<Psi_T|phi> and ORs AFQMC_W_SINGULAR.
+ * afqmc_greens_function: theta_out[s] device double2 [W][M][Nt]:
+ *   Theta = phi (Psi^T phi)^-1 per spin block (G_pq = sum_i Psi_pi Theta_qi).
+ * afqmc_force_bias: vbias_out[s] device double2 [W][G], vbias_g as above.
+ */
+afqmc_status afqmc_overlap(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream);
+afqmc_status afqmc_greens_function(afqmc_ctx *ctx, const afqmc_walkers *w,
+                                   void *const *theta_out, void *hip_stream);
+afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w,
+                              void *const *vbias_out, void *hip_stream);
+
+/* Set-up scalars of system `isys`.  AFQMC_ERR_ARG on NULL or bad index. */
+afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out);
+
+/* Phase timers.  While enabled, the library brackets each kernel phase with a
+ * pair of HIP events on the stream the phase runs on; afqmc_get_timings waits
+ * for the recorded events and returns the accumulated milliseconds and launch
+ * counts per phase since timing was (re-)enabled. */
+enum {
+  AFQMC_PH_OVERLAP = 0,   /* overlap, LU, log det and Theta               */
+  AFQMC_PH_FORCE_BIAS,    /* vbias contraction                            */
+  AFQMC_PH_FB_EPILOGUE,   /* xbar, y, per-walker sums (or EJ)             */
+  AFQMC_PH_VHS,           /* V_HS = -i sum_g y_g L^g                      */
+  AFQMC_PH_ONE_BODY,      /* B1 phi (both half steps)                     */
+  AFQMC_PH_TAYLOR,        /* Taylor series of exp(sqrt(dt) V_HS)          */
+  AFQMC_PH_WEIGHT,        /* phaseless weight update                      */
+  AFQMC_PH_ENERGY_1B,     /* one-body energy                              */
+  AFQMC_PH_EXCHANGE,      /* exchange energy                              */
+  AFQMC_PH_COMBINE,       /* energy combination and estimator             */
+  AFQMC_PH_REORTHO,       /* modified Gram-Schmidt                        */
+  AFQMC_NPHASES
+};
+typedef struct {
+  double ms[AFQMC_NPHASES];
+  int64_t count[AFQMC_NPHASES];
+} afqmc_timings;
+
+/* Turns the phase timers on (enable != 0, which also zeroes them) or off. */
+afqmc_status afqmc_set_timing(afqmc_ctx *ctx, int32_t enable);
+/* Blocks until every recorded event has completed, then fills `out`. */
+afqmc_status afqmc_get_timings(afqmc_ctx *ctx, afqmc_timings *out);
+
+/* Frees the context and all device memory it owns.  NULL is a no-op.
+ * Synchronises the device first so no queued kernel still uses the memory. */
+void afqmc_destroy(afqmc_ctx *ctx);
+
+/* Message for the last non-OK status on the calling thread ("" if none). */
+const char *afqmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFQMC_H */

@@ -98,8 +98,10 @@ def build(h1, chol, ecore, trial, nalpha, nbeta, dt) -> OracleHamiltonian:
     ham = OracleHamiltonian(np.asarray(h1, float), np.asarray(chol, float), float(ecore),
                             np.asarray(trial, float), int(nalpha), int(nbeta), float(dt))
     L = ham.chol
-    # sum_r (pr|rq) = sum_g sum_r L^g_pr L^g_rq = sum_g (L^g L^g)_pq
-    exch = np.einsum("gpr,grq->pq", L, L)
+    G, M = L.shape[0], L.shape[1]
+    # sum_r (pr|rq) = sum_g sum_r L^g_pr L^g_rq = sum_g (L^g L^g)_pq, written as
+    # one product over the combined index (g, r)
+    exch = L.transpose(1, 0, 2).reshape(M, G * M) @ L.reshape(G * M, M)
     ham.v0 = ham.h1 - 0.5 * exch
     # mean-field shift: <v_g>_T = i sum_s sum_pq L^g_pq <a+_p a_q>_T, with the
     # trial's density matrix P_s = Psi_s Psi_s^T (orthonormal real orbitals)
@@ -108,8 +110,8 @@ def build(h1, chol, ecore, trial, nalpha, nbeta, dt) -> OracleHamiltonian:
     for sl in ham.spins():
         psi = ham.trial[:, sl]
         P = psi @ psi.T
-        lmf += np.einsum("gpq,pq->g", L, P)
-        ham.lhalf.append(np.einsum("pi,gpq->giq", psi, L))
+        lmf += L.reshape(G, M * M) @ P.ravel()
+        ham.lhalf.append(np.matmul(psi.T, L))            # [G, N_s, M]
         ham.hhalf.append(psi.T @ ham.h1)
     ham.lmf = lmf
     ham.H1 = ham.v0 + np.tensordot(lmf, L, axes=1)
@@ -154,7 +156,9 @@ def force_bias(ham: OracleHamiltonian, thetas) -> np.ndarray:
     <v_g> = i vbias_g (eq. fb numerator before the mean-field subtraction)."""
     vb = np.zeros(ham.nchol, dtype=np.complex128)
     for s, th in enumerate(thetas):
-        vb += np.einsum("giq,qi->g", ham.lhalf[s], th)
+        lh = ham.lhalf[s].reshape(ham.nchol, -1)      # [G, (i, q)]
+        t = th.T.ravel()                              # Theta_qi ordered as (i, q)
+        vb += lh @ np.ascontiguousarray(t.real) + 1j * (lh @ np.ascontiguousarray(t.imag))
     return vb
 
 
@@ -182,7 +186,9 @@ def local_energy(ham: OracleHamiltonian, phi: np.ndarray):
         if lh.shape[1] == 0:
             continue
         G, n, M = lh.shape
-        T = (lh.reshape(G * n, M) @ th).reshape(G, n, n)
+        lh2 = lh.reshape(G * n, M)
+        tr, ti = np.ascontiguousarray(th.real), np.ascontiguousarray(th.imag)
+        T = (lh2 @ tr + 1j * (lh2 @ ti)).reshape(G, n, n)
         ek += -0.5 * np.einsum("gij,gji->", T, T)
     e2 = ej + ek
     return e1 + e2, e1, e2
@@ -222,7 +228,7 @@ def two_body_generator(ham: OracleHamiltonian, y: np.ndarray) -> np.ndarray:
     """A = -sqrt(dt) sum_g y_g (i L^g): the orbital matrix of
     exp(-sqrt(dt) y.v) by Thouless' theorem (sqrt(dt) times V_HS)."""
     L2 = ham.chol.reshape(ham.nchol, -1)
-    vhs = -1j * ((y.real @ L2) + 1j * (y.imag @ L2))
+    vhs = -1j * ((np.ascontiguousarray(y.real) @ L2) + 1j * (np.ascontiguousarray(y.imag) @ L2))
     return np.sqrt(ham.dt) * vhs.reshape(ham.nbasis, ham.nbasis)
 
 

@@ -1,0 +1,110 @@
+// Internal declarations of libafqmc: per-system device state and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "afqmc.h"
+
+namespace afqmc {
+
+constexpr int kMaxSpinOrbitals = 56;  // widest spin block: N^2 complex fits the 64 KiB LDS budget
+constexpr int kThreads = 256;
+
+// Device buffers and scalars of one system.  Layouts (row-major):
+//   L      [G][M][M]     Cholesky vectors
+//   LtT    [G][M][Nt]    half-rotated vectors, LtT[g][q][i'] = (Psi_s^T L^g)_{i q}
+//   htT    [M][Nt]       htT[q][i'] = (Psi_s^T h)_{i q}
+//   trial  [M][Nt]
+//   B1     [M][M]        exp(-dt/2 H1)
+//   lmf    [G]           mean-field shift l_g (m_g = i l_g)
+// Workspaces sized for W walkers:
+//   theta  [W][M][Nt] double2        Green's-function factor Theta
+//   fbpart [ks][W][G] double2        split-K partial sums of vbias
+//   yp     [W][2][G]                 sqrt(dt) * (Im y, -Re y): rows of the VHS product
+//   vhs    [W][2][M][M]              A = sqrt(dt) V_HS as real and imaginary planes
+//   tA,tB,tacc [W][M][Nt] double2    Taylor-series term ping-pong and accumulator
+//   logo_now, logo_new [W] double2   log overlaps before/after the step
+//   stat_now, stat_new [W] uint32    singular markers of the two LU passes
+//   wsc    [W][6]                    sum x.xbar, sum xbar.xbar, sum y.l (complex)
+//   e1, ej [W] double2; ekpart [W][2][ngb] double2
+struct System {
+  int M = 0, Na = 0, Nb = 0, Nt = 0, G = 0, W = 0;
+  double dt = 0, sqdt = 0, ecore = 0, e_hf = 0, e_shift = 0, const_c = 0;
+  uint64_t bytes = 0;
+
+  double *L = nullptr, *LtT = nullptr, *htT = nullptr, *trial = nullptr, *B1 = nullptr, *lmf = nullptr;
+  double2 *theta = nullptr, *fbpart = nullptr, *tA = nullptr, *tB = nullptr, *tacc = nullptr;
+  double *yp = nullptr, *vhs = nullptr, *wsc = nullptr;
+  double2 *logo_now = nullptr, *logo_new = nullptr, *e1 = nullptr, *ej = nullptr, *ekpart = nullptr;
+  uint32_t *stat_now = nullptr, *stat_new = nullptr;
+
+  int fb_ksplit = 1;  // split-K slices of the force-bias contraction
+  int ex_gb = 1;      // Cholesky vectors per exchange workgroup
+  int ex_ngb = 1;     // number of exchange workgroups along G
+  size_t ex_lds = 0;  // dynamic LDS of the exchange kernel
+};
+
+struct Options {
+  int precision = AFQMC_FP64;
+  int taylor_order = 6;
+  double fb_cap = 1.0;
+};
+
+// ---- kernel launchers (each returns the hipGetLastError() of its launch) ----
+
+// Generic strided FP64 GEMM: C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j)
+// with A(i,k) = A[b*sab + i*sai + k*sak], B(k,j) = B[b*sbb + k*sbk + j*sbj],
+// C(i,j) = C[b*scb + s*scs + i*sci + j*scj] where s is the split-K slice.
+struct GemmArgs {
+  int m = 0, n = 0, k = 0, batch = 1, ksplit = 1;
+  const double *A = nullptr; long sai = 0, sak = 0, sab = 0;
+  const double *B = nullptr; long sbk = 0, sbj = 0, sbb = 0;
+  double *C = nullptr; long sci = 0, scj = 0, scb = 0, scs = 0;
+  double alpha = 1.0, beta = 0.0;
+};
+hipError_t gemm_f64(const GemmArgs &a, hipStream_t st);
+
+// Overlap, log-determinant and (optionally) Theta for every walker.
+hipError_t launch_ovlp_theta(const double2 *phi, const double *trial, int M, int Na, int Nb, int W,
+                             double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or,
+                             hipStream_t st);
+// Modified Gram-Schmidt per spin block, log_ovlp -= sum log R_ii.
+hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st);
+
+// Force bias: split-K contraction into fbpart, then the epilogues.
+hipError_t launch_force_bias_gemm(const System &s, const double2 *theta, int W, hipStream_t st);
+hipError_t launch_fb_propagate_epilogue(const System &s, const Options &o, const double *x, int W,
+                                        uint32_t *flags, hipStream_t st);
+hipError_t launch_fb_energy_epilogue(const System &s, int W, double2 *vbias_out, hipStream_t st);
+
+// Two-body generator A = sqrt(dt) V_HS for every walker.
+hipError_t launch_vhs(const System &s, int W, hipStream_t st);
+// out_w = B1 in_w for every walker (real M x M times complex M x Nt).
+hipError_t launch_b1(const System &s, const double2 *in, double2 *out, int W, hipStream_t st);
+// Taylor term: tout = alpha * A_w tin; tacc += tout.
+hipError_t launch_taylor_term(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
+                              hipStream_t st);
+// Weight update of the phaseless step.
+hipError_t launch_weight_update(const System &s, const afqmc_walkers &w, int W, hipStream_t st);
+
+// Energies.
+hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStream_t st);
+hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st);
+hipError_t launch_energy_combine(const System &s, int W, double2 *e_out, hipStream_t st);
+hipError_t launch_estimator(const double *weight, const double2 *e_out, int W, double *est, hipStream_t st);
+
+// Set-up helpers.
+hipError_t launch_row_dot(const double *A, const double *v, long len, int rows, double *out, hipStream_t st);
+hipError_t launch_sum_slices(const double *parts, int nslices, long n, double alpha, double *inout,
+                             hipStream_t st);
+hipError_t launch_add_identity(double *A, int M, double diag, hipStream_t st);
+hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, hipStream_t st);
+
+// Exchange launch geometry for a spin block width.
+void exchange_geometry(int nmax, int *gb, size_t *lds);
+
+}  // namespace afqmc

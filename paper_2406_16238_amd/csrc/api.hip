@@ -1,0 +1,647 @@
+// C ABI of libafqmc: argument validation, set-up of the derived Hamiltonian on
+// the device, and the enqueueing of the step kernels.  No exception crosses the
+// boundary; every failure returns a status and records a thread-local message.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "afqmc_internal.h"
+
+using namespace afqmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+afqmc_status fail(afqmc_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define AFQMC_HIP(call, what)                                                                \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail(AFQMC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct afqmc_ctx {
+  std::vector<System> sys;
+  Options opt;
+  int device = 0;
+  std::vector<void *> allocs;
+  // phase timers
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<int> ev_phase;
+  size_t ev_used = 0;
+  double ph_ms[AFQMC_NPHASES] = {0};
+  int64_t ph_count[AFQMC_NPHASES] = {0};
+};
+
+namespace {
+
+// Folds every recorded event pair into the per-phase totals (waits for them).
+void fold_timings(afqmc_ctx *c) {
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(c->ev_stop[i]) == hipSuccess &&
+        hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]) == hipSuccess) {
+      c->ph_ms[c->ev_phase[i]] += ms;
+      c->ph_count[c->ev_phase[i]] += 1;
+    }
+  }
+  c->ev_used = 0;
+}
+
+// Brackets one phase with events when timing is on.
+struct Phase {
+  afqmc_ctx *c;
+  hipStream_t st;
+  size_t slot = (size_t)-1;
+  Phase(afqmc_ctx *c_, int phase, hipStream_t st_) : c(c_), st(st_) {
+    if (!c || !c->timing) return;
+    if (c->ev_used == 4096) fold_timings(c);
+    if (c->ev_used == c->ev_start.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+      c->ev_start.push_back(a);
+      c->ev_stop.push_back(b);
+      c->ev_phase.push_back(0);
+    }
+    slot = c->ev_used++;
+    c->ev_phase[slot] = phase;
+    (void)hipEventRecord(c->ev_start[slot], st);
+  }
+  ~Phase() {
+    if (slot != (size_t)-1) (void)hipEventRecord(c->ev_stop[slot], st);
+  }
+};
+
+}  // namespace
+
+namespace {
+
+void free_all(afqmc_ctx *c) {
+  for (void *p : c->allocs)
+    if (p) (void)hipFree(p);
+  c->allocs.clear();
+}
+
+// Device allocation recorded in the context; returns false on failure.
+template <class T>
+bool dalloc(afqmc_ctx *c, T **p, size_t count) {
+  void *q = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+  }
+  c->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return true;
+}
+
+// Set-up temporaries: freed (after a stream synchronisation) when the holder dies.
+struct Temps {
+  std::vector<void *> ptrs;
+  hipStream_t st = nullptr;
+  ~Temps() {
+    if (!ptrs.empty()) (void)hipStreamSynchronize(st);
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  bool get(T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, (count ? count : 1) * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    ptrs.push_back(q);
+    *p = static_cast<T *>(q);
+    return true;
+  }
+};
+
+bool valid_desc(const afqmc_system_desc &d, std::string &why) {
+  if (!d.h1 || !d.chol || !d.trial) { why = "h1, chol and trial must be non-NULL host pointers"; return false; }
+  if (d.nbasis <= 0 || d.nchol <= 0 || d.nwalkers <= 0) { why = "nbasis, nchol and nwalkers must be positive"; return false; }
+  if (d.nalpha < 0 || d.nbeta < 0 || d.nalpha + d.nbeta <= 0) { why = "need at least one electron"; return false; }
+  if (d.nalpha > d.nbasis || d.nbeta > d.nbasis) { why = "more electrons of one spin than orbitals"; return false; }
+  if (!(d.dt > 0.0) || !std::isfinite(d.dt)) { why = "dt must be positive and finite"; return false; }
+  if (!std::isfinite(d.ecore)) { why = "ecore must be finite"; return false; }
+  return true;
+}
+
+// Sizes of every buffer of one system (doubles, double2s, uint32s).
+struct Plan {
+  size_t L, LtT, htT, trial, B1, lmf, theta, fbpart, yp, vhs, tbuf, wsc, wvec2, ekpart, stat;
+  uint64_t bytes() const {
+    return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc) +
+           16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat;
+  }
+};
+
+Plan plan_for(const System &s) {
+  Plan p{};
+  const size_t M = s.M, Nt = s.Nt, G = s.G, W = s.W;
+  p.L = G * M * M;
+  p.LtT = G * M * Nt;
+  p.htT = M * Nt;
+  p.trial = M * Nt;
+  p.B1 = M * M;
+  p.lmf = G;
+  p.theta = W * M * Nt;
+  p.fbpart = (size_t)s.fb_ksplit * W * G;
+  p.yp = 2 * W * G;
+  p.vhs = 2 * W * M * M;
+  p.tbuf = W * M * Nt;
+  p.wsc = 6 * W;
+  p.wvec2 = W;  // logo_now, logo_new, e1, ej (+1 spare)
+  p.ekpart = W * 2 * (size_t)s.ex_ngb;
+  p.stat = W;
+  return p;
+}
+
+int choose_fb_ksplit(int W, int G, long K) {
+  const long tiles = 2L * ((W + 63) / 64) * ((G + 63) / 64);
+  long ks = (1024 + tiles - 1) / tiles;
+  ks = std::min(ks, std::max(1L, K / 512));
+  return (int)std::max(1L, std::min(ks, 64L));
+}
+
+// Local energy of W walkers of system s into e_out (device double2 [W][3]).
+// `c` may be NULL (set-up); it only supplies the phase timers.
+afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W, double2 *e_out, double *est,
+                              const double *weight, hipStream_t st) {
+  {
+    Phase ph(c, AFQMC_PH_OVERLAP, st);
+    AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_new, s.stat_new, nullptr, st),
+              "overlap kernel");
+  }
+  {
+    Phase ph(c, AFQMC_PH_FORCE_BIAS, st);
+    AFQMC_HIP(launch_force_bias_gemm(s, s.theta, W, st), "force-bias kernel");
+  }
+  {
+    Phase ph(c, AFQMC_PH_FB_EPILOGUE, st);
+    AFQMC_HIP(launch_fb_energy_epilogue(s, W, nullptr, st), "Coulomb epilogue");
+  }
+  {
+    Phase ph(c, AFQMC_PH_ENERGY_1B, st);
+    AFQMC_HIP(launch_energy_e1(s, s.theta, W, st), "one-body energy kernel");
+  }
+  {
+    Phase ph(c, AFQMC_PH_EXCHANGE, st);
+    AFQMC_HIP(launch_exchange(s, s.theta, W, st), "exchange kernel");
+  }
+  {
+    Phase ph(c, AFQMC_PH_COMBINE, st);
+    AFQMC_HIP(launch_energy_combine(s, W, e_out, st), "energy combine kernel");
+    if (est) AFQMC_HIP(launch_estimator(weight, e_out, W, est, st), "estimator kernel");
+  }
+  return AFQMC_OK;
+}
+
+// exp(f X) for a real M x M device matrix X by a degree-20 Taylor series with
+// scaling and squaring: f X is scaled by 2^-k until its 1-norm is at most 1/2
+// (truncation error below 1e-22 relative), then squared k times.
+afqmc_status device_expm(Temps &t, const double *X, double f, double xnorm1, int M, double *out,
+                         hipStream_t st) {
+  int sq = 0;
+  double nrm = std::fabs(f) * xnorm1;
+  while (nrm > 0.5) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double scale = f * std::ldexp(1.0, -sq);
+  double *term = nullptr, *tmp = nullptr, *xs = nullptr;
+  const size_t mm = (size_t)M * M;
+  if (!t.get(&term, mm) || !t.get(&tmp, mm) || !t.get(&xs, mm))
+    return fail(AFQMC_ERR_OOM, "device allocation failed (matrix exponential)");
+  AFQMC_HIP(hipMemsetAsync(out, 0, mm * sizeof(double), st), "memset");
+  AFQMC_HIP(launch_add_identity(out, M, 1.0, st), "identity");
+  AFQMC_HIP(hipMemsetAsync(xs, 0, mm * sizeof(double), st), "memset");
+  AFQMC_HIP(launch_axpby(X, scale, xs, 0.0, (long)mm, st), "scale");
+  AFQMC_HIP(hipMemcpyAsync(term, xs, mm * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  AFQMC_HIP(launch_axpby(term, 1.0, out, 1.0, (long)mm, st), "axpy");
+  for (int k = 2; k <= 20; ++k) {
+    GemmArgs g;
+    g.m = M; g.n = M; g.k = M;
+    g.A = term; g.sai = M; g.sak = 1;
+    g.B = xs; g.sbk = M; g.sbj = 1;
+    g.C = tmp; g.sci = M; g.scj = 1;
+    g.alpha = 1.0 / k;
+    AFQMC_HIP(gemm_f64(g, st), "expm gemm");
+    std::swap(term, tmp);
+    AFQMC_HIP(launch_axpby(term, 1.0, out, 1.0, (long)mm, st), "axpy");
+  }
+  for (int k = 0; k < sq; ++k) {
+    GemmArgs g;
+    g.m = M; g.n = M; g.k = M;
+    g.A = out; g.sai = M; g.sak = 1;
+    g.B = out; g.sbk = M; g.sbj = 1;
+    g.C = tmp; g.sci = M; g.scj = 1;
+    AFQMC_HIP(gemm_f64(g, st), "expm squaring");
+    AFQMC_HIP(hipMemcpyAsync(out, tmp, mm * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipStream_t st,
+                       uint64_t *bytes_used, uint64_t limit) {
+  s.M = d.nbasis; s.Na = d.nalpha; s.Nb = d.nbeta; s.Nt = d.nalpha + d.nbeta; s.G = d.nchol;
+  s.W = d.nwalkers; s.dt = d.dt; s.sqdt = std::sqrt(d.dt); s.ecore = d.ecore;
+  const int nmax = std::max(s.Na, s.Nb);
+  if (nmax > kMaxSpinOrbitals)
+    return fail(AFQMC_ERR_UNSUPPORTED, "a spin block wider than " + std::to_string(kMaxSpinOrbitals) +
+                                           " orbitals is not supported");
+  s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
+  exchange_geometry(nmax, &s.ex_gb, &s.ex_lds);
+  s.ex_ngb = (s.G + s.ex_gb - 1) / s.ex_gb;
+  const Plan p = plan_for(s);
+  const size_t M = s.M, Nt = s.Nt, G = s.G;
+  const uint64_t setup_tmp = 8ull * (4 * M * M + M * M * 64 + M * M + G) + 16ull * (M * Nt + 3);
+  s.bytes = p.bytes();
+  if (limit && *bytes_used + s.bytes + setup_tmp > limit)
+    return fail(AFQMC_ERR_OOM, "device memory needed (" + std::to_string(*bytes_used + s.bytes + setup_tmp) +
+                                   " bytes) exceeds mem_limit_bytes");
+  bool ok = dalloc(c, &s.L, p.L) && dalloc(c, &s.LtT, p.LtT) && dalloc(c, &s.htT, p.htT) &&
+            dalloc(c, &s.trial, p.trial) && dalloc(c, &s.B1, p.B1) && dalloc(c, &s.lmf, p.lmf) &&
+            dalloc(c, &s.theta, p.theta) && dalloc(c, &s.fbpart, p.fbpart) && dalloc(c, &s.yp, p.yp) &&
+            dalloc(c, &s.vhs, p.vhs) && dalloc(c, &s.tA, p.tbuf) && dalloc(c, &s.tB, p.tbuf) &&
+            dalloc(c, &s.tacc, p.tbuf) && dalloc(c, &s.wsc, p.wsc) && dalloc(c, &s.logo_now, p.wvec2) &&
+            dalloc(c, &s.logo_new, p.wvec2) && dalloc(c, &s.e1, p.wvec2) && dalloc(c, &s.ej, p.wvec2) &&
+            dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat);
+  if (!ok) return fail(AFQMC_ERR_OOM, "device allocation failed");
+  *bytes_used += s.bytes;
+
+  const size_t mm = M * M;
+  AFQMC_HIP(hipMemcpyAsync(s.L, d.chol, p.L * sizeof(double), hipMemcpyHostToDevice, st), "upload chol");
+  AFQMC_HIP(hipMemcpyAsync(s.trial, d.trial, p.trial * sizeof(double), hipMemcpyHostToDevice, st),
+            "upload trial");
+  // temporaries of set-up
+  Temps tmp;
+  tmp.st = st;
+  double *h = nullptr, *P = nullptr, *v0 = nullptr, *H1 = nullptr, *parts = nullptr;
+  const int tiles = (int)(((M + 63) / 64) * ((M + 63) / 64));
+  const long Kx = (long)G * M;
+  int ksx = std::max(1, std::min((1024 + tiles - 1) / tiles, (int)std::max(1L, Kx / 256)));
+  ksx = std::min(ksx, 64);
+  if (!tmp.get(&h, mm) || !tmp.get(&P, mm) || !tmp.get(&v0, mm) || !tmp.get(&H1, mm) ||
+      !tmp.get(&parts, (size_t)ksx * mm))
+    return fail(AFQMC_ERR_OOM, "device allocation failed (set-up temporaries)");
+  AFQMC_HIP(hipMemcpyAsync(h, d.h1, mm * sizeof(double), hipMemcpyHostToDevice, st), "upload h1");
+  // trial density matrix P = sum_s Psi_s Psi_s^T (host)
+  std::vector<double> hP(mm, 0.0);
+  for (size_t pp = 0; pp < M; ++pp)
+    for (size_t qq = 0; qq < M; ++qq) {
+      double a = 0.0;
+      for (size_t i = 0; i < Nt; ++i) a += d.trial[pp * Nt + i] * d.trial[qq * Nt + i];
+      hP[pp * M + qq] = a;
+    }
+  AFQMC_HIP(hipMemcpyAsync(P, hP.data(), mm * sizeof(double), hipMemcpyHostToDevice, st), "upload P");
+  // l_g = sum_pq L^g_pq P_pq
+  AFQMC_HIP(launch_row_dot(s.L, P, (long)mm, s.G, s.lmf, st), "mean-field shift");
+  // v0 = h - 1/2 sum_g L^g L^g; with L viewed as a (G M) x M matrix B, sum_g L^g L^g = B^T B
+  {
+    GemmArgs g;
+    g.m = s.M; g.n = s.M; g.k = (int)Kx; g.ksplit = ksx;
+    g.A = s.L; g.sai = 1; g.sak = s.M;
+    g.B = s.L; g.sbk = s.M; g.sbj = 1;
+    g.C = parts; g.sci = s.M; g.scj = 1; g.scs = (long)mm;
+    AFQMC_HIP(gemm_f64(g, st), "v0 gemm");
+    AFQMC_HIP(hipMemcpyAsync(v0, h, mm * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+    AFQMC_HIP(launch_sum_slices(parts, ksx, (long)mm, -0.5, v0, st), "v0 reduce");
+  }
+  // H1 = v0 + sum_g l_g L^g
+  {
+    AFQMC_HIP(hipMemcpyAsync(H1, v0, mm * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+    GemmArgs g;
+    g.m = 1; g.n = (int)mm; g.k = s.G;
+    g.A = s.lmf; g.sai = 0; g.sak = 1;
+    g.B = s.L; g.sbk = (long)mm; g.sbj = 1;
+    g.C = H1; g.sci = 0; g.scj = 1; g.beta = 1.0;
+    AFQMC_HIP(gemm_f64(g, st), "H1 gemm");
+  }
+  // half rotation: LtT[g] = L^g Psi (= (Psi^T L^g)^T), htT = h Psi
+  {
+    GemmArgs g;
+    g.m = s.M; g.n = s.Nt; g.k = s.M; g.batch = s.G;
+    g.A = s.L; g.sai = s.M; g.sak = 1; g.sab = (long)mm;
+    g.B = s.trial; g.sbk = s.Nt; g.sbj = 1; g.sbb = 0;
+    g.C = s.LtT; g.sci = s.Nt; g.scj = 1; g.scb = (long)M * Nt;
+    AFQMC_HIP(gemm_f64(g, st), "half-rotation gemm");
+    GemmArgs gh = g;
+    gh.batch = 1; gh.A = h; gh.sab = 0; gh.C = s.htT; gh.scb = 0;
+    AFQMC_HIP(gemm_f64(gh, st), "half-rotation of h");
+  }
+  // scalars and B1 = exp(-dt/2 H1)
+  std::vector<double> hl(G), hH1(mm);
+  AFQMC_HIP(hipMemcpyAsync(hl.data(), s.lmf, G * sizeof(double), hipMemcpyDeviceToHost, st), "download l");
+  AFQMC_HIP(hipMemcpyAsync(hH1.data(), H1, mm * sizeof(double), hipMemcpyDeviceToHost, st), "download H1");
+  AFQMC_HIP(hipStreamSynchronize(st), "set-up synchronise");
+  double l2 = 0.0;
+  for (double v : hl) l2 += v * v;
+  s.const_c = s.ecore - 0.5 * l2;
+  double n1 = 0.0;
+  for (size_t qq = 0; qq < M; ++qq) {
+    double col = 0.0;
+    for (size_t pp = 0; pp < M; ++pp) col += std::fabs(hH1[pp * M + qq]);
+    n1 = std::max(n1, col);
+  }
+  {
+    afqmc_status r = device_expm(tmp, H1, -0.5 * s.dt, n1, s.M, s.B1, st);
+    if (r != AFQMC_OK) return r;
+  }
+  // trial energy E_HF: the local energy of the walker phi = Psi
+  {
+    double2 *phi_t = nullptr, *e_t = nullptr;
+    if (!tmp.get(&phi_t, M * Nt) || !tmp.get(&e_t, 3))
+      return fail(AFQMC_ERR_OOM, "device allocation failed (trial energy)");
+    std::vector<double2> hphi(M * Nt);
+    for (size_t k = 0; k < M * Nt; ++k) hphi[k] = make_double2(d.trial[k], 0.0);
+    AFQMC_HIP(hipMemcpyAsync(phi_t, hphi.data(), M * Nt * sizeof(double2), hipMemcpyHostToDevice, st),
+              "upload trial walker");
+    afqmc_status r = local_energy_sys(nullptr, s, phi_t, 1, e_t, nullptr, nullptr, st);
+    if (r != AFQMC_OK) return r;
+    double2 he[3];
+    AFQMC_HIP(hipMemcpyAsync(he, e_t, sizeof(he), hipMemcpyDeviceToHost, st), "download trial energy");
+    AFQMC_HIP(hipStreamSynchronize(st), "set-up synchronise");
+    s.e_hf = he[0].x;
+  }
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+afqmc_status afqmc_default_options(afqmc_options *opt) {
+  if (!opt) return fail(AFQMC_ERR_ARG, "opt is NULL");
+  memset(opt, 0, sizeof(*opt));
+  opt->precision = AFQMC_FP64;
+  opt->taylor_order = 6;
+  opt->fb_cap = 1.0;
+  opt->e_shift = NAN;
+  opt->mem_limit_bytes = 0;
+  return AFQMC_OK;
+}
+
+const char *afqmc_last_error(void) { return g_last_error.c_str(); }
+
+afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys, const afqmc_options *opt,
+                                     void *hip_stream, afqmc_ctx **out) {
+  if (!out) return fail(AFQMC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sys || nsys <= 0) return fail(AFQMC_ERR_ARG, "need nsys >= 1 system descriptions");
+  afqmc_options o;
+  if (opt) o = *opt;
+  else afqmc_default_options(&o);
+  if (o.precision != AFQMC_FP64 && o.precision != AFQMC_FP32_CONTRACT && o.precision != AFQMC_BF16X3_CONTRACT)
+    return fail(AFQMC_ERR_ARG, "unknown precision");
+  if (o.taylor_order < 1 || o.taylor_order > 16) return fail(AFQMC_ERR_ARG, "taylor_order must be in 1..16");
+  if (std::isnan(o.fb_cap) || std::isinf(o.fb_cap)) return fail(AFQMC_ERR_ARG, "fb_cap must be finite");
+  for (int i = 0; i < nsys; ++i) {
+    std::string why;
+    if (!valid_desc(sys[i], why)) return fail(AFQMC_ERR_ARG, "system " + std::to_string(i) + ": " + why);
+  }
+  for (int i = 0; i < nsys; ++i)
+    if (std::max(sys[i].nalpha, sys[i].nbeta) > kMaxSpinOrbitals)
+      return fail(AFQMC_ERR_UNSUPPORTED, "system " + std::to_string(i) + ": a spin block wider than " +
+                                             std::to_string(kMaxSpinOrbitals) + " orbitals is not supported");
+  if (o.precision != AFQMC_FP64)
+    return fail(AFQMC_ERR_UNSUPPORTED, "reduced-precision contractions are not built into this library");
+  afqmc_ctx *c = new (std::nothrow) afqmc_ctx();
+  if (!c) return fail(AFQMC_ERR_OOM, "host allocation failed");
+  c->opt.precision = o.precision;
+  c->opt.taylor_order = o.taylor_order;
+  c->opt.fb_cap = o.fb_cap;
+  (void)hipGetDevice(&c->device);
+  c->sys.resize(nsys);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  uint64_t used = 0;
+  for (int i = 0; i < nsys; ++i) {
+    afqmc_status r = setup_one(c, sys[i], c->sys[i], st, &used, o.mem_limit_bytes);
+    if (r != AFQMC_OK) {
+      (void)hipStreamSynchronize(st);
+      free_all(c);
+      delete c;
+      return r;
+    }
+    System &sy = c->sys[i];
+    sy.e_shift = std::isnan(o.e_shift) ? sy.e_hf : o.e_shift;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    free_all(c);
+    delete c;
+    return fail(AFQMC_ERR_HIP, "set-up failed on the device");
+  }
+  *out = c;
+  return AFQMC_OK;
+}
+
+static afqmc_status check_walkers(const afqmc_walkers &w, int i) {
+  if (!w.phi || !w.weight || !w.log_ovlp || !w.flags)
+    return fail(AFQMC_ERR_ARG, "walkers of system " + std::to_string(i) + " have a NULL buffer");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *hip_stream) {
+  if (!ctx || !w || !x) return fail(AFQMC_ERR_ARG, "NULL context, walkers or fields");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+    if (!x[i]) return fail(AFQMC_ERR_ARG, "fields of system " + std::to_string(i) + " are NULL");
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    System &s = ctx->sys[i];
+    const afqmc_walkers &wk = w[i];
+    double2 *phi = static_cast<double2 *>(wk.phi);
+    const int W = s.W;
+    {
+      Phase ph(ctx, AFQMC_PH_OVERLAP, st);
+      AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_now, s.stat_now, nullptr, st),
+                "overlap kernel");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_FORCE_BIAS, st);
+      AFQMC_HIP(launch_force_bias_gemm(s, s.theta, W, st), "force-bias kernel");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_FB_EPILOGUE, st);
+      AFQMC_HIP(launch_fb_propagate_epilogue(s, ctx->opt, x[i], W, wk.flags, st), "force-bias epilogue");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_VHS, st);
+      AFQMC_HIP(launch_vhs(s, W, st), "V_HS kernel");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
+      AFQMC_HIP(launch_b1(s, phi, s.tacc, W, st), "one-body kernel");
+      AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice,
+                               st),
+                "copy");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_TAYLOR, st);
+      double2 *tin = s.tA, *tout = s.tB;
+      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
+        AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st), "Taylor kernel");
+        std::swap(tin, tout);
+      }
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
+      AFQMC_HIP(launch_b1(s, s.tacc, phi, W, st), "one-body kernel");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_OVERLAP, st);
+      AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, nullptr, s.logo_new, s.stat_new, nullptr, st),
+                "overlap kernel");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_WEIGHT, st);
+      AFQMC_HIP(launch_weight_update(s, wk, W, st), "weight kernel");
+    }
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *e_out, double *est_out,
+                                void *hip_stream) {
+  if (!ctx || !w || !e_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers or e_out");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+    if (!e_out[i]) return fail(AFQMC_ERR_ARG, "e_out of system " + std::to_string(i) + " is NULL");
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    System &s = ctx->sys[i];
+    afqmc_status r = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W,
+                                      static_cast<double2 *>(e_out[i]), est_out ? est_out + 4 * i : nullptr,
+                                      w[i].weight, st);
+    if (r != AFQMC_OK) return r;
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream) {
+  if (!ctx || !w) return fail(AFQMC_ERR_ARG, "NULL context or walkers");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    System &s = ctx->sys[i];
+    Phase ph(ctx, AFQMC_PH_REORTHO, st);
+    AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
+                         static_cast<double2 *>(w[i].log_ovlp), st),
+              "Gram-Schmidt kernel");
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_overlap(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream) {
+  if (!ctx || !w) return fail(AFQMC_ERR_ARG, "NULL context or walkers");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    System &s = ctx->sys[i];
+    AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, nullptr,
+                                static_cast<double2 *>(w[i].log_ovlp), s.stat_new, w[i].flags, st),
+              "overlap kernel");
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_greens_function(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *theta_out,
+                                   void *hip_stream) {
+  if (!ctx || !w || !theta_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers or theta_out");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    if (!w[i].phi || !theta_out[i]) return fail(AFQMC_ERR_ARG, "NULL phi or theta_out");
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    System &s = ctx->sys[i];
+    AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W,
+                                static_cast<double2 *>(theta_out[i]), s.logo_new, s.stat_new, nullptr, st),
+              "overlap kernel");
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *vbias_out, void *hip_stream) {
+  if (!ctx || !w || !vbias_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers or vbias_out");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    if (!w[i].phi || !vbias_out[i]) return fail(AFQMC_ERR_ARG, "NULL phi or vbias_out");
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    System &s = ctx->sys[i];
+    AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
+                                s.logo_new, s.stat_new, nullptr, st),
+              "overlap kernel");
+    AFQMC_HIP(launch_force_bias_gemm(s, s.theta, s.W, st), "force-bias kernel");
+    AFQMC_HIP(launch_fb_energy_epilogue(s, s.W, static_cast<double2 *>(vbias_out[i]), st), "force-bias epilogue");
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_set_timing(afqmc_ctx *ctx, int32_t enable) {
+  if (!ctx) return fail(AFQMC_ERR_ARG, "NULL context");
+  fold_timings(ctx);
+  ctx->timing = enable != 0;
+  if (ctx->timing)
+    for (int i = 0; i < AFQMC_NPHASES; ++i) {
+      ctx->ph_ms[i] = 0.0;
+      ctx->ph_count[i] = 0;
+    }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_get_timings(afqmc_ctx *ctx, afqmc_timings *out) {
+  if (!ctx || !out) return fail(AFQMC_ERR_ARG, "NULL context or out");
+  fold_timings(ctx);
+  for (int i = 0; i < AFQMC_NPHASES; ++i) {
+    out->ms[i] = ctx->ph_ms[i];
+    out->count[i] = ctx->ph_count[i];
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out) {
+  if (!ctx || !out) return fail(AFQMC_ERR_ARG, "NULL context or out");
+  if (isys < 0 || isys >= (int)ctx->sys.size()) return fail(AFQMC_ERR_ARG, "system index out of range");
+  const System &s = ctx->sys[isys];
+  out->e_hf = s.e_hf;
+  out->e_shift = s.e_shift;
+  out->const_c = s.const_c;
+  out->device_bytes = s.bytes;
+  return AFQMC_OK;
+}
+
+void afqmc_destroy(afqmc_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->ev_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ev_stop) (void)hipEventDestroy(e);
+  free_all(ctx);
+  delete ctx;
+}
+
+}  // extern "C"

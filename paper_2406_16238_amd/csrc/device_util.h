@@ -1,0 +1,63 @@
+// Device helpers: complex arithmetic on interleaved double2 and deterministic
+// workgroup reductions built from 64-lane wavefront shuffles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace afqmc {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// a / b by Smith's scaling, safe for |b| over a wide range
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  double r = b.x / b.y, d = b.x * r + b.y;
+  return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Sum over a workgroup of kThreads threads (4 waves); result valid in thread 0.
+// Fixed shuffle tree, so the result is bitwise reproducible.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch /* [4*NV] shared */) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) scratch[wid * NV + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = scratch[i];
+      for (int k = 1; k < nw; ++k) s += scratch[k * NV + i];
+      v[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double wrap_phase(double a) {
+  const double twopi = 6.283185307179586476925286766559;
+  double r = a - twopi * rint(a / twopi);
+  if (r <= -3.14159265358979323846) r += twopi;
+  return r;
+}
+
+}  // namespace afqmc

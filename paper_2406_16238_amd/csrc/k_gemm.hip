@@ -1,0 +1,199 @@
+// FP64 contraction kernels of the propagation step and of set-up:
+//  * a strided, batched, split-K real GEMM (LDS-tiled, 64x64 tiles, 4x4 register
+//    micro-tiles per thread) used for the force bias, the two-body generator
+//    V_HS, the one-body factor B1 and the set-up products;
+//  * the complex Taylor-term product t' = alpha A_w t with A_w = sqrt(dt) V_HS
+//    held as real/imaginary planes (Sec. 2, eq. Bprop: exp(-sqrt(dt) y.v) acts
+//    on the orbitals as the matrix exponential of sqrt(dt) V_HS).
+#include "afqmc_internal.h"
+#include "device_util.h"
+
+namespace afqmc {
+
+namespace {
+constexpr int TBM = 64, TBN = 64, TBK = 16;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a, int kchunk) {
+  __shared__ double As[TBK][TBM + 4];
+  __shared__ double Bs[TBK][TBN + 4];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int j0 = blockIdx.x * TBN, i0 = blockIdx.y * TBM;
+  const int bz = blockIdx.z;
+  const int b = bz / a.ksplit, s = bz - b * a.ksplit;
+  const int kbeg = s * kchunk;
+  const int kend = min(a.k, kbeg + kchunk);
+  const double *A = a.A + (size_t)b * a.sab;
+  const double *B = a.B + (size_t)b * a.sbb;
+  const bool a_kfast = (a.sak == 1);
+  const bool b_jfast = (a.sbj == 1);
+
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+
+  for (int k0 = kbeg; k0 < kend; k0 += TBK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int ii, kk;
+      if (a_kfast) { kk = tid & 15; ii = (tid >> 4) + 16 * r; }
+      else { ii = tid & 63; kk = (tid >> 6) + 4 * r; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < a.m && gk < kend) ? A[(size_t)gi * a.sai + (size_t)gk * a.sak] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int jj, kk;
+      if (b_jfast) { jj = tid & 63; kk = (tid >> 6) + 4 * r; }
+      else { kk = tid & 15; jj = (tid >> 4) + 16 * r; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      Bs[kk][jj] = (gj < a.n && gk < kend) ? B[(size_t)gk * a.sbk + (size_t)gj * a.sbj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TBK; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty * 4 + r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+
+  double *C = a.C + (size_t)b * a.scb + (size_t)s * a.scs;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int gi = i0 + ty * 4 + r;
+    if (gi >= a.m) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gj = j0 + tx * 4 + c;
+      if (gj >= a.n) continue;
+      double *p = C + (size_t)gi * a.sci + (size_t)gj * a.scj;
+      const double v = a.alpha * acc[r][c];
+      *p = (a.beta != 0.0) ? fma(a.beta, *p, v) : v;
+    }
+  }
+}
+
+hipError_t gemm_f64(const GemmArgs &a, hipStream_t st) {
+  if (a.m <= 0 || a.n <= 0 || a.batch <= 0) return hipSuccess;
+  const int ks = a.ksplit < 1 ? 1 : a.ksplit;
+  int kchunk = (a.k + ks - 1) / ks;
+  kchunk = ((kchunk + TBK - 1) / TBK) * TBK;
+  GemmArgs b = a;
+  b.ksplit = ks;
+  dim3 grid((a.n + TBN - 1) / TBN, (a.m + TBM - 1) / TBM, a.batch * ks);
+  hipLaunchKernelGGL(k_gemm_f64, grid, dim3(kThreads), 0, st, b, kchunk);
+  return hipGetLastError();
+}
+
+// ---- force bias: vbias[w][g] = sum_k LtT[g][k] Theta[w][k], k = (q, i') -----
+hipError_t launch_force_bias_gemm(const System &s, const double2 *theta, int W, hipStream_t st) {
+  const long K = (long)s.M * s.Nt;
+  GemmArgs a;
+  a.m = s.G; a.n = W; a.k = (int)K; a.batch = 2; a.ksplit = s.fb_ksplit;
+  a.A = s.LtT; a.sai = K; a.sak = 1; a.sab = 0;
+  a.B = reinterpret_cast<const double *>(theta); a.sbk = 2; a.sbj = 2 * K; a.sbb = 1;
+  a.C = reinterpret_cast<double *>(s.fbpart); a.sci = 2; a.scj = 2L * s.G; a.scb = 1;
+  a.scs = 2L * W * s.G;
+  return gemm_f64(a, st);
+}
+
+// ---- two-body generator: vhs[w][c][pq] = sum_g yp[w][c][g] L[g][pq] ----------
+hipError_t launch_vhs(const System &s, int W, hipStream_t st) {
+  const long MM = (long)s.M * s.M;
+  GemmArgs a;
+  a.m = 2 * W; a.n = (int)MM; a.k = s.G;
+  a.A = s.yp; a.sai = s.G; a.sak = 1;
+  a.B = s.L; a.sbk = MM; a.sbj = 1;
+  a.C = s.vhs; a.sci = MM; a.scj = 1;
+  return gemm_f64(a, st);
+}
+
+// ---- one-body half step: out_w = B1 in_w (complex columns as real pairs) -----
+hipError_t launch_b1(const System &s, const double2 *in, double2 *out, int W, hipStream_t st) {
+  const long n2 = 2L * s.Nt;
+  GemmArgs a;
+  a.m = s.M; a.n = (int)n2; a.k = s.M; a.batch = W;
+  a.A = s.B1; a.sai = s.M; a.sak = 1; a.sab = 0;
+  a.B = reinterpret_cast<const double *>(in); a.sbk = n2; a.sbj = 1; a.sbb = (long)s.M * n2;
+  a.C = reinterpret_cast<double *>(out); a.sci = n2; a.scj = 1; a.scb = (long)s.M * n2;
+  return gemm_f64(a, st);
+}
+
+// ---- Taylor term: tout = alpha (Ar + i Ai) tin, tacc += tout -----------------
+// Tile: 64 rows x 16 complex columns per workgroup; each thread owns 4 rows of
+// one column.  Ar/Ai rows are contiguous in the contraction index.
+__global__ __launch_bounds__(kThreads) void k_taylor_term(const double *__restrict__ vhs,
+                                                         const double2 *__restrict__ tin,
+                                                         double2 *__restrict__ tout,
+                                                         double2 *__restrict__ tacc, int M, int Nt,
+                                                         double alpha) {
+  __shared__ double Ar[TBK][TBM + 4];
+  __shared__ double Ai[TBK][TBM + 4];
+  __shared__ double2 Ts[TBK][16];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int j0 = blockIdx.x * 16, i0 = blockIdx.y * TBM, w = blockIdx.z;
+  const size_t MM = (size_t)M * M;
+  const double *ar = vhs + (size_t)w * 2 * MM;
+  const double *ai = ar + MM;
+  const double2 *t = tin + (size_t)w * M * Nt;
+  double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < M; k0 += TBK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kk = tid & 15, ii = (tid >> 4) + 16 * r;
+      const int gi = i0 + ii, gk = k0 + kk;
+      const bool ok = gi < M && gk < M;
+      Ar[kk][ii] = ok ? ar[(size_t)gi * M + gk] : 0.0;
+      Ai[kk][ii] = ok ? ai[(size_t)gi * M + gk] : 0.0;
+    }
+    {
+      const int kk = tid >> 4, jj = tid & 15;
+      const int gk = k0 + kk, gj = j0 + jj;
+      Ts[kk][jj] = (gk < M && gj < Nt) ? t[(size_t)gk * Nt + gj] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TBK; ++kk) {
+      const double2 b = Ts[kk][tx];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double xr = Ar[kk][ty * 4 + r], xi = Ai[kk][ty * 4 + r];
+        re[r] = fma(xr, b.x, fma(-xi, b.y, re[r]));
+        im[r] = fma(xr, b.y, fma(xi, b.x, im[r]));
+      }
+    }
+    __syncthreads();
+  }
+  const int gj = j0 + tx;
+  if (gj >= Nt) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int gi = i0 + ty * 4 + r;
+    if (gi >= M) continue;
+    const size_t e = (size_t)w * M * Nt + (size_t)gi * Nt + gj;
+    const double2 v = make_double2(alpha * re[r], alpha * im[r]);
+    tout[e] = v;
+    tacc[e] = cadd(tacc[e], v);
+  }
+}
+
+hipError_t launch_taylor_term(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
+                              hipStream_t st) {
+  dim3 grid((s.Nt + 15) / 16, (s.M + TBM - 1) / TBM, W);
+  hipLaunchKernelGGL(k_taylor_term, grid, dim3(kThreads), 0, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt,
+                     alpha);
+  return hipGetLastError();
+}
+
+}  // namespace afqmc

@@ -1,0 +1,228 @@
+// Overlap, log-determinant and Green's-function factor of every walker, and the
+// modified Gram-Schmidt re-orthogonalisation.  FP64 throughout.
+//
+// Overlap (Sec. 2, eq. ovlp_ratio and the walker expansion): for each spin block
+// O_s = Psi_s^T phi_s (N_s x N_s), <Psi_T|phi> = prod_s det O_s, and the mixed
+// Green's function G^s_pq = <a+_p a_q> = sum_i Psi_pi Theta_qi with
+// Theta_s = phi_s O_s^-1.  One workgroup per walker holds O_s in LDS and inverts
+// it in place by Gauss-Jordan elimination with partial (row) pivoting; the
+// pivots give the determinant.
+#include "afqmc_internal.h"
+#include "device_util.h"
+
+namespace afqmc {
+
+__global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restrict__ phi,
+                                                        const double *__restrict__ trial, int M, int Na,
+                                                        int Nb, double2 *__restrict__ theta,
+                                                        double2 *__restrict__ logo,
+                                                        uint32_t *__restrict__ stat,
+                                                        uint32_t *__restrict__ flags_or) {
+  extern __shared__ double2 sA[];  // [N][N]
+  __shared__ double2 scol[kMaxSpinOrbitals];
+  __shared__ int spiv[kMaxSpinOrbitals];
+  __shared__ double2 spivval;
+  __shared__ int ssing;
+
+  const int w = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int Nt = Na + Nb;
+  const double2 *ph = phi + (size_t)w * M * Nt;
+  double lre = 0.0, lim = 0.0;  // log det accumulated by thread 0
+  int singular = 0;
+
+  for (int s = 0; s < 2 && !singular; ++s) {
+    const int N = s ? Nb : Na;
+    const int off = s ? Na : 0;
+    if (N == 0) continue;
+    // O = Psi_s^T phi_s
+    for (int e = tid; e < N * N; e += blockDim.x) {
+      const int i = e / N, j = e - (e / N) * N;
+      double re = 0.0, im = 0.0;
+      for (int q = 0; q < M; ++q) {
+        const double t = trial[(size_t)q * Nt + off + i];
+        const double2 p = ph[(size_t)q * Nt + off + j];
+        re = fma(t, p.x, re);
+        im = fma(t, p.y, im);
+      }
+      sA[e] = make_double2(re, im);
+    }
+    if (tid == 0) ssing = 0;
+    __syncthreads();
+
+    for (int k = 0; k < N; ++k) {
+      // pivot: largest |A_ik| for i >= k (first index on ties), found by wave 0
+      if (tid < 64) {
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < N; i += 64) {
+          const double a = cabs2(sA[i * N + k]);
+          if (a > best) { best = a; bi = i; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ob = __shfl_down(best, o, 64);
+          const int oi = __shfl_down(bi, o, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (tid == 0) {
+          spiv[k] = bi;
+          const double2 pv = sA[bi * N + k];
+          spivval = pv;
+          if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) ssing = 1;
+        }
+      }
+      __syncthreads();
+      if (ssing) break;
+      const int p = spiv[k];
+      const double2 pv = spivval;
+      if (p != k) {
+        for (int j = tid; j < N; j += blockDim.x) {
+          const double2 a = sA[k * N + j];
+          sA[k * N + j] = sA[p * N + j];
+          sA[p * N + j] = a;
+        }
+      }
+      if (tid == 0) {
+        lre += 0.5 * log(cabs2(pv));
+        lim += atan2(pv.y, pv.x) + (p != k ? 3.14159265358979323846 : 0.0);
+      }
+      __syncthreads();
+      // save column k of the other rows, then scale the pivot row (the pivot
+      // position becomes 1 / pivot); the two touch disjoint entries
+      const double2 inv = cdiv(make_double2(1.0, 0.0), pv);
+      for (int i = tid; i < N; i += blockDim.x)
+        if (i != k) scol[i] = sA[i * N + k];
+      for (int j = tid; j < N; j += blockDim.x) {
+        const double2 a = (j == k) ? make_double2(1.0, 0.0) : sA[k * N + j];
+        sA[k * N + j] = cmul(a, inv);
+      }
+      __syncthreads();
+      // eliminate column k from every other row
+      for (int e = tid; e < N * N; e += blockDim.x) {
+        const int i = e / N, j = e - (e / N) * N;
+        if (i == k) continue;
+        const double2 a = (j == k) ? make_double2(0.0, 0.0) : sA[e];
+        sA[e] = csub(a, cmul(scol[i], sA[k * N + j]));
+      }
+      __syncthreads();
+    }
+    if (ssing) {
+      singular = 1;
+      break;
+    }
+    // undo the row interchanges as column interchanges, last first
+    for (int k = N - 1; k >= 0; --k) {
+      const int p = spiv[k];
+      if (p != k) {
+        for (int i = tid; i < N; i += blockDim.x) {
+          const double2 a = sA[i * N + k];
+          sA[i * N + k] = sA[i * N + p];
+          sA[i * N + p] = a;
+        }
+      }
+      __syncthreads();
+    }
+    // Theta_s = phi_s O_s^-1
+    if (theta) {
+      double2 *th = theta + (size_t)w * M * Nt;
+      for (int e = tid; e < M * N; e += blockDim.x) {
+        const int q = e / N, j = e - (e / N) * N;
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < N; ++k) {
+          const double2 p = ph[(size_t)q * Nt + off + k];
+          const double2 x = sA[k * N + j];
+          re += p.x * x.x - p.y * x.y;
+          im += p.x * x.y + p.y * x.x;
+        }
+        th[(size_t)q * Nt + off + j] = make_double2(re, im);
+      }
+    }
+    __syncthreads();
+  }
+
+  if (singular && theta) {
+    double2 *th = theta + (size_t)w * M * Nt;
+    for (int e = tid; e < M * Nt; e += blockDim.x) th[e] = make_double2(0.0, 0.0);
+  }
+  if (tid == 0) {
+    logo[w] = singular ? make_double2(0.0, 0.0) : make_double2(lre, wrap_phase(lim));
+    if (stat) stat[w] = singular ? (uint32_t)AFQMC_W_SINGULAR : 0u;
+    if (flags_or && singular) flags_or[w] |= AFQMC_W_SINGULAR;
+  }
+}
+
+hipError_t launch_ovlp_theta(const double2 *phi, const double *trial, int M, int Na, int Nb, int W,
+                             double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or,
+                             hipStream_t st) {
+  const int nmax = Na > Nb ? Na : Nb;
+  const size_t lds = (size_t)nmax * nmax * sizeof(double2);
+  hipLaunchKernelGGL(k_ovlp_theta, dim3(W), dim3(kThreads), lds, st, phi, trial, M, Na, Nb, theta, logo,
+                     stat, flags_or);
+  return hipGetLastError();
+}
+
+// Modified Gram-Schmidt of each spin block: for k = 0..N-1, r_kk = |phi_k|,
+// phi_k /= r_kk, r_kj = phi_k^H phi_j and phi_j -= r_kj phi_k for j > k.
+// One workgroup per walker; wave v handles columns j = k+1+v, k+1+v+4, ...
+__global__ __launch_bounds__(kThreads) void k_mgs(double2 *__restrict__ phi, int M, int Na, int Nb,
+                                                 double2 *__restrict__ logo) {
+  __shared__ double2 sr[kMaxSpinOrbitals];
+  __shared__ double snorm;
+  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  const int Nt = Na + Nb;
+  double2 *ph = phi + (size_t)w * M * Nt;
+  double logr = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int N = s ? Nb : Na;
+    const int off = s ? Na : 0;
+    for (int k = 0; k < N; ++k) {
+      const int ck = off + k;
+      if (wid == 0) {
+        double a = 0.0;
+        for (int q = lane; q < M; q += 64) a += cabs2(ph[(size_t)q * Nt + ck]);
+        a = wave_sum(a);
+        if (lane == 0) snorm = sqrt(a);
+      }
+      __syncthreads();
+      const double r = snorm;
+      const double ir = 1.0 / r;
+      for (int q = tid; q < M; q += blockDim.x) {
+        const size_t e = (size_t)q * Nt + ck;
+        ph[e] = cscale(ph[e], ir);
+      }
+      if (tid == 0) logr += log(r);
+      __syncthreads();
+      for (int j = k + 1 + wid; j < N; j += nw) {
+        double re = 0.0, im = 0.0;
+        for (int q = lane; q < M; q += 64) {
+          const double2 a = ph[(size_t)q * Nt + ck];
+          const double2 b = ph[(size_t)q * Nt + off + j];
+          re += a.x * b.x + a.y * b.y;  // conj(a) b
+          im += a.x * b.y - a.y * b.x;
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) sr[j] = make_double2(re, im);
+      }
+      __syncthreads();
+      const int nrest = N - k - 1;
+      for (int e = tid; e < M * nrest; e += blockDim.x) {
+        const int q = e / nrest, j = k + 1 + (e - (e / nrest) * nrest);
+        const double2 a = ph[(size_t)q * Nt + ck];
+        const size_t ej = (size_t)q * Nt + off + j;
+        ph[ej] = csub(ph[ej], cmul(sr[j], a));
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) logo[w].x -= logr;
+}
+
+hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st) {
+  hipLaunchKernelGGL(k_mgs, dim3(W), dim3(kThreads), 0, st, phi, M, Na, Nb, logo);
+  return hipGetLastError();
+}
+
+}  // namespace afqmc

@@ -1,0 +1,132 @@
+"""The C ABI library loads, exports every declared entry point and rejects bad
+arguments before touching the device (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2406_16238_amd import afqmc as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(A.LIB_PATH):
+        from paper_2406_16238_amd import build
+        build.build()
+    return A.load_library()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "afqmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(afqmc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(A.EXPORTS)
+
+
+def test_default_options(lib):
+    o = A.default_options()
+    assert o.precision == A.FP64 and o.taylor_order == 6 and o.fb_cap == 1.0
+    assert math.isnan(o.e_shift) and o.mem_limit_bytes == 0
+    assert lib.afqmc_default_options(None) == A.ERR_ARG
+
+
+def _desc(m=6, na=2, nb=2, g=4, w=3, dt=0.01):
+    h1 = np.eye(m)
+    chol = np.zeros((g, m, m))
+    trial = np.zeros((m, na + nb))
+    keep = (h1, chol, trial)
+    d = A.SystemDesc(m, na, nb, g, w, h1.ctypes.data, chol.ctypes.data, 0.0, trial.ctypes.data, dt)
+    return d, keep
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("nbasis", 0, A.ERR_ARG), ("nchol", -1, A.ERR_ARG), ("nwalkers", 0, A.ERR_ARG),
+    ("nalpha", 7, A.ERR_ARG), ("dt", 0.0, A.ERR_ARG), ("dt", float("nan"), A.ERR_ARG),
+    ("ecore", float("inf"), A.ERR_ARG), ("h1", None, A.ERR_ARG), ("trial", None, A.ERR_ARG),
+])
+def test_setup_rejects_bad_descriptions(lib, field, value, status):
+    d, keep = _desc()
+    setattr(d, field, value)
+    out = ctypes.c_void_p(123)
+    r = lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, None, None, ctypes.byref(out))
+    assert r == status
+    assert out.value is None
+    assert len(A.last_error()) > 0
+
+
+def test_setup_rejects_wide_spin_blocks(lib):
+    d, keep = _desc(m=80, na=60, nb=2)
+    out = ctypes.c_void_p()
+    assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, None, None, ctypes.byref(out)) == A.ERR_UNSUPPORTED
+
+
+def test_setup_rejects_bad_options(lib):
+    d, keep = _desc()
+    out = ctypes.c_void_p()
+    for field, value in (("taylor_order", 0), ("taylor_order", 17), ("precision", 9), ("fb_cap", float("nan"))):
+        o = A.default_options()
+        setattr(o, field, value)
+        assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, ctypes.byref(o), None, ctypes.byref(out)) \
+            == A.ERR_ARG, field
+    assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 0, None, None, ctypes.byref(out)) == A.ERR_ARG
+    assert lib.afqmc_setup_hamiltonian(None, 1, None, None, ctypes.byref(out)) == A.ERR_ARG
+    assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, None, None, None) == A.ERR_ARG
+
+
+def test_step_calls_reject_null_context(lib):
+    w = A.CWalkers()
+    assert lib.afqmc_propagate(None, ctypes.byref(w), None, None) == A.ERR_ARG
+    assert lib.afqmc_local_energy(None, ctypes.byref(w), None, None, None) == A.ERR_ARG
+    assert lib.afqmc_reorthogonalize(None, ctypes.byref(w), None) == A.ERR_ARG
+    assert lib.afqmc_overlap(None, None, None) == A.ERR_ARG
+    assert lib.afqmc_greens_function(None, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_force_bias(None, None, None, None) == A.ERR_ARG
+    info = A.Info()
+    assert lib.afqmc_get_info(None, 0, ctypes.byref(info)) == A.ERR_ARG
+    assert lib.afqmc_set_timing(None, 1) == A.ERR_ARG
+    assert lib.afqmc_get_timings(None, None) == A.ERR_ARG
+    lib.afqmc_destroy(None)  # no-op
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes layouts equal what a C compiler makes of include/afqmc.h."""
+    import subprocess
+    fields = {"afqmc_system_desc": (A.SystemDesc, ["nbasis", "nalpha", "nbeta", "nchol", "nwalkers", "h1", "chol",
+                                                   "ecore", "trial", "dt"]),
+              "afqmc_options": (A.Options, ["precision", "taylor_order", "fb_cap", "e_shift", "mem_limit_bytes",
+                                            "reserved"]),
+              "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
+              "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes"]),
+              "afqmc_timings": (A.Timings, ["ms", "count"])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "afqmc.h"', "int main(void) {"]
+    for cname, (_, fl) in fields.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fl:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, (cls, fl) in fields.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in fl:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
