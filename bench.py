@@ -147,7 +147,7 @@ def main(argv=None):
     achieved = ex_flops / (ex_ms / ex_n * 1e-3) / 1e12 if ex_n else 0.0
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None,
-                "kernel": "exchange (k_exchange_v1)", "avg_launch_ms": round(ex_ms / max(ex_n, 1), 4),
+                "kernel": "exchange (k_exchange_mfma)", "avg_launch_ms": round(ex_ms / max(ex_n, 1), 4),
                 "flops_per_launch": ex_flops}
     step_tf = step_flops(M, s.nalpha, s.nbeta, G) * W / (ms_per_step * 1e-3) / 1e12
 

@@ -80,7 +80,10 @@ typedef struct {
   double fb_cap;            /* force-bias modulus cap; default 1.0, <= 0 disables  */
   double e_shift;           /* energy shift E_T; NaN (default) = the trial's E_HF  */
   uint64_t mem_limit_bytes; /* refuse set-up needing more device memory; 0 = none  */
-  int32_t reserved[8];
+  int32_t reserved[8];      /* reserved[0] bit 0: VALU (non-MFMA) exchange kernel;
+                               bit 1: VALU kernels for the force bias, V_HS, B1
+                               and Taylor products (both for comparison runs);
+                               other bits and entries: zero                       */
 } afqmc_options;
 
 /* Walker state of one system; every pointer is device memory owned by the caller. */

@@ -31,6 +31,14 @@ constexpr int kThreads = 256;
 //   stat_now, stat_new [W] uint32    singular markers of the two LU passes
 //   wsc    [W][6]                    sum x.xbar, sum xbar.xbar, sum y.l (complex)
 //   e1, ej [W] double2; ekpart [W][2][ngb] double2
+// Launch plan of the MFMA exchange kernel for one spin block of width N.
+struct ExchangePlan {
+  int N = 0, NR = 0, GC = 1, RT = 0, CT = 0, ngb = 0;
+  size_t lds = 0;
+  bool mfma = false;
+};
+ExchangePlan exchange_plan(int N, int G);
+
 struct System {
   int M = 0, Na = 0, Nb = 0, Nt = 0, G = 0, W = 0;
   double dt = 0, sqdt = 0, ecore = 0, e_hf = 0, e_shift = 0, const_c = 0;
@@ -43,9 +51,14 @@ struct System {
   uint32_t *stat_now = nullptr, *stat_new = nullptr;
 
   int fb_ksplit = 1;  // split-K slices of the force-bias contraction
-  int ex_gb = 1;      // Cholesky vectors per exchange workgroup
-  int ex_ngb = 1;     // number of exchange workgroups along G
-  size_t ex_lds = 0;  // dynamic LDS of the exchange kernel
+  int ex_gb = 1;      // Cholesky vectors per workgroup of the VALU exchange kernel
+  int ex_ngb = 1;     // its number of workgroups along G
+  size_t ex_lds = 0;  // its dynamic LDS
+  bool use_mfma_gemm = true;   // MFMA kernels for force bias, V_HS, B1 and Taylor terms
+  bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
+  ExchangePlan ex_plan[2];     // its per-spin plans
+  int ex_stride = 1;           // partials per (walker, spin) in ekpart
+  int ex_nparts[2] = {0, 0};   // partials actually written per spin
 };
 
 struct Options {
@@ -65,13 +78,26 @@ struct GemmArgs {
   const double *B = nullptr; long sbk = 0, sbj = 0, sbb = 0;
   double *C = nullptr; long sci = 0, scj = 0, scb = 0, scs = 0;
   double alpha = 1.0, beta = 0.0;
+  // MFMA GEMM extras: contraction split point and plane offset of a complex A
+  // held as planes, a second output accumulated with the same values, and
+  // interleaved-complex output rows.
+  int khalf = 0;
+  long aplane = 0;
+  double *C2 = nullptr;
+  int cplx_rows = 0;
 };
 hipError_t gemm_f64(const GemmArgs &a, hipStream_t st);
+hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st);
+hipError_t gemm_b1_mfma(const GemmArgs &a, hipStream_t st);
+hipError_t gemm_taylor_mfma(const GemmArgs &a, hipStream_t st);
+hipError_t gemm_fb_mfma(const GemmArgs &a, hipStream_t st);
+hipError_t gemm_nn_mfma(const GemmArgs &a, hipStream_t st);
 
 // Overlap, log-determinant and (optionally) Theta for every walker.
 hipError_t launch_ovlp_theta(const double2 *phi, const double *trial, int M, int Na, int Nb, int W,
                              double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or,
                              hipStream_t st);
+hipError_t ovlp_enable_lds(int nmax);
 // Modified Gram-Schmidt per spin block, log_ovlp -= sum log R_ii.
 hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st);
 
@@ -94,6 +120,7 @@ hipError_t launch_weight_update(const System &s, const afqmc_walkers &w, int W, 
 // Energies.
 hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStream_t st);
 hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st);
+hipError_t exchange_enable_lds(const System &s);
 hipError_t launch_energy_combine(const System &s, int W, double2 *e_out, hipStream_t st);
 hipError_t launch_estimator(const double *weight, const double2 *e_out, int W, double *est, hipStream_t st);
 

@@ -36,6 +36,8 @@ struct afqmc_ctx {
   Options opt;
   int device = 0;
   std::vector<void *> allocs;
+  bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
+  bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   // phase timers
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -166,13 +168,14 @@ Plan plan_for(const System &s) {
   p.tbuf = W * M * Nt;
   p.wsc = 6 * W;
   p.wvec2 = W;  // logo_now, logo_new, e1, ej (+1 spare)
-  p.ekpart = W * 2 * (size_t)s.ex_ngb;
+  p.ekpart = W * 2 * (size_t)s.ex_stride;
   p.stat = W;
   return p;
 }
 
 int choose_fb_ksplit(int W, int G, long K) {
-  const long tiles = 2L * ((W + 63) / 64) * ((G + 63) / 64);
+  // 64 x 64 output tiles over (2W rows) x (G columns)
+  const long tiles = (long)((2 * W + 63) / 64) * ((G + 63) / 64);
   long ks = (1024 + tiles - 1) / tiles;
   ks = std::min(ks, std::max(1L, K / 512));
   return (int)std::max(1L, std::min(ks, 64L));
@@ -264,9 +267,20 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   if (nmax > kMaxSpinOrbitals)
     return fail(AFQMC_ERR_UNSUPPORTED, "a spin block wider than " + std::to_string(kMaxSpinOrbitals) +
                                            " orbitals is not supported");
+  s.use_mfma_gemm = !c->force_valu_gemm;
   s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
   exchange_geometry(nmax, &s.ex_gb, &s.ex_lds);
   s.ex_ngb = (s.G + s.ex_gb - 1) / s.ex_gb;
+  s.ex_plan[0] = exchange_plan(s.Na, s.G);
+  s.ex_plan[1] = exchange_plan(s.Nb, s.G);
+  s.ex_mfma = (s.Na == 0 || s.ex_plan[0].mfma) && (s.Nb == 0 || s.ex_plan[1].mfma) && !c->force_valu_exchange;
+  if (s.ex_mfma) {
+    s.ex_nparts[0] = s.ex_plan[0].ngb;
+    s.ex_nparts[1] = s.ex_plan[1].ngb;
+    s.ex_stride = std::max(1, std::max(s.ex_nparts[0], s.ex_nparts[1]));
+  } else {
+    s.ex_nparts[0] = s.ex_nparts[1] = s.ex_stride = s.ex_ngb;
+  }
   const Plan p = plan_for(s);
   const size_t M = s.M, Nt = s.Nt, G = s.G;
   const uint64_t setup_tmp = 8ull * (4 * M * M + M * M * 64 + M * M + G) + 16ull * (M * Nt + 3);
@@ -283,6 +297,8 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
             dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat);
   if (!ok) return fail(AFQMC_ERR_OOM, "device allocation failed");
   *bytes_used += s.bytes;
+  AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
+  AFQMC_HIP(ovlp_enable_lds(nmax), "overlap kernel LDS attribute");
 
   const size_t mm = M * M;
   AFQMC_HIP(hipMemcpyAsync(s.L, d.chol, p.L * sizeof(double), hipMemcpyHostToDevice, st), "upload chol");
@@ -425,6 +441,8 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->opt.precision = o.precision;
   c->opt.taylor_order = o.taylor_order;
   c->opt.fb_cap = o.fb_cap;
+  c->force_valu_exchange = (o.reserved[0] & 1) != 0;
+  c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   (void)hipGetDevice(&c->device);
   c->sys.resize(nsys);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);

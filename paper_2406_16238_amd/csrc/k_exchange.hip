@@ -127,11 +127,219 @@ __global__ __launch_bounds__(kThreads) void k_exchange_v1(const double *__restri
   if (tid == 0) ekpart[((size_t)w * 2 + s) * ngb + gb] = make_double2(-0.5 * part[0], -0.5 * part[1]);
 }
 
+// ---- MFMA form ---------------------------------------------------------------
+// For one spin block the exchange matrices of all Cholesky vectors and all
+// walkers are one real GEMM
+//   C[(g, i)][(w, c)] = sum_q Ltilde[g][i][q] * Theta_w[q][c],  c = 2 j + {re, im},
+// A = the half-rotated vectors (rows (g, i), padded to NR rows per g), B = the
+// walkers' Theta with interleaved complex columns (padded to CP per walker).
+// A workgroup owns GC whole Cholesky vectors (RT = GC*NR/16 row tiles) and four
+// whole walkers (one per wave, CT = CP/16 column tiles), so every T^{g}_w is
+// complete inside one wave and the trace needs no other workgroup.  The K loop
+// stages 16 contraction rows of A and B in LDS (double-buffered through
+// registers) and issues RT*CT v_mfma_f64_16x16x4f64 per 4 rows.
+// MFMA lane layout (16x16x4, f64): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator item r of lane l is D[l/16 + 4 r][l%16].
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int XKC = 16;     // contraction rows per LDS stage
+constexpr int XWALK = 4;    // walkers per workgroup (one per wave)
+}  // namespace
+
+template <int RT, int CT>
+__global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__restrict__ LtT,
+                                                           const double *__restrict__ theta, int M, int Nt,
+                                                           int off, int N, int NR, int GC, int G, int W,
+                                                           int stride, int spin, double2 *__restrict__ ekpart) {
+  constexpr int ROWS = RT * 16;
+  constexpr int CP = CT * 16;
+  constexpr int ASZ = XKC * ROWS;            // doubles per A stage
+  constexpr int BSZ = XWALK * XKC * CP;      // doubles per B stage
+  constexpr int APT = ASZ / kThreads;        // = RT
+  constexpr int BPT = BSZ / kThreads;        // = 4 * CT
+  extern __shared__ double smem[];
+  double *sA = smem;                 // [2][XKC][ROWS]
+  double *sB = smem + 2 * ASZ;       // [2][XWALK][XKC][CP]
+
+  const int gb = blockIdx.x, wb = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g0 = gb * GC, w0 = wb * XWALK;
+  const int twoN = 2 * N;
+  const size_t wstride = (size_t)M * Nt * 2;  // doubles per walker
+
+  double ra[APT], rb[BPT];
+  auto load = [&](int q0) {
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * kThreads;
+      const int q = e / ROWS, row = e - q * ROWS;
+      const int gl = row / NR, i = row - gl * NR;
+      const int g = g0 + gl, gq = q0 + q;
+      ra[r] = (i < N && g < G && gq < M) ? LtT[((size_t)g * M + gq) * Nt + off + i] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = tid + r * kThreads;
+      const int c = e % CP, t = e / CP;
+      const int q = t % XKC, wl = t / XKC;
+      const int w = w0 + wl, gq = q0 + q;
+      rb[r] = (c < twoN && w < W && gq < M) ? theta[(size_t)w * wstride + (size_t)gq * Nt * 2 + 2 * off + c] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+    double *a = sA + buf * ASZ;
+    double *b = sB + buf * BSZ;
+#pragma unroll
+    for (int r = 0; r < APT; ++r) a[tid + r * kThreads] = ra[r];
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) b[tid + r * kThreads] = rb[r];
+  };
+
+  dvec4 acc[RT][CT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = dvec4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunk = (M + XKC - 1) / XKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * XKC);
+    const double *a = sA + buf * ASZ;
+    const double *b = sB + buf * BSZ + wv * XKC * CP;
+#pragma unroll
+    for (int ks = 0; ks < XKC / 4; ++ks) {
+      double av[RT], bv[CT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) av[i] = a[(ks * 4 + lk) * ROWS + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) bv[j] = b[(ks * 4 + lk) * CP + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: one Cholesky vector at a time, each wave writes its walker's T
+  // (N rows x 2N interleaved columns) to its own LDS region and forms
+  // sum_ij T_ij T_ji.
+  double *sT = smem + (size_t)wv * N * twoN;
+  const int w = w0 + wv;
+  double pre = 0.0, pim = 0.0;
+  for (int gl = 0; gl < GC; ++gl) {
+    const int rbase = gl * NR;
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i * 16 + lk + 4 * r - rbase;
+          const int col = j * 16 + lr;
+          if (row >= 0 && row < N && col < twoN) sT[row * twoN + col] = acc[i][j][r];
+        }
+    __syncthreads();
+    if (g0 + gl < G && w < W) {
+      for (int e = lane; e < N * N; e += 64) {
+        const int i = e / N, j = e - i * N;
+        const double ar = sT[i * twoN + 2 * j], ai = sT[i * twoN + 2 * j + 1];
+        const double br = sT[j * twoN + 2 * i], bi = sT[j * twoN + 2 * i + 1];
+        pre += ar * br - ai * bi;
+        pim += ar * bi + ai * br;
+      }
+    }
+    __syncthreads();
+  }
+  pre = wave_sum(pre);
+  pim = wave_sum(pim);
+  if (lane == 0 && w < W) ekpart[((size_t)w * 2 + spin) * stride + gb] = make_double2(-0.5 * pre, -0.5 * pim);
+}
+
+namespace {
+
+using ExKernel = void (*)(const double *, const double *, int, int, int, int, int, int, int, int, int, int,
+                          double2 *);
+
+template <int RT>
+ExKernel pick_ct(int ct) {
+  switch (ct) {
+    case 1: return k_exchange_mfma<RT, 1>;
+    case 2: return k_exchange_mfma<RT, 2>;
+    case 3: return k_exchange_mfma<RT, 3>;
+    case 4: return k_exchange_mfma<RT, 4>;
+    case 5: return k_exchange_mfma<RT, 5>;
+    case 6: return k_exchange_mfma<RT, 6>;
+    default: return nullptr;
+  }
+}
+
+ExKernel pick_exchange(int rt, int ct) {
+  switch (rt) {
+    case 1: return pick_ct<1>(ct);
+    case 2: return pick_ct<2>(ct);
+    case 3: return pick_ct<3>(ct);
+    case 5: return pick_ct<5>(ct);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+ExchangePlan exchange_plan(int N, int G) {
+  ExchangePlan p;
+  p.N = N;
+  if (N <= 0) return p;
+  p.NR = ((N + 7) / 8) * 8;
+  p.GC = (p.NR % 16 == 0) ? 1 : 2;
+  p.RT = p.GC * p.NR / 16;
+  p.CT = (2 * N + 15) / 16;
+  p.ngb = (G + p.GC - 1) / p.GC;
+  const size_t stage = 2ull * (XKC * p.RT * 16 + XWALK * XKC * p.CT * 16) * sizeof(double);
+  const size_t epi = (size_t)XWALK * N * 2 * N * sizeof(double);
+  p.lds = stage > epi ? stage : epi;
+  p.mfma = pick_exchange(p.RT, p.CT) != nullptr && p.lds <= 160 * 1024;
+  if (!p.mfma) p.ngb = 0;
+  return p;
+}
+
 hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st) {
+  if (s.ex_mfma) {
+    for (int spin = 0; spin < 2; ++spin) {
+      const ExchangePlan &p = s.ex_plan[spin];
+      if (p.N == 0) continue;
+      ExKernel k = pick_exchange(p.RT, p.CT);
+      dim3 grid(p.ngb, (W + XWALK - 1) / XWALK);
+      hipLaunchKernelGGL(k, grid, dim3(kThreads), p.lds, st, s.LtT, reinterpret_cast<const double *>(theta), s.M,
+                         s.Nt, spin ? s.Na : 0, p.N, p.NR, p.GC, s.G, W, s.ex_stride, spin, s.ekpart);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   dim3 grid(s.ex_ngb, 2, W);
   hipLaunchKernelGGL(k_exchange_v1, grid, dim3(kThreads), s.ex_lds, st, s.LtT, theta, s.M, s.Na, s.Nb, s.G,
                      s.ex_gb, s.ex_ngb, s.ekpart);
   return hipGetLastError();
+}
+
+hipError_t exchange_enable_lds(const System &s) {
+  if (!s.ex_mfma) return hipSuccess;
+  for (int spin = 0; spin < 2; ++spin) {
+    const ExchangePlan &p = s.ex_plan[spin];
+    if (p.N == 0) continue;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_exchange(p.RT, p.CT)),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace afqmc

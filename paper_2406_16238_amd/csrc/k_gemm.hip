@@ -97,9 +97,19 @@ hipError_t gemm_f64(const GemmArgs &a, hipStream_t st) {
 }
 
 // ---- force bias: vbias[w][g] = sum_k LtT[g][k] Theta[w][k], k = (q, i') -----
+// MFMA form: rows (w, re/im) of the walker slabs times the half-rotated vectors,
+// split over K; VALU form: the strided GEMM above with the roles swapped.
 hipError_t launch_force_bias_gemm(const System &s, const double2 *theta, int W, hipStream_t st) {
   const long K = (long)s.M * s.Nt;
   GemmArgs a;
+  if (s.use_mfma_gemm) {
+    a.m = 2 * W; a.n = s.G; a.k = (int)K; a.ksplit = s.fb_ksplit;
+    a.A = reinterpret_cast<const double *>(theta); a.sai = 2 * K;
+    a.B = s.LtT; a.sbj = K;
+    a.C = reinterpret_cast<double *>(s.fbpart); a.sci = 2L * s.G; a.scj = 2; a.scs = 2L * W * s.G;
+    a.cplx_rows = 1;
+    return gemm_fb_mfma(a, st);
+  }
   a.m = s.G; a.n = W; a.k = (int)K; a.batch = 2; a.ksplit = s.fb_ksplit;
   a.A = s.LtT; a.sai = K; a.sak = 1; a.sab = 0;
   a.B = reinterpret_cast<const double *>(theta); a.sbk = 2; a.sbj = 2 * K; a.sbb = 1;
@@ -116,7 +126,7 @@ hipError_t launch_vhs(const System &s, int W, hipStream_t st) {
   a.A = s.yp; a.sai = s.G; a.sak = 1;
   a.B = s.L; a.sbk = MM; a.sbj = 1;
   a.C = s.vhs; a.sci = MM; a.scj = 1;
-  return gemm_f64(a, st);
+  return s.use_mfma_gemm ? gemm_vhs_mfma(a, st) : gemm_f64(a, st);
 }
 
 // ---- one-body half step: out_w = B1 in_w (complex columns as real pairs) -----
@@ -127,7 +137,7 @@ hipError_t launch_b1(const System &s, const double2 *in, double2 *out, int W, hi
   a.A = s.B1; a.sai = s.M; a.sak = 1; a.sab = 0;
   a.B = reinterpret_cast<const double *>(in); a.sbk = n2; a.sbj = 1; a.sbb = (long)s.M * n2;
   a.C = reinterpret_cast<double *>(out); a.sci = n2; a.scj = 1; a.scb = (long)s.M * n2;
-  return gemm_f64(a, st);
+  return s.use_mfma_gemm ? gemm_b1_mfma(a, st) : gemm_f64(a, st);
 }
 
 // ---- Taylor term: tout = alpha (Ar + i Ai) tin, tacc += tout -----------------
@@ -190,6 +200,18 @@ __global__ __launch_bounds__(kThreads) void k_taylor_term(const double *__restri
 
 hipError_t launch_taylor_term(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
                               hipStream_t st) {
+  if (s.use_mfma_gemm) {
+    // [Re A | Im A] (M x 2M) times [T ; iT] (2M x 2Nt) per walker
+    const long n2 = 2L * s.Nt, MM = (long)s.M * s.M;
+    GemmArgs a;
+    a.m = s.M; a.n = (int)n2; a.k = 2 * s.M; a.batch = W;
+    a.A = s.vhs; a.sai = s.M; a.sab = 2 * MM; a.khalf = s.M; a.aplane = MM;
+    a.B = reinterpret_cast<const double *>(tin); a.sbk = n2; a.sbb = (long)s.M * n2;
+    a.C = reinterpret_cast<double *>(tout); a.sci = n2; a.scj = 1; a.scb = (long)s.M * n2;
+    a.C2 = reinterpret_cast<double *>(s.tacc);
+    a.alpha = alpha;
+    return gemm_taylor_mfma(a, st);
+  }
   dim3 grid((s.Nt + 15) / 16, (s.M + TBM - 1) / TBM, W);
   hipLaunchKernelGGL(k_taylor_term, grid, dim3(kThreads), 0, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt,
                      alpha);

@@ -1,0 +1,245 @@
+// FP64 MFMA GEMM for the dense contractions of the propagation step.
+//
+//   C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j)   [and C2(i,j) += that value]
+//
+// Workgroup tile BM x BN = (WM*TM*16) x (WN*TN*16) on a WM x WN grid of waves,
+// each wave owning TM x TN accumulators of v_mfma_f64_16x16x4f64.  The K loop
+// stages 16 contraction indices of A and B in LDS (k-major, so every MFMA
+// operand fragment is 16 consecutive doubles), double-buffered through
+// registers.  Operand access modes:
+//   A mode 0: A(i,k) = A[i*sai + k]                (k contiguous)
+//   A mode 1: A(i,k) = A[i + k*sak]                (i contiguous)
+//   A mode 2: k < kh: A[i*sai + k]; k >= kh: A[aplane + i*sai + k - kh]
+//             (a complex matrix held as real and imaginary planes, with the
+//              contraction running over both: [Re A | Im A])
+//   A mode 3: A(i,k) = A[(i/2)*sai + 2k + i%2]      (rows = interleaved complex
+//             vectors stored one after another: walker slabs read as (re, im))
+//   B mode 0: B(k,j) = B[k*sbk + j]                (j contiguous)
+//   B mode 1: B(k,j) = B[k + j*sbj]                (k contiguous)
+//   B mode 3: k < kh: B[k*sbk + j]; k >= kh: the same row of the complex matrix
+//             multiplied by i, (re, im) -> (-im, re)  ([T ; iT] for [Re A | Im A])
+// With cplx_rows set, output row i goes to C[(i/2)*sci + i%2 + j*scj] (the two
+// rows of one complex vector interleave).
+// Workgroups are remapped so that each XCD (every 8th workgroup id) walks a
+// contiguous range of tiles, row tiles fastest, which keeps a B column panel in
+// one XCD's L2 while all row tiles consume it.
+#include "afqmc_internal.h"
+#include "device_util.h"
+
+namespace afqmc {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int MKC = 16;
+}
+
+template <int WM, int WN, int TM, int TN, int AMODE, int BMODE>
+__global__ __launch_bounds__(kThreads) void k_gemm_mfma(GemmArgs a, int kchunk, int gx, int gy) {
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  constexpr int LDA = BM + 1, LDB = BN + 1;     // padded LDS rows
+  constexpr int APT = (AMODE == 3) ? BM * MKC / (2 * kThreads) : BM * MKC / kThreads;
+  constexpr int BPT = BN * MKC / kThreads;
+  static_assert(WM * WN == 4, "four waves");
+  extern __shared__ double smem[];
+  double *sA = smem;                        // [2][MKC][LDA]
+  double *sB = smem + 2 * MKC * LDA;        // [2][MKC][LDB]
+
+  // XCD-aware tile order
+  const int nb = gx * gy;
+  int lin = blockIdx.x;
+  const int per = nb / 8;
+  if (lin < per * 8) lin = (lin % 8) * per + lin / 8;
+  const int bx = lin % gx, by = lin / gx;
+  const int i0 = bx * BM, j0 = by * BN;
+  const int bz = blockIdx.z;
+  const int b = bz / a.ksplit, s = bz - b * a.ksplit;
+  const int kbeg = s * kchunk;
+  const int kend = min(a.k, kbeg + kchunk);
+  const double *A = a.A + (size_t)b * a.sab;
+  const double *B = a.B + (size_t)b * a.sbb;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv / WN, wn = wv - (wv / WN) * WN;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  double ra[(AMODE == 3) ? 2 * APT : APT];
+  double rb[BPT];
+  auto load = [&](int k0) {
+    if (AMODE == 3) {
+#pragma unroll
+      for (int r = 0; r < APT; ++r) {
+        const int e = tid + r * kThreads;
+        const int kk = e % MKC, wl = e / MKC;
+        const int gi = i0 + 2 * wl, gk = k0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (gi < a.m && gk < kend) v = *reinterpret_cast<const double2 *>(A + (size_t)(gi / 2) * a.sai + 2 * (size_t)gk);
+        ra[2 * r] = v.x;
+        ra[2 * r + 1] = v.y;
+      }
+    } else
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * kThreads;
+      int ii, kk;
+      if (AMODE == 1) { ii = e % BM; kk = e / BM; }
+      else { kk = e % MKC; ii = e / MKC; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < a.m && gk < kend) {
+        if (AMODE == 0) v = A[(size_t)gi * a.sai + gk];
+        else if (AMODE == 1) v = A[(size_t)gi + (size_t)gk * a.sak];
+        else v = (gk < a.khalf) ? A[(size_t)gi * a.sai + gk] : A[a.aplane + (size_t)gi * a.sai + (gk - a.khalf)];
+      }
+      ra[r] = v;
+    }
+    {
+#pragma unroll
+      for (int r = 0; r < BPT; ++r) {
+        const int e = tid + r * kThreads;
+        int jj, kk;
+        if (BMODE == 1) { kk = e % MKC; jj = e / MKC; }
+        else { jj = e % BN; kk = e / BN; }
+        const int gj = j0 + jj, gk = k0 + kk;
+        double v = 0.0;
+        if (gj < a.n && gk < kend) {
+          if (BMODE == 0) v = B[(size_t)gk * a.sbk + gj];
+          else if (BMODE == 1) v = B[(size_t)gk + (size_t)gj * a.sbj];
+          else {
+            if (gk < a.khalf) v = B[(size_t)gk * a.sbk + gj];
+            else {
+              const size_t row = (size_t)(gk - a.khalf) * a.sbk;
+              v = (gj & 1) ? B[row + gj - 1] : -B[row + gj + 1];
+            }
+          }
+        }
+        rb[r] = v;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    double *sa = sA + buf * MKC * LDA;
+    double *sb = sB + buf * MKC * LDB;
+    if (AMODE == 3) {
+#pragma unroll
+      for (int r = 0; r < APT; ++r) {
+        const int e = tid + r * kThreads;
+        const int kk = e % MKC, wl = e / MKC;
+        sa[kk * LDA + 2 * wl] = ra[2 * r];
+        sa[kk * LDA + 2 * wl + 1] = ra[2 * r + 1];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < APT; ++r) {
+        const int e = tid + r * kThreads;
+        int ii, kk;
+        if (AMODE == 1) { ii = e % BM; kk = e / BM; }
+        else { kk = e % MKC; ii = e / MKC; }
+        sa[kk * LDA + ii] = ra[r];
+      }
+    }
+    {
+#pragma unroll
+      for (int r = 0; r < BPT; ++r) {
+        const int e = tid + r * kThreads;
+        int jj, kk;
+        if (BMODE == 1) { kk = e % MKC; jj = e / MKC; }
+        else { jj = e % BN; kk = e / BN; }
+        sb[kk * LDB + jj] = rb[r];
+      }
+    }
+  };
+
+  dvec4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = dvec4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunk = (kend - kbeg + MKC - 1) / MKC;
+  if (nchunk > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load(kbeg + (ch + 1) * MKC);
+    const double *sa = sA + buf * MKC * LDA + wm * TM * 16 + lr;
+    const double *sb = sB + buf * MKC * LDB + wn * TN * 16 + lr;
+#pragma unroll
+    for (int ks = 0; ks < MKC / 4; ++ks) {
+      double av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = sa[(ks * 4 + lk) * LDA + i * 16];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = sb[(ks * 4 + lk) * LDB + j * 16];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  double *C = a.C + (size_t)b * a.scb + (size_t)s * a.scs;
+  double *C2 = a.C2 ? a.C2 + (size_t)b * a.scb : nullptr;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int gj = j0 + wn * TN * 16 + j * 16 + lr;
+      if (gj >= a.n) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wm * TM * 16 + i * 16 + lk + 4 * r;
+        if (gi >= a.m) continue;
+        const size_t off = (a.cplx_rows ? (size_t)(gi >> 1) * a.sci + (gi & 1) : (size_t)gi * a.sci) +
+                           (size_t)gj * a.scj;
+        double v = a.alpha * acc[i][j][r];
+        if (a.beta != 0.0) v = fma(a.beta, C[off], v);
+        C[off] = v;
+        if (C2) C2[off] += v;
+      }
+    }
+}
+
+namespace {
+
+template <int WM, int WN, int TM, int TN, int AMODE, int BMODE>
+hipError_t run(const GemmArgs &a, hipStream_t st) {
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
+  const int ks = a.ksplit < 1 ? 1 : a.ksplit;
+  int kchunk = (a.k + ks - 1) / ks;
+  kchunk = ((kchunk + MKC - 1) / MKC) * MKC;
+  GemmArgs g = a;
+  g.ksplit = ks;
+  const int gx = (a.m + BM - 1) / BM, gy = (a.n + BN - 1) / BN;
+  const size_t lds = (size_t)2 * MKC * ((BM + 1) + (BN + 1)) * sizeof(double);
+  auto k = k_gemm_mfma<WM, WN, TM, TN, AMODE, BMODE>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k, dim3(gx * gy, 1, a.batch * ks), dim3(kThreads), lds, st, g, kchunk, gx, gy);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// V_HS planes: rows (w, c) = 2W, columns M^2, contraction over G.
+hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st) { return run<2, 2, 4, 4, 0, 0>(a, st); }
+// B1 times walker slabs: M rows, 2 Nt real columns, batched over walkers.
+hipError_t gemm_b1_mfma(const GemmArgs &a, hipStream_t st) { return run<4, 1, 1, 5, 0, 0>(a, st); }
+// Taylor term: [Re A | Im A] times [T ; iT], batched over walkers.
+hipError_t gemm_taylor_mfma(const GemmArgs &a, hipStream_t st) { return run<4, 1, 1, 5, 2, 3>(a, st); }
+// Force bias: walker rows (interleaved complex) times Ltilde columns, split-K.
+hipError_t gemm_fb_mfma(const GemmArgs &a, hipStream_t st) { return run<2, 2, 2, 2, 3, 1>(a, st); }
+// Generic square-ish products of set-up (row-major, no transposes).
+hipError_t gemm_nn_mfma(const GemmArgs &a, hipStream_t st) { return run<2, 2, 2, 2, 0, 0>(a, st); }
+
+}  // namespace afqmc

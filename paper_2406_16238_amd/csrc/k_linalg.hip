@@ -12,13 +12,20 @@
 
 namespace afqmc {
 
+namespace {
+constexpr int OKQ = 32;                                   // rows of phi / Psi staged per pass
+constexpr int OMAXE = (kMaxSpinOrbitals * kMaxSpinOrbitals + kThreads - 1) / kThreads;  // O entries per thread
+}  // namespace
+
+// One workgroup per walker, spin blocks in turn.  LDS: O (N x N complex, inverted
+// in place), plus staging for OKQ rows of Psi_s (real) and phi_s (complex).
 __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restrict__ phi,
                                                         const double *__restrict__ trial, int M, int Na,
                                                         int Nb, double2 *__restrict__ theta,
                                                         double2 *__restrict__ logo,
                                                         uint32_t *__restrict__ stat,
                                                         uint32_t *__restrict__ flags_or) {
-  extern __shared__ double2 sA[];  // [N][N]
+  extern __shared__ double2 sdyn[];
   __shared__ double2 scol[kMaxSpinOrbitals];
   __shared__ int spiv[kMaxSpinOrbitals];
   __shared__ double2 spivval;
@@ -27,6 +34,10 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
   const int w = blockIdx.x;
   const int tid = threadIdx.x;
   const int Nt = Na + Nb;
+  const int nmax = Na > Nb ? Na : Nb;
+  double2 *sA = sdyn;                                        // [N][N]
+  double2 *sPh = sdyn + nmax * nmax;                         // [OKQ][N]
+  double *sPs = reinterpret_cast<double *>(sPh + OKQ * nmax);  // [OKQ][N]
   const double2 *ph = phi + (size_t)w * M * Nt;
   double lre = 0.0, lim = 0.0;  // log det accumulated by thread 0
   int singular = 0;
@@ -35,17 +46,40 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
     const int N = s ? Nb : Na;
     const int off = s ? Na : 0;
     if (N == 0) continue;
-    // O = Psi_s^T phi_s
-    for (int e = tid; e < N * N; e += blockDim.x) {
-      const int i = e / N, j = e - (e / N) * N;
-      double re = 0.0, im = 0.0;
-      for (int q = 0; q < M; ++q) {
-        const double t = trial[(size_t)q * Nt + off + i];
-        const double2 p = ph[(size_t)q * Nt + off + j];
-        re = fma(t, p.x, re);
-        im = fma(t, p.y, im);
+    const int NN = N * N;
+    // O = Psi_s^T phi_s, OKQ rows at a time through LDS
+    double2 o[OMAXE];
+#pragma unroll
+    for (int r = 0; r < OMAXE; ++r) o[r] = make_double2(0.0, 0.0);
+    for (int q0 = 0; q0 < M; q0 += OKQ) {
+      const int nq = min(OKQ, M - q0);
+      for (int e = tid; e < nq * N; e += blockDim.x) {
+        const int qq = e / N, j = e - (e / N) * N;
+        sPh[qq * N + j] = ph[(size_t)(q0 + qq) * Nt + off + j];
+        sPs[qq * N + j] = trial[(size_t)(q0 + qq) * Nt + off + j];
       }
-      sA[e] = make_double2(re, im);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < OMAXE; ++r) {
+        const int e = tid + r * kThreads;
+        if (e < NN) {
+          const int i = e / N, j = e - (e / N) * N;
+          double re = o[r].x, im = o[r].y;
+          for (int qq = 0; qq < nq; ++qq) {
+            const double t = sPs[qq * N + i];
+            const double2 p = sPh[qq * N + j];
+            re = fma(t, p.x, re);
+            im = fma(t, p.y, im);
+          }
+          o[r] = make_double2(re, im);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < OMAXE; ++r) {
+      const int e = tid + r * kThreads;
+      if (e < NN) sA[e] = o[r];
     }
     if (tid == 0) ssing = 0;
     __syncthreads();
@@ -60,9 +94,9 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
           if (a > best) { best = a; bi = i; }
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const double ob = __shfl_down(best, o, 64);
-          const int oi = __shfl_down(bi, o, 64);
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+          const double ob = __shfl_down(best, o2, 64);
+          const int oi = __shfl_down(bi, o2, 64);
           if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
         if (tid == 0) {
@@ -99,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       }
       __syncthreads();
       // eliminate column k from every other row
-      for (int e = tid; e < N * N; e += blockDim.x) {
+      for (int e = tid; e < NN; e += blockDim.x) {
         const int i = e / N, j = e - (e / N) * N;
         if (i == k) continue;
         const double2 a = (j == k) ? make_double2(0.0, 0.0) : sA[e];
@@ -123,19 +157,28 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       }
       __syncthreads();
     }
-    // Theta_s = phi_s O_s^-1
+    // Theta_s = phi_s O_s^-1, OKQ rows of phi_s at a time through LDS
     if (theta) {
       double2 *th = theta + (size_t)w * M * Nt;
-      for (int e = tid; e < M * N; e += blockDim.x) {
-        const int q = e / N, j = e - (e / N) * N;
-        double re = 0.0, im = 0.0;
-        for (int k = 0; k < N; ++k) {
-          const double2 p = ph[(size_t)q * Nt + off + k];
-          const double2 x = sA[k * N + j];
-          re += p.x * x.x - p.y * x.y;
-          im += p.x * x.y + p.y * x.x;
+      for (int q0 = 0; q0 < M; q0 += OKQ) {
+        const int nq = min(OKQ, M - q0);
+        for (int e = tid; e < nq * N; e += blockDim.x) {
+          const int qq = e / N, j = e - (e / N) * N;
+          sPh[qq * N + j] = ph[(size_t)(q0 + qq) * Nt + off + j];
         }
-        th[(size_t)q * Nt + off + j] = make_double2(re, im);
+        __syncthreads();
+        for (int e = tid; e < nq * N; e += blockDim.x) {
+          const int qq = e / N, j = e - (e / N) * N;
+          double re = 0.0, im = 0.0;
+          for (int k = 0; k < N; ++k) {
+            const double2 p = sPh[qq * N + k];
+            const double2 x = sA[k * N + j];
+            re += p.x * x.x - p.y * x.y;
+            im += p.x * x.y + p.y * x.x;
+          }
+          th[(size_t)(q0 + qq) * Nt + off + j] = make_double2(re, im);
+        }
+        __syncthreads();
       }
     }
     __syncthreads();
@@ -152,13 +195,21 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
   }
 }
 
+size_t ovlp_lds_bytes(int nmax) {
+  return (size_t)nmax * nmax * sizeof(double2) + (size_t)OKQ * nmax * (sizeof(double2) + sizeof(double));
+}
+
+hipError_t ovlp_enable_lds(int nmax) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(k_ovlp_theta), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)ovlp_lds_bytes(kMaxSpinOrbitals));
+}
+
 hipError_t launch_ovlp_theta(const double2 *phi, const double *trial, int M, int Na, int Nb, int W,
                              double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or,
                              hipStream_t st) {
   const int nmax = Na > Nb ? Na : Nb;
-  const size_t lds = (size_t)nmax * nmax * sizeof(double2);
-  hipLaunchKernelGGL(k_ovlp_theta, dim3(W), dim3(kThreads), lds, st, phi, trial, M, Na, Nb, theta, logo,
-                     stat, flags_or);
+  hipLaunchKernelGGL(k_ovlp_theta, dim3(W), dim3(kThreads), ovlp_lds_bytes(nmax), st, phi, trial, M, Na, Nb, theta,
+                     logo, stat, flags_or);
   return hipGetLastError();
 }
 

@@ -161,16 +161,20 @@ hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStr
 // ---- combine: E2 = EJ + sum of exchange partials (fixed order), E = E1 + E2 ---
 __global__ __launch_bounds__(kThreads) void k_energy_combine(const double2 *__restrict__ e1,
                                                             const double2 *__restrict__ ej,
-                                                            const double2 *__restrict__ ekpart, int nparts,
-                                                            const uint32_t *__restrict__ stat,
+                                                            const double2 *__restrict__ ekpart, int stride,
+                                                            int n0, int n1, const uint32_t *__restrict__ stat,
                                                             double2 *__restrict__ e_out) {
   __shared__ double red[4 * 2];
   const int w = blockIdx.x;
-  const double2 *p = ekpart + (size_t)w * nparts;
+  const double2 *p = ekpart + (size_t)w * 2 * stride;
   double acc[2] = {0.0, 0.0};
-  for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
+  for (int k = threadIdx.x; k < n0; k += blockDim.x) {
     acc[0] += p[k].x;
     acc[1] += p[k].y;
+  }
+  for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+    acc[0] += p[stride + k].x;
+    acc[1] += p[stride + k].y;
   }
   block_sum<2>(acc, red);
   if (threadIdx.x == 0) {
@@ -185,8 +189,8 @@ __global__ __launch_bounds__(kThreads) void k_energy_combine(const double2 *__re
 }
 
 hipError_t launch_energy_combine(const System &s, int W, double2 *e_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_combine, dim3(W), dim3(kThreads), 0, st, s.e1, s.ej, s.ekpart, 2 * s.ex_ngb,
-                     s.stat_new, e_out);
+  hipLaunchKernelGGL(k_energy_combine, dim3(W), dim3(kThreads), 0, st, s.e1, s.ej, s.ekpart, s.ex_stride,
+                     s.ex_nparts[0], s.ex_nparts[1], s.stat_new, e_out);
   return hipGetLastError();
 }
 

@@ -209,3 +209,20 @@ def test_full_size_sampled(spec):
             assert cmp_rel(e[k], oe) < TOL
     finally:
         p.close()
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3], ids=["valu-exchange", "valu-gemm", "valu-all"])
+@pytest.mark.parametrize("spec,W", [(RAGGED, 7), (TILED, 70)], ids=["ragged", "tiled"])
+def test_valu_kernels_match_oracle(spec, W, bits):
+    """The VALU kernels (kept for comparison runs and as the exchange fallback
+    where the MFMA tiling does not apply) stay at parity too; reserved[0]
+    selects them."""
+    from paper_2406_16238_amd import afqmc as A
+    o = A.default_options()
+    o.reserved[0] = bits
+    p = Pair(spec, W, 0.01, options=o)
+    try:
+        worst, g, _ = run_both(p, 2, gi.initial_walkers(p.trial, W, noise=0.05, seed=21), reortho_every=0)
+        assert worst["e"] < TOL and worst["w"] < TOL and worst["phi"] < TOL, worst
+    finally:
+        p.close()
