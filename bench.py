@@ -37,6 +37,9 @@ def parse_args(argv=None):
     ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
     ap.add_argument("--phases", action="store_true", help="print the per-phase table to stderr")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the run, copy a device buffer of this many MiB (a plain copy kernel of known "
+                         "size, for scaling the HBM byte counters of a profile)")
     return ap.parse_args(argv)
 
 
@@ -99,6 +102,14 @@ def main(argv=None):
     import torch
     import afqmc_inputs as gi
     from paper_2406_16238_amd import afqmc as A
+
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     spec = {"headline": gi.HEADLINE, "medium": gi.MEDIUM, "small": gi.SMALL}[args.workload]
     s = spec.system

@@ -33,11 +33,13 @@ constexpr int kThreads = 256;
 //   e1, ej [W] double2; ekpart [W][2][ngb] double2
 // Launch plan of the MFMA exchange kernel for one spin block of width N.
 struct ExchangePlan {
-  int N = 0, NR = 0, GC = 1, RT = 0, CT = 0, ngb = 0;
+  int N = 0, NR = 0, GC = 1, RT = 0, CT = 0, WX = 4, WY = 1;
+  int ngroups = 0;  // partial sums written per (walker, spin)
+  int nwg = 0;      // workgroups along the Cholesky index
   size_t lds = 0;
   bool mfma = false;
 };
-ExchangePlan exchange_plan(int N, int G);
+ExchangePlan exchange_plan(int N, int G, int wx);
 
 struct System {
   int M = 0, Na = 0, Nb = 0, Nt = 0, G = 0, W = 0;
@@ -45,6 +47,7 @@ struct System {
   uint64_t bytes = 0;
 
   double *L = nullptr, *LtT = nullptr, *htT = nullptr, *trial = nullptr, *B1 = nullptr, *lmf = nullptr;
+  double *LtS[2] = {nullptr, nullptr};  // per spin [G][M][NR]: half-rotated, rows padded for the exchange
   double2 *theta = nullptr, *fbpart = nullptr, *tA = nullptr, *tB = nullptr, *tacc = nullptr;
   double *yp = nullptr, *vhs = nullptr, *wsc = nullptr;
   double2 *logo_now = nullptr, *logo_new = nullptr, *e1 = nullptr, *ej = nullptr, *ekpart = nullptr;
@@ -121,6 +124,9 @@ hipError_t launch_weight_update(const System &s, const afqmc_walkers &w, int W, 
 hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStream_t st);
 hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st);
 hipError_t exchange_enable_lds(const System &s);
+// LtS[g][q][i] = LtT[g][q][off + i] for i < N, zero for N <= i < NR.
+hipError_t launch_pad_half_rotated(const double *LtT, int G, int M, int Nt, int off, int N, int NR, double *LtS,
+                                   hipStream_t st);
 hipError_t launch_energy_combine(const System &s, int W, double2 *e_out, hipStream_t st);
 hipError_t launch_estimator(const double *weight, const double2 *e_out, int W, double *est, hipStream_t st);
 

@@ -38,6 +38,7 @@ struct afqmc_ctx {
   std::vector<void *> allocs;
   bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
+  int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
   // phase timers
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -145,9 +146,9 @@ bool valid_desc(const afqmc_system_desc &d, std::string &why) {
 
 // Sizes of every buffer of one system (doubles, double2s, uint32s).
 struct Plan {
-  size_t L, LtT, htT, trial, B1, lmf, theta, fbpart, yp, vhs, tbuf, wsc, wvec2, ekpart, stat;
+  size_t L, LtT, htT, trial, B1, lmf, theta, fbpart, yp, vhs, tbuf, wsc, wvec2, ekpart, stat, LtS0, LtS1;
   uint64_t bytes() const {
-    return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc) +
+    return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc + LtS0 + LtS1) +
            16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat;
   }
 };
@@ -169,6 +170,8 @@ Plan plan_for(const System &s) {
   p.wsc = 6 * W;
   p.wvec2 = W;  // logo_now, logo_new, e1, ej (+1 spare)
   p.ekpart = W * 2 * (size_t)s.ex_stride;
+  p.LtS0 = s.ex_mfma && s.Na > 0 ? G * M * (size_t)s.ex_plan[0].NR : 0;
+  p.LtS1 = s.ex_mfma && s.Nb > 0 ? G * M * (size_t)s.ex_plan[1].NR : 0;
   p.stat = W;
   return p;
 }
@@ -271,12 +274,12 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
   exchange_geometry(nmax, &s.ex_gb, &s.ex_lds);
   s.ex_ngb = (s.G + s.ex_gb - 1) / s.ex_gb;
-  s.ex_plan[0] = exchange_plan(s.Na, s.G);
-  s.ex_plan[1] = exchange_plan(s.Nb, s.G);
+  s.ex_plan[0] = exchange_plan(s.Na, s.G, c->ex_wx);
+  s.ex_plan[1] = exchange_plan(s.Nb, s.G, c->ex_wx);
   s.ex_mfma = (s.Na == 0 || s.ex_plan[0].mfma) && (s.Nb == 0 || s.ex_plan[1].mfma) && !c->force_valu_exchange;
   if (s.ex_mfma) {
-    s.ex_nparts[0] = s.ex_plan[0].ngb;
-    s.ex_nparts[1] = s.ex_plan[1].ngb;
+    s.ex_nparts[0] = s.ex_plan[0].ngroups;
+    s.ex_nparts[1] = s.ex_plan[1].ngroups;
     s.ex_stride = std::max(1, std::max(s.ex_nparts[0], s.ex_nparts[1]));
   } else {
     s.ex_nparts[0] = s.ex_nparts[1] = s.ex_stride = s.ex_ngb;
@@ -294,7 +297,8 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
             dalloc(c, &s.vhs, p.vhs) && dalloc(c, &s.tA, p.tbuf) && dalloc(c, &s.tB, p.tbuf) &&
             dalloc(c, &s.tacc, p.tbuf) && dalloc(c, &s.wsc, p.wsc) && dalloc(c, &s.logo_now, p.wvec2) &&
             dalloc(c, &s.logo_new, p.wvec2) && dalloc(c, &s.e1, p.wvec2) && dalloc(c, &s.ej, p.wvec2) &&
-            dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat);
+            dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat) &&
+            (p.LtS0 == 0 || dalloc(c, &s.LtS[0], p.LtS0)) && (p.LtS1 == 0 || dalloc(c, &s.LtS[1], p.LtS1));
   if (!ok) return fail(AFQMC_ERR_OOM, "device allocation failed");
   *bytes_used += s.bytes;
   AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
@@ -359,6 +363,11 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     GemmArgs gh = g;
     gh.batch = 1; gh.A = h; gh.sab = 0; gh.C = s.htT; gh.scb = 0;
     AFQMC_HIP(gemm_f64(gh, st), "half-rotation of h");
+    for (int sp = 0; sp < 2; ++sp)
+      if (s.LtS[sp])
+        AFQMC_HIP(launch_pad_half_rotated(s.LtT, s.G, s.M, s.Nt, sp ? s.Na : 0, sp ? s.Nb : s.Na,
+                                          s.ex_plan[sp].NR, s.LtS[sp], st),
+                  "padded half rotation");
   }
   // scalars and B1 = exp(-dt/2 H1)
   std::vector<double> hl(G), hH1(mm);
@@ -443,6 +452,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->opt.fb_cap = o.fb_cap;
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
+  if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) c->ex_wx = o.reserved[1];
   (void)hipGetDevice(&c->device);
   c->sys.resize(nsys);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);

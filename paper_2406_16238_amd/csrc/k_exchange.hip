@@ -131,182 +131,201 @@ __global__ __launch_bounds__(kThreads) void k_exchange_v1(const double *__restri
 // For one spin block the exchange matrices of all Cholesky vectors and all
 // walkers are one real GEMM
 //   C[(g, i)][(w, c)] = sum_q Ltilde[g][i][q] * Theta_w[q][c],  c = 2 j + {re, im},
-// A = the half-rotated vectors (rows (g, i), padded to NR rows per g), B = the
-// walkers' Theta with interleaved complex columns (padded to CP per walker).
-// A workgroup owns GC whole Cholesky vectors (RT = GC*NR/16 row tiles) and four
-// whole walkers (one per wave, CT = CP/16 column tiles), so every T^{g}_w is
-// complete inside one wave and the trace needs no other workgroup.  The K loop
-// stages 16 contraction rows of A and B in LDS (double-buffered through
-// registers) and issues RT*CT v_mfma_f64_16x16x4f64 per 4 rows.
-// MFMA lane layout (16x16x4, f64): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; accumulator item r of lane l is D[l/16 + 4 r][l%16].
-typedef double dvec4 __attribute__((ext_vector_type(4)));
-
+// A = the half-rotated vectors of this spin, stored for this kernel as
+// LtS[g][q][NR] (rows i padded with zeros to NR = ceil(N/8)*8), B = the walkers'
+// Theta with interleaved complex columns (padded with zeros to CP = 2 NR per walker).
+// The four waves of a workgroup form a WY x WX grid: wave (wy, wx) owns GC whole
+// Cholesky vectors (RT = GC*NR/16 sixteen-row tiles) of the workgroup's WY*GC
+// and one whole walker (CT = CP/16 sixteen-column groups) of its WX, so every
+// T^{g}_w is complete inside one wave and the trace needs no other workgroup.
+// The K loop stages 16 contraction rows of A and B in LDS with 16-byte loads
+// (double-buffered through registers) and issues 4*RT*CT
+// v_mfma_f64_4x4x4_4b_f64 per 4 rows: the four blocks of one instruction are
+// the four 4-column groups of a 16-column group and share one 4-row slab of A
+// (lane 16k+4b+i supplies A_b[i][k], lane 16k+4b+j supplies B_b[k][j], lane
+// 16i+4b+j receives D_b[i][j]); on gfx950 this form runs near the FP64 peak.
+// Trace: each wave writes T (N x 2N interleaved, row stride 2N+2) to LDS, then
+// every lane multiplies the entry it holds, Re T_ij (even column) or Im T_ij
+// (odd column), by T_ji read back from LDS:
+//   Re sum = sum (Re T_ij Re T_ji - Im T_ij Im T_ji),
+//   Im sum = sum (Re T_ij Im T_ji + Im T_ij Re T_ji).
 namespace {
 constexpr int XKC = 16;     // contraction rows per LDS stage
-constexpr int XWALK = 4;    // walkers per workgroup (one per wave)
 }  // namespace
 
-template <int RT, int CT>
-__global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__restrict__ LtT,
+template <int NR, int WX>
+__global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__restrict__ LtS,
                                                            const double *__restrict__ theta, int M, int Nt,
-                                                           int off, int N, int NR, int GC, int G, int W,
-                                                           int stride, int spin, double2 *__restrict__ ekpart) {
-  constexpr int ROWS = RT * 16;
-  constexpr int CP = CT * 16;
+                                                           int off, int N, int G, int W, int stride, int spin,
+                                                           double2 *__restrict__ ekpart) {
+  constexpr int GC = (NR % 16 == 0) ? 1 : 2;  // Cholesky vectors per wave
+  constexpr int WY = 4 / WX;
+  constexpr int ROWW = GC * NR;              // rows per wave
+  constexpr int RT = ROWW / 16;
+  constexpr int CP = 2 * NR;                 // interleaved columns per walker (= ceil(2N/16)*16)
+  constexpr int CT = CP / 16;
+  constexpr int ROWS = WY * ROWW;            // rows per workgroup
   constexpr int ASZ = XKC * ROWS;            // doubles per A stage
-  constexpr int BSZ = XWALK * XKC * CP;      // doubles per B stage
-  constexpr int APT = ASZ / kThreads;        // = RT
-  constexpr int BPT = BSZ / kThreads;        // = 4 * CT
+  constexpr int BSZ = WX * XKC * CP;         // doubles per B stage
+  constexpr int APT = (ASZ / 2 + kThreads - 1) / kThreads;  // double2 loads per thread
+  constexpr int BPT = (BSZ / 2 + kThreads - 1) / kThreads;
+  constexpr int TSTRIDE = CP + 2;            // LDS row stride of T (even, breaks bank aliasing)
   extern __shared__ double smem[];
   double *sA = smem;                 // [2][XKC][ROWS]
-  double *sB = smem + 2 * ASZ;       // [2][XWALK][XKC][CP]
+  double *sB = smem + 2 * ASZ;       // [2][WX][XKC][CP]
 
   const int gb = blockIdx.x, wb = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int g0 = gb * GC, w0 = wb * XWALK;
+  const int wy = wv / WX, wx = wv - (wv / WX) * WX;
+  const int g0 = gb * WY * GC, w0 = wb * WX;
   const int twoN = 2 * N;
   const size_t wstride = (size_t)M * Nt * 2;  // doubles per walker
 
-  double ra[APT], rb[BPT];
+  double2 ra[APT], rb[BPT];
   auto load = [&](int q0) {
 #pragma unroll
     for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * kThreads;
+      const int e = 2 * (tid + r * kThreads);  // first of two consecutive rows
       const int q = e / ROWS, row = e - q * ROWS;
       const int gl = row / NR, i = row - gl * NR;
       const int g = g0 + gl, gq = q0 + q;
-      ra[r] = (i < N && g < G && gq < M) ? LtT[((size_t)g * M + gq) * Nt + off + i] : 0.0;
+      ra[r] = (e < ASZ && g < G && gq < M)
+                  ? *reinterpret_cast<const double2 *>(LtS + ((size_t)g * M + gq) * NR + i)
+                  : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * kThreads;
+      const int e = 2 * (tid + r * kThreads);
       const int c = e % CP, t = e / CP;
       const int q = t % XKC, wl = t / XKC;
       const int w = w0 + wl, gq = q0 + q;
-      rb[r] = (c < twoN && w < W && gq < M) ? theta[(size_t)w * wstride + (size_t)gq * Nt * 2 + 2 * off + c] : 0.0;
+      rb[r] = (e < BSZ && c < twoN && w < W && gq < M)
+                  ? *reinterpret_cast<const double2 *>(theta + (size_t)w * wstride + (size_t)gq * Nt * 2 + 2 * off + c)
+                  : make_double2(0.0, 0.0);
     }
   };
   auto store = [&](int buf) {
-    double *a = sA + buf * ASZ;
-    double *b = sB + buf * BSZ;
+    double2 *a = reinterpret_cast<double2 *>(sA + buf * ASZ);
+    double2 *b = reinterpret_cast<double2 *>(sB + buf * BSZ);
 #pragma unroll
-    for (int r = 0; r < APT; ++r) a[tid + r * kThreads] = ra[r];
+    for (int r = 0; r < APT; ++r)
+      if (2 * (tid + r * kThreads) < ASZ) a[tid + r * kThreads] = ra[r];
 #pragma unroll
-    for (int r = 0; r < BPT; ++r) b[tid + r * kThreads] = rb[r];
+    for (int r = 0; r < BPT; ++r)
+      if (2 * (tid + r * kThreads) < BSZ) b[tid + r * kThreads] = rb[r];
   };
 
-  dvec4 acc[RT][CT];
+  constexpr int TR = 4 * RT;  // 4-row slabs per wave
+  double acc[TR][CT];
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+  for (int i = 0; i < TR; ++i)
 #pragma unroll
-    for (int j = 0; j < CT; ++j) acc[i][j] = dvec4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < CT; ++j) acc[i][j] = 0.0;
 
   const int nchunk = (M + XKC - 1) / XKC;
   load(0);
   store(0);
   __syncthreads();
-  const int lr = lane & 15, lk = lane >> 4;
+  const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nchunk) load((ch + 1) * XKC);
-    const double *a = sA + buf * ASZ;
-    const double *b = sB + buf * BSZ + wv * XKC * CP;
+    const double *a = sA + buf * ASZ + wy * ROWW + l4;
+    const double *b = sB + buf * BSZ + wx * XKC * CP + lr;
 #pragma unroll
     for (int ks = 0; ks < XKC / 4; ++ks) {
-      double av[RT], bv[CT];
+      double av[TR], bv[CT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) av[i] = a[(ks * 4 + lk) * ROWS + i * 16 + lr];
+      for (int i = 0; i < TR; ++i) av[i] = a[(ks * 4 + lk) * ROWS + i * 4];
 #pragma unroll
-      for (int j = 0; j < CT; ++j) bv[j] = b[(ks * 4 + lk) * CP + j * 16 + lr];
+      for (int j = 0; j < CT; ++j) bv[j] = b[(ks * 4 + lk) * CP + j * 16];
 #pragma unroll
-      for (int i = 0; i < RT; ++i)
+      for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < CT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     if (ch + 1 < nchunk) store(buf ^ 1);
     __syncthreads();
   }
 
-  // epilogue: one Cholesky vector at a time, each wave writes its walker's T
-  // (N rows x 2N interleaved columns) to its own LDS region and forms
-  // sum_ij T_ij T_ji.
-  double *sT = smem + (size_t)wv * N * twoN;
-  const int w = w0 + wv;
+  // Trace, one Cholesky vector of each wave's group at a time.  Padded rows and
+  // columns of T are exact zeros (zero rows of LtS, zero columns of B), so the
+  // whole NR x CP block is written and read without bounds tests.
+  double *sT = smem + (size_t)wv * NR * TSTRIDE;
+  const int w = w0 + wx;
+  const bool odd = lr & 1;
   double pre = 0.0, pim = 0.0;
+#pragma unroll
   for (int gl = 0; gl < GC; ++gl) {
-    const int rbase = gl * NR;
+    constexpr int SL = NR / 4;  // slabs per Cholesky vector
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+    for (int i = 0; i < SL; ++i)
 #pragma unroll
-      for (int j = 0; j < CT; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = i * 16 + lk + 4 * r - rbase;
-          const int col = j * 16 + lr;
-          if (row >= 0 && row < N && col < twoN) sT[row * twoN + col] = acc[i][j][r];
-        }
+      for (int j = 0; j < CT; ++j) sT[(i * 4 + lk) * TSTRIDE + j * 16 + lr] = acc[gl * SL + i][j];
     __syncthreads();
-    if (g0 + gl < G && w < W) {
-      for (int e = lane; e < N * N; e += 64) {
-        const int i = e / N, j = e - i * N;
-        const double ar = sT[i * twoN + 2 * j], ai = sT[i * twoN + 2 * j + 1];
-        const double br = sT[j * twoN + 2 * i], bi = sT[j * twoN + 2 * i + 1];
-        pre += ar * br - ai * bi;
-        pim += ar * bi + ai * br;
+#pragma unroll
+    for (int i = 0; i < SL; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        const int row = i * 4 + lk, col = j * 16 + lr;
+        const double2 tji = *reinterpret_cast<const double2 *>(sT + (col >> 1) * TSTRIDE + 2 * row);
+        const double v = acc[gl * SL + i][j];
+        pre = fma(v, odd ? -tji.y : tji.x, pre);
+        pim = fma(v, odd ? tji.x : tji.y, pim);
       }
-    }
     __syncthreads();
   }
   pre = wave_sum(pre);
   pim = wave_sum(pim);
-  if (lane == 0 && w < W) ekpart[((size_t)w * 2 + spin) * stride + gb] = make_double2(-0.5 * pre, -0.5 * pim);
+  if (lane == 0 && w < W && g0 + wy * GC < G)
+    ekpart[((size_t)w * 2 + spin) * stride + gb * WY + wy] = make_double2(-0.5 * pre, -0.5 * pim);
 }
 
 namespace {
 
-using ExKernel = void (*)(const double *, const double *, int, int, int, int, int, int, int, int, int, int,
-                          double2 *);
+using ExKernel = void (*)(const double *, const double *, int, int, int, int, int, int, int, int, double2 *);
 
-template <int RT>
-ExKernel pick_ct(int ct) {
-  switch (ct) {
-    case 1: return k_exchange_mfma<RT, 1>;
-    case 2: return k_exchange_mfma<RT, 2>;
-    case 3: return k_exchange_mfma<RT, 3>;
-    case 4: return k_exchange_mfma<RT, 4>;
-    case 5: return k_exchange_mfma<RT, 5>;
-    case 6: return k_exchange_mfma<RT, 6>;
+template <int WX>
+ExKernel pick_nr(int nr) {
+  switch (nr) {
+    case 8: return k_exchange_mfma<8, WX>;
+    case 16: return k_exchange_mfma<16, WX>;
+    case 24: return k_exchange_mfma<24, WX>;
+    case 32: return k_exchange_mfma<32, WX>;
+    case 40: return k_exchange_mfma<40, WX>;
+    case 48: return k_exchange_mfma<48, WX>;
     default: return nullptr;
   }
 }
 
-ExKernel pick_exchange(int rt, int ct) {
-  switch (rt) {
-    case 1: return pick_ct<1>(ct);
-    case 2: return pick_ct<2>(ct);
-    case 3: return pick_ct<3>(ct);
-    case 5: return pick_ct<5>(ct);
+ExKernel pick_exchange(int nr, int wx) {
+  switch (wx) {
+    case 4: return pick_nr<4>(nr);
+    case 2: return pick_nr<2>(nr);
+    case 1: return pick_nr<1>(nr);
     default: return nullptr;
   }
 }
 
 }  // namespace
 
-ExchangePlan exchange_plan(int N, int G) {
+ExchangePlan exchange_plan(int N, int G, int wx) {
   ExchangePlan p;
   p.N = N;
   if (N <= 0) return p;
   p.NR = ((N + 7) / 8) * 8;
   p.GC = (p.NR % 16 == 0) ? 1 : 2;
   p.RT = p.GC * p.NR / 16;
-  p.CT = (2 * N + 15) / 16;
-  p.ngb = (G + p.GC - 1) / p.GC;
-  const size_t stage = 2ull * (XKC * p.RT * 16 + XWALK * XKC * p.CT * 16) * sizeof(double);
-  const size_t epi = (size_t)XWALK * N * 2 * N * sizeof(double);
+  p.CT = p.NR / 8;
+  p.WX = wx;
+  p.WY = 4 / wx;
+  p.ngroups = (G + p.GC - 1) / p.GC;              // one partial per Cholesky-vector group
+  p.nwg = (G + p.WY * p.GC - 1) / (p.WY * p.GC);  // workgroups along G
+  const size_t stage = 2ull * (XKC * p.WY * p.RT * 16 + p.WX * XKC * p.CT * 16) * sizeof(double);
+  const size_t epi = 4ull * p.NR * (2 * p.NR + 2) * sizeof(double);
   p.lds = stage > epi ? stage : epi;
-  p.mfma = pick_exchange(p.RT, p.CT) != nullptr && p.lds <= 160 * 1024;
-  if (!p.mfma) p.ngb = 0;
+  p.mfma = pick_exchange(p.NR, wx) != nullptr && p.lds <= 160 * 1024;
+  if (!p.mfma) p.ngroups = 0;
   return p;
 }
 
@@ -315,10 +334,10 @@ hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStre
     for (int spin = 0; spin < 2; ++spin) {
       const ExchangePlan &p = s.ex_plan[spin];
       if (p.N == 0) continue;
-      ExKernel k = pick_exchange(p.RT, p.CT);
-      dim3 grid(p.ngb, (W + XWALK - 1) / XWALK);
-      hipLaunchKernelGGL(k, grid, dim3(kThreads), p.lds, st, s.LtT, reinterpret_cast<const double *>(theta), s.M,
-                         s.Nt, spin ? s.Na : 0, p.N, p.NR, p.GC, s.G, W, s.ex_stride, spin, s.ekpart);
+      ExKernel k = pick_exchange(p.NR, p.WX);
+      dim3 grid(p.nwg, (W + p.WX - 1) / p.WX);
+      hipLaunchKernelGGL(k, grid, dim3(kThreads), p.lds, st, s.LtS[spin], reinterpret_cast<const double *>(theta),
+                         s.M, s.Nt, spin ? s.Na : 0, p.N, s.G, W, s.ex_stride, spin, s.ekpart);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -330,12 +349,30 @@ hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStre
   return hipGetLastError();
 }
 
+__global__ void k_pad_half_rotated(const double *__restrict__ LtT, long rows, int Nt, int off, int N, int NR,
+                                   double *__restrict__ LtS) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * NR) return;
+  const long r = e / NR;
+  const int i = (int)(e - r * NR);
+  LtS[e] = (i < N) ? LtT[r * Nt + off + i] : 0.0;
+}
+
+hipError_t launch_pad_half_rotated(const double *LtT, int G, int M, int Nt, int off, int N, int NR, double *LtS,
+                                   hipStream_t st) {
+  const long rows = (long)G * M;
+  const long n = rows * NR;
+  hipLaunchKernelGGL(k_pad_half_rotated, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, LtT, rows, Nt, off, N,
+                     NR, LtS);
+  return hipGetLastError();
+}
+
 hipError_t exchange_enable_lds(const System &s) {
   if (!s.ex_mfma) return hipSuccess;
   for (int spin = 0; spin < 2; ++spin) {
     const ExchangePlan &p = s.ex_plan[spin];
     if (p.N == 0) continue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_exchange(p.RT, p.CT)),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_exchange(p.NR, p.WX)),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
     if (e != hipSuccess) return e;
   }

@@ -2,11 +2,17 @@
 //
 //   C(i,j) = alpha * sum_k A(i,k) B(k,j) + beta * C(i,j)   [and C2(i,j) += that value]
 //
-// Workgroup tile BM x BN = (WM*TM*16) x (WN*TN*16) on a WM x WN grid of waves,
-// each wave owning TM x TN accumulators of v_mfma_f64_16x16x4f64.  The K loop
-// stages 16 contraction indices of A and B in LDS (k-major, so every MFMA
-// operand fragment is 16 consecutive doubles), double-buffered through
-// registers.  Operand access modes:
+// Workgroup tile BM x BN = (WM*TM*16) x (WN*TN*16) on a WM x WN grid of waves.
+// Each wave issues v_mfma_f64_4x4x4_4b_f64 (four independent 4x4x4 products per
+// instruction; on gfx950 it sustains close to the FP64 peak, about 1.6x the
+// 16x16x4 form): the four blocks are four 4-column groups of one 16-column
+// group, all sharing one 4-row slab of A.  Lane layout: lane 16k+4b+i supplies
+// A_b[i][k], lane 16k+4b+j supplies B_b[k][j], lane 16i+4b+j receives D_b[i][j],
+// so a B operand is 16 consecutive columns of one k row per lane group and the
+// result of slab r, group c sits at row 4r + lane/16, column 16c + lane%16.
+// A wave owns 4*TM x TN such accumulators.  The K loop stages 16 contraction
+// indices of A and B in LDS (k-major), double-buffered through registers.
+// Operand access modes:
 //   A mode 0: A(i,k) = A[i*sai + k]                (k contiguous)
 //   A mode 1: A(i,k) = A[i + k*sak]                (i contiguous)
 //   A mode 2: k < kh: A[i*sai + k]; k >= kh: A[aplane + i*sai + k - kh]
@@ -27,8 +33,6 @@
 #include "device_util.h"
 
 namespace afqmc {
-
-typedef double dvec4 __attribute__((ext_vector_type(4)));
 
 namespace {
 constexpr int MKC = 16;
@@ -150,11 +154,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(GemmArgs a, int kchunk, 
     }
   };
 
-  dvec4 acc[TM][TN];
+  constexpr int TR = 4 * TM;  // 4-row slabs per wave
+  double acc[TR][TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TR; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = dvec4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
+  const int l4 = lane & 3;
 
   const int nchunk = (kend - kbeg + MKC - 1) / MKC;
   if (nchunk > 0) {
@@ -165,19 +171,19 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(GemmArgs a, int kchunk, 
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nchunk) load(kbeg + (ch + 1) * MKC);
-    const double *sa = sA + buf * MKC * LDA + wm * TM * 16 + lr;
+    const double *sa = sA + buf * MKC * LDA + wm * TM * 16 + l4;
     const double *sb = sB + buf * MKC * LDB + wn * TN * 16 + lr;
 #pragma unroll
     for (int ks = 0; ks < MKC / 4; ++ks) {
-      double av[TM], bv[TN];
+      double av[TR], bv[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) av[i] = sa[(ks * 4 + lk) * LDA + i * 16];
+      for (int i = 0; i < TR; ++i) av[i] = sa[(ks * 4 + lk) * LDA + i * 4];
 #pragma unroll
       for (int j = 0; j < TN; ++j) bv[j] = sb[(ks * 4 + lk) * LDB + j * 16];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     if (ch + 1 < nchunk) store(buf ^ 1);
     __syncthreads();
@@ -186,23 +192,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(GemmArgs a, int kchunk, 
   double *C = a.C + (size_t)b * a.scb + (size_t)s * a.scs;
   double *C2 = a.C2 ? a.C2 + (size_t)b * a.scb : nullptr;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TR; ++i) {
+    const int gi = i0 + wm * TM * 16 + i * 4 + lk;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int gj = j0 + wn * TN * 16 + j * 16 + lr;
-      if (gj >= a.n) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gi = i0 + wm * TM * 16 + i * 16 + lk + 4 * r;
-        if (gi >= a.m) continue;
-        const size_t off = (a.cplx_rows ? (size_t)(gi >> 1) * a.sci + (gi & 1) : (size_t)gi * a.sci) +
-                           (size_t)gj * a.scj;
-        double v = a.alpha * acc[i][j][r];
-        if (a.beta != 0.0) v = fma(a.beta, C[off], v);
-        C[off] = v;
-        if (C2) C2[off] += v;
-      }
+      if (gj >= a.n || gi >= a.m) continue;
+      const size_t off = (a.cplx_rows ? (size_t)(gi >> 1) * a.sci + (gi & 1) : (size_t)gi * a.sci) +
+                         (size_t)gj * a.scj;
+      double v = a.alpha * acc[i][j];
+      if (a.beta != 0.0) v = fma(a.beta, C[off], v);
+      C[off] = v;
+      if (C2) C2[off] += v;
     }
+  }
 }
 
 namespace {
