@@ -36,6 +36,9 @@ def parse_args(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
+    ap.add_argument("--api", default="step", choices=["step", "separate"],
+                    help="step: afqmc_step (one overlap/LU and one force bias per step); separate: "
+                         "afqmc_propagate + afqmc_reorthogonalize + afqmc_local_energy")
     ap.add_argument("--phases", action="store_true", help="print the per-phase table to stderr")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the run, copy a device buffer of this many MiB (a plain copy kernel of known "
@@ -127,8 +130,12 @@ def main(argv=None):
     est = torch.empty((1, 4), dtype=torch.float64, device="cuda")
 
     def step(k):
+        reo = (k + 1) % spec.reortho_every == 0
+        if args.api == "step":
+            A.step(ctx, walkers, xs[k], e_out, est, reortho=reo)
+            return
         A.propagate(ctx, walkers, xs[k])
-        if (k + 1) % spec.reortho_every == 0:
+        if reo:
             A.reorthogonalize(ctx, walkers)
         A.local_energy(ctx, walkers, e_out, est)
 
@@ -169,7 +176,7 @@ def main(argv=None):
                    "exp(-g/tau)/M, trial = lowest orbitals of a Fock-like matrix, N(0,1) fields)",
            "config": {"workload": spec.name, "nbasis": M, "nalpha": s.nalpha, "nbeta": s.nbeta, "nchol": G,
                       "nwalkers": W, "dt": spec.dt, "reortho_every": spec.reortho_every,
-                      "precision": "fp64", "taylor_order": 6},
+                      "precision": "fp64", "taylor_order": 6, "api": args.api},
            "roofline": roofline,
            "step_algorithmic_tflops": round(step_tf, 3),
            "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},

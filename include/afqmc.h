@@ -161,6 +161,24 @@ afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w,
 afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream);
 
 /*
+ * One full walker step with fewer passes over the walkers: afqmc_propagate,
+ * then afqmc_reorthogonalize if (flags & AFQMC_STEP_REORTHO), then
+ * afqmc_local_energy of the new walkers (outputs as in those calls).
+ * Theta = phi (Psi^T phi)^-1 and vbias of the new walkers serve both this
+ * step's local energy and the next step's force bias (Theta, hence vbias, is
+ * unchanged when phi is re-orthogonalised, phi -> phi R^-1), so one overlap/LU
+ * and one force-bias contraction are done per step instead of three and two.
+ * The context keeps them for the walker buffers of its last afqmc_step; they
+ * are recomputed when the buffers differ, after any other call on the context,
+ * or when (flags & AFQMC_STEP_FRESH) says the walkers were changed elsewhere.
+ * When they are reused, log<Psi_T|phi> of the walkers is taken from
+ * walkers.log_ovlp (which propagation and re-orthogonalisation keep current).
+ */
+enum { AFQMC_STEP_REORTHO = 1u, AFQMC_STEP_FRESH = 2u };
+afqmc_status afqmc_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
+                        double *est_out, uint32_t flags, void *hip_stream);
+
+/*
  * Trial-object operations of Sec. 3.3 (calc_overlap, calc_greens_function,
  * calc_force_bias) exposed on their own, for initialisation and tests.
  * afqmc_overlap: writes log_ovlp = log<Psi_T|phi> and ORs AFQMC_W_SINGULAR.

@@ -64,8 +64,10 @@ class Timings(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * len(PHASES)), ("count", ctypes.c_int64 * len(PHASES))]
 
 
+STEP_REORTHO, STEP_FRESH = 1, 2
+
 EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate",
-           "afqmc_local_energy", "afqmc_reorthogonalize", "afqmc_overlap",
+           "afqmc_local_energy", "afqmc_reorthogonalize", "afqmc_step", "afqmc_overlap",
            "afqmc_greens_function", "afqmc_force_bias", "afqmc_get_info",
            "afqmc_set_timing", "afqmc_get_timings", "afqmc_destroy", "afqmc_last_error")
 
@@ -90,6 +92,7 @@ def load_library() -> ctypes.CDLL:
         "afqmc_propagate": ([P, ctypes.POINTER(CWalkers), pp, P], ctypes.c_int),
         "afqmc_local_energy": ([P, ctypes.POINTER(CWalkers), pp, P, P], ctypes.c_int),
         "afqmc_reorthogonalize": ([P, ctypes.POINTER(CWalkers), P], ctypes.c_int),
+        "afqmc_step": ([P, ctypes.POINTER(CWalkers), pp, pp, P, ctypes.c_uint32, P], ctypes.c_int),
         "afqmc_overlap": ([P, ctypes.POINTER(CWalkers), P], ctypes.c_int),
         "afqmc_greens_function": ([P, ctypes.POINTER(CWalkers), pp, P], ctypes.c_int),
         "afqmc_force_bias": ([P, ctypes.POINTER(CWalkers), pp, P], ctypes.c_int),
@@ -284,6 +287,22 @@ def local_energy(ctx: Context, walkers, e_out, est_out=None, stream=None):
             raise ValueError("est_out must be a float64 CUDA tensor of shape (nsys, 4)")
         est = est_out.data_ptr()
     _check(load_library().afqmc_local_energy(ctx.handle, w, es, est, _stream_handle(stream)))
+
+
+def step(ctx: Context, walkers, x, e_out, est_out=None, reortho=False, fresh=False, stream=None):
+    """afqmc_step: propagate, optionally re-orthogonalise, then local energy, with
+    one overlap/LU and one force-bias contraction per step."""
+    import torch
+    w = _walker_array(ctx, walkers)
+    xs = _ptr_array(ctx, x, [(s.nwalkers, s.nchol) for s in ctx.systems], torch.float64)
+    es = _ptr_array(ctx, e_out, [(s.nwalkers, 3) for s in ctx.systems], torch.complex128)
+    est = None
+    if est_out is not None:
+        if est_out.dtype != torch.float64 or not est_out.is_cuda or tuple(est_out.shape) != (ctx.nsys, 4):
+            raise ValueError("est_out must be a float64 CUDA tensor of shape (nsys, 4)")
+        est = est_out.data_ptr()
+    flags = (STEP_REORTHO if reortho else 0) | (STEP_FRESH if fresh else 0)
+    _check(load_library().afqmc_step(ctx.handle, w, xs, es, est, flags, _stream_handle(stream)))
 
 
 def reorthogonalize(ctx: Context, walkers, stream=None):

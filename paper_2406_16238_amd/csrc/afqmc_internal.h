@@ -62,6 +62,8 @@ struct System {
   ExchangePlan ex_plan[2];     // its per-spin plans
   int ex_stride = 1;           // partials per (walker, spin) in ekpart
   int ex_nparts[2] = {0, 0};   // partials actually written per spin
+  // Theta / vbias partials in `theta` / `fbpart` belong to these walker buffers
+  const void *cache_phi = nullptr;
 };
 
 struct Options {

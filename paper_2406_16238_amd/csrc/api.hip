@@ -187,8 +187,8 @@ int choose_fb_ksplit(int W, int G, long K) {
 // Local energy of W walkers of system s into e_out (device double2 [W][3]).
 // `c` may be NULL (set-up); it only supplies the phase timers.
 afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W, double2 *e_out, double *est,
-                              const double *weight, hipStream_t st) {
-  {
+                              const double *weight, hipStream_t st, bool have_theta = false) {
+  if (!have_theta) {
     Phase ph(c, AFQMC_PH_OVERLAP, st);
     AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_new, s.stat_new, nullptr, st),
               "overlap kernel");
@@ -477,25 +477,20 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   return AFQMC_OK;
 }
 
-static afqmc_status check_walkers(const afqmc_walkers &w, int i) {
-  if (!w.phi || !w.weight || !w.log_ovlp || !w.flags)
-    return fail(AFQMC_ERR_ARG, "walkers of system " + std::to_string(i) + " have a NULL buffer");
-  return AFQMC_OK;
-}
-
-afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *hip_stream) {
-  if (!ctx || !w || !x) return fail(AFQMC_ERR_ARG, "NULL context, walkers or fields");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
-    afqmc_status r = check_walkers(w[i], (int)i);
-    if (r != AFQMC_OK) return r;
-    if (!x[i]) return fail(AFQMC_ERR_ARG, "fields of system " + std::to_string(i) + " are NULL");
-  }
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
-    System &s = ctx->sys[i];
-    const afqmc_walkers &wk = w[i];
-    double2 *phi = static_cast<double2 *>(wk.phi);
-    const int W = s.W;
+// One propagation step of system s.  With `reuse`, theta / fbpart already hold
+// Theta and the vbias partials of the current walkers, and their log-overlaps
+// are taken from walkers.log_ovlp.  With `want_theta` the overlap pass after
+// the step also writes Theta of the new walkers (for a local energy next).
+static afqmc_status propagate_sys(afqmc_ctx *ctx, System &s, const afqmc_walkers &wk, const double *x, bool reuse,
+                                  bool want_theta, hipStream_t st) {
+  double2 *phi = static_cast<double2 *>(wk.phi);
+  const int W = s.W;
+  if (reuse) {
+    AFQMC_HIP(hipMemcpyAsync(s.logo_now, wk.log_ovlp, (size_t)W * sizeof(double2), hipMemcpyDeviceToDevice, st),
+              "copy");
+    AFQMC_HIP(hipMemcpyAsync(s.stat_now, s.stat_new, (size_t)W * sizeof(uint32_t), hipMemcpyDeviceToDevice, st),
+              "copy");
+  } else {
     {
       Phase ph(ctx, AFQMC_PH_OVERLAP, st);
       AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_now, s.stat_now, nullptr, st),
@@ -505,42 +500,98 @@ afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const doubl
       Phase ph(ctx, AFQMC_PH_FORCE_BIAS, st);
       AFQMC_HIP(launch_force_bias_gemm(s, s.theta, W, st), "force-bias kernel");
     }
-    {
-      Phase ph(ctx, AFQMC_PH_FB_EPILOGUE, st);
-      AFQMC_HIP(launch_fb_propagate_epilogue(s, ctx->opt, x[i], W, wk.flags, st), "force-bias epilogue");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_FB_EPILOGUE, st);
+    AFQMC_HIP(launch_fb_propagate_epilogue(s, ctx->opt, x, W, wk.flags, st), "force-bias epilogue");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_VHS, st);
+    AFQMC_HIP(launch_vhs(s, W, st), "V_HS kernel");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
+    AFQMC_HIP(launch_b1(s, phi, s.tacc, W, st), "one-body kernel");
+    AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice, st),
+              "copy");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_TAYLOR, st);
+    double2 *tin = s.tA, *tout = s.tB;
+    for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
+      AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st), "Taylor kernel");
+      std::swap(tin, tout);
     }
-    {
-      Phase ph(ctx, AFQMC_PH_VHS, st);
-      AFQMC_HIP(launch_vhs(s, W, st), "V_HS kernel");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
+    AFQMC_HIP(launch_b1(s, s.tacc, phi, W, st), "one-body kernel");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_OVERLAP, st);
+    AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, want_theta ? s.theta : nullptr, s.logo_new,
+                                s.stat_new, nullptr, st),
+              "overlap kernel");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_WEIGHT, st);
+    AFQMC_HIP(launch_weight_update(s, wk, W, st), "weight kernel");
+  }
+  return AFQMC_OK;
+}
+
+static void invalidate_caches(afqmc_ctx *ctx) {
+  for (System &s : ctx->sys) s.cache_phi = nullptr;
+}
+
+static afqmc_status check_walkers(const afqmc_walkers &w, int i) {
+  if (!w.phi || !w.weight || !w.log_ovlp || !w.flags)
+    return fail(AFQMC_ERR_ARG, "walkers of system " + std::to_string(i) + " have a NULL buffer");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *hip_stream) {
+  if (!ctx || !w || !x) return fail(AFQMC_ERR_ARG, "NULL context, walkers or fields");
+  invalidate_caches(ctx);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+    if (!x[i]) return fail(AFQMC_ERR_ARG, "fields of system " + std::to_string(i) + " are NULL");
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = propagate_sys(ctx, ctx->sys[i], w[i], x[i], false, false, st);
+    if (r != AFQMC_OK) return r;
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
+                        double *est_out, uint32_t flags, void *hip_stream) {
+  if (!ctx || !w || !x || !e_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers, fields or e_out");
+  if (flags & ~(uint32_t)(AFQMC_STEP_REORTHO | AFQMC_STEP_FRESH)) return fail(AFQMC_ERR_ARG, "unknown step flags");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+    if (!x[i] || !e_out[i]) return fail(AFQMC_ERR_ARG, "NULL fields or e_out of system " + std::to_string(i));
+  }
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    System &s = ctx->sys[i];
+    const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
+    s.cache_phi = nullptr;
+    afqmc_status r = propagate_sys(ctx, s, w[i], x[i], reuse, true, st);
+    if (r != AFQMC_OK) return r;
+    if (flags & AFQMC_STEP_REORTHO) {
+      Phase ph(ctx, AFQMC_PH_REORTHO, st);
+      AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
+                           static_cast<double2 *>(w[i].log_ovlp), st),
+                "Gram-Schmidt kernel");
     }
-    {
-      Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
-      AFQMC_HIP(launch_b1(s, phi, s.tacc, W, st), "one-body kernel");
-      AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice,
-                               st),
-                "copy");
-    }
-    {
-      Phase ph(ctx, AFQMC_PH_TAYLOR, st);
-      double2 *tin = s.tA, *tout = s.tB;
-      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
-        AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st), "Taylor kernel");
-        std::swap(tin, tout);
-      }
-    }
-    {
-      Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
-      AFQMC_HIP(launch_b1(s, s.tacc, phi, W, st), "one-body kernel");
-    }
-    {
-      Phase ph(ctx, AFQMC_PH_OVERLAP, st);
-      AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, nullptr, s.logo_new, s.stat_new, nullptr, st),
-                "overlap kernel");
-    }
-    {
-      Phase ph(ctx, AFQMC_PH_WEIGHT, st);
-      AFQMC_HIP(launch_weight_update(s, wk, W, st), "weight kernel");
-    }
+    r = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, static_cast<double2 *>(e_out[i]),
+                         est_out ? est_out + 4 * i : nullptr, w[i].weight, st, true);
+    if (r != AFQMC_OK) return r;
+    s.cache_phi = w[i].phi;
   }
   return AFQMC_OK;
 }
@@ -548,6 +599,7 @@ afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const doubl
 afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *e_out, double *est_out,
                                 void *hip_stream) {
   if (!ctx || !w || !e_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers or e_out");
+  invalidate_caches(ctx);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (size_t i = 0; i < ctx->sys.size(); ++i) {
     afqmc_status r = check_walkers(w[i], (int)i);
@@ -566,6 +618,7 @@ afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w, void *co
 
 afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream) {
   if (!ctx || !w) return fail(AFQMC_ERR_ARG, "NULL context or walkers");
+  invalidate_caches(ctx);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (size_t i = 0; i < ctx->sys.size(); ++i) {
     afqmc_status r = check_walkers(w[i], (int)i);
@@ -583,6 +636,7 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void 
 
 afqmc_status afqmc_overlap(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream) {
   if (!ctx || !w) return fail(AFQMC_ERR_ARG, "NULL context or walkers");
+  invalidate_caches(ctx);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (size_t i = 0; i < ctx->sys.size(); ++i) {
     afqmc_status r = check_walkers(w[i], (int)i);
@@ -600,6 +654,7 @@ afqmc_status afqmc_overlap(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_str
 afqmc_status afqmc_greens_function(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *theta_out,
                                    void *hip_stream) {
   if (!ctx || !w || !theta_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers or theta_out");
+  invalidate_caches(ctx);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (size_t i = 0; i < ctx->sys.size(); ++i) {
     if (!w[i].phi || !theta_out[i]) return fail(AFQMC_ERR_ARG, "NULL phi or theta_out");
@@ -615,6 +670,7 @@ afqmc_status afqmc_greens_function(afqmc_ctx *ctx, const afqmc_walkers *w, void 
 
 afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *vbias_out, void *hip_stream) {
   if (!ctx || !w || !vbias_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers or vbias_out");
+  invalidate_caches(ctx);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (size_t i = 0; i < ctx->sys.size(); ++i) {
     if (!w[i].phi || !vbias_out[i]) return fail(AFQMC_ERR_ARG, "NULL phi or vbias_out");

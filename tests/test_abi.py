@@ -29,7 +29,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) >= 13
+    assert len(names) >= 14
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(A.EXPORTS)
@@ -90,6 +90,7 @@ def test_step_calls_reject_null_context(lib):
     assert lib.afqmc_propagate(None, ctypes.byref(w), None, None) == A.ERR_ARG
     assert lib.afqmc_local_energy(None, ctypes.byref(w), None, None, None) == A.ERR_ARG
     assert lib.afqmc_reorthogonalize(None, ctypes.byref(w), None) == A.ERR_ARG
+    assert lib.afqmc_step(None, ctypes.byref(w), None, None, None, 0, None) == A.ERR_ARG
     assert lib.afqmc_overlap(None, None, None) == A.ERR_ARG
     assert lib.afqmc_greens_function(None, None, None, None) == A.ERR_ARG
     assert lib.afqmc_force_bias(None, None, None, None) == A.ERR_ARG

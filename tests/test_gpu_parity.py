@@ -226,3 +226,38 @@ def test_valu_kernels_match_oracle(spec, W, bits):
         assert worst["e"] < TOL and worst["w"] < TOL and worst["phi"] < TOL, worst
     finally:
         p.close()
+
+
+@pytest.mark.parametrize("which", ["small", "tiled"])
+def test_fused_step_matches_oracle(which, small):
+    """afqmc_step (one LU and one force bias per step, Theta and vbias reused
+    across the energy and the next propagation) against the oracle's separate
+    propagate / re-orthogonalise / energy sequence."""
+    p = small if which == "small" else Pair(TILED, 70, 0.005)
+    try:
+        W = p.W
+        phis = gi.initial_walkers(p.trial, W, noise=0.03, seed=17)
+        fields = gi.FieldStream(3, W, p.ham.nchol)
+        w = p.walkers(phis)
+        e = p.torch.empty((W, 3), dtype=p.torch.complex128, device="cuda")
+        est = p.torch.empty((1, 4), dtype=p.torch.float64, device="cuda")
+        ophi, ow, ologo = phis.copy(), np.ones(W), O.initial_logo(p.ham, phis)
+        for step in range(1, 8):
+            x = fields.next()
+            reo = step % 3 == 0
+            p.A.step(p.ctx, w, p.torch.as_tensor(x, device="cuda"), e, est, reortho=reo)
+            ophi, ow, ologo, _ = O.propagate(p.ham, ophi, ow, ologo, x)
+            if reo:
+                ophi, ologo = O.reorthogonalize(p.ham, ophi, ologo)
+            oe = O.local_energies(p.ham, ophi)
+            gphi, gw, glogo, gflags = p.to_host(w)
+            ge = e.cpu().numpy()
+            assert cmp_rel(ge, oe) < TOL, step
+            assert cmp_rel(gw, ow) < TOL, step
+            assert phase_diff(glogo, ologo) < TOL, step
+            assert cmp_rel(gphi, ophi, np.max(np.abs(ophi))) < TOL, step
+            oest = O.estimator(ow, oe)
+            assert abs(est.cpu().numpy()[0, 0] - oest["ENumer"]) < TOL * abs(oest["ENumer"])
+    finally:
+        if p is not small:
+            p.close()
