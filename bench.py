@@ -1,15 +1,18 @@
 #!/usr/bin/env python3
 """Walker-step throughput of the phaseless-AFQMC hot path on one MI355X.
 
-One step = afqmc_propagate (overlap/LU, force bias, V_HS, B1 T6(sqrt(dt) V_HS) B1,
-weight update) + afqmc_local_energy (overlap/LU, Coulomb, one-body, exchange,
-estimator), with afqmc_reorthogonalize every 5th step, for every walker of the
-headline workload (M=400 orbitals, 40+40 electrons, 1600 Cholesky vectors,
-256 walkers, dt=0.005; seeded synthetic Hamiltonian, trial and fields).
+One walker-step = propagation (overlap/LU, force bias, V_HS, B1 T6(sqrt(dt) V_HS)
+B1, weight update) + local energy (one-body, Coulomb, exchange, estimator), with
+re-orthogonalisation every 5th step, for every walker of the headline workload
+(M=400 orbitals, 40+40 electrons, 1600 Cholesky vectors, 256 walkers, dt=0.005;
+seeded synthetic Hamiltonian, trial and fields, resident in HBM before timing).
 
-Prints ONE JSON line with walker-steps/s, the roofline position of the
-dominant kernel (exchange) measured with the library's HIP-event phase timers
-inside the timed region, and the CPU oracle timed on a bounded sample.
+By default the FP64 path and the precision form (exchange and force bias in
+split BF16, everything else FP64) are both timed; the JSON line reports the
+precision form's walker-steps/s, its speed-up over FP64, and its per-walker
+energy error against the FP64 path on identical walker states (the bar is
+0.1 mHa).  The roofline object is the dominant kernel (exchange) of the reported
+path, timed by the library's HIP-event phase timers inside the timed region.
 """
 from __future__ import annotations
 
@@ -24,7 +27,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "walker-steps/s (propagate+energy) at M=400,N=40; speed-up vs FP64 at 0.1 mHa"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+# dense MI355X peaks per arithmetic type (TFLOP/s)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PRECISION_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6}
 
 
 def parse_args(argv=None):
@@ -33,13 +39,15 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small"])
-    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
+                    help="path reported in the JSON line (the FP64 path is timed too, for the speed-up)")
     ap.add_argument("--api", default="step", choices=["step", "separate"],
                     help="step: afqmc_step (one overlap/LU and one force bias per step); separate: "
                          "afqmc_propagate + afqmc_reorthogonalize + afqmc_local_energy")
-    ap.add_argument("--phases", action="store_true", help="print the per-phase table to stderr")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
+    ap.add_argument("--phases", action="store_true", help="print the per-phase tables to stderr")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the run, copy a device buffer of this many MiB (a plain copy kernel of known "
                          "size, for scaling the HBM byte counters of a profile)")
@@ -47,20 +55,20 @@ def parse_args(argv=None):
 
 
 def exchange_flops(M, na, nb, G, W):
-    """Algorithmic flops of one exchange launch: T = Ltilde Theta (real x complex,
-    4 flops per (i, j, q)) and the trace sum_ij T_ij T_ji (8 flops per (i, j))."""
+    """Algorithmic flops of one exchange launch pair (both spins): T = Ltilde Theta
+    (real x complex, 4 flops per (i, j, q)) and the trace sum_ij T_ij T_ji."""
     n2 = na * na + nb * nb
     return float(W) * (4.0 * n2 * M * G + 8.0 * n2 * G)
 
 
 def step_flops(M, na, nb, G):
     """Algorithmic flops of one walker-step (both spins, real L and trial,
-    complex walkers): exchange + trace + V_HS + Taylor(6) + B1 (twice) +
-    force bias and Coulomb (twice) + overlaps and solves."""
+    complex walkers): exchange + trace + V_HS + Taylor(6) + B1 (twice) + force
+    bias + overlaps and solves."""
     n2 = na * na + nb * nb
     nt = na + nb
     return (4.0 * n2 * M * G + 8.0 * n2 * G + 4.0 * G * M * M + 6 * 8.0 * M * M * nt + 2 * 4.0 * M * M * nt
-            + 2 * 4.0 * G * M * nt + 2 * 16.0 * M * n2)
+            + 4.0 * G * M * nt + 2 * 16.0 * M * n2)
 
 
 def cpu_baseline(spec, n_walkers, n_steps):
@@ -89,8 +97,49 @@ def cpu_baseline(spec, n_walkers, n_steps):
         O.local_energies(ham, phis)
     dt = time.perf_counter() - t0
     return {"value": n_walkers * n_steps / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_walkers} walkers x {n_steps} steps (propagate + local energy) of {spec.name}, "
+            "sample": f"{n_walkers} walkers x {n_steps} steps (propagate + local energy, FP64) of {spec.name}, "
                       f"{dt:.1f} s on the host CPU, numpy complex128"}
+
+
+def time_path(A, torch, ctx, spec, trial, xs, args):
+    """Warm up, then time args.steps steps; returns timing, phases and walkers."""
+    import afqmc_inputs as gi
+    W = spec.nwalkers
+    walkers = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
+    A.overlap(ctx, walkers)
+    e_out = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+    est = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+
+    def step(k):
+        reo = (k + 1) % spec.reortho_every == 0
+        if args.api == "step":
+            A.step(ctx, walkers, xs[k], e_out, est, reortho=reo)
+            return
+        A.propagate(ctx, walkers, xs[k])
+        if reo:
+            A.reorthogonalize(ctx, walkers)
+        A.local_energy(ctx, walkers, e_out, est)
+
+    nsteps = args.warmup + args.steps
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    A.set_timing(ctx, True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for k in range(args.warmup, nsteps):
+        step(k)
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    phases = A.get_timings(ctx)
+    A.set_timing(ctx, False)
+    h = est.cpu().numpy()[0]
+    return {"total_ms": total_ms, "phases": phases, "walkers": walkers,
+            "mixed_energy": float(h[0] / h[1]) if h[1] > 0 else float("nan"),
+            "flagged": int((walkers.flags.cpu().numpy() != 0).sum())}
 
 
 def main(argv=None):
@@ -98,7 +147,7 @@ def main(argv=None):
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures the walker step on one GPU only; multi-GPU runs are not part of this "
-              "build (walkers shard across GPUs with a 16-byte all-reduce per step).", file=sys.stderr)
+              "build (walkers shard across GPUs with a 32-byte all-reduce per step).", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -118,74 +167,72 @@ def main(argv=None):
     s = spec.system
     W, G, M = spec.nwalkers, s.nchol, s.nbasis
     h1, chol, ecore, trial = gi.make_system(s)
-    ctx = A.setup_hamiltonian(A.SystemInput(h1, chol, ecore, trial, s.nalpha, s.nbeta, W, spec.dt))
-    del chol
-    walkers = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
-    A.overlap(ctx, walkers)
+    sysin = A.SystemInput(h1, chol, ecore, trial, s.nalpha, s.nbeta, W, spec.dt)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(spec.field_seed)
-    nsteps = args.warmup + args.steps
-    xs = torch.randn((nsteps, W, G), dtype=torch.float64, device="cuda", generator=gen)
-    e_out = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
-    est = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+    xs = torch.randn((args.warmup + args.steps, W, G), dtype=torch.float64, device="cuda", generator=gen)
 
-    def step(k):
-        reo = (k + 1) % spec.reortho_every == 0
-        if args.api == "step":
-            A.step(ctx, walkers, xs[k], e_out, est, reortho=reo)
-            return
-        A.propagate(ctx, walkers, xs[k])
-        if reo:
-            A.reorthogonalize(ctx, walkers)
-        A.local_energy(ctx, walkers, e_out, est)
+    forms = ["fp64"] if args.precision == "fp64" else ["fp64", args.precision]
+    ctxs, runs = {}, {}
+    for form in forms:
+        ctxs[form] = A.setup_hamiltonian(sysin, A.default_options(precision=PRECISION_CODE[form]))
+        runs[form] = time_path(A, torch, ctxs[form], spec, trial, xs, args)
+    del chol
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    A.set_timing(ctx, True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for k in range(args.warmup, nsteps):
-        step(k)
-    ev1.record()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    phases = A.get_timings(ctx)
-    A.set_timing(ctx, False)
-    est_h = est.cpu().numpy()[0]
-    flags = walkers.flags.cpu().numpy()
-    energy = est_h[0] / est_h[1] if est_h[1] > 0 else float("nan")
-
-    ms_per_step = total_ms / args.steps
-    value = W * args.steps / (total_ms * 1e-3)
-    ex_ms, ex_n = phases["exchange"]
+    rep = args.precision
+    r = runs[rep]
+    ms_per_step = r["total_ms"] / args.steps
+    value = W * args.steps / (r["total_ms"] * 1e-3)
+    ex_ms, ex_n = r["phases"]["exchange"]
     ex_flops = exchange_flops(M, s.nalpha, s.nbeta, G, W)
-    achieved = ex_flops / (ex_ms / ex_n * 1e-3) / 1e12 if ex_n else 0.0
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None,
-                "kernel": "exchange (k_exchange_mfma)", "avg_launch_ms": round(ex_ms / max(ex_n, 1), 4),
-                "flops_per_launch": ex_flops}
+    avg_ms = ex_ms / max(ex_n, 1)
+    achieved = ex_flops / (avg_ms * 1e-3) / 1e12 if ex_n else 0.0
+    kernel = {"fp64": "k_exchange_mfma", "fp32": "k_exchange_f32", "bf16x3": "k_exchange_bf16x3"}[rep]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[rep], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS[rep], 4), "traffic": None,
+                "kernel": f"exchange ({kernel}, both spin blocks)", "avg_launch_ms": round(avg_ms, 4),
+                "flops_per_launch": ex_flops,
+                "executed_tflops": round(achieved * PRODUCTS[rep], 3)}
     step_tf = step_flops(M, s.nalpha, s.nbeta, G) * W / (ms_per_step * 1e-3) / 1e12
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if rep == "fp64" else f"{rep} (exchange, force bias) + f64 (rest)",
            "data": "synthetic (seeded generator: random symmetric h and Cholesky vectors scaled by "
                    "exp(-g/tau)/M, trial = lowest orbitals of a Fock-like matrix, N(0,1) fields)",
            "config": {"workload": spec.name, "nbasis": M, "nalpha": s.nalpha, "nbeta": s.nbeta, "nchol": G,
                       "nwalkers": W, "dt": spec.dt, "reortho_every": spec.reortho_every,
-                      "precision": "fp64", "taylor_order": 6, "api": args.api},
+                      "precision": rep, "taylor_order": 6, "api": args.api},
            "roofline": roofline,
            "step_algorithmic_tflops": round(step_tf, 3),
-           "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
-           "mixed_energy": round(float(energy), 8), "walkers_flagged": int((flags != 0).sum())}
+           "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
+           "mixed_energy": round(r["mixed_energy"], 8), "walkers_flagged": r["flagged"]}
+    if rep != "fp64":
+        f = runs["fp64"]
+        fp64_value = W * args.steps / (f["total_ms"] * 1e-3)
+        # energy error of the reduced form on identical walker states: its own
+        # final walkers evaluated by both paths
+        e_lp = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        e_64 = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        A.local_energy(ctxs[rep], r["walkers"], e_lp)
+        A.local_energy(ctxs["fp64"], r["walkers"], e_64)
+        torch.cuda.synchronize()
+        d = np.abs(e_lp.cpu().numpy()[:, 0] - e_64.cpu().numpy()[:, 0])
+        out["speedup_vs_fp64"] = round(value / fp64_value, 3)
+        out["fp64_path"] = {"value": round(fp64_value, 2), "ms_per_step": round(f["total_ms"] / args.steps, 4),
+                            "exchange_ms_per_step": round(f["phases"]["exchange"][0] / args.steps, 4),
+                            "mixed_energy": round(f["mixed_energy"], 8)}
+        out["energy_error_vs_fp64_ha"] = {"max": float(d.max()), "rms": float(np.sqrt((d ** 2).mean())),
+                                          "bar": 1e-4, "within_bar": bool(d.max() <= 1e-4)}
     if args.phases:
-        for k, (ms, n) in phases.items():
-            print(f"{k:12s} {ms / args.steps:9.3f} ms/step  {n:6d} launches", file=sys.stderr)
-    ctx.close()
-    del xs, walkers
+        for form in forms:
+            print(f"-- {form}", file=sys.stderr)
+            for k, (ms, n) in runs[form]["phases"].items():
+                print(f"{k:12s} {ms / args.steps:9.3f} ms/step  {n:6d} launches", file=sys.stderr)
+    for c in ctxs.values():
+        c.close()
+    del xs, runs
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_walkers, args.cpu_steps)

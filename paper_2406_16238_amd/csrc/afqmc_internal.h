@@ -64,7 +64,19 @@ struct System {
   int ex_nparts[2] = {0, 0};   // partials actually written per spin
   // Theta / vbias partials in `theta` / `fbpart` belong to these walker buffers
   const void *cache_phi = nullptr;
+  int fb_slices = 0;           // slices of fbpart holding the current vbias
+  // reduced-precision exchange (and force bias): per-spin operands
+  int precision = AFQMC_FP64;
+  void *lp_lhs[2] = {nullptr, nullptr};  // Ltilde as FP32 [G][M][NR] or BF16 planes [3][G][NR][Kp]
+  void *lp_rhs[2] = {nullptr, nullptr};  // Theta as FP32 [W][M][CP] or BF16 planes [3][W][CP][Kp]
 };
+
+// Reduced-precision exchange (k_exchange_lp.hip).
+bool lp_exchange_supported(int precision, int nr);
+size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs);
+hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st);
+hipError_t lp_enable_lds(const System &s);
+hipError_t launch_exchange_lp(const System &s, const double2 *theta, int W, hipStream_t st, double2 *vbpart);
 
 struct Options {
   int precision = AFQMC_FP64;
@@ -108,9 +120,11 @@ hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo,
 
 // Force bias: split-K contraction into fbpart, then the epilogues.
 hipError_t launch_force_bias_gemm(const System &s, const double2 *theta, int W, hipStream_t st);
+// The epilogues sum the `nslices` slices [nslices][W][G] of fbpart (split-K
+// partials of the force-bias GEMM, or the two spin parts from the exchange).
 hipError_t launch_fb_propagate_epilogue(const System &s, const Options &o, const double *x, int W,
-                                        uint32_t *flags, hipStream_t st);
-hipError_t launch_fb_energy_epilogue(const System &s, int W, double2 *vbias_out, hipStream_t st);
+                                        uint32_t *flags, int nslices, hipStream_t st);
+hipError_t launch_fb_energy_epilogue(const System &s, int W, double2 *vbias_out, int nslices, hipStream_t st);
 
 // Two-body generator A = sqrt(dt) V_HS for every walker.
 hipError_t launch_vhs(const System &s, int W, hipStream_t st);
@@ -124,7 +138,10 @@ hipError_t launch_weight_update(const System &s, const afqmc_walkers &w, int W, 
 
 // Energies.
 hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStream_t st);
-hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st);
+// With vbpart (MFMA path only) the kernel also writes this spin's trace of T,
+// sum_i T^{g s}_ii, to vbpart[s][w][g]: the spin parts of vbias_g.
+hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st,
+                           double2 *vbpart = nullptr);
 hipError_t exchange_enable_lds(const System &s);
 // LtS[g][q][i] = LtT[g][q][off + i] for i < N, zero for N <= i < NR.
 hipError_t launch_pad_half_rotated(const double *LtT, int G, int M, int Nt, int off, int N, int NR, double *LtS,
@@ -138,6 +155,7 @@ hipError_t launch_sum_slices(const double *parts, int nslices, long n, double al
                              hipStream_t st);
 hipError_t launch_add_identity(double *A, int M, double diag, hipStream_t st);
 hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, hipStream_t st);
+hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
 
 // Exchange launch geometry for a spin block width.
 void exchange_geometry(int nmax, int *gb, size_t *lds);

@@ -147,9 +147,11 @@ bool valid_desc(const afqmc_system_desc &d, std::string &why) {
 // Sizes of every buffer of one system (doubles, double2s, uint32s).
 struct Plan {
   size_t L, LtT, htT, trial, B1, lmf, theta, fbpart, yp, vhs, tbuf, wsc, wvec2, ekpart, stat, LtS0, LtS1;
+  size_t lp_bytes[2][2];  // reduced-precision operands per spin: [lhs, rhs] in bytes
   uint64_t bytes() const {
     return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc + LtS0 + LtS1) +
-           16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat;
+           16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat + lp_bytes[0][0] +
+           lp_bytes[0][1] + lp_bytes[1][0] + lp_bytes[1][1];
   }
 };
 
@@ -163,7 +165,7 @@ Plan plan_for(const System &s) {
   p.B1 = M * M;
   p.lmf = G;
   p.theta = W * M * Nt;
-  p.fbpart = (size_t)s.fb_ksplit * W * G;
+  p.fbpart = (size_t)std::max(s.fb_ksplit, 2) * W * G;
   p.yp = 2 * W * G;
   p.vhs = 2 * W * M * M;
   p.tbuf = W * M * Nt;
@@ -172,6 +174,12 @@ Plan plan_for(const System &s) {
   p.ekpart = W * 2 * (size_t)s.ex_stride;
   p.LtS0 = s.ex_mfma && s.Na > 0 ? G * M * (size_t)s.ex_plan[0].NR : 0;
   p.LtS1 = s.ex_mfma && s.Nb > 0 ? G * M * (size_t)s.ex_plan[1].NR : 0;
+  const size_t esz = s.precision == AFQMC_FP32_CONTRACT ? 4 : 2;
+  for (int sp = 0; sp < 2; ++sp) {
+    const bool on = s.precision != AFQMC_FP64 && s.ex_plan[sp].N > 0;
+    p.lp_bytes[sp][0] = on ? esz * lp_operand_elems(s.precision, s.G, s.M, s.W, s.ex_plan[sp].NR, true) : 0;
+    p.lp_bytes[sp][1] = on ? esz * lp_operand_elems(s.precision, s.G, s.M, s.W, s.ex_plan[sp].NR, false) : 0;
+  }
   p.stat = W;
   return p;
 }
@@ -193,13 +201,14 @@ afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W
     AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_new, s.stat_new, nullptr, st),
               "overlap kernel");
   }
-  {
-    Phase ph(c, AFQMC_PH_FORCE_BIAS, st);
-    AFQMC_HIP(launch_force_bias_gemm(s, s.theta, W, st), "force-bias kernel");
-  }
-  {
-    Phase ph(c, AFQMC_PH_FB_EPILOGUE, st);
-    AFQMC_HIP(launch_fb_energy_epilogue(s, W, nullptr, st), "Coulomb epilogue");
+  // vbias: as the trace of the exchange matrices (MFMA exchange), else by its own contraction
+  const bool fused_vb = s.ex_mfma;
+  if (!fused_vb) {
+    {
+      Phase ph(c, AFQMC_PH_FORCE_BIAS, st);
+      AFQMC_HIP(launch_force_bias_gemm(s, s.theta, W, st), "force-bias kernel");
+    }
+    s.fb_slices = s.fb_ksplit;
   }
   {
     Phase ph(c, AFQMC_PH_ENERGY_1B, st);
@@ -207,7 +216,15 @@ afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W
   }
   {
     Phase ph(c, AFQMC_PH_EXCHANGE, st);
-    AFQMC_HIP(launch_exchange(s, s.theta, W, st), "exchange kernel");
+    if (s.precision != AFQMC_FP64)
+      AFQMC_HIP(launch_exchange_lp(s, s.theta, W, st, s.fbpart), "reduced-precision exchange kernel");
+    else
+      AFQMC_HIP(launch_exchange(s, s.theta, W, st, fused_vb ? s.fbpart : nullptr), "exchange kernel");
+  }
+  if (fused_vb) s.fb_slices = 2;
+  {
+    Phase ph(c, AFQMC_PH_FB_EPILOGUE, st);
+    AFQMC_HIP(launch_fb_energy_epilogue(s, W, nullptr, s.fb_slices, st), "Coulomb epilogue");
   }
   {
     Phase ph(c, AFQMC_PH_COMBINE, st);
@@ -271,12 +288,18 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     return fail(AFQMC_ERR_UNSUPPORTED, "a spin block wider than " + std::to_string(kMaxSpinOrbitals) +
                                            " orbitals is not supported");
   s.use_mfma_gemm = !c->force_valu_gemm;
+  s.precision = c->opt.precision;
   s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
   exchange_geometry(nmax, &s.ex_gb, &s.ex_lds);
   s.ex_ngb = (s.G + s.ex_gb - 1) / s.ex_gb;
   s.ex_plan[0] = exchange_plan(s.Na, s.G, c->ex_wx);
   s.ex_plan[1] = exchange_plan(s.Nb, s.G, c->ex_wx);
   s.ex_mfma = (s.Na == 0 || s.ex_plan[0].mfma) && (s.Nb == 0 || s.ex_plan[1].mfma) && !c->force_valu_exchange;
+  if (s.precision != AFQMC_FP64) {
+    const bool ok = s.ex_mfma && (s.Na == 0 || lp_exchange_supported(s.precision, s.ex_plan[0].NR)) &&
+                    (s.Nb == 0 || lp_exchange_supported(s.precision, s.ex_plan[1].NR));
+    if (!ok) return fail(AFQMC_ERR_UNSUPPORTED, "reduced precision is built for spin blocks of up to 48 orbitals");
+  }
   if (s.ex_mfma) {
     s.ex_nparts[0] = s.ex_plan[0].ngroups;
     s.ex_nparts[1] = s.ex_plan[1].ngroups;
@@ -299,10 +322,17 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
             dalloc(c, &s.logo_new, p.wvec2) && dalloc(c, &s.e1, p.wvec2) && dalloc(c, &s.ej, p.wvec2) &&
             dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat) &&
             (p.LtS0 == 0 || dalloc(c, &s.LtS[0], p.LtS0)) && (p.LtS1 == 0 || dalloc(c, &s.LtS[1], p.LtS1));
+  for (int sp = 0; sp < 2 && ok; ++sp) {
+    unsigned char *b0 = nullptr, *b1 = nullptr;
+    if (p.lp_bytes[sp][0]) ok = ok && dalloc(c, &b0, p.lp_bytes[sp][0]) && dalloc(c, &b1, p.lp_bytes[sp][1]);
+    s.lp_lhs[sp] = b0;
+    s.lp_rhs[sp] = b1;
+  }
   if (!ok) return fail(AFQMC_ERR_OOM, "device allocation failed");
   *bytes_used += s.bytes;
   AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
   AFQMC_HIP(ovlp_enable_lds(nmax), "overlap kernel LDS attribute");
+  if (s.precision != AFQMC_FP64) AFQMC_HIP(lp_enable_lds(s), "reduced-precision exchange LDS attribute");
 
   const size_t mm = M * M;
   AFQMC_HIP(hipMemcpyAsync(s.L, d.chol, p.L * sizeof(double), hipMemcpyHostToDevice, st), "upload chol");
@@ -368,6 +398,8 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
         AFQMC_HIP(launch_pad_half_rotated(s.LtT, s.G, s.M, s.Nt, sp ? s.Na : 0, sp ? s.Nb : s.Na,
                                           s.ex_plan[sp].NR, s.LtS[sp], st),
                   "padded half rotation");
+    for (int sp = 0; sp < 2; ++sp)
+      if (s.lp_lhs[sp]) AFQMC_HIP(lp_prepare_lhs(s, sp, st), "reduced-precision half rotation");
   }
   // scalars and B1 = exp(-dt/2 H1)
   std::vector<double> hl(G), hH1(mm);
@@ -396,7 +428,10 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     for (size_t k = 0; k < M * Nt; ++k) hphi[k] = make_double2(d.trial[k], 0.0);
     AFQMC_HIP(hipMemcpyAsync(phi_t, hphi.data(), M * Nt * sizeof(double2), hipMemcpyHostToDevice, st),
               "upload trial walker");
+    const int prec = s.precision;
+    s.precision = AFQMC_FP64;  // the trial energy (and default E_T) in FP64
     afqmc_status r = local_energy_sys(nullptr, s, phi_t, 1, e_t, nullptr, nullptr, st);
+    s.precision = prec;
     if (r != AFQMC_OK) return r;
     double2 he[3];
     AFQMC_HIP(hipMemcpyAsync(he, e_t, sizeof(he), hipMemcpyDeviceToHost, st), "download trial energy");
@@ -443,11 +478,11 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     if (std::max(sys[i].nalpha, sys[i].nbeta) > kMaxSpinOrbitals)
       return fail(AFQMC_ERR_UNSUPPORTED, "system " + std::to_string(i) + ": a spin block wider than " +
                                              std::to_string(kMaxSpinOrbitals) + " orbitals is not supported");
-  if (o.precision != AFQMC_FP64)
-    return fail(AFQMC_ERR_UNSUPPORTED, "reduced-precision contractions are not built into this library");
   afqmc_ctx *c = new (std::nothrow) afqmc_ctx();
   if (!c) return fail(AFQMC_ERR_OOM, "host allocation failed");
   c->opt.precision = o.precision;
+  if (o.precision != AFQMC_FP64 && (o.reserved[0] & 1))
+    { delete c; return fail(AFQMC_ERR_UNSUPPORTED, "reduced precision needs the MFMA exchange kernel"); }
   c->opt.taylor_order = o.taylor_order;
   c->opt.fb_cap = o.fb_cap;
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
@@ -500,10 +535,11 @@ static afqmc_status propagate_sys(afqmc_ctx *ctx, System &s, const afqmc_walkers
       Phase ph(ctx, AFQMC_PH_FORCE_BIAS, st);
       AFQMC_HIP(launch_force_bias_gemm(s, s.theta, W, st), "force-bias kernel");
     }
+    s.fb_slices = s.fb_ksplit;
   }
   {
     Phase ph(ctx, AFQMC_PH_FB_EPILOGUE, st);
-    AFQMC_HIP(launch_fb_propagate_epilogue(s, ctx->opt, x, W, wk.flags, st), "force-bias epilogue");
+    AFQMC_HIP(launch_fb_propagate_epilogue(s, ctx->opt, x, W, wk.flags, s.fb_slices, st), "force-bias epilogue");
   }
   {
     Phase ph(ctx, AFQMC_PH_VHS, st);
@@ -681,7 +717,9 @@ afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w, void *cons
                                 s.logo_new, s.stat_new, nullptr, st),
               "overlap kernel");
     AFQMC_HIP(launch_force_bias_gemm(s, s.theta, s.W, st), "force-bias kernel");
-    AFQMC_HIP(launch_fb_energy_epilogue(s, s.W, static_cast<double2 *>(vbias_out[i]), st), "force-bias epilogue");
+    s.fb_slices = s.fb_ksplit;
+    AFQMC_HIP(launch_fb_energy_epilogue(s, s.W, static_cast<double2 *>(vbias_out[i]), s.fb_slices, st),
+              "force-bias epilogue");
   }
   return AFQMC_OK;
 }

@@ -157,7 +157,7 @@ template <int NR, int WX>
 __global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__restrict__ LtS,
                                                            const double *__restrict__ theta, int M, int Nt,
                                                            int off, int N, int G, int W, int stride, int spin,
-                                                           double2 *__restrict__ ekpart) {
+                                                           double2 *__restrict__ ekpart, double2 *__restrict__ vbpart) {
   constexpr int GC = (NR % 16 == 0) ? 1 : 2;  // Cholesky vectors per wave
   constexpr int WY = 4 / WX;
   constexpr int ROWW = GC * NR;              // rows per wave
@@ -255,6 +255,9 @@ __global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__rest
   const int w = w0 + wx;
   const bool odd = lr & 1;
   double pre = 0.0, pim = 0.0;
+  double dg[GC];  // this lane's share of Tr T per Cholesky vector (re or im by column parity)
+#pragma unroll
+  for (int gl = 0; gl < GC; ++gl) dg[gl] = 0.0;
 #pragma unroll
   for (int gl = 0; gl < GC; ++gl) {
     constexpr int SL = NR / 4;  // slabs per Cholesky vector
@@ -272,18 +275,32 @@ __global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__rest
         const double v = acc[gl * SL + i][j];
         pre = fma(v, odd ? -tji.y : tji.x, pre);
         pim = fma(v, odd ? tji.x : tji.y, pim);
+        dg[gl] += ((col >> 1) == row) ? v : 0.0;
       }
     __syncthreads();
   }
   pre = wave_sum(pre);
   pim = wave_sum(pim);
+  // this spin's part of the force bias, Tr T^{g} = sum_i T_ii: even lanes hold
+  // the real parts of the diagonal, odd lanes the imaginary parts
+  if (vbpart) {
+#pragma unroll
+    for (int gl = 0; gl < GC; ++gl) {
+      double dre = odd ? 0.0 : dg[gl], dim = odd ? dg[gl] : 0.0;
+      dre = wave_sum(dre);
+      dim = wave_sum(dim);
+      const int g = g0 + wy * GC + gl;
+      if (lane == 0 && w < W && g < G) vbpart[((size_t)spin * W + w) * G + g] = make_double2(dre, dim);
+    }
+  }
   if (lane == 0 && w < W && g0 + wy * GC < G)
     ekpart[((size_t)w * 2 + spin) * stride + gb * WY + wy] = make_double2(-0.5 * pre, -0.5 * pim);
 }
 
 namespace {
 
-using ExKernel = void (*)(const double *, const double *, int, int, int, int, int, int, int, int, double2 *);
+using ExKernel = void (*)(const double *, const double *, int, int, int, int, int, int, int, int, double2 *,
+                          double2 *);
 
 template <int WX>
 ExKernel pick_nr(int nr) {
@@ -329,15 +346,21 @@ ExchangePlan exchange_plan(int N, int G, int wx) {
   return p;
 }
 
-hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st) {
+hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st, double2 *vbpart) {
   if (s.ex_mfma) {
     for (int spin = 0; spin < 2; ++spin) {
       const ExchangePlan &p = s.ex_plan[spin];
-      if (p.N == 0) continue;
+      if (p.N == 0) {
+        if (vbpart) {
+          hipError_t e = launch_zero2(vbpart + (size_t)spin * W * s.G, (long)W * s.G, st);
+          if (e != hipSuccess) return e;
+        }
+        continue;
+      }
       ExKernel k = pick_exchange(p.NR, p.WX);
       dim3 grid(p.nwg, (W + p.WX - 1) / p.WX);
       hipLaunchKernelGGL(k, grid, dim3(kThreads), p.lds, st, s.LtS[spin], reinterpret_cast<const double *>(theta),
-                         s.M, s.Nt, spin ? s.Na : 0, p.N, s.G, W, s.ex_stride, spin, s.ekpart);
+                         s.M, s.Nt, spin ? s.Na : 0, p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

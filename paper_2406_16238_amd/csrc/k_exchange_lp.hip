@@ -1,0 +1,517 @@
+// Reduced-precision forms of the exchange contraction (and of the force bias,
+// which is its trace):
+//   T^{g s}_w = Ltilde^{g s} Theta_{s,w},  EK = -1/2 sum_g sum_s Tr(T T),
+//   vbias_g = sum_s Tr T^{g s}  (Sec. 2, eqs. Eloc and fb, by Wick's theorem).
+// FP32 form: Ltilde and Theta rounded to FP32, v_mfma_f32_16x16x4f32, FP32
+//   accumulation over the orbital index.
+// BF16x3 form: every FP32 operand x is split into three bfloat16 terms
+//   x = h + m + l (h = bf16(x), m = bf16(x - h), l = bf16(x - h - m)), and the
+//   product is recovered from the six terms of order <= 2,
+//   hh + hm + mh + mm + hl + lh, on v_mfma_f32_16x16x32_bf16 with FP32
+//   accumulation (the dropped ml + lm + ll terms are below FP32 rounding).
+// In both forms T is kept in LDS as FP32 and the traces are accumulated in FP64.
+// Overlaps, LU, propagation, weights and re-orthogonalisation stay FP64.
+//
+// Work decomposition as in the FP64 kernel: one GEMM per spin block with rows
+// (g, i) padded to NR per Cholesky vector and columns (w, j, re/im) padded to
+// CP = 2 NR per walker; wave (wy, wx) of a 2x2 grid owns GC whole Cholesky
+// vectors and one whole walker.  MFMA lane layouts (gfx950, checked on the
+// device): f32 16x16x4: lane l supplies A[l%16][l/16], B[l/16][l%16];
+// bf16 16x16x32: lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
+// B[8(l/16) .. +7][l%16]; both: accumulator item r of lane l is
+// D[4(l/16) + r][l%16].
+#include <hip/hip_bf16.h>
+
+#include "afqmc_internal.h"
+#include "device_util.h"
+
+namespace afqmc {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+namespace {
+constexpr int LWX = 2;      // walkers per workgroup
+constexpr int LWY = 2;      // Cholesky-vector groups per workgroup
+constexpr int LKC = 32;     // contraction rows per LDS stage
+constexpr int BPAD = 8;     // bf16 padding of a staged row (row stride 40 elements = 80 bytes)
+}  // namespace
+
+// Trace epilogue shared by both forms.  T of each wave (ROWW x CP floats) is in
+// LDS at row stride TSF; every lane pairs each accumulator entry with the
+// transposed entry of the same Cholesky vector and accumulates in FP64.
+template <int NR, int CT, int RT>
+__device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *sT, int TSF, int lane,
+                                         double &pre, double &pim, double *dg) {
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool odd = lr & 1;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + 4 * lk + r;
+        const int gl = row / NR, i = row - gl * NR;
+        const int col = ct * 16 + lr, j = col >> 1;
+        const float2 t = *reinterpret_cast<const float2 *>(sT + (gl * NR + j) * TSF + 2 * i);
+        const double v = (double)acc[rt][ct][r];
+        pre = fma(v, odd ? -(double)t.y : (double)t.x, pre);
+        pim = fma(v, odd ? (double)t.x : (double)t.y, pim);
+        const double d = (j == i) ? v : 0.0;
+        if (gl == 0) dg[0] += d;
+        else dg[1] += d;
+      }
+}
+
+template <int GC>
+__device__ __forceinline__ void lp_finish(double pre, double pim, const double *dg, int lane, int w, int W, int g0w,
+                                          int G, int spin, int stride, int part, double2 *ekpart,
+                                          double2 *vbpart) {
+  pre = wave_sum(pre);
+  pim = wave_sum(pim);
+  if (lane == 0 && w < W && g0w < G) ekpart[((size_t)w * 2 + spin) * stride + part] = make_double2(-0.5 * pre, -0.5 * pim);
+  if (vbpart) {
+    const bool odd = lane & 1;
+#pragma unroll
+    for (int gl = 0; gl < GC; ++gl) {
+      double dre = odd ? 0.0 : dg[gl], dim = odd ? dg[gl] : 0.0;
+      dre = wave_sum(dre);
+      dim = wave_sum(dim);
+      const int g = g0w + gl;
+      if (lane == 0 && w < W && g < G) vbpart[((size_t)spin * W + w) * G + g] = make_double2(dre, dim);
+    }
+  }
+}
+
+// ---- FP32 form ----------------------------------------------------------------
+// LtF[g][q][NR] (float, padded rows), ThF[w][q][CP] (float, interleaved complex,
+// padded columns) for one spin block.
+template <int NR>
+__global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restrict__ LtF,
+                                                          const float *__restrict__ ThF, int M, int N, int G, int W,
+                                                          int stride, int spin, double2 *__restrict__ ekpart,
+                                                          double2 *__restrict__ vbpart) {
+  constexpr int GC = (NR % 16 == 0) ? 1 : 2;
+  constexpr int ROWW = GC * NR, RT = ROWW / 16;
+  constexpr int CP = 2 * NR, CT = CP / 16;
+  constexpr int ROWS = LWY * ROWW;
+  constexpr int ASZ = LKC * ROWS, BSZ = LWX * LKC * CP;          // floats per stage
+  constexpr int APT = (ASZ / 4 + kThreads - 1) / kThreads;      // float4 loads per thread
+  constexpr int BPT = (BSZ / 4 + kThreads - 1) / kThreads;
+  constexpr int TSF = CP + 2;
+  extern __shared__ float fsm[];
+  float *sA = fsm, *sB = fsm + 2 * ASZ;
+
+  const int gb = blockIdx.x, wb = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wy = wv / LWX, wx = wv - (wv / LWX) * LWX;
+  const int g0 = gb * LWY * GC, w0 = wb * LWX;
+
+  float4 ra[APT], rb[BPT];
+  auto load = [&](int q0) {
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = 4 * (tid + r * kThreads);
+      const int q = e / ROWS, row = e - q * ROWS;
+      const int gl = row / NR, i = row - gl * NR;
+      const int g = g0 + gl, gq = q0 + q;
+      ra[r] = (e < ASZ && g < G && gq < M) ? *reinterpret_cast<const float4 *>(LtF + ((size_t)g * M + gq) * NR + i)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = 4 * (tid + r * kThreads);
+      const int c = e % CP, t = e / CP;
+      const int q = t % LKC, wl = t / LKC;
+      const int w = w0 + wl, gq = q0 + q;
+      rb[r] = (e < BSZ && w < W && gq < M) ? *reinterpret_cast<const float4 *>(ThF + ((size_t)w * M + gq) * CP + c)
+                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store = [&](int buf) {
+    float4 *a = reinterpret_cast<float4 *>(sA + buf * ASZ);
+    float4 *b = reinterpret_cast<float4 *>(sB + buf * BSZ);
+#pragma unroll
+    for (int r = 0; r < APT; ++r)
+      if (4 * (tid + r * kThreads) < ASZ) a[tid + r * kThreads] = ra[r];
+#pragma unroll
+    for (int r = 0; r < BPT; ++r)
+      if (4 * (tid + r * kThreads) < BSZ) b[tid + r * kThreads] = rb[r];
+  };
+
+  f4v acc[RT][CT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunk = (M + LKC - 1) / LKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * LKC);
+    const float *a = sA + buf * ASZ + wy * ROWW + lr;
+    const float *b = sB + buf * BSZ + wx * LKC * CP + lr;
+#pragma unroll
+    for (int ks = 0; ks < LKC / 4; ++ks) {
+      float av[RT], bv[CT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) av[i] = a[(ks * 4 + lk) * ROWS + i * 16];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) bv[j] = b[(ks * 4 + lk) * CP + j * 16];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  float *sT = fsm + (size_t)wv * ROWW * TSF;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
+  __syncthreads();
+  double pre = 0.0, pim = 0.0, dg[2] = {0.0, 0.0};
+  lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg);
+  lp_finish<GC>(pre, pim, dg, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart, vbpart);
+}
+
+// ---- BF16x3 form --------------------------------------------------------------
+// LtB[p][g][NR][Kp], ThB[p][w][CP][Kp] (bf16, p = h, m, l; contraction index
+// contiguous and zero-padded to Kp, a multiple of 32) for one spin block.
+template <int NR>
+__global__ __launch_bounds__(kThreads) void k_exchange_bf16x3(const __bf16 *__restrict__ LtB,
+                                                             const __bf16 *__restrict__ ThB, int Kp, int N, int G,
+                                                             int W, int stride, int spin,
+                                                             double2 *__restrict__ ekpart,
+                                                             double2 *__restrict__ vbpart) {
+  constexpr int GC = (NR % 16 == 0) ? 1 : 2;
+  constexpr int ROWW = GC * NR, RT = ROWW / 16;
+  constexpr int CP = 2 * NR, CT = CP / 16;
+  constexpr int ROWS = LWY * ROWW;
+  constexpr int COLS = LWX * CP;
+  constexpr int RS = LKC + BPAD;                 // staged row stride (bf16)
+  constexpr int ASZ = 3 * ROWS * RS, BSZ = 3 * COLS * RS;   // bf16 per stage
+  constexpr int AV = 3 * ROWS * (LKC / 8), BV = 3 * COLS * (LKC / 8);  // 16-byte vectors per stage
+  constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
+  constexpr int TSF = CP + 2;
+  extern __shared__ __bf16 bsm[];
+  __bf16 *sA = bsm, *sB = bsm + 2 * ASZ;
+
+  const int gb = blockIdx.x, wb = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wy = wv / LWX, wx = wv - (wv / LWX) * LWX;
+  const int g0 = gb * LWY * GC, w0 = wb * LWX;
+  const size_t aplane = (size_t)G * NR * Kp, bplane = (size_t)W * CP * Kp;
+
+  uint4 ra[APT], rb[BPT];
+  auto load = [&](int q0) {
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int v = tid + r * kThreads;                  // (p, row, k8)
+      const int k8 = v % (LKC / 8), t = v / (LKC / 8);
+      const int row = t % ROWS, p = t / ROWS;
+      const int gl = row / NR, i = row - gl * NR, g = g0 + gl;
+      ra[r] = (v < AV && g < G)
+                  ? *reinterpret_cast<const uint4 *>(LtB + p * aplane + ((size_t)g * NR + i) * Kp + q0 + 8 * k8)
+                  : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int v = tid + r * kThreads;                  // (p, col, k8)
+      const int k8 = v % (LKC / 8), t = v / (LKC / 8);
+      const int col = t % COLS, p = t / COLS;
+      const int wl = col / CP, c = col - wl * CP, w = w0 + wl;
+      rb[r] = (v < BV && w < W)
+                  ? *reinterpret_cast<const uint4 *>(ThB + p * bplane + ((size_t)w * CP + c) * Kp + q0 + 8 * k8)
+                  : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store = [&](int buf) {
+    __bf16 *a = sA + buf * ASZ;
+    __bf16 *b = sB + buf * BSZ;
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int v = tid + r * kThreads;
+      if (v < AV) {
+        const int k8 = v % (LKC / 8), t = v / (LKC / 8);
+        *reinterpret_cast<uint4 *>(a + t * RS + 8 * k8) = ra[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int v = tid + r * kThreads;
+      if (v < BV) {
+        const int k8 = v % (LKC / 8), t = v / (LKC / 8);
+        *reinterpret_cast<uint4 *>(b + t * RS + 8 * k8) = rb[r];
+      }
+    }
+  };
+
+  f4v acc[RT][CT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunk = Kp / LKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * LKC);
+    const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * lk;
+    const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * lk;
+    bf8v ah[RT], am[RT], al[RT], bh[CT], bm[CT], bl[CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      ah[i] = *reinterpret_cast<const bf8v *>(a + (0 * ROWS + i * 16) * RS);
+      am[i] = *reinterpret_cast<const bf8v *>(a + (1 * ROWS + i * 16) * RS);
+      al[i] = *reinterpret_cast<const bf8v *>(a + (2 * ROWS + i * 16) * RS);
+    }
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      bh[j] = *reinterpret_cast<const bf8v *>(b + (0 * COLS + j * 16) * RS);
+      bm[j] = *reinterpret_cast<const bf8v *>(b + (1 * COLS + j * 16) * RS);
+      bl[j] = *reinterpret_cast<const bf8v *>(b + (2 * COLS + j * 16) * RS);
+    }
+    // six sweeps, each over all accumulators, so dependent MFMAs are far apart
+#define AFQMC_SWEEP(X, Y)                                                                         \
+  _Pragma("unroll") for (int i = 0; i < RT; ++i) _Pragma("unroll") for (int j = 0; j < CT; ++j) \
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(X[i], Y[j], acc[i][j], 0, 0, 0);
+    AFQMC_SWEEP(al, bh)
+    AFQMC_SWEEP(ah, bl)
+    AFQMC_SWEEP(am, bm)
+    AFQMC_SWEEP(am, bh)
+    AFQMC_SWEEP(ah, bm)
+    AFQMC_SWEEP(ah, bh)
+#undef AFQMC_SWEEP
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * ROWW * TSF;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
+  __syncthreads();
+  double pre = 0.0, pim = 0.0, dg[2] = {0.0, 0.0};
+  lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg);
+  lp_finish<GC>(pre, pim, dg, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart, vbpart);
+}
+
+// ---- operand preparation -------------------------------------------------------
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+  h = (__bf16)x;
+  const float r1 = x - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
+
+// LtF[g][q][i] = float(LtS[g][q][i])
+__global__ void k_lt_to_f32(const double *__restrict__ LtS, long n, float *__restrict__ LtF) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) LtF[e] = (float)LtS[e];
+}
+
+// LtB[p][g][i][q] from LtS[g][q][i] (rows i < NR, q < Kp, zero for q >= M)
+__global__ void k_lt_to_bf16x3(const double *__restrict__ LtS, int G, int M, int NR, int Kp, __bf16 *__restrict__ LtB) {
+  const long n = (long)G * NR * Kp;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int q = (int)(e % Kp);
+  const long t = e / Kp;
+  const int i = (int)(t % NR);
+  const int g = (int)(t / NR);
+  const float x = (q < M) ? (float)LtS[((size_t)g * M + q) * NR + i] : 0.f;
+  __bf16 h, m, l;
+  split3(x, h, m, l);
+  LtB[e] = h;
+  LtB[n + e] = m;
+  LtB[2 * n + e] = l;
+}
+
+// ThF[w][q][c] (c < CP) from Theta[w][q][off + c/2] (re/im by parity), zero-padded
+__global__ void k_theta_to_f32(const double2 *__restrict__ theta, int W, int M, int Nt, int off, int N, int CP,
+                               float *__restrict__ ThF) {
+  const long n = (long)W * M * CP;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e % CP);
+  const long wq = e / CP;
+  float v = 0.f;
+  if (c < 2 * N) {
+    const double2 z = theta[(size_t)wq * Nt + off + (c >> 1)];
+    v = (float)((c & 1) ? z.y : z.x);
+  }
+  ThF[e] = v;
+}
+
+// ThB[p][w][c][q] (q < Kp) from Theta[w][q][off + c/2]; one workgroup per
+// (walker, 32 rows q) transposes through LDS
+__global__ __launch_bounds__(kThreads) void k_theta_to_bf16x3(const double2 *__restrict__ theta, int W, int M, int Nt,
+                                                             int off, int N, int CP, int Kp,
+                                                             __bf16 *__restrict__ ThB) {
+  extern __shared__ float tsm[];  // [32][CP + 1]
+  const int w = blockIdx.y, q0 = blockIdx.x * 32;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 32 * CP; e += blockDim.x) {
+    const int qq = e / CP, c = e - qq * CP;
+    const int q = q0 + qq;
+    float v = 0.f;
+    if (q < M && c < 2 * N) {
+      const double2 z = theta[((size_t)w * M + q) * Nt + off + (c >> 1)];
+      v = (float)((c & 1) ? z.y : z.x);
+    }
+    tsm[qq * (CP + 1) + c] = v;
+  }
+  __syncthreads();
+  const size_t plane = (size_t)W * CP * Kp;
+  for (int e = tid; e < 32 * CP; e += blockDim.x) {
+    const int c = e / 32, qq = e - c * 32;
+    __bf16 h, m, l;
+    split3(tsm[qq * (CP + 1) + c], h, m, l);
+    const size_t o = ((size_t)w * CP + c) * Kp + q0 + qq;
+    ThB[o] = h;
+    ThB[plane + o] = m;
+    ThB[2 * plane + o] = l;
+  }
+}
+
+// ---- dispatch -------------------------------------------------------------------
+namespace {
+using F32Kernel = void (*)(const float *, const float *, int, int, int, int, int, int, double2 *, double2 *);
+using BFKernel = void (*)(const __bf16 *, const __bf16 *, int, int, int, int, int, int, double2 *, double2 *);
+
+F32Kernel pick_f32(int nr) {
+  switch (nr) {
+    case 8: return k_exchange_f32<8>;
+    case 16: return k_exchange_f32<16>;
+    case 24: return k_exchange_f32<24>;
+    case 32: return k_exchange_f32<32>;
+    case 40: return k_exchange_f32<40>;
+    case 48: return k_exchange_f32<48>;
+    default: return nullptr;
+  }
+}
+BFKernel pick_bf(int nr) {
+  switch (nr) {
+    case 8: return k_exchange_bf16x3<8>;
+    case 16: return k_exchange_bf16x3<16>;
+    case 24: return k_exchange_bf16x3<24>;
+    case 32: return k_exchange_bf16x3<32>;
+    case 40: return k_exchange_bf16x3<40>;
+    case 48: return k_exchange_bf16x3<48>;
+    default: return nullptr;
+  }
+}
+size_t lds_f32(int nr) {
+  const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
+  const size_t stage = 2ull * (LKC * LWY * roww + LWX * LKC * cp) * sizeof(float);
+  const size_t epi = 4ull * roww * (cp + 2) * sizeof(float);
+  return stage > epi ? stage : epi;
+}
+size_t lds_bf(int nr) {
+  const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
+  const size_t stage = 2ull * 3 * (LWY * roww + LWX * cp) * (LKC + BPAD) * sizeof(__bf16);
+  const size_t epi = 4ull * roww * (cp + 2) * sizeof(float);
+  return stage > epi ? stage : epi;
+}
+}  // namespace
+
+bool lp_exchange_supported(int precision, int nr) {
+  if (precision == AFQMC_FP32_CONTRACT) return pick_f32(nr) && lds_f32(nr) <= 160 * 1024;
+  if (precision == AFQMC_BF16X3_CONTRACT) return pick_bf(nr) && lds_bf(nr) <= 160 * 1024;
+  return false;
+}
+
+size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs) {
+  const int kp = ((M + LKC - 1) / LKC) * LKC;
+  if (precision == AFQMC_FP32_CONTRACT) return lhs ? (size_t)G * M * nr : (size_t)W * M * 2 * nr;
+  return lhs ? 3ull * G * nr * kp : 3ull * W * 2 * nr * kp;
+}
+
+hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st) {
+  const ExchangePlan &p = s.ex_plan[spin];
+  if (p.N == 0) return hipSuccess;
+  if (s.precision == AFQMC_FP32_CONTRACT) {
+    const long n = (long)s.G * s.M * p.NR;
+    hipLaunchKernelGGL(k_lt_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtS[spin], n,
+                       static_cast<float *>(s.lp_lhs[spin]));
+  } else {
+    const int kp = ((s.M + LKC - 1) / LKC) * LKC;
+    const long n = (long)s.G * p.NR * kp;
+    hipLaunchKernelGGL(k_lt_to_bf16x3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtS[spin], s.G, s.M,
+                       p.NR, kp, static_cast<__bf16 *>(s.lp_lhs[spin]));
+  }
+  return hipGetLastError();
+}
+
+hipError_t lp_enable_lds(const System &s) {
+  for (int spin = 0; spin < 2; ++spin) {
+    const ExchangePlan &p = s.ex_plan[spin];
+    if (p.N == 0) continue;
+    hipError_t e = hipSuccess;
+    if (s.precision == AFQMC_FP32_CONTRACT)
+      e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_f32(p.NR)),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f32(p.NR));
+    else
+      e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_bf(p.NR)),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bf(p.NR));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_exchange_lp(const System &s, const double2 *theta, int W, hipStream_t st, double2 *vbpart) {
+  const int kp = ((s.M + LKC - 1) / LKC) * LKC;
+  for (int spin = 0; spin < 2; ++spin) {
+    const ExchangePlan &p = s.ex_plan[spin];
+    const int off = spin ? s.Na : 0;
+    if (p.N == 0) {
+      if (vbpart) {
+        hipError_t e = launch_zero2(vbpart + (size_t)spin * W * s.G, (long)W * s.G, st);
+        if (e != hipSuccess) return e;
+      }
+      continue;
+    }
+    const int CP = 2 * p.NR;
+    const int gc = p.GC;
+    dim3 grid((s.G + LWY * gc - 1) / (LWY * gc), (W + LWX - 1) / LWX);
+    if (s.precision == AFQMC_FP32_CONTRACT) {
+      float *thf = static_cast<float *>(s.lp_rhs[spin]);
+      const long n = (long)W * s.M * CP;
+      hipLaunchKernelGGL(k_theta_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, W, s.M, s.Nt,
+                         off, p.N, CP, thf);
+      hipLaunchKernelGGL(pick_f32(p.NR), grid, dim3(kThreads), lds_f32(p.NR), st,
+                         static_cast<const float *>(s.lp_lhs[spin]), thf, s.M, p.N, s.G, W, s.ex_stride, spin,
+                         s.ekpart, vbpart);
+    } else {
+      __bf16 *thb = static_cast<__bf16 *>(s.lp_rhs[spin]);
+      hipLaunchKernelGGL(k_theta_to_bf16x3, dim3(kp / 32, W), dim3(kThreads), 32 * (CP + 1) * sizeof(float), st,
+                         theta, W, s.M, s.Nt, off, p.N, CP, kp, thb);
+      hipLaunchKernelGGL(pick_bf(p.NR), grid, dim3(kThreads), lds_bf(p.NR), st,
+                         static_cast<const __bf16 *>(s.lp_lhs[spin]), thb, kp, p.N, s.G, W, s.ex_stride, spin,
+                         s.ekpart, vbpart);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace afqmc

@@ -60,8 +60,8 @@ __global__ __launch_bounds__(kThreads) void k_fb_propagate(const double2 *__rest
 }
 
 hipError_t launch_fb_propagate_epilogue(const System &s, const Options &o, const double *x, int W,
-                                        uint32_t *flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_fb_propagate, dim3(W), dim3(kThreads), 0, st, s.fbpart, s.fb_ksplit, s.lmf, x, s.G,
+                                        uint32_t *flags, int nslices, hipStream_t st) {
+  hipLaunchKernelGGL(k_fb_propagate, dim3(W), dim3(kThreads), 0, st, s.fbpart, nslices, s.lmf, x, s.G,
                      W, s.sqdt, o.fb_cap, s.yp, s.wsc, flags);
   return hipGetLastError();
 }
@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kThreads) void k_fb_energy(const double2 *__restric
   if (tid == 0) ej[w] = make_double2(0.5 * acc[0], 0.5 * acc[1]);
 }
 
-hipError_t launch_fb_energy_epilogue(const System &s, int W, double2 *vbias_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_fb_energy, dim3(W), dim3(kThreads), 0, st, s.fbpart, s.fb_ksplit, s.G, W, s.ej,
+hipError_t launch_fb_energy_epilogue(const System &s, int W, double2 *vbias_out, int nslices, hipStream_t st) {
+  hipLaunchKernelGGL(k_fb_energy, dim3(W), dim3(kThreads), 0, st, s.fbpart, nslices, s.G, W, s.ej,
                      vbias_out);
   return hipGetLastError();
 }
@@ -259,6 +259,17 @@ __global__ void k_add_identity(double *A, int M, double diag) {
 
 hipError_t launch_add_identity(double *A, int M, double diag, hipStream_t st) {
   hipLaunchKernelGGL(k_add_identity, dim3((M + 255) / 256), dim3(256), 0, st, A, M, diag);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_zero2(double2 *__restrict__ p, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_zero2(double2 *p, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

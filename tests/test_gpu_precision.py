@@ -1,0 +1,116 @@
+"""Precision form: exchange and force bias in FP32 or in split BF16 (three
+bfloat16 terms, six products, FP32 accumulation); overlaps, LU, propagation,
+weights and re-orthogonalisation in FP64.
+
+Bar: per-walker local energies within 0.1 mHa of the FP64 path (and of the
+oracle) on identical walker states; the mixed estimator of a short trajectory
+driven by the same fields within 0.1 mHa of the FP64 trajectory's.
+"""
+import numpy as np
+import pytest
+
+import afqmc_inputs as gi
+from oracle import afqmc_oracle as O
+from pairs import Pair, cmp_rel
+
+pytestmark = pytest.mark.gpu
+MHA = 1e-3
+FORMS = {"fp32": 1, "bf16x3": 2}
+
+
+def ctx_for(p, precision):
+    A = p.A
+    return A.setup_hamiltonian(A.SystemInput(p.h1, p.chol, p.ecore, p.trial, p.spec.nalpha, p.spec.nbeta, p.W,
+                                             p.dt), A.default_options(precision=precision))
+
+
+def energies(p, ctx, phis):
+    A, torch = p.A, p.torch
+    w = A.Walkers.from_numpy(phis)
+    A.overlap(ctx, w)
+    e = torch.empty((p.W, 3), dtype=torch.complex128, device="cuda")
+    A.local_energy(ctx, w, e)
+    torch.cuda.synchronize()
+    return e.cpu().numpy()
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("spec,W", [(gi.SMALL.system, 10), (gi.SystemSpec(100, 10, 10, 200, tau=75.0, seed=11), 70),
+                                    (gi.HEADLINE.system, 256)], ids=["small", "tiled", "headline"])
+def test_energy_error_on_identical_walkers(form, spec, W):
+    p = Pair(spec, W, 0.005)
+    ctx = ctx_for(p, FORMS[form])
+    try:
+        phis = gi.initial_walkers(p.trial, W, noise=0.02, seed=31)
+        e64 = energies(p, p.ctx, phis)
+        elp = energies(p, ctx, phis)
+        err = np.abs(elp - e64)
+        print(f"{form} M={spec.nbasis}: max |dE| {err[:, 0].max():.2e} Ha, rms {np.sqrt((err[:, 0]**2).mean()):.2e}")
+        assert err.max() < 0.1 * MHA
+        for k in np.unique(np.linspace(0, W - 1, 3).astype(int)):
+            oe = np.array(O.local_energy(p.ham, phis[k]))
+            assert np.abs(elp[k] - oe).max() < 0.1 * MHA
+        # the reduced form is not silently the FP64 path
+        if form == "fp32":
+            assert err[:, 2].max() > 0.0
+    finally:
+        ctx.close()
+        p.close()
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_force_bias_error(form):
+    """vbias enters through the trace of the exchange matrices: check it by the
+    Coulomb energy EJ = 1/2 sum vbias^2 of the FP32/BF16 path after a step."""
+    spec = gi.SystemSpec(100, 10, 10, 200, tau=75.0, seed=11)
+    p = Pair(spec, 32, 0.005)
+    ctx = ctx_for(p, FORMS[form])
+    try:
+        A, torch = p.A, p.torch
+        phis = gi.initial_walkers(p.trial, 32, noise=0.02, seed=5)
+        fields = gi.FieldStream(2, 32, spec.nchol)
+        outs = []
+        for c in (p.ctx, ctx):
+            w = A.Walkers.from_numpy(phis)
+            A.overlap(c, w)
+            e = torch.empty((32, 3), dtype=torch.complex128, device="cuda")
+            fl = gi.FieldStream(2, 32, spec.nchol)
+            for step in range(4):
+                A.step(c, w, torch.as_tensor(fl.next(), device="cuda"), e, reortho=(step == 2))
+            torch.cuda.synchronize()
+            outs.append((e.cpu().numpy(), w.weight.cpu().numpy(), w.phi.cpu().numpy()))
+        (e64, w64, f64), (elp, wlp, flp) = outs
+        assert np.abs(elp - e64).max() < 0.1 * MHA
+        assert cmp_rel(wlp, w64) < 1e-4       # the force bias moved the weights only slightly
+        assert cmp_rel(flp, f64, np.abs(f64).max()) < 1e-4
+    finally:
+        ctx.close()
+        p.close()
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_mixed_estimator_of_a_trajectory(form):
+    spec = gi.MEDIUM.system
+    p = Pair(spec, 128, 0.005)
+    ctx = ctx_for(p, FORMS[form])
+    try:
+        A, torch = p.A, p.torch
+        res = []
+        for c in (p.ctx, ctx):
+            w = A.Walkers.from_numpy(gi.initial_walkers(p.trial, 128))
+            A.overlap(c, w)
+            e = torch.empty((128, 3), dtype=torch.complex128, device="cuda")
+            est = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+            fl = gi.FieldStream(0, 128, spec.nchol)
+            mixed = []
+            for step in range(1, 11):
+                A.step(c, w, torch.as_tensor(fl.next(), device="cuda"), e, est, reortho=(step % 5 == 0))
+                h = est.cpu().numpy()[0]
+                mixed.append(h[0] / h[1])
+            res.append(np.array(mixed))
+        d = np.abs(res[1] - res[0])
+        print(f"{form}: mixed-estimator difference over 10 steps max {d.max():.2e} Ha")
+        assert d.max() < 0.1 * MHA
+    finally:
+        ctx.close()
+        p.close()
