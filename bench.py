@@ -33,12 +33,40 @@ PRECISION_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6}
 
 
+KERNEL_NAME = {"fp64": "k_exchange_mfma", "fp32": "k_exchange_f32", "bf16x3": "k_exchange_bf16x3"}
+KERNEL_SOURCE = {"k_exchange_mfma": "k_exchange.hip", "k_exchange_f32": "k_exchange_lp.hip",
+                 "k_exchange_bf16x3": "k_exchange_lp.hip"}
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "exchange_hbm_traffic.md")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    profile, or None when there is none for this workload or the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2406_16238_amd", "csrc", KERNEL_SOURCE[kernel])
+    try:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        # machine-readable rows: "traffic <kernel> <workload> <bytes per launch> <source sha256[:16]>"
+        f = line.strip().strip("`").split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[2] == workload:
+            return float(f[3]) if f[4] == digest else None
+    return None
+
+
 def parse_args(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batching"],
+                    help="batching: the sixteen-system set (aggregate walker-steps/s of separate contexts run "
+                         "one after another, of one set context over internal streams, and of that context "
+                         "replaying a hipGraph)")
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
                     help="path reported in the JSON line (the FP64 path is timed too, for the speed-up)")
     ap.add_argument("--api", default="step", choices=["step", "separate"],
@@ -142,6 +170,100 @@ def time_path(A, torch, ctx, spec, trial, xs, args):
             "flagged": int((walkers.flags.cpu().numpy() != 0).sum())}
 
 
+def bench_batching(args):
+    """Aggregate throughput of the sixteen-system set, FP64 and FP32."""
+    import numpy as np
+    import torch
+    import afqmc_inputs as gi
+    from paper_2406_16238_amd import afqmc as A
+
+    runs = gi.batching_specs()
+    inputs = []
+    for r in runs:
+        h1, chol, ecore, trial = gi.make_system(r.system)
+        inputs.append((A.SystemInput(h1, chol, ecore, trial, r.system.nalpha, r.system.nbeta, r.nwalkers, r.dt),
+                       trial))
+    total_w = sum(r.nwalkers for r in runs)
+    nsteps = args.warmup + args.steps
+
+    def buffers(idx):
+        ws, xs, es = [], [], []
+        for j in idx:
+            sysin, trial = inputs[j]
+            ws.append(A.Walkers.from_numpy(gi.initial_walkers(trial, sysin.nwalkers, seed=j)))
+            xs.append(torch.empty((sysin.nwalkers, sysin.nchol), dtype=torch.float64, device="cuda"))
+            es.append(torch.empty((sysin.nwalkers, 3), dtype=torch.complex128, device="cuda"))
+        return ws, xs, es
+
+    def timed(step_all, fill):
+        for k in range(args.warmup):
+            fill(k)
+            step_all(k)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for k in range(args.warmup, nsteps):
+            fill(k)
+            step_all(k)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    gen = torch.Generator(device="cuda")
+
+    def filler(xs):
+        def fill(k):
+            gen.manual_seed(1000 + k)
+            for x in xs:
+                x.normal_(generator=gen)
+        return fill
+
+    out_modes = {}
+    for prec_name, prec in (("fp64", 0), ("fp32", 1)):
+        modes = {}
+        # separate contexts, one after another on one stream
+        ctxs = [A.setup_hamiltonian(inputs[j][0], A.default_options(precision=prec, streams=1))
+                for j in range(len(inputs))]
+        ws, xs, es = buffers(range(len(inputs)))
+        for c, w in zip(ctxs, ws):
+            A.overlap(c, w)
+
+        def seq(k):
+            for c, w, x, e in zip(ctxs, ws, xs, es):
+                A.step(c, w, x, e, reortho=(k + 1) % 5 == 0)
+        ms = timed(seq, filler(xs))
+        modes["sequential"] = total_w * args.steps / (ms * 1e-3)
+        for c in ctxs:
+            c.close()
+        del ctxs, ws, xs, es
+        torch.cuda.empty_cache()
+        for label, graph in (("streams", 0), ("streams+graph", 1)):
+            ctx = A.setup_hamiltonian([i for i, _ in inputs], A.default_options(precision=prec, use_graph=graph))
+            ws, xs, es = buffers(range(len(inputs)))
+            A.overlap(ctx, ws)
+
+            def together(k):
+                A.step(ctx, ws, xs, es, reortho=(k + 1) % 5 == 0)
+            ms = timed(together, filler(xs))
+            modes[label] = total_w * args.steps / (ms * 1e-3)
+            ctx.close()
+            del ctx, ws, xs, es
+            torch.cuda.empty_cache()
+        out_modes[prec_name] = {k: round(v, 2) for k, v in modes.items()}
+        out_modes[prec_name]["speedup_vs_sequential"] = round(max(modes["streams"], modes["streams+graph"]) /
+                                                               modes["sequential"], 3)
+    best = max(out_modes["fp64"]["streams"], out_modes["fp64"]["streams+graph"])
+    out = {"metric": "aggregate walker-steps/s (propagate+energy), 16 uneven systems", "value": best,
+           "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded generator per system)",
+           "config": {"workload": "batching-16-systems-M60-360", "nbasis": [r.system.nbasis for r in runs],
+                      "nwalkers": [r.nwalkers for r in runs], "nchol": "4M", "n_per_spin": "M/10"},
+           "modes": out_modes}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -149,6 +271,9 @@ def main(argv=None):
         print("bench.py measures the walker step on one GPU only; multi-GPU runs are not part of this "
               "build (walkers shard across GPUs with a 32-byte all-reduce per step).", file=sys.stderr)
         return 2
+
+    if args.workload == "batching":
+        return bench_batching(args)
 
     import numpy as np
     import torch
@@ -183,14 +308,18 @@ def main(argv=None):
     r = runs[rep]
     ms_per_step = r["total_ms"] / args.steps
     value = W * args.steps / (r["total_ms"] * 1e-3)
+    # one exchange launch = one spin block of every walker (the phase timer
+    # brackets each launch on the library's stream)
     ex_ms, ex_n = r["phases"]["exchange"]
-    ex_flops = exchange_flops(M, s.nalpha, s.nbeta, G, W)
+    blocks = [n for n in (s.nalpha, s.nbeta) if n > 0]
+    ex_flops = exchange_flops(M, s.nalpha, s.nbeta, G, W) / len(blocks)
     avg_ms = ex_ms / max(ex_n, 1)
     achieved = ex_flops / (avg_ms * 1e-3) / 1e12 if ex_n else 0.0
-    kernel = {"fp64": "k_exchange_mfma", "fp32": "k_exchange_f32", "bf16x3": "k_exchange_bf16x3"}[rep]
+    kernel = KERNEL_NAME[rep]
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[rep], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[rep], 4), "traffic": None,
-                "kernel": f"exchange ({kernel}, both spin blocks)", "avg_launch_ms": round(avg_ms, 4),
+                "frac": round(achieved / PEAK_TFLOPS[rep], 4),
+                "traffic": measured_traffic(kernel, spec.name),
+                "kernel": f"{kernel} (one spin block of {W} walkers per launch)", "avg_launch_ms": round(avg_ms, 4),
                 "flops_per_launch": ex_flops,
                 "executed_tflops": round(achieved * PRODUCTS[rep], 3)}
     step_tf = step_flops(M, s.nalpha, s.nbeta, G) * W / (ms_per_step * 1e-3) / 1e12

@@ -73,6 +73,13 @@ typedef struct {
   double dt;            /* imaginary time step (eq. afqmc), > 0                     */
 } afqmc_system_desc;
 
+/* Exchange-energy mode of afqmc_local_energy and afqmc_step. */
+enum {
+  AFQMC_EX_FULL = 0,  /* exact exchange for every walker                               */
+  AFQMC_EX_CV = 1     /* learned control variate: a network's prediction for every
+                         walker, corrected by the exact exchange of a random subset  */
+};
+
 /* Options (zero-initialise, then call afqmc_default_options). */
 typedef struct {
   int32_t precision;        /* AFQMC_FP64 (default) or a *_CONTRACT form          */
@@ -80,10 +87,27 @@ typedef struct {
   double fb_cap;            /* force-bias modulus cap; default 1.0, <= 0 disables  */
   double e_shift;           /* energy shift E_T; NaN (default) = the trial's E_HF  */
   uint64_t mem_limit_bytes; /* refuse set-up needing more device memory; 0 = none  */
+  int32_t streams;          /* systems of a set run concurrently on this many
+                               internal streams (default 0 = min(nsys, 4));
+                               1 = one after another on the caller's stream.
+                               Results do not depend on it.                       */
+  int32_t use_graph;        /* afqmc_step records the whole step of every system
+                               into a hipGraph the first time it sees a set of
+                               buffers and flags, and replays it when they repeat
+                               (default 0).  Phase timers do not see replays.     */
+  int32_t tune;             /* time the exchange kernel's walker tiling (1, 2 or 4
+                               walkers per workgroup) at set-up and keep the
+                               fastest; default 1.  Results do not depend on it.  */
+  int32_t ex_mode;          /* AFQMC_EX_FULL (default) or AFQMC_EX_CV              */
+  double cv_fraction;       /* AFQMC_EX_CV: share of walkers whose exact exchange
+                               is computed per call, k = ceil(cv_fraction W);
+                               default 0.125, in (0, 1]                           */
+  uint64_t cv_seed;         /* AFQMC_EX_CV: seed of the subset draws; default 7   */
   int32_t reserved[8];      /* reserved[0] bit 0: VALU (non-MFMA) exchange kernel;
                                bit 1: VALU kernels for the force bias, V_HS, B1
                                and Taylor products (both for comparison runs);
-                               other bits and entries: zero                       */
+                               reserved[1]: walkers per exchange workgroup (1, 2
+                               or 4; overrides tune); other entries: zero         */
 } afqmc_options;
 
 /* Walker state of one system; every pointer is device memory owned by the caller. */
@@ -100,6 +124,10 @@ typedef struct {
   double e_shift;     /* E_T in use                                            */
   double const_c;     /* ecore - 1/2 sum_g l_g^2 (mean-field constant)         */
   uint64_t device_bytes; /* device memory held by this system                 */
+  int32_t exchange_tile; /* walkers per FP64 exchange workgroup in use (1/2/4)  */
+  int32_t lane;          /* internal stream of a system set (-1: caller's)      */
+  int64_t graph_captures; /* afqmc_step graphs recorded so far (whole context)  */
+  int64_t graph_replays;  /* afqmc_step graph replays so far (whole context)    */
 } afqmc_info;
 
 /* Fills `opt` with the defaults listed above.  Returns AFQMC_ERR_ARG on NULL. */
@@ -208,9 +236,10 @@ enum {
   AFQMC_PH_TAYLOR,        /* Taylor series of exp(sqrt(dt) V_HS)          */
   AFQMC_PH_WEIGHT,        /* phaseless weight update                      */
   AFQMC_PH_ENERGY_1B,     /* one-body energy                              */
-  AFQMC_PH_EXCHANGE,      /* exchange energy                              */
+  AFQMC_PH_EXCHANGE,      /* exchange energy: one interval per spin block */
   AFQMC_PH_COMBINE,       /* energy combination and estimator             */
   AFQMC_PH_REORTHO,       /* modified Gram-Schmidt                        */
+  AFQMC_PH_OPERANDS,      /* FP32 / split-BF16 copies of Theta            */
   AFQMC_NPHASES
 };
 typedef struct {

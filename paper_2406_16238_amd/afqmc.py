@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 OK, ERR_ARG, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 FP64, FP32_CONTRACT, BF16X3_CONTRACT = 0, 1, 2
 W_SINGULAR, W_NONFINITE, W_DEAD = 1, 2, 4
+EX_FULL, EX_CV = 0, 1
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
 
 
@@ -43,7 +44,9 @@ class SystemDesc(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("taylor_order", ctypes.c_int32),
                 ("fb_cap", ctypes.c_double), ("e_shift", ctypes.c_double),
-                ("mem_limit_bytes", ctypes.c_uint64), ("reserved", ctypes.c_int32 * 8)]
+                ("mem_limit_bytes", ctypes.c_uint64), ("streams", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("tune", ctypes.c_int32), ("ex_mode", ctypes.c_int32), ("cv_fraction", ctypes.c_double),
+                ("cv_seed", ctypes.c_uint64), ("reserved", ctypes.c_int32 * 8)]
 
 
 class CWalkers(ctypes.Structure):
@@ -53,11 +56,13 @@ class CWalkers(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("e_hf", ctypes.c_double), ("e_shift", ctypes.c_double),
-                ("const_c", ctypes.c_double), ("device_bytes", ctypes.c_uint64)]
+                ("const_c", ctypes.c_double), ("device_bytes", ctypes.c_uint64),
+                ("exchange_tile", ctypes.c_int32), ("lane", ctypes.c_int32),
+                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
 
 
 PHASES = ("overlap", "force_bias", "fb_epilogue", "vhs", "one_body", "taylor", "weight",
-          "energy_1b", "exchange", "combine", "reortho")
+          "energy_1b", "exchange", "combine", "reortho", "operands")
 
 
 class Timings(ctypes.Structure):

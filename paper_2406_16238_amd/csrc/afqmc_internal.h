@@ -76,7 +76,10 @@ bool lp_exchange_supported(int precision, int nr);
 size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs);
 hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st);
 hipError_t lp_enable_lds(const System &s);
-hipError_t launch_exchange_lp(const System &s, const double2 *theta, int W, hipStream_t st, double2 *vbpart);
+// Reduced-precision copy of one spin block of Theta (the right operand of the
+// exchange contraction), then the exchange of that spin block from it.
+hipError_t lp_prepare_rhs(const System &s, const double2 *theta, int W, int spin, hipStream_t st);
+hipError_t launch_exchange_lp(const System &s, int W, int spin, hipStream_t st, double2 *vbpart);
 
 struct Options {
   int precision = AFQMC_FP64;
@@ -140,8 +143,9 @@ hipError_t launch_weight_update(const System &s, const afqmc_walkers &w, int W, 
 hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStream_t st);
 // With vbpart (MFMA path only) the kernel also writes this spin's trace of T,
 // sum_i T^{g s}_ii, to vbpart[s][w][g]: the spin parts of vbias_g.
+// spin = 0 or 1 launches that spin block only, -1 both.
 hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st,
-                           double2 *vbpart = nullptr);
+                           double2 *vbpart = nullptr, int spin = -1);
 hipError_t exchange_enable_lds(const System &s);
 // LtS[g][q][i] = LtT[g][q][off + i] for i < N, zero for N <= i < NR.
 hipError_t launch_pad_half_rotated(const double *LtT, int G, int M, int Nt, int off, int N, int NR, double *LtS,

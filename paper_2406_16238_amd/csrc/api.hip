@@ -5,7 +5,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +42,25 @@ struct afqmc_ctx {
   bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
+  bool ex_wx_forced = false;
+  bool tune = true;
+  // system sets: internal streams (default priority) the systems are spread
+  // over, and the events that fork them from / join them into the caller's stream
+  std::vector<hipStream_t> lanes;
+  std::vector<int> lane_of;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
+  // graph replay of afqmc_step
+  bool use_graph = false;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t g_in = nullptr, g_out = nullptr;
+  struct GraphEntry {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;  // most recent last
+  int64_t graph_captures = 0, graph_replays = 0;
   // phase timers
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -69,7 +91,7 @@ struct Phase {
   hipStream_t st;
   size_t slot = (size_t)-1;
   Phase(afqmc_ctx *c_, int phase, hipStream_t st_) : c(c_), st(st_) {
-    if (!c || !c->timing) return;
+    if (!c || !c->timing || c->capturing) return;
     if (c->ev_used == 4096) fold_timings(c);
     if (c->ev_used == c->ev_start.size()) {
       hipEvent_t a, b;
@@ -96,6 +118,27 @@ void free_all(afqmc_ctx *c) {
   for (void *p : c->allocs)
     if (p) (void)hipFree(p);
   c->allocs.clear();
+}
+
+// Releases everything the context holds (after the device has finished with it).
+void release(afqmc_ctx *c) {
+  (void)hipDeviceSynchronize();
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+  for (hipStream_t l : c->lanes) (void)hipStreamDestroy(l);
+  c->lanes.clear();
+  for (hipEvent_t e : c->join_ev) (void)hipEventDestroy(e);
+  c->join_ev.clear();
+  for (hipEvent_t e : {c->fork_ev, c->g_in, c->g_out})
+    if (e) (void)hipEventDestroy(e);
+  c->fork_ev = c->g_in = c->g_out = nullptr;
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
+  for (hipEvent_t e : c->ev_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_stop) (void)hipEventDestroy(e);
+  c->ev_start.clear();
+  c->ev_stop.clear();
+  free_all(c);
 }
 
 // Device allocation recorded in the context; returns false on failure.
@@ -214,12 +257,18 @@ afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W
     Phase ph(c, AFQMC_PH_ENERGY_1B, st);
     AFQMC_HIP(launch_energy_e1(s, s.theta, W, st), "one-body energy kernel");
   }
-  {
-    Phase ph(c, AFQMC_PH_EXCHANGE, st);
-    if (s.precision != AFQMC_FP64)
-      AFQMC_HIP(launch_exchange_lp(s, s.theta, W, st, s.fbpart), "reduced-precision exchange kernel");
-    else
-      AFQMC_HIP(launch_exchange(s, s.theta, W, st, fused_vb ? s.fbpart : nullptr), "exchange kernel");
+  for (int spin = 0; spin < 2; ++spin) {
+    if (s.precision != AFQMC_FP64) {
+      {
+        Phase ph(c, AFQMC_PH_OPERANDS, st);
+        AFQMC_HIP(lp_prepare_rhs(s, s.theta, W, spin, st), "reduced-precision operand kernel");
+      }
+      Phase ph(c, AFQMC_PH_EXCHANGE, st);
+      AFQMC_HIP(launch_exchange_lp(s, W, spin, st, s.fbpart), "reduced-precision exchange kernel");
+    } else {
+      Phase ph(c, AFQMC_PH_EXCHANGE, st);
+      AFQMC_HIP(launch_exchange(s, s.theta, W, st, fused_vb ? s.fbpart : nullptr, spin), "exchange kernel");
+    }
   }
   if (fused_vb) s.fb_slices = 2;
   {
@@ -441,6 +490,123 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   return AFQMC_OK;
 }
 
+// Walker tiling of the FP64 exchange kernel: 1, 2 or 4 walkers per workgroup
+// (the four waves then split 4, 2 or 1 ways over Cholesky vectors).  Every
+// wave sums the same group of Cholesky vectors of one walker in the same
+// order whatever the tiling, so the choice changes speed only.  Timed on the
+// system's own shapes (Theta zeroed); the choice is kept per shape for the
+// rest of the process, so every context of one shape uses the same tiling.
+afqmc_status tune_exchange(System &s, hipStream_t st) {
+  static std::mutex mu;
+  static std::map<std::array<int, 5>, int> chosen;
+  const std::array<int, 5> key{s.M, s.Na, s.Nb, s.G, s.W};
+  int best = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = chosen.find(key);
+    if (it != chosen.end()) best = it->second;
+  }
+  if (best == 0) {
+    AFQMC_HIP(launch_zero2(s.theta, (long)s.W * s.M * s.Nt, st), "zero fill");
+    hipEvent_t e0, e1;
+    AFQMC_HIP(hipEventCreate(&e0), "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(AFQMC_ERR_HIP, "event create");
+    }
+    float best_ms = 0.0f;
+    hipError_t err = hipSuccess;
+    for (int wx : {1, 2, 4}) {
+      const ExchangePlan p0 = exchange_plan(s.Na, s.G, wx), p1 = exchange_plan(s.Nb, s.G, wx);
+      if ((s.Na > 0 && !p0.mfma) || (s.Nb > 0 && !p1.mfma)) continue;
+      s.ex_plan[0] = p0;
+      s.ex_plan[1] = p1;
+      if ((err = exchange_enable_lds(s)) != hipSuccess) break;
+      if ((err = launch_exchange(s, s.theta, s.W, st, s.fbpart)) != hipSuccess) break;
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 3 && err == hipSuccess; ++r) err = launch_exchange(s, s.theta, s.W, st, s.fbpart);
+      (void)hipEventRecord(e1, st);
+      if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best == 0 || ms < best_ms) {
+        best = wx;
+        best_ms = ms;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(AFQMC_ERR_HIP, std::string("exchange tuning: ") + hipGetErrorString(err));
+    if (best == 0) return AFQMC_OK;
+    std::lock_guard<std::mutex> lock(mu);
+    chosen.emplace(key, best);
+  }
+  s.ex_plan[0] = exchange_plan(s.Na, s.G, best);
+  s.ex_plan[1] = exchange_plan(s.Nb, s.G, best);
+  AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
+  return AFQMC_OK;
+}
+
+// Estimated cost of one step of system s (flops; for spreading systems over lanes).
+double step_cost(const System &s) {
+  const double M = s.M, G = s.G, n2 = (double)s.Na * s.Na + (double)s.Nb * s.Nb;
+  return s.W * (4.0 * n2 * M * G + 4.0 * G * M * M + 64.0 * M * M * s.Nt) + 2.0e7;
+}
+
+// Runs body(i, stream) for every system: in order on the caller's stream, or
+// spread over the context's lanes, forked after the work already enqueued on
+// `st` and joined back into it.  Each system's work stays in order on its lane.
+template <class F>
+afqmc_status for_each_system(afqmc_ctx *c, hipStream_t st, F body) {
+  const int n = (int)c->sys.size();
+  if (c->lanes.empty()) {
+    for (int i = 0; i < n; ++i) {
+      afqmc_status r = body(i, st);
+      if (r != AFQMC_OK) return r;
+    }
+    return AFQMC_OK;
+  }
+  AFQMC_HIP(hipEventRecord(c->fork_ev, st), "event record");
+  for (hipStream_t l : c->lanes) AFQMC_HIP(hipStreamWaitEvent(l, c->fork_ev, 0), "stream wait");
+  afqmc_status res = AFQMC_OK;
+  for (int i = 0; i < n && res == AFQMC_OK; ++i) res = body(i, c->lanes[c->lane_of[i]]);
+  // join every lane, also after a failure, so that no lane runs ahead of `st`
+  for (size_t l = 0; l < c->lanes.size(); ++l) {
+    AFQMC_HIP(hipEventRecord(c->join_ev[l], c->lanes[l]), "event record");
+    AFQMC_HIP(hipStreamWaitEvent(st, c->join_ev[l], 0), "stream wait");
+  }
+  return res;
+}
+
+// Internal streams of a system set, with systems assigned largest first to the
+// least-loaded lane.
+afqmc_status make_lanes(afqmc_ctx *c, int nl) {
+  const int n = (int)c->sys.size();
+  if (nl <= 1 || n <= 1) return AFQMC_OK;
+  nl = std::min(nl, n);
+  for (int l = 0; l < nl; ++l) {
+    hipStream_t h;
+    AFQMC_HIP(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), "stream create");
+    c->lanes.push_back(h);
+    hipEvent_t e;
+    AFQMC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
+    c->join_ev.push_back(e);
+  }
+  AFQMC_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "event create");
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return step_cost(c->sys[a]) > step_cost(c->sys[b]); });
+  std::vector<double> load(nl, 0.0);
+  c->lane_of.assign(n, 0);
+  for (int i : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    c->lane_of[i] = l;
+    load[l] += step_cost(c->sys[i]);
+  }
+  return AFQMC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -453,6 +619,12 @@ afqmc_status afqmc_default_options(afqmc_options *opt) {
   opt->fb_cap = 1.0;
   opt->e_shift = NAN;
   opt->mem_limit_bytes = 0;
+  opt->streams = 0;
+  opt->use_graph = 0;
+  opt->tune = 1;
+  opt->ex_mode = AFQMC_EX_FULL;
+  opt->cv_fraction = 0.125;
+  opt->cv_seed = 7;
   return AFQMC_OK;
 }
 
@@ -470,6 +642,10 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     return fail(AFQMC_ERR_ARG, "unknown precision");
   if (o.taylor_order < 1 || o.taylor_order > 16) return fail(AFQMC_ERR_ARG, "taylor_order must be in 1..16");
   if (std::isnan(o.fb_cap) || std::isinf(o.fb_cap)) return fail(AFQMC_ERR_ARG, "fb_cap must be finite");
+  if (o.streams < 0) return fail(AFQMC_ERR_ARG, "streams must be >= 0");
+  if (o.ex_mode != AFQMC_EX_FULL && o.ex_mode != AFQMC_EX_CV) return fail(AFQMC_ERR_ARG, "unknown ex_mode");
+  if (!(o.cv_fraction > 0.0 && o.cv_fraction <= 1.0)) return fail(AFQMC_ERR_ARG, "cv_fraction must be in (0, 1]");
+  if (o.ex_mode == AFQMC_EX_CV) return fail(AFQMC_ERR_UNSUPPORTED, "the control-variate exchange is not built yet");
   for (int i = 0; i < nsys; ++i) {
     std::string why;
     if (!valid_desc(sys[i], why)) return fail(AFQMC_ERR_ARG, "system " + std::to_string(i) + ": " + why);
@@ -487,26 +663,40 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->opt.fb_cap = o.fb_cap;
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
-  if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) c->ex_wx = o.reserved[1];
+  if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
+    c->ex_wx = o.reserved[1];
+    c->ex_wx_forced = true;
+  }
+  c->tune = o.tune != 0 && !c->ex_wx_forced;
+  c->use_graph = o.use_graph != 0;
   (void)hipGetDevice(&c->device);
   c->sys.resize(nsys);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   uint64_t used = 0;
   for (int i = 0; i < nsys; ++i) {
     afqmc_status r = setup_one(c, sys[i], c->sys[i], st, &used, o.mem_limit_bytes);
+    System &sy = c->sys[i];
+    if (r == AFQMC_OK && c->tune && sy.ex_mfma && sy.precision == AFQMC_FP64) r = tune_exchange(sy, st);
     if (r != AFQMC_OK) {
       (void)hipStreamSynchronize(st);
-      free_all(c);
+      release(c);
       delete c;
       return r;
     }
-    System &sy = c->sys[i];
     sy.e_shift = std::isnan(o.e_shift) ? sy.e_hf : o.e_shift;
   }
-  if (hipStreamSynchronize(st) != hipSuccess) {
-    free_all(c);
+  afqmc_status r = make_lanes(c, o.streams == 0 ? 4 : o.streams);
+  if (r == AFQMC_OK && c->use_graph) {
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->g_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->g_out, hipEventDisableTiming) != hipSuccess)
+      r = fail(AFQMC_ERR_HIP, "graph stream or event create");
+  }
+  if (r == AFQMC_OK && hipStreamSynchronize(st) != hipSuccess) r = fail(AFQMC_ERR_HIP, "set-up failed on the device");
+  if (r != AFQMC_OK) {
+    release(c);
     delete c;
-    return fail(AFQMC_ERR_HIP, "set-up failed on the device");
+    return r;
   }
   *out = c;
   return AFQMC_OK;
@@ -595,12 +785,98 @@ afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const doubl
     if (r != AFQMC_OK) return r;
     if (!x[i]) return fail(AFQMC_ERR_ARG, "fields of system " + std::to_string(i) + " are NULL");
   }
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
-    afqmc_status r = propagate_sys(ctx, ctx->sys[i], w[i], x[i], false, false, st);
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
+    return propagate_sys(ctx, ctx->sys[i], w[i], x[i], false, false, ls);
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// The body of afqmc_step (arguments already checked).
+afqmc_status step_body(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
+                       double *est_out, uint32_t flags, hipStream_t st) {
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
+    System &s = ctx->sys[i];
+    const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
+    s.cache_phi = nullptr;
+    afqmc_status r = propagate_sys(ctx, s, w[i], x[i], reuse, true, ls);
     if (r != AFQMC_OK) return r;
+    if (flags & AFQMC_STEP_REORTHO) {
+      Phase ph(ctx, AFQMC_PH_REORTHO, ls);
+      AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
+                           static_cast<double2 *>(w[i].log_ovlp), ls),
+                "Gram-Schmidt kernel");
+    }
+    r = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, static_cast<double2 *>(e_out[i]),
+                         est_out ? est_out + 4 * i : nullptr, w[i].weight, ls, true);
+    if (r != AFQMC_OK) return r;
+    s.cache_phi = w[i].phi;
+    return AFQMC_OK;
+  });
+}
+
+// afqmc_step through a hipGraph: the step is recorded on the context's own
+// stream (never the caller's, which may be the legacy default stream) the first
+// time a combination of buffers, flags and cached state is seen, and replayed
+// after that.  Up to eight recorded steps are kept (a run alternates between a
+// few: the first step, plain steps and re-orthogonalising steps).
+afqmc_status step_graph(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
+                        double *est_out, uint32_t flags, hipStream_t st) {
+  std::vector<uintptr_t> key;
+  key.push_back(flags);
+  key.push_back(reinterpret_cast<uintptr_t>(est_out));
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    const System &s = ctx->sys[i];
+    const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
+    for (const void *p : {(const void *)w[i].phi, (const void *)w[i].weight, (const void *)w[i].log_ovlp,
+                          (const void *)w[i].flags, (const void *)x[i], (const void *)e_out[i]})
+      key.push_back(reinterpret_cast<uintptr_t>(p));
+    key.push_back(reuse ? 1u : 0u);
   }
+  hipGraphExec_t exec = nullptr;
+  for (auto &g : ctx->graphs)
+    if (g.key == key) exec = g.exec;
+  if (!exec) {
+    AFQMC_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    ctx->capturing = true;
+    afqmc_status r = step_body(ctx, w, x, e_out, est_out, flags, ctx->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    ctx->capturing = false;
+    if (r == AFQMC_OK && e != hipSuccess) r = fail(AFQMC_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e));
+    if (r == AFQMC_OK) {
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) r = fail(AFQMC_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (r != AFQMC_OK) {
+      for (System &s : ctx->sys) s.cache_phi = nullptr;
+      return r;
+    }
+    if (ctx->graphs.size() == 8) {
+      (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+      ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({key, exec});
+    ++ctx->graph_captures;
+  } else {
+    // the host-side state a recorded step leaves behind
+    for (size_t i = 0; i < ctx->sys.size(); ++i) ctx->sys[i].cache_phi = w[i].phi;
+    ++ctx->graph_replays;
+  }
+  AFQMC_HIP(hipEventRecord(ctx->g_in, st), "event record");
+  AFQMC_HIP(hipStreamWaitEvent(ctx->cap_stream, ctx->g_in, 0), "stream wait");
+  AFQMC_HIP(hipGraphLaunch(exec, ctx->cap_stream), "graph launch");
+  AFQMC_HIP(hipEventRecord(ctx->g_out, ctx->cap_stream), "event record");
+  AFQMC_HIP(hipStreamWaitEvent(st, ctx->g_out, 0), "stream wait");
   return AFQMC_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 afqmc_status afqmc_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
                         double *est_out, uint32_t flags, void *hip_stream) {
@@ -612,24 +888,8 @@ afqmc_status afqmc_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *co
     if (r != AFQMC_OK) return r;
     if (!x[i] || !e_out[i]) return fail(AFQMC_ERR_ARG, "NULL fields or e_out of system " + std::to_string(i));
   }
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
-    System &s = ctx->sys[i];
-    const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
-    s.cache_phi = nullptr;
-    afqmc_status r = propagate_sys(ctx, s, w[i], x[i], reuse, true, st);
-    if (r != AFQMC_OK) return r;
-    if (flags & AFQMC_STEP_REORTHO) {
-      Phase ph(ctx, AFQMC_PH_REORTHO, st);
-      AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
-                           static_cast<double2 *>(w[i].log_ovlp), st),
-                "Gram-Schmidt kernel");
-    }
-    r = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, static_cast<double2 *>(e_out[i]),
-                         est_out ? est_out + 4 * i : nullptr, w[i].weight, st, true);
-    if (r != AFQMC_OK) return r;
-    s.cache_phi = w[i].phi;
-  }
-  return AFQMC_OK;
+  if (ctx->use_graph) return step_graph(ctx, w, x, e_out, est_out, flags, st);
+  return step_body(ctx, w, x, e_out, est_out, flags, st);
 }
 
 afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *e_out, double *est_out,
@@ -642,14 +902,11 @@ afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w, void *co
     if (r != AFQMC_OK) return r;
     if (!e_out[i]) return fail(AFQMC_ERR_ARG, "e_out of system " + std::to_string(i) + " is NULL");
   }
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
     System &s = ctx->sys[i];
-    afqmc_status r = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W,
-                                      static_cast<double2 *>(e_out[i]), est_out ? est_out + 4 * i : nullptr,
-                                      w[i].weight, st);
-    if (r != AFQMC_OK) return r;
-  }
-  return AFQMC_OK;
+    return local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, static_cast<double2 *>(e_out[i]),
+                            est_out ? est_out + 4 * i : nullptr, w[i].weight, ls);
+  });
 }
 
 afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream) {
@@ -660,14 +917,14 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void 
     afqmc_status r = check_walkers(w[i], (int)i);
     if (r != AFQMC_OK) return r;
   }
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
     System &s = ctx->sys[i];
-    Phase ph(ctx, AFQMC_PH_REORTHO, st);
+    Phase ph(ctx, AFQMC_PH_REORTHO, ls);
     AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
-                         static_cast<double2 *>(w[i].log_ovlp), st),
+                         static_cast<double2 *>(w[i].log_ovlp), ls),
               "Gram-Schmidt kernel");
-  }
-  return AFQMC_OK;
+    return AFQMC_OK;
+  });
 }
 
 afqmc_status afqmc_overlap(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_stream) {
@@ -678,13 +935,13 @@ afqmc_status afqmc_overlap(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_str
     afqmc_status r = check_walkers(w[i], (int)i);
     if (r != AFQMC_OK) return r;
   }
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
     System &s = ctx->sys[i];
     AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, nullptr,
-                                static_cast<double2 *>(w[i].log_ovlp), s.stat_new, w[i].flags, st),
+                                static_cast<double2 *>(w[i].log_ovlp), s.stat_new, w[i].flags, ls),
               "overlap kernel");
-  }
-  return AFQMC_OK;
+    return AFQMC_OK;
+  });
 }
 
 afqmc_status afqmc_greens_function(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *theta_out,
@@ -754,15 +1011,16 @@ afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out)
   out->e_shift = s.e_shift;
   out->const_c = s.const_c;
   out->device_bytes = s.bytes;
+  out->exchange_tile = s.ex_mfma ? s.ex_plan[s.Na > 0 ? 0 : 1].WX : 0;
+  out->lane = ctx->lanes.empty() ? -1 : ctx->lane_of[isys];
+  out->graph_captures = ctx->graph_captures;
+  out->graph_replays = ctx->graph_replays;
   return AFQMC_OK;
 }
 
 void afqmc_destroy(afqmc_ctx *ctx) {
   if (!ctx) return;
-  (void)hipDeviceSynchronize();
-  for (hipEvent_t e : ctx->ev_start) (void)hipEventDestroy(e);
-  for (hipEvent_t e : ctx->ev_stop) (void)hipEventDestroy(e);
-  free_all(ctx);
+  release(ctx);
   delete ctx;
 }
 

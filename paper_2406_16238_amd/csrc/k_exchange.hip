@@ -346,9 +346,11 @@ ExchangePlan exchange_plan(int N, int G, int wx) {
   return p;
 }
 
-hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st, double2 *vbpart) {
+hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStream_t st, double2 *vbpart,
+                           int only) {
   if (s.ex_mfma) {
     for (int spin = 0; spin < 2; ++spin) {
+      if (only >= 0 && spin != only) continue;
       const ExchangePlan &p = s.ex_plan[spin];
       if (p.N == 0) {
         if (vbpart) {
@@ -366,6 +368,7 @@ hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStre
     }
     return hipSuccess;
   }
+  if (only == 1) return hipSuccess;  // the VALU kernel covers both spin blocks in one launch
   dim3 grid(s.ex_ngb, 2, W);
   hipLaunchKernelGGL(k_exchange_v1, grid, dim3(kThreads), s.ex_lds, st, s.LtT, theta, s.M, s.Na, s.Nb, s.G,
                      s.ex_gb, s.ex_ngb, s.ekpart);

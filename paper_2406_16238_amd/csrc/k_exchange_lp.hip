@@ -477,41 +477,39 @@ hipError_t lp_enable_lds(const System &s) {
   return hipSuccess;
 }
 
-hipError_t launch_exchange_lp(const System &s, const double2 *theta, int W, hipStream_t st, double2 *vbpart) {
-  const int kp = ((s.M + LKC - 1) / LKC) * LKC;
-  for (int spin = 0; spin < 2; ++spin) {
-    const ExchangePlan &p = s.ex_plan[spin];
-    const int off = spin ? s.Na : 0;
-    if (p.N == 0) {
-      if (vbpart) {
-        hipError_t e = launch_zero2(vbpart + (size_t)spin * W * s.G, (long)W * s.G, st);
-        if (e != hipSuccess) return e;
-      }
-      continue;
-    }
-    const int CP = 2 * p.NR;
-    const int gc = p.GC;
-    dim3 grid((s.G + LWY * gc - 1) / (LWY * gc), (W + LWX - 1) / LWX);
-    if (s.precision == AFQMC_FP32_CONTRACT) {
-      float *thf = static_cast<float *>(s.lp_rhs[spin]);
-      const long n = (long)W * s.M * CP;
-      hipLaunchKernelGGL(k_theta_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, W, s.M, s.Nt,
-                         off, p.N, CP, thf);
-      hipLaunchKernelGGL(pick_f32(p.NR), grid, dim3(kThreads), lds_f32(p.NR), st,
-                         static_cast<const float *>(s.lp_lhs[spin]), thf, s.M, p.N, s.G, W, s.ex_stride, spin,
-                         s.ekpart, vbpart);
-    } else {
-      __bf16 *thb = static_cast<__bf16 *>(s.lp_rhs[spin]);
-      hipLaunchKernelGGL(k_theta_to_bf16x3, dim3(kp / 32, W), dim3(kThreads), 32 * (CP + 1) * sizeof(float), st,
-                         theta, W, s.M, s.Nt, off, p.N, CP, kp, thb);
-      hipLaunchKernelGGL(pick_bf(p.NR), grid, dim3(kThreads), lds_bf(p.NR), st,
-                         static_cast<const __bf16 *>(s.lp_lhs[spin]), thb, kp, p.N, s.G, W, s.ex_stride, spin,
-                         s.ekpart, vbpart);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t lp_prepare_rhs(const System &s, const double2 *theta, int W, int spin, hipStream_t st) {
+  const ExchangePlan &p = s.ex_plan[spin];
+  if (p.N == 0) return hipSuccess;
+  const int off = spin ? s.Na : 0;
+  const int CP = 2 * p.NR;
+  if (s.precision == AFQMC_FP32_CONTRACT) {
+    const long n = (long)W * s.M * CP;
+    hipLaunchKernelGGL(k_theta_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, W, s.M, s.Nt,
+                       off, p.N, CP, static_cast<float *>(s.lp_rhs[spin]));
+  } else {
+    const int kp = ((s.M + LKC - 1) / LKC) * LKC;
+    hipLaunchKernelGGL(k_theta_to_bf16x3, dim3(kp / 32, W), dim3(kThreads), 32 * (CP + 1) * sizeof(float), st,
+                       theta, W, s.M, s.Nt, off, p.N, CP, kp, static_cast<__bf16 *>(s.lp_rhs[spin]));
   }
-  return hipSuccess;
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange_lp(const System &s, int W, int spin, hipStream_t st, double2 *vbpart) {
+  const ExchangePlan &p = s.ex_plan[spin];
+  if (p.N == 0) return vbpart ? launch_zero2(vbpart + (size_t)spin * W * s.G, (long)W * s.G, st) : hipSuccess;
+  const int gc = p.GC;
+  dim3 grid((s.G + LWY * gc - 1) / (LWY * gc), (W + LWX - 1) / LWX);
+  if (s.precision == AFQMC_FP32_CONTRACT) {
+    hipLaunchKernelGGL(pick_f32(p.NR), grid, dim3(kThreads), lds_f32(p.NR), st,
+                       static_cast<const float *>(s.lp_lhs[spin]), static_cast<const float *>(s.lp_rhs[spin]), s.M,
+                       p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart);
+  } else {
+    const int kp = ((s.M + LKC - 1) / LKC) * LKC;
+    hipLaunchKernelGGL(pick_bf(p.NR), grid, dim3(kThreads), lds_bf(p.NR), st,
+                       static_cast<const __bf16 *>(s.lp_lhs[spin]), static_cast<const __bf16 *>(s.lp_rhs[spin]), kp,
+                       p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace afqmc

@@ -39,6 +39,8 @@ def test_default_options(lib):
     o = A.default_options()
     assert o.precision == A.FP64 and o.taylor_order == 6 and o.fb_cap == 1.0
     assert math.isnan(o.e_shift) and o.mem_limit_bytes == 0
+    assert o.streams == 0 and o.use_graph == 0 and o.tune == 1 and o.ex_mode == A.EX_FULL
+    assert o.cv_fraction == 0.125 and o.cv_seed == 7
     assert lib.afqmc_default_options(None) == A.ERR_ARG
 
 
@@ -75,7 +77,9 @@ def test_setup_rejects_wide_spin_blocks(lib):
 def test_setup_rejects_bad_options(lib):
     d, keep = _desc()
     out = ctypes.c_void_p()
-    for field, value in (("taylor_order", 0), ("taylor_order", 17), ("precision", 9), ("fb_cap", float("nan"))):
+    for field, value in (("taylor_order", 0), ("taylor_order", 17), ("precision", 9), ("fb_cap", float("nan")),
+                         ("streams", -1), ("ex_mode", 2), ("cv_fraction", 0.0), ("cv_fraction", 1.5),
+                         ("cv_fraction", float("nan"))):
         o = A.default_options()
         setattr(o, field, value)
         assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, ctypes.byref(o), None, ctypes.byref(out)) \
@@ -107,9 +111,11 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {"afqmc_system_desc": (A.SystemDesc, ["nbasis", "nalpha", "nbeta", "nchol", "nwalkers", "h1", "chol",
                                                    "ecore", "trial", "dt"]),
               "afqmc_options": (A.Options, ["precision", "taylor_order", "fb_cap", "e_shift", "mem_limit_bytes",
+                                            "streams", "use_graph", "tune", "ex_mode", "cv_fraction", "cv_seed",
                                             "reserved"]),
               "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
-              "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes"]),
+              "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "lane",
+                                      "graph_captures", "graph_replays"]),
               "afqmc_timings": (A.Timings, ["ms", "count"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "afqmc.h"', "int main(void) {"]
     for cname, (_, fl) in fields.items():
