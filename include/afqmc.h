@@ -52,7 +52,7 @@ typedef enum {
 
 /* Precision of the force-bias and exchange contractions (overlap LU,
  * determinant ratios, re-orthogonalisation and weights are always FP64). */
-enum { AFQMC_FP64 = 0, AFQMC_FP32_CONTRACT = 1, AFQMC_BF16X3_CONTRACT = 2 };
+enum { AFQMC_FP64 = 0, AFQMC_FP32_CONTRACT = 1, AFQMC_BF16X3_CONTRACT = 2, AFQMC_BF16X2_CONTRACT = 3 };
 
 /* Per-walker flag bits, OR-ed into afqmc_walkers.flags by the library. */
 enum {
@@ -107,7 +107,10 @@ typedef struct {
                                bit 1: VALU kernels for the force bias, V_HS, B1
                                and Taylor products (both for comparison runs);
                                reserved[1]: walkers per exchange workgroup (1, 2
-                               or 4; overrides tune); other entries: zero         */
+                               or 4); reserved[2]: exchange tile order (1 = Cholesky
+                               block fastest, g > 1 = groups of g walker blocks);
+                               either one fixes the launch shape (no tuning);
+                               other entries: zero                                */
 } afqmc_options;
 
 /* Walker state of one system; every pointer is device memory owned by the caller. */
@@ -125,6 +128,8 @@ typedef struct {
   double const_c;     /* ecore - 1/2 sum_g l_g^2 (mean-field constant)         */
   uint64_t device_bytes; /* device memory held by this system                 */
   int32_t exchange_tile; /* walkers per FP64 exchange workgroup in use (1/2/4)  */
+  int32_t exchange_order; /* exchange tile order: 0 = Cholesky block fastest,
+                             g > 0 = groups of g walker blocks (-1: VALU path) */
   int32_t lane;          /* internal stream of a system set (-1: caller's)      */
   int64_t graph_captures; /* afqmc_step graphs recorded so far (whole context)  */
   int64_t graph_replays;  /* afqmc_step graph replays so far (whole context)    */

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 
 OK, ERR_ARG, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = 0, 1, 2, 3, 4
-FP64, FP32_CONTRACT, BF16X3_CONTRACT = 0, 1, 2
+FP64, FP32_CONTRACT, BF16X3_CONTRACT, BF16X2_CONTRACT = 0, 1, 2, 3
 W_SINGULAR, W_NONFINITE, W_DEAD = 1, 2, 4
 EX_FULL, EX_CV = 0, 1
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
@@ -57,7 +57,7 @@ class CWalkers(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("e_hf", ctypes.c_double), ("e_shift", ctypes.c_double),
                 ("const_c", ctypes.c_double), ("device_bytes", ctypes.c_uint64),
-                ("exchange_tile", ctypes.c_int32), ("lane", ctypes.c_int32),
+                ("exchange_tile", ctypes.c_int32), ("exchange_order", ctypes.c_int32), ("lane", ctypes.c_int32),
                 ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
 
 

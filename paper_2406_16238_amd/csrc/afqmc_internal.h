@@ -60,6 +60,7 @@ struct System {
   bool use_mfma_gemm = true;   // MFMA kernels for force bias, V_HS, B1 and Taylor terms
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans
+  int ex_group = 0;            // tile order of the MFMA exchange launches (see tile_of)
   int ex_stride = 1;           // partials per (walker, spin) in ekpart
   int ex_nparts[2] = {0, 0};   // partials actually written per spin
   // Theta / vbias partials in `theta` / `fbpart` belong to these walker buffers
@@ -160,6 +161,7 @@ hipError_t launch_sum_slices(const double *parts, int nslices, long n, double al
 hipError_t launch_add_identity(double *A, int M, double diag, hipStream_t st);
 hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, hipStream_t st);
 hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
+hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
 
 // Exchange launch geometry for a spin block width.
 void exchange_geometry(int nmax, int *gb, size_t *lds);

@@ -42,7 +42,8 @@ struct afqmc_ctx {
   bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
-  bool ex_wx_forced = false;
+  int ex_group = 8;                  // exchange tile order (reserved[2]: 1 = plain, g > 1 = groups of g)
+  bool ex_wx_forced = false;         // launch shape fixed by the caller: no tuning
   bool tune = true;
   // system sets: internal streams (default priority) the systems are spread
   // over, and the events that fork them from / join them into the caller's stream
@@ -343,6 +344,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   s.ex_ngb = (s.G + s.ex_gb - 1) / s.ex_gb;
   s.ex_plan[0] = exchange_plan(s.Na, s.G, c->ex_wx);
   s.ex_plan[1] = exchange_plan(s.Nb, s.G, c->ex_wx);
+  s.ex_group = c->ex_group;
   s.ex_mfma = (s.Na == 0 || s.ex_plan[0].mfma) && (s.Nb == 0 || s.ex_plan[1].mfma) && !c->force_valu_exchange;
   if (s.precision != AFQMC_FP64) {
     const bool ok = s.ex_mfma && (s.Na == 0 || lp_exchange_supported(s.precision, s.ex_plan[0].NR)) &&
@@ -490,24 +492,29 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   return AFQMC_OK;
 }
 
-// Walker tiling of the FP64 exchange kernel: 1, 2 or 4 walkers per workgroup
-// (the four waves then split 4, 2 or 1 ways over Cholesky vectors).  Every
-// wave sums the same group of Cholesky vectors of one walker in the same
-// order whatever the tiling, so the choice changes speed only.  Timed on the
-// system's own shapes (Theta zeroed); the choice is kept per shape for the
-// rest of the process, so every context of one shape uses the same tiling.
+// Launch shape of the exchange kernels, timed on the system's own sizes with
+// Theta filled by a fixed pattern: the walker tiling of the FP64 kernel (1, 2
+// or 4 walkers per workgroup; the four waves then split 4, 2 or 1 ways over
+// Cholesky vectors) and the tile order (tile_of: Cholesky block fastest, or
+// groups of 4, 8 or 16 walker blocks).  Every wave sums the same Cholesky
+// vectors of one walker in the same order whatever the shape, so the choice
+// changes speed only.  It is kept per shape for the rest of the process, so
+// every context of one shape launches alike.
 afqmc_status tune_exchange(System &s, hipStream_t st) {
   static std::mutex mu;
-  static std::map<std::array<int, 5>, int> chosen;
-  const std::array<int, 5> key{s.M, s.Na, s.Nb, s.G, s.W};
-  int best = 0;
+  static std::map<std::array<int, 6>, std::pair<int, int>> chosen;
+  const std::array<int, 6> key{s.M, s.Na, s.Nb, s.G, s.W, s.precision};
+  std::pair<int, int> best{0, 0};
   {
     std::lock_guard<std::mutex> lock(mu);
     auto it = chosen.find(key);
     if (it != chosen.end()) best = it->second;
   }
-  if (best == 0) {
-    AFQMC_HIP(launch_zero2(s.theta, (long)s.W * s.M * s.Nt, st), "zero fill");
+  const bool lp = s.precision != AFQMC_FP64;
+  if (best.first == 0) {
+    AFQMC_HIP(launch_fill_pattern2(s.theta, (long)s.W * s.M * s.Nt, st), "pattern fill");
+    if (lp)
+      for (int sp = 0; sp < 2; ++sp) AFQMC_HIP(lp_prepare_rhs(s, s.theta, s.W, sp, st), "operand kernel");
     hipEvent_t e0, e1;
     AFQMC_HIP(hipEventCreate(&e0), "event create");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -516,33 +523,47 @@ afqmc_status tune_exchange(System &s, hipStream_t st) {
     }
     float best_ms = 0.0f;
     hipError_t err = hipSuccess;
+    auto run = [&]() -> hipError_t {
+      for (int sp = 0; sp < 2; ++sp) {
+        hipError_t e = lp ? launch_exchange_lp(s, s.W, sp, st, s.fbpart)
+                          : launch_exchange(s, s.theta, s.W, st, s.fbpart, sp);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
     for (int wx : {1, 2, 4}) {
+      if (lp && wx != 2) continue;  // the reduced-precision kernels have a fixed walker tiling
       const ExchangePlan p0 = exchange_plan(s.Na, s.G, wx), p1 = exchange_plan(s.Nb, s.G, wx);
       if ((s.Na > 0 && !p0.mfma) || (s.Nb > 0 && !p1.mfma)) continue;
       s.ex_plan[0] = p0;
       s.ex_plan[1] = p1;
       if ((err = exchange_enable_lds(s)) != hipSuccess) break;
-      if ((err = launch_exchange(s, s.theta, s.W, st, s.fbpart)) != hipSuccess) break;
-      (void)hipEventRecord(e0, st);
-      for (int r = 0; r < 3 && err == hipSuccess; ++r) err = launch_exchange(s, s.theta, s.W, st, s.fbpart);
-      (void)hipEventRecord(e1, st);
-      if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (best == 0 || ms < best_ms) {
-        best = wx;
-        best_ms = ms;
+      for (int group : {0, 4, 8, 16}) {
+        s.ex_group = group;
+        if ((err = run()) != hipSuccess) break;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < 2 && err == hipSuccess; ++r) err = run();
+        (void)hipEventRecord(e1, st);
+        if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best.first == 0 || ms < best_ms) {
+          best = {wx, group};
+          best_ms = ms;
+        }
       }
+      if (err != hipSuccess) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return fail(AFQMC_ERR_HIP, std::string("exchange tuning: ") + hipGetErrorString(err));
-    if (best == 0) return AFQMC_OK;
+    if (best.first == 0) return AFQMC_OK;
     std::lock_guard<std::mutex> lock(mu);
     chosen.emplace(key, best);
   }
-  s.ex_plan[0] = exchange_plan(s.Na, s.G, best);
-  s.ex_plan[1] = exchange_plan(s.Nb, s.G, best);
+  s.ex_plan[0] = exchange_plan(s.Na, s.G, best.first);
+  s.ex_plan[1] = exchange_plan(s.Nb, s.G, best.first);
+  s.ex_group = best.second;
   AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
   return AFQMC_OK;
 }
@@ -638,7 +659,8 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   afqmc_options o;
   if (opt) o = *opt;
   else afqmc_default_options(&o);
-  if (o.precision != AFQMC_FP64 && o.precision != AFQMC_FP32_CONTRACT && o.precision != AFQMC_BF16X3_CONTRACT)
+  if (o.precision != AFQMC_FP64 && o.precision != AFQMC_FP32_CONTRACT && o.precision != AFQMC_BF16X3_CONTRACT &&
+      o.precision != AFQMC_BF16X2_CONTRACT)
     return fail(AFQMC_ERR_ARG, "unknown precision");
   if (o.taylor_order < 1 || o.taylor_order > 16) return fail(AFQMC_ERR_ARG, "taylor_order must be in 1..16");
   if (std::isnan(o.fb_cap) || std::isinf(o.fb_cap)) return fail(AFQMC_ERR_ARG, "fb_cap must be finite");
@@ -667,6 +689,10 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     c->ex_wx = o.reserved[1];
     c->ex_wx_forced = true;
   }
+  if (o.reserved[2] > 0) {
+    c->ex_group = o.reserved[2] == 1 ? 0 : o.reserved[2];
+    c->ex_wx_forced = true;
+  }
   c->tune = o.tune != 0 && !c->ex_wx_forced;
   c->use_graph = o.use_graph != 0;
   (void)hipGetDevice(&c->device);
@@ -676,7 +702,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   for (int i = 0; i < nsys; ++i) {
     afqmc_status r = setup_one(c, sys[i], c->sys[i], st, &used, o.mem_limit_bytes);
     System &sy = c->sys[i];
-    if (r == AFQMC_OK && c->tune && sy.ex_mfma && sy.precision == AFQMC_FP64) r = tune_exchange(sy, st);
+    if (r == AFQMC_OK && c->tune && sy.ex_mfma) r = tune_exchange(sy, st);
     if (r != AFQMC_OK) {
       (void)hipStreamSynchronize(st);
       release(c);
@@ -1012,6 +1038,7 @@ afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out)
   out->const_c = s.const_c;
   out->device_bytes = s.bytes;
   out->exchange_tile = s.ex_mfma ? s.ex_plan[s.Na > 0 ? 0 : 1].WX : 0;
+  out->exchange_order = s.ex_mfma ? s.ex_group : -1;
   out->lane = ctx->lanes.empty() ? -1 : ctx->lane_of[isys];
   out->graph_captures = ctx->graph_captures;
   out->graph_replays = ctx->graph_replays;

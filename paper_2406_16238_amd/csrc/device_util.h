@@ -53,6 +53,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch /* [4
   __syncthreads();
 }
 
+// Tile (gb, wb) of block `bid` in a 1-D launch over ngb x nwb tiles (ngb
+// Cholesky-vector blocks, nwb walker blocks).  group == 0: gb fastest.
+// group > 0: an order that keeps the operands of in-flight workgroups in each
+// XCD's L2.  Workgroups are dealt to the 8 XCDs round-robin (XCD = bid mod 8),
+// so each XCD is given one contiguous stretch of the tile order, and the order
+// takes `group` walker blocks at a time across all Cholesky blocks, walker
+// block fastest: a Cholesky tile is then read by `group` walker blocks while
+// it is in L2, and their Theta stays resident.  Bijective for every size.
+__device__ __forceinline__ void tile_of(int bid, int ntiles, int ngb, int nwb, int group, int &gb, int &wb) {
+  if (group <= 0) {
+    wb = bid / ngb;
+    gb = bid - wb * ngb;
+    return;
+  }
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  const int x = bid & 7, j = bid >> 3;
+  const int t = x * per + min(x, rem) + j;
+  const int span = group * ngb;
+  const int g = t / span, within = t - g * span;
+  const int gsize = min(group, nwb - g * group);
+  wb = g * group + within % gsize;
+  gb = within / gsize;
+}
+
 __device__ __forceinline__ double wrap_phase(double a) {
   const double twopi = 6.283185307179586476925286766559;
   double r = a - twopi * rint(a / twopi);

@@ -157,7 +157,8 @@ template <int NR, int WX>
 __global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__restrict__ LtS,
                                                            const double *__restrict__ theta, int M, int Nt,
                                                            int off, int N, int G, int W, int stride, int spin,
-                                                           double2 *__restrict__ ekpart, double2 *__restrict__ vbpart) {
+                                                           double2 *__restrict__ ekpart, double2 *__restrict__ vbpart,
+                                                           int ngb, int nwb, int group) {
   constexpr int GC = (NR % 16 == 0) ? 1 : 2;  // Cholesky vectors per wave
   constexpr int WY = 4 / WX;
   constexpr int ROWW = GC * NR;              // rows per wave
@@ -174,7 +175,8 @@ __global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__rest
   double *sA = smem;                 // [2][XKC][ROWS]
   double *sB = smem + 2 * ASZ;       // [2][WX][XKC][CP]
 
-  const int gb = blockIdx.x, wb = blockIdx.y;
+  int gb, wb;
+  tile_of(blockIdx.x, ngb * nwb, ngb, nwb, group, gb, wb);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wy = wv / WX, wx = wv - (wv / WX) * WX;
   const int g0 = gb * WY * GC, w0 = wb * WX;
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_exchange_mfma(const double *__rest
 namespace {
 
 using ExKernel = void (*)(const double *, const double *, int, int, int, int, int, int, int, int, double2 *,
-                          double2 *);
+                          double2 *, int, int, int);
 
 template <int WX>
 ExKernel pick_nr(int nr) {
@@ -360,9 +362,10 @@ hipError_t launch_exchange(const System &s, const double2 *theta, int W, hipStre
         continue;
       }
       ExKernel k = pick_exchange(p.NR, p.WX);
-      dim3 grid(p.nwg, (W + p.WX - 1) / p.WX);
-      hipLaunchKernelGGL(k, grid, dim3(kThreads), p.lds, st, s.LtS[spin], reinterpret_cast<const double *>(theta),
-                         s.M, s.Nt, spin ? s.Na : 0, p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart);
+      const int nwb = (W + p.WX - 1) / p.WX;
+      hipLaunchKernelGGL(k, dim3((unsigned)(p.nwg * nwb)), dim3(kThreads), p.lds, st, s.LtS[spin],
+                         reinterpret_cast<const double *>(theta), s.M, s.Nt, spin ? s.Na : 0, p.N, s.G, W,
+                         s.ex_stride, spin, s.ekpart, vbpart, p.nwg, nwb, s.ex_group);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

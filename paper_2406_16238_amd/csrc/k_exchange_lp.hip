@@ -4,11 +4,13 @@
 //   vbias_g = sum_s Tr T^{g s}  (Sec. 2, eqs. Eloc and fb, by Wick's theorem).
 // FP32 form: Ltilde and Theta rounded to FP32, v_mfma_f32_16x16x4f32, FP32
 //   accumulation over the orbital index.
-// BF16x3 form: every FP32 operand x is split into three bfloat16 terms
-//   x = h + m + l (h = bf16(x), m = bf16(x - h), l = bf16(x - h - m)), and the
-//   product is recovered from the six terms of order <= 2,
-//   hh + hm + mh + mm + hl + lh, on v_mfma_f32_16x16x32_bf16 with FP32
-//   accumulation (the dropped ml + lm + ll terms are below FP32 rounding).
+// Split-BF16 forms: every FP32 operand x is split into bfloat16 terms
+//   x = h + m (+ l) (h = bf16(x), m = bf16(x - h), l = bf16(x - h - m)), and the
+//   product is recovered on v_mfma_f32_16x16x32_bf16 with FP32 accumulation from
+//   BF16x3: the six terms of order <= 2, hh + hm + mh + mm + hl + lh (the
+//           dropped ml + lm + ll are below FP32 rounding);
+//   BF16x2: the three terms hh + hm + mh (x is kept to about 2^-17 relative and
+//           the dropped mm is of order 2^-18 of the product).
 // In both forms T is kept in LDS as FP32 and the traces are accumulated in FP64.
 // Overlaps, LU, propagation, weights and re-orthogonalisation stay FP64.
 //
@@ -91,7 +93,8 @@ template <int NR>
 __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restrict__ LtF,
                                                           const float *__restrict__ ThF, int M, int N, int G, int W,
                                                           int stride, int spin, double2 *__restrict__ ekpart,
-                                                          double2 *__restrict__ vbpart) {
+                                                          double2 *__restrict__ vbpart, int ngb, int nwb,
+                                                          int group) {
   constexpr int GC = (NR % 16 == 0) ? 1 : 2;
   constexpr int ROWW = GC * NR, RT = ROWW / 16;
   constexpr int CP = 2 * NR, CT = CP / 16;
@@ -103,7 +106,8 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
   extern __shared__ float fsm[];
   float *sA = fsm, *sB = fsm + 2 * ASZ;
 
-  const int gb = blockIdx.x, wb = blockIdx.y;
+  int gb, wb;
+  tile_of(blockIdx.x, ngb * nwb, ngb, nwb, group, gb, wb);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wy = wv / LWX, wx = wv - (wv / LWX) * LWX;
   const int g0 = gb * LWY * GC, w0 = wb * LWX;
@@ -185,29 +189,32 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
   lp_finish<GC>(pre, pim, dg, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart, vbpart);
 }
 
-// ---- BF16x3 form --------------------------------------------------------------
-// LtB[p][g][NR][Kp], ThB[p][w][CP][Kp] (bf16, p = h, m, l; contraction index
-// contiguous and zero-padded to Kp, a multiple of 32) for one spin block.
-template <int NR>
-__global__ __launch_bounds__(kThreads) void k_exchange_bf16x3(const __bf16 *__restrict__ LtB,
+// ---- split-BF16 forms ----------------------------------------------------------
+// LtB[p][g][NR][Kp], ThB[p][w][CP][Kp] (bf16, p = h, m (, l) for NT = 2 (3)
+// terms; contraction index contiguous and zero-padded to Kp, a multiple of 32)
+// for one spin block.
+template <int NR, int NT>
+__global__ __launch_bounds__(kThreads) void k_exchange_bf16(const __bf16 *__restrict__ LtB,
                                                              const __bf16 *__restrict__ ThB, int Kp, int N, int G,
                                                              int W, int stride, int spin,
                                                              double2 *__restrict__ ekpart,
-                                                             double2 *__restrict__ vbpart) {
+                                                             double2 *__restrict__ vbpart, int ngb, int nwb,
+                                                             int group) {
   constexpr int GC = (NR % 16 == 0) ? 1 : 2;
   constexpr int ROWW = GC * NR, RT = ROWW / 16;
   constexpr int CP = 2 * NR, CT = CP / 16;
   constexpr int ROWS = LWY * ROWW;
   constexpr int COLS = LWX * CP;
   constexpr int RS = LKC + BPAD;                 // staged row stride (bf16)
-  constexpr int ASZ = 3 * ROWS * RS, BSZ = 3 * COLS * RS;   // bf16 per stage
-  constexpr int AV = 3 * ROWS * (LKC / 8), BV = 3 * COLS * (LKC / 8);  // 16-byte vectors per stage
+  constexpr int ASZ = NT * ROWS * RS, BSZ = NT * COLS * RS;   // bf16 per stage
+  constexpr int AV = NT * ROWS * (LKC / 8), BV = NT * COLS * (LKC / 8);  // 16-byte vectors per stage
   constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
   constexpr int TSF = CP + 2;
   extern __shared__ __bf16 bsm[];
   __bf16 *sA = bsm, *sB = bsm + 2 * ASZ;
 
-  const int gb = blockIdx.x, wb = blockIdx.y;
+  int gb, wb;
+  tile_of(blockIdx.x, ngb * nwb, ngb, nwb, group, gb, wb);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wy = wv / LWX, wx = wv - (wv / LWX) * LWX;
   const int g0 = gb * LWY * GC, w0 = wb * LWX;
@@ -273,26 +280,32 @@ __global__ __launch_bounds__(kThreads) void k_exchange_bf16x3(const __bf16 *__re
     if (ch + 1 < nchunk) load((ch + 1) * LKC);
     const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * lk;
     const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * lk;
-    bf8v ah[RT], am[RT], al[RT], bh[CT], bm[CT], bl[CT];
+    bf8v ah[RT], am[RT], bh[CT], bm[CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       ah[i] = *reinterpret_cast<const bf8v *>(a + (0 * ROWS + i * 16) * RS);
       am[i] = *reinterpret_cast<const bf8v *>(a + (1 * ROWS + i * 16) * RS);
-      al[i] = *reinterpret_cast<const bf8v *>(a + (2 * ROWS + i * 16) * RS);
     }
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
       bh[j] = *reinterpret_cast<const bf8v *>(b + (0 * COLS + j * 16) * RS);
       bm[j] = *reinterpret_cast<const bf8v *>(b + (1 * COLS + j * 16) * RS);
-      bl[j] = *reinterpret_cast<const bf8v *>(b + (2 * COLS + j * 16) * RS);
     }
-    // six sweeps, each over all accumulators, so dependent MFMAs are far apart
+    // one sweep over all accumulators per term, so dependent MFMAs are far
+    // apart; the smallest terms first
 #define AFQMC_SWEEP(X, Y)                                                                         \
   _Pragma("unroll") for (int i = 0; i < RT; ++i) _Pragma("unroll") for (int j = 0; j < CT; ++j) \
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(X[i], Y[j], acc[i][j], 0, 0, 0);
-    AFQMC_SWEEP(al, bh)
-    AFQMC_SWEEP(ah, bl)
-    AFQMC_SWEEP(am, bm)
+    if constexpr (NT == 3) {
+      bf8v al[RT], bl[CT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) al[i] = *reinterpret_cast<const bf8v *>(a + (2 * ROWS + i * 16) * RS);
+#pragma unroll
+      for (int j = 0; j < CT; ++j) bl[j] = *reinterpret_cast<const bf8v *>(b + (2 * COLS + j * 16) * RS);
+      AFQMC_SWEEP(al, bh)
+      AFQMC_SWEEP(ah, bl)
+      AFQMC_SWEEP(am, bm)
+    }
     AFQMC_SWEEP(am, bh)
     AFQMC_SWEEP(ah, bm)
     AFQMC_SWEEP(ah, bh)
@@ -328,8 +341,9 @@ __global__ void k_lt_to_f32(const double *__restrict__ LtS, long n, float *__res
   if (e < n) LtF[e] = (float)LtS[e];
 }
 
-// LtB[p][g][i][q] from LtS[g][q][i] (rows i < NR, q < Kp, zero for q >= M)
-__global__ void k_lt_to_bf16x3(const double *__restrict__ LtS, int G, int M, int NR, int Kp, __bf16 *__restrict__ LtB) {
+// LtB[p][g][i][q] (p < NT) from LtS[g][q][i] (rows i < NR, q < Kp, zero for q >= M)
+template <int NT>
+__global__ void k_lt_to_bf16(const double *__restrict__ LtS, int G, int M, int NR, int Kp, __bf16 *__restrict__ LtB) {
   const long n = (long)G * NR * Kp;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
@@ -342,7 +356,7 @@ __global__ void k_lt_to_bf16x3(const double *__restrict__ LtS, int G, int M, int
   split3(x, h, m, l);
   LtB[e] = h;
   LtB[n + e] = m;
-  LtB[2 * n + e] = l;
+  if (NT == 3) LtB[2 * n + e] = l;
 }
 
 // ThF[w][q][c] (c < CP) from Theta[w][q][off + c/2] (re/im by parity), zero-padded
@@ -361,9 +375,10 @@ __global__ void k_theta_to_f32(const double2 *__restrict__ theta, int W, int M, 
   ThF[e] = v;
 }
 
-// ThB[p][w][c][q] (q < Kp) from Theta[w][q][off + c/2]; one workgroup per
-// (walker, 32 rows q) transposes through LDS
-__global__ __launch_bounds__(kThreads) void k_theta_to_bf16x3(const double2 *__restrict__ theta, int W, int M, int Nt,
+// ThB[p][w][c][q] (p < NT, q < Kp) from Theta[w][q][off + c/2]; one workgroup
+// per (walker, 32 rows q) transposes through LDS
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_theta_to_bf16(const double2 *__restrict__ theta, int W, int M, int Nt,
                                                              int off, int N, int CP, int Kp,
                                                              __bf16 *__restrict__ ThB) {
   extern __shared__ float tsm[];  // [32][CP + 1]
@@ -388,14 +403,16 @@ __global__ __launch_bounds__(kThreads) void k_theta_to_bf16x3(const double2 *__r
     const size_t o = ((size_t)w * CP + c) * Kp + q0 + qq;
     ThB[o] = h;
     ThB[plane + o] = m;
-    ThB[2 * plane + o] = l;
+    if (NT == 3) ThB[2 * plane + o] = l;
   }
 }
 
 // ---- dispatch -------------------------------------------------------------------
 namespace {
-using F32Kernel = void (*)(const float *, const float *, int, int, int, int, int, int, double2 *, double2 *);
-using BFKernel = void (*)(const __bf16 *, const __bf16 *, int, int, int, int, int, int, double2 *, double2 *);
+using F32Kernel = void (*)(const float *, const float *, int, int, int, int, int, int, double2 *, double2 *, int,
+                           int, int);
+using BFKernel = void (*)(const __bf16 *, const __bf16 *, int, int, int, int, int, int, double2 *, double2 *, int,
+                          int, int);
 
 F32Kernel pick_f32(int nr) {
   switch (nr) {
@@ -408,26 +425,32 @@ F32Kernel pick_f32(int nr) {
     default: return nullptr;
   }
 }
-BFKernel pick_bf(int nr) {
+template <int NT>
+BFKernel pick_bf_nt(int nr) {
   switch (nr) {
-    case 8: return k_exchange_bf16x3<8>;
-    case 16: return k_exchange_bf16x3<16>;
-    case 24: return k_exchange_bf16x3<24>;
-    case 32: return k_exchange_bf16x3<32>;
-    case 40: return k_exchange_bf16x3<40>;
-    case 48: return k_exchange_bf16x3<48>;
+    case 8: return k_exchange_bf16<8, NT>;
+    case 16: return k_exchange_bf16<16, NT>;
+    case 24: return k_exchange_bf16<24, NT>;
+    case 32: return k_exchange_bf16<32, NT>;
+    case 40: return k_exchange_bf16<40, NT>;
+    case 48: return k_exchange_bf16<48, NT>;
     default: return nullptr;
   }
 }
+// bfloat16 terms per operand of a split-BF16 precision (0: not a split form)
+int bf_terms(int precision) {
+  return precision == AFQMC_BF16X3_CONTRACT ? 3 : precision == AFQMC_BF16X2_CONTRACT ? 2 : 0;
+}
+BFKernel pick_bf(int nr, int nt) { return nt == 3 ? pick_bf_nt<3>(nr) : nt == 2 ? pick_bf_nt<2>(nr) : nullptr; }
 size_t lds_f32(int nr) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
   const size_t stage = 2ull * (LKC * LWY * roww + LWX * LKC * cp) * sizeof(float);
   const size_t epi = 4ull * roww * (cp + 2) * sizeof(float);
   return stage > epi ? stage : epi;
 }
-size_t lds_bf(int nr) {
+size_t lds_bf(int nr, int nt) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
-  const size_t stage = 2ull * 3 * (LWY * roww + LWX * cp) * (LKC + BPAD) * sizeof(__bf16);
+  const size_t stage = 2ull * nt * (LWY * roww + LWX * cp) * (LKC + BPAD) * sizeof(__bf16);
   const size_t epi = 4ull * roww * (cp + 2) * sizeof(float);
   return stage > epi ? stage : epi;
 }
@@ -435,14 +458,16 @@ size_t lds_bf(int nr) {
 
 bool lp_exchange_supported(int precision, int nr) {
   if (precision == AFQMC_FP32_CONTRACT) return pick_f32(nr) && lds_f32(nr) <= 160 * 1024;
-  if (precision == AFQMC_BF16X3_CONTRACT) return pick_bf(nr) && lds_bf(nr) <= 160 * 1024;
+  const int nt = bf_terms(precision);
+  if (nt) return pick_bf(nr, nt) && lds_bf(nr, nt) <= 160 * 1024;
   return false;
 }
 
 size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs) {
   const int kp = ((M + LKC - 1) / LKC) * LKC;
   if (precision == AFQMC_FP32_CONTRACT) return lhs ? (size_t)G * M * nr : (size_t)W * M * 2 * nr;
-  return lhs ? 3ull * G * nr * kp : 3ull * W * 2 * nr * kp;
+  const size_t nt = bf_terms(precision);
+  return lhs ? nt * G * nr * kp : nt * W * 2 * nr * kp;
 }
 
 hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st) {
@@ -455,8 +480,9 @@ hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st) {
   } else {
     const int kp = ((s.M + LKC - 1) / LKC) * LKC;
     const long n = (long)s.G * p.NR * kp;
-    hipLaunchKernelGGL(k_lt_to_bf16x3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtS[spin], s.G, s.M,
-                       p.NR, kp, static_cast<__bf16 *>(s.lp_lhs[spin]));
+    hipLaunchKernelGGL(bf_terms(s.precision) == 3 ? k_lt_to_bf16<3> : k_lt_to_bf16<2>,
+                       dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtS[spin], s.G, s.M, p.NR, kp,
+                       static_cast<__bf16 *>(s.lp_lhs[spin]));
   }
   return hipGetLastError();
 }
@@ -470,8 +496,8 @@ hipError_t lp_enable_lds(const System &s) {
       e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_f32(p.NR)),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f32(p.NR));
     else
-      e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_bf(p.NR)),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bf(p.NR));
+      e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_bf(p.NR, bf_terms(s.precision))),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bf(p.NR, bf_terms(s.precision)));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -488,8 +514,9 @@ hipError_t lp_prepare_rhs(const System &s, const double2 *theta, int W, int spin
                        off, p.N, CP, static_cast<float *>(s.lp_rhs[spin]));
   } else {
     const int kp = ((s.M + LKC - 1) / LKC) * LKC;
-    hipLaunchKernelGGL(k_theta_to_bf16x3, dim3(kp / 32, W), dim3(kThreads), 32 * (CP + 1) * sizeof(float), st,
-                       theta, W, s.M, s.Nt, off, p.N, CP, kp, static_cast<__bf16 *>(s.lp_rhs[spin]));
+    hipLaunchKernelGGL(bf_terms(s.precision) == 3 ? k_theta_to_bf16<3> : k_theta_to_bf16<2>, dim3(kp / 32, W),
+                       dim3(kThreads), 32 * (CP + 1) * sizeof(float), st, theta, W, s.M, s.Nt, off, p.N, CP, kp,
+                       static_cast<__bf16 *>(s.lp_rhs[spin]));
   }
   return hipGetLastError();
 }
@@ -498,16 +525,18 @@ hipError_t launch_exchange_lp(const System &s, int W, int spin, hipStream_t st, 
   const ExchangePlan &p = s.ex_plan[spin];
   if (p.N == 0) return vbpart ? launch_zero2(vbpart + (size_t)spin * W * s.G, (long)W * s.G, st) : hipSuccess;
   const int gc = p.GC;
-  dim3 grid((s.G + LWY * gc - 1) / (LWY * gc), (W + LWX - 1) / LWX);
+  const int ngb = (s.G + LWY * gc - 1) / (LWY * gc), nwb = (W + LWX - 1) / LWX;
+  const dim3 grid((unsigned)(ngb * nwb));
   if (s.precision == AFQMC_FP32_CONTRACT) {
     hipLaunchKernelGGL(pick_f32(p.NR), grid, dim3(kThreads), lds_f32(p.NR), st,
                        static_cast<const float *>(s.lp_lhs[spin]), static_cast<const float *>(s.lp_rhs[spin]), s.M,
-                       p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart);
+                       p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart, ngb, nwb, s.ex_group);
   } else {
     const int kp = ((s.M + LKC - 1) / LKC) * LKC;
-    hipLaunchKernelGGL(pick_bf(p.NR), grid, dim3(kThreads), lds_bf(p.NR), st,
+    const int nt = bf_terms(s.precision);
+    hipLaunchKernelGGL(pick_bf(p.NR, nt), grid, dim3(kThreads), lds_bf(p.NR, nt), st,
                        static_cast<const __bf16 *>(s.lp_lhs[spin]), static_cast<const __bf16 *>(s.lp_rhs[spin]), kp,
-                       p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart);
+                       p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart, ngb, nwb, s.ex_group);
   }
   return hipGetLastError();
 }

@@ -273,6 +273,24 @@ hipError_t launch_zero2(double2 *p, long n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Deterministic values in [-1/2, 1/2) from an integer hash of the index, for
+// timing kernels on data with realistic bit patterns.
+__global__ void k_fill_pattern2(double2 *__restrict__ p, long n) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  unsigned long long z = (unsigned long long)e * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 31)) * 0xD6E8FEB86659FD93ull;
+  z ^= z >> 32;
+  const double a = (double)(z & 0xFFFFFFFFull) * 0x1p-32 - 0.5, b = (double)(z >> 32) * 0x1p-32 - 0.5;
+  p[e] = make_double2(a, b);
+}
+
+hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_pattern2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
 __global__ void k_axpby(const double *__restrict__ x, double a, double *__restrict__ y, double b, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = a * x[i] + b * y[i];

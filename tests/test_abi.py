@@ -114,7 +114,7 @@ def test_struct_layouts_match_header(tmp_path):
                                             "streams", "use_graph", "tune", "ex_mode", "cv_fraction", "cv_seed",
                                             "reserved"]),
               "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
-              "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "lane",
+              "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "exchange_order", "lane",
                                       "graph_captures", "graph_replays"]),
               "afqmc_timings": (A.Timings, ["ms", "count"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "afqmc.h"', "int main(void) {"]

@@ -136,19 +136,25 @@ def test_graph_replays_match_eager_each_step():
         graph.close()
 
 
-def test_exchange_tiling_does_not_change_results():
+@pytest.mark.parametrize("precision", [0, 1, 2, 3], ids=["fp64", "fp32", "bf16x3", "bf16x2"])
+def test_exchange_launch_shape_does_not_change_results(precision):
+    """Walker tiling (FP64 kernel) and tile order (all exchange kernels) are
+    speed knobs only: results are bitwise equal for every choice."""
     A, torch = _lib()
     inputs = make_inputs(A, [(gi.SystemSpec(100, 10, 9, 200, tau=75.0, seed=11), 37)])
     outs = []
-    for wx in (1, 2, 4):
-        o = A.default_options()
+    shapes = [(1, 1), (2, 4), (4, 16), (2, 1), (2, 5)] if precision == 0 else [(2, 1), (2, 4), (2, 16), (2, 3)]
+    for wx, order in shapes:
+        o = A.default_options(precision=precision)
         o.reserved[1] = wx
+        o.reserved[2] = order
         ctx = A.setup_hamiltonian(inputs[0][0], o)
         try:
-            assert A.get_info(ctx, 0).exchange_tile == wx
+            info = A.get_info(ctx, 0)
+            assert info.exchange_tile == wx and info.exchange_order == (0 if order == 1 else order)
             walkers, ebuf, est = run_steps(A, torch, ctx, inputs, 3)
             outs.append(snapshot(walkers, ebuf, est, 0))
         finally:
             ctx.close()
-    assert_bitwise(outs[0], outs[1], "1 vs 2 walkers per workgroup")
-    assert_bitwise(outs[0], outs[2], "1 vs 4 walkers per workgroup")
+    for k in range(1, len(outs)):
+        assert_bitwise(outs[0], outs[k], f"launch shape {shapes[0]} vs {shapes[k]}")

@@ -1,6 +1,7 @@
 """Precision form: exchange and force bias in FP32 or in split BF16 (three
-bfloat16 terms, six products, FP32 accumulation); overlaps, LU, propagation,
-weights and re-orthogonalisation in FP64.
+bfloat16 terms and six products, or two terms and three products; FP32
+accumulation); overlaps, LU, propagation, weights and re-orthogonalisation in
+FP64.
 
 Bar: per-walker local energies within 0.1 mHa of the FP64 path (and of the
 oracle) on identical walker states; the mixed estimator of a short trajectory
@@ -15,7 +16,7 @@ from pairs import Pair, cmp_rel
 
 pytestmark = pytest.mark.gpu
 MHA = 1e-3
-FORMS = {"fp32": 1, "bf16x3": 2}
+FORMS = {"fp32": 1, "bf16x3": 2, "bf16x2": 3}
 
 
 def ctx_for(p, precision):
