@@ -65,16 +65,20 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batching"],
+    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batching", "cv"],
                     help="batching: the sixteen-system set (aggregate walker-steps/s of separate contexts run "
                          "one after another, of one set context over internal streams, and of that context "
-                         "replaying a hipGraph)")
+                         "replaying a hipGraph); cv: the learned control variate at the headline shape "
+                         "(training on the path's own trajectory, then full exchange vs the 1/8 subset)")
     ap.add_argument("--precision", default="bf16x2", choices=["fp64", "fp32", "bf16x3", "bf16x2"],
                     help="path reported in the JSON line (the FP64 path is timed too, for the speed-up)")
     ap.add_argument("--api", default="step", choices=["step", "separate"],
                     help="step: afqmc_step (one overlap/LU and one force bias per step); separate: "
                          "afqmc_propagate + afqmc_reorthogonalize + afqmc_local_energy")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cv-train-steps", type=int, default=60, help="cv: trajectory steps whose walkers train the network")
+    ap.add_argument("--cv-epochs", type=int, default=30, help="cv: training passes")
+    ap.add_argument("--cv-draws", type=int, default=60, help="cv: subset draws at fixed walkers")
     ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
     ap.add_argument("--phases", action="store_true", help="print the per-phase tables to stderr")
@@ -266,6 +270,108 @@ def bench_batching(args):
     return 0
 
 
+def bench_cv(args):
+    """Learned control variate at the headline shape: walker-steps/s with the
+    exact exchange on a 1/8 subset against full exchange, and the estimator's
+    bias and spread at fixed walkers against plain subsampling."""
+    import numpy as np
+    import torch
+    import afqmc_inputs as gi
+    from paper_2406_16238_amd import afqmc as A
+
+    spec = gi.HEADLINE
+    s = spec.system
+    W, G = spec.nwalkers, s.nchol
+    h1, chol, ecore, trial = gi.make_system(s)
+    sysin = A.SystemInput(h1, chol, ecore, trial, s.nalpha, s.nbeta, W, spec.dt)
+    prec = PRECISION_CODE[args.precision]
+    gen = torch.Generator(device="cuda")
+    x = torch.empty((W, G), dtype=torch.float64, device="cuda")
+    e = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+    est = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+
+    def run(ctx, walkers, nsteps, seed0, hook=None):
+        for k in range(nsteps):
+            gen.manual_seed(seed0 + k)
+            x.normal_(generator=gen)
+            A.step(ctx, walkers, x, e, est, reortho=(k + 1) % 5 == 0)
+            if hook:
+                hook(k)
+
+    out = {}
+    ctx = A.setup_hamiltonian(sysin, A.default_options(precision=prec, ex_mode=A.EX_CV))
+    full = A.setup_hamiltonian(sysin, A.default_options(precision=prec))
+    del chol
+    # training samples: features and exact exchange along the path's own trajectory
+    w = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
+    A.overlap(ctx, w)
+    feats, eks = [], []
+
+    def grab(k):
+        f = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+        q = torch.empty(W, dtype=torch.complex128, device="cuda")
+        A.cv_collect(ctx, w, f, q)
+        feats.append(f)
+        eks.append(q)
+    t0 = time.time()
+    run(ctx, w, args.cv_train_steps, 5000, grab)
+    losses = A.cv_train(ctx, torch.cat(feats), torch.cat(eks), args.cv_epochs, 256, 2e-3).cpu().numpy()
+    out["training"] = {"steps": args.cv_train_steps, "samples": args.cv_train_steps * W, "epochs": args.cv_epochs,
+                       "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                       "seconds": round(time.time() - t0, 2)}
+    del feats, eks
+    # throughput: the same trajectory continued with full exchange and with the control variate
+    rates = {}
+    for label, c in (("full_exchange", full), ("control_variate", ctx)):
+        wk = A.Walkers(w.phi.clone(), w.weight.clone(), w.log_ovlp.clone(), w.flags.clone())
+        A.overlap(c, wk)
+        run(c, wk, args.warmup, 9000)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        run(c, wk, args.steps, 9100)
+        ev1.record()
+        torch.cuda.synchronize()
+        rates[label] = W * args.steps / (ev0.elapsed_time(ev1) * 1e-3)
+    # estimator at fixed walkers: R subset draws, against the exact value and plain subsampling
+    wt = w.weight.cpu().numpy()
+    om = wt / wt.sum()
+    A.local_energy(full, w, e)
+    exact = float(np.sum(om * e.cpu().numpy()[:, 2].real))
+
+    def draws(R):
+        v = []
+        for _ in range(R):
+            A.local_energy(ctx, w, e)
+            v.append(np.sum(om * e.cpu().numpy()[:, 2].real))
+        return np.array(v)
+    cvd = draws(args.cv_draws)
+    A.cv_set_params(ctx, torch.zeros(A.CV_NPARAMS, dtype=torch.float32, device="cuda"),
+                    torch.tensor([0.0] * 8 + [1.0] * 8 + [0.0, 0.0, 1.0, 1.0], dtype=torch.float64, device="cuda"))
+    pld = draws(args.cv_draws)
+    ctx.close()
+    full.close()
+    k = -(-W // 8)
+    out.update({
+        "metric": "walker-steps/s (propagate+energy) at M=400,N=40 with the learned exchange control variate",
+        "value": round(rates["control_variate"], 2), "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else f"{args.precision} (exchange, force bias) + f64 (rest)",
+        "data": "synthetic (seeded generator; network trained on the run's own trajectory)",
+        "config": {"workload": spec.name, "nwalkers": W, "exact_exchange_walkers_per_call": k,
+                   "precision": args.precision},
+        "full_exchange_value": round(rates["full_exchange"], 2),
+        "speedup_vs_full_exchange": round(rates["control_variate"] / rates["full_exchange"], 3),
+        "estimator_at_fixed_walkers": {
+            "draws": args.cv_draws, "exact_e2_ha": exact,
+            "cv_bias_ha": float(cvd.mean() - exact), "cv_stderr_ha": float(cvd.std(ddof=1) / np.sqrt(len(cvd))),
+            "cv_spread_ha": float(cvd.std(ddof=1)),
+            "plain_bias_ha": float(pld.mean() - exact), "plain_spread_ha": float(pld.std(ddof=1)),
+            "variance_ratio_cv_over_plain": float(cvd.var(ddof=1) / pld.var(ddof=1))}})
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -276,6 +382,8 @@ def main(argv=None):
 
     if args.workload == "batching":
         return bench_batching(args)
+    if args.workload == "cv":
+        return bench_cv(args)
 
     import numpy as np
     import torch

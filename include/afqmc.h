@@ -133,6 +133,8 @@ typedef struct {
   int32_t lane;          /* internal stream of a system set (-1: caller's)      */
   int64_t graph_captures; /* afqmc_step graphs recorded so far (whole context)  */
   int64_t graph_replays;  /* afqmc_step graph replays so far (whole context)    */
+  int32_t cv_subset;      /* walkers with exact exchange per energy call (EX_CV), else 0 */
+  int32_t reserved_info;
 } afqmc_info;
 
 /* Fills `opt` with the defaults listed above.  Returns AFQMC_ERR_ARG on NULL. */
@@ -225,6 +227,69 @@ afqmc_status afqmc_greens_function(afqmc_ctx *ctx, const afqmc_walkers *w,
 afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w,
                               void *const *vbias_out, void *hip_stream);
 
+/*
+ * Learned control variate of the exchange energy (options.ex_mode =
+ * AFQMC_EX_CV).  The mixed estimator of eq. Eloc needs E2 = EJ + EK per walker;
+ * in this mode afqmc_local_energy and afqmc_step return, as the exchange part
+ * of E2, the Horvitz-Thompson estimate
+ *   g_w = f_w + [w in S] (EK_w - f_w) / pi,   pi = k / W,  k = ceil(cv_fraction W),
+ * where f_w is a network's prediction of EK_w and S a uniform subset of k
+ * walkers drawn without replacement (keys: the SplitMix64 output function of
+ * cv_seed + call * 2^32 + w * 0x9E3779B97F4A7C15, call = 0, 1, ... counting the
+ * energy calls of the system; the k smallest keys, ties to the lower index),
+ * on which alone the exact exchange is computed.  E_S[g_w] = EK_w, so the
+ * estimator is unbiased given the walkers (weights never depend on energies).
+ * W <= 4096 in this mode (AFQMC_ERR_UNSUPPORTED otherwise).
+ *
+ * Features (double [W][8]): Re EJ, Im EJ, Re E1, Im E1, sum_g |vbias_g - l_g|^2,
+ * Re sum_g (vbias_g - l_g)^2, cos and sin of arg <Psi_T|phi>.
+ * Network (FP32): standardised features -> tanh(W1 x + b1) (128) ->
+ * tanh(W2 h + b2) (128) -> W3 h + b3 = standardised (Re EK, Im EK).
+ * Parameters: float [AFQMC_CV_NPARAMS] = W1 [128][8], b1 [128], W2 [128][128],
+ * b2 [128], W3 [2][128], b3 [2] (row-major, (out, in)); normalisation:
+ * double [AFQMC_CV_NNORM] = feature means [8], deviations [8], target means
+ * [2], deviations [2].  At set-up the weights are Glorot-uniform from a fixed
+ * seed, the biases zero and the normalisation the identity.  Each system of a
+ * context has its own network.
+ *
+ * afqmc_cv_collect: for every walker, features and the exact EK (full
+ *   exchange in the context's precision), as training samples:
+ *   feat_out[s] device double [W][8], ek_out[s] device double2 [W].
+ * afqmc_cv_train: sets the normalisation from the n samples (means and
+ *   population deviations), then runs `epochs` passes of Adam (beta1 0.9,
+ *   beta2 0.999, eps 1e-8, bias-corrected, moments reset at the start) over
+ *   minibatches of `batch` consecutive samples on the mean of 1/2 ||y - t||^2.
+ *   loss_out: NULL or device double [epochs], the mean loss of each pass.
+ *   Synchronous (allocates and frees its workspace); inputs are device pointers.
+ * afqmc_cv_set_params / afqmc_cv_get_params: device copies of the parameters
+ *   and normalisation (either pointer may be NULL); set resets the Adam moments.
+ * afqmc_cv_predict: f_out device double2 [n] = the network's EK for raw
+ *   features feat device double [n][8].
+ * afqmc_cv_loss_grad: loss (device double [1]) and gradient (device float
+ *   [AFQMC_CV_NPARAMS]) of the mean of 1/2 ||y - t||^2 over n standardised
+ *   samples x device float [n][8], t device float [n][2].  Synchronous.
+ * afqmc_cv_state: device copies of the last energy call's predictions
+ *   (double2 [W]), subset (int32 [k], increasing) and call index (uint64 [1]).
+ * Errors: AFQMC_ERR_ARG on NULL context, bad index or sizes; AFQMC_ERR_OOM;
+ * AFQMC_ERR_HIP.
+ */
+#define AFQMC_CV_NFEAT 8
+#define AFQMC_CV_NPARAMS 17922
+#define AFQMC_CV_NNORM 20
+afqmc_status afqmc_cv_collect(afqmc_ctx *ctx, const afqmc_walkers *w, double *const *feat_out,
+                              void *const *ek_out, void *hip_stream);
+afqmc_status afqmc_cv_train(afqmc_ctx *ctx, int32_t isys, const double *feat, const void *ek, int64_t n,
+                            int32_t epochs, int32_t batch, double lr, double *loss_out, void *hip_stream);
+afqmc_status afqmc_cv_set_params(afqmc_ctx *ctx, int32_t isys, const float *params, const double *norm,
+                                 void *hip_stream);
+afqmc_status afqmc_cv_get_params(afqmc_ctx *ctx, int32_t isys, float *params, double *norm, void *hip_stream);
+afqmc_status afqmc_cv_predict(afqmc_ctx *ctx, int32_t isys, const double *feat, int64_t n, void *f_out,
+                              void *hip_stream);
+afqmc_status afqmc_cv_loss_grad(afqmc_ctx *ctx, int32_t isys, const float *x, const float *t, int64_t n,
+                                float *grad_out, double *loss_out, void *hip_stream);
+afqmc_status afqmc_cv_state(afqmc_ctx *ctx, int32_t isys, void *f_out, int32_t *subset_out, uint64_t *call_out,
+                            void *hip_stream);
+
 /* Set-up scalars of system `isys`.  AFQMC_ERR_ARG on NULL or bad index. */
 afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out);
 
@@ -245,6 +310,7 @@ enum {
   AFQMC_PH_COMBINE,       /* energy combination and estimator             */
   AFQMC_PH_REORTHO,       /* modified Gram-Schmidt                        */
   AFQMC_PH_OPERANDS,      /* FP32 / split-BF16 copies of Theta            */
+  AFQMC_PH_CV,            /* features, network, subset draw and gather    */
   AFQMC_NPHASES
 };
 typedef struct {

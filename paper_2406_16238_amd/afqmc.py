@@ -58,11 +58,12 @@ class Info(ctypes.Structure):
     _fields_ = [("e_hf", ctypes.c_double), ("e_shift", ctypes.c_double),
                 ("const_c", ctypes.c_double), ("device_bytes", ctypes.c_uint64),
                 ("exchange_tile", ctypes.c_int32), ("exchange_order", ctypes.c_int32), ("lane", ctypes.c_int32),
-                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
+                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
+                ("cv_subset", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
 
 
 PHASES = ("overlap", "force_bias", "fb_epilogue", "vhs", "one_body", "taylor", "weight",
-          "energy_1b", "exchange", "combine", "reortho", "operands")
+          "energy_1b", "exchange", "combine", "reortho", "operands", "cv")
 
 
 class Timings(ctypes.Structure):
@@ -74,7 +75,10 @@ STEP_REORTHO, STEP_FRESH = 1, 2
 EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate",
            "afqmc_local_energy", "afqmc_reorthogonalize", "afqmc_step", "afqmc_overlap",
            "afqmc_greens_function", "afqmc_force_bias", "afqmc_get_info",
-           "afqmc_set_timing", "afqmc_get_timings", "afqmc_destroy", "afqmc_last_error")
+           "afqmc_set_timing", "afqmc_get_timings", "afqmc_destroy", "afqmc_last_error",
+           "afqmc_cv_collect", "afqmc_cv_train", "afqmc_cv_set_params", "afqmc_cv_get_params",
+           "afqmc_cv_predict", "afqmc_cv_loss_grad", "afqmc_cv_state")
+CV_NFEAT, CV_NPARAMS, CV_NNORM = 8, 17922, 20
 
 _lib = None
 
@@ -106,6 +110,14 @@ def load_library() -> ctypes.CDLL:
         "afqmc_get_timings": ([P, ctypes.POINTER(Timings)], ctypes.c_int),
         "afqmc_destroy": ([P], None),
         "afqmc_last_error": ([], ctypes.c_char_p),
+        "afqmc_cv_collect": ([P, ctypes.POINTER(CWalkers), pp, pp, P], ctypes.c_int),
+        "afqmc_cv_train": ([P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_double, P, P], ctypes.c_int),
+        "afqmc_cv_set_params": ([P, ctypes.c_int32, P, P, P], ctypes.c_int),
+        "afqmc_cv_get_params": ([P, ctypes.c_int32, P, P, P], ctypes.c_int),
+        "afqmc_cv_predict": ([P, ctypes.c_int32, P, ctypes.c_int64, P, P], ctypes.c_int),
+        "afqmc_cv_loss_grad": ([P, ctypes.c_int32, P, P, ctypes.c_int64, P, P, P], ctypes.c_int),
+        "afqmc_cv_state": ([P, ctypes.c_int32, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -357,4 +369,87 @@ def get_timings(ctx: Context) -> dict:
 
 def destroy(ctx: Context):
     ctx.close()
+
+
+# ---- learned control variate ---------------------------------------------------------
+
+def _dev(t, dtype, shape, what):
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}")
+    return t.data_ptr()
+
+
+def cv_collect(ctx: Context, walkers, feat_out, ek_out, stream=None):
+    """afqmc_cv_collect: features float64 [W, 8] and exact exchange complex128 [W] per system."""
+    import torch
+    w = _walker_array(ctx, walkers)
+    fs = _ptr_array(ctx, feat_out, [(s.nwalkers, CV_NFEAT) for s in ctx.systems], torch.float64)
+    es = _ptr_array(ctx, ek_out, [(s.nwalkers,) for s in ctx.systems], torch.complex128)
+    _check(load_library().afqmc_cv_collect(ctx.handle, w, fs, es, _stream_handle(stream)))
+
+
+def cv_train(ctx: Context, feat, ek, epochs: int, batch: int, lr: float, isys: int = 0, stream=None):
+    """afqmc_cv_train (synchronous); returns the mean loss of each pass (float64 [epochs], on the GPU)."""
+    import torch
+    n = feat.shape[0]
+    f = _dev(feat, torch.float64, (n, CV_NFEAT), "feat")
+    e = _dev(ek, torch.complex128, (n,), "ek")
+    loss = torch.zeros(max(1, epochs), dtype=torch.float64, device=feat.device)
+    _check(load_library().afqmc_cv_train(ctx.handle, isys, f, e, n, epochs, batch, lr, loss.data_ptr(),
+                                         _stream_handle(stream)))
+    return loss[:epochs]
+
+
+def cv_set_params(ctx: Context, params=None, norm=None, isys: int = 0, stream=None):
+    """afqmc_cv_set_params: params float32 [17922] and/or norm float64 [20] (device)."""
+    import torch
+    p = _dev(params, torch.float32, (CV_NPARAMS,), "params") if params is not None else None
+    q = _dev(norm, torch.float64, (CV_NNORM,), "norm") if norm is not None else None
+    _check(load_library().afqmc_cv_set_params(ctx.handle, isys, p, q, _stream_handle(stream)))
+
+
+def cv_get_params(ctx: Context, isys: int = 0, stream=None):
+    """afqmc_cv_get_params: (params float32 [17922], norm float64 [20]) on the GPU."""
+    import torch
+    params = torch.empty(CV_NPARAMS, dtype=torch.float32, device="cuda")
+    norm = torch.empty(CV_NNORM, dtype=torch.float64, device="cuda")
+    _check(load_library().afqmc_cv_get_params(ctx.handle, isys, params.data_ptr(), norm.data_ptr(),
+                                              _stream_handle(stream)))
+    return params, norm
+
+
+def cv_predict(ctx: Context, feat, isys: int = 0, stream=None):
+    """afqmc_cv_predict: predicted exchange energies (complex128 [n]) for raw features float64 [n, 8]."""
+    import torch
+    n = feat.shape[0]
+    f = _dev(feat, torch.float64, (n, CV_NFEAT), "feat")
+    out = torch.empty(n, dtype=torch.complex128, device=feat.device)
+    _check(load_library().afqmc_cv_predict(ctx.handle, isys, f, n, out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def cv_loss_grad(ctx: Context, x, t, isys: int = 0, stream=None):
+    """afqmc_cv_loss_grad (synchronous): (loss float64 [1], gradient float32 [17922]) on the GPU."""
+    import torch
+    n = x.shape[0]
+    xp = _dev(x, torch.float32, (n, CV_NFEAT), "x")
+    tp = _dev(t, torch.float32, (n, 2), "t")
+    grad = torch.empty(CV_NPARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(load_library().afqmc_cv_loss_grad(ctx.handle, isys, xp, tp, n, grad.data_ptr(), loss.data_ptr(),
+                                             _stream_handle(stream)))
+    return loss, grad
+
+
+def cv_state(ctx: Context, isys: int = 0, stream=None):
+    """afqmc_cv_state: (predictions complex128 [W], subset int32 [k], call index int64 [1]) of the last energy call."""
+    import torch
+    s = ctx.systems[isys]
+    k = get_info(ctx, isys).cv_subset
+    f = torch.empty(s.nwalkers, dtype=torch.complex128, device="cuda")
+    sub = torch.empty(max(1, k), dtype=torch.int32, device="cuda")
+    call = torch.empty(1, dtype=torch.int64, device="cuda")
+    _check(load_library().afqmc_cv_state(ctx.handle, isys, f.data_ptr(), sub.data_ptr() if k else None,
+                                         call.data_ptr(), _stream_handle(stream)))
+    return f, sub[:k], call
 

@@ -13,6 +13,11 @@ namespace afqmc {
 
 constexpr int kMaxSpinOrbitals = 56;  // widest spin block: N^2 complex fits the 64 KiB LDS budget
 constexpr int kThreads = 256;
+// learned control variate: network sizes and the largest walker count of its subset draw
+constexpr int kCvFeatures = 8, kCvHidden = 128;
+constexpr int kCvParams = kCvHidden * kCvFeatures + kCvHidden + kCvHidden * kCvHidden + kCvHidden + 2 * kCvHidden + 2;
+constexpr int kCvNorm = 2 * kCvFeatures + 4;
+constexpr int kCvMaxWalkers = 4096;
 
 // Device buffers and scalars of one system.  Layouts (row-major):
 //   L      [G][M][M]     Cholesky vectors
@@ -61,6 +66,17 @@ struct System {
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans
   int ex_group = 0;            // tile order of the MFMA exchange launches (see tile_of)
+  // learned control variate of the exchange energy
+  int ex_mode = AFQMC_EX_FULL;
+  int cv_k = 0;                          // walkers with exact exchange per call
+  uint64_t cv_seed = 7;
+  float *cv_params = nullptr, *cv_m = nullptr, *cv_v = nullptr;  // [kCvParams] each
+  double *cv_norm = nullptr;             // [kCvNorm]
+  double *cv_feat = nullptr;             // [W][kCvFeatures]
+  double2 *cv_f = nullptr;               // [W] predictions
+  int *cv_sel = nullptr, *cv_pos = nullptr;  // [W]
+  uint64_t *cv_counter = nullptr;        // [2]: next call, last call
+  double2 *cv_theta = nullptr;           // [cv_k][M][Nt] Theta of the subset
   int ex_stride = 1;           // partials per (walker, spin) in ekpart
   int ex_nparts[2] = {0, 0};   // partials actually written per spin
   // Theta / vbias partials in `theta` / `fbpart` belong to these walker buffers
@@ -86,6 +102,9 @@ struct Options {
   int precision = AFQMC_FP64;
   int taylor_order = 6;
   double fb_cap = 1.0;
+  int ex_mode = AFQMC_EX_FULL;
+  double cv_fraction = 0.125;
+  uint64_t cv_seed = 7;
 };
 
 // ---- kernel launchers (each returns the hipGetLastError() of its launch) ----
@@ -162,6 +181,24 @@ hipError_t launch_add_identity(double *A, int M, double diag, hipStream_t st);
 hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, hipStream_t st);
 hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
 hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
+
+// learned control variate (k_cv.hip)
+hipError_t cv_enable_lds();
+hipError_t launch_cv_init(const System &s, uint64_t seed, hipStream_t st);
+hipError_t launch_cv_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_cv_features(const System &s, int W, double *feat, hipStream_t st);
+hipError_t launch_cv_predict(const System &s, const double *feat, long n, double2 *f, hipStream_t st);
+hipError_t launch_cv_subset(const System &s, int W, int k, uint64_t seed, hipStream_t st);
+hipError_t launch_cv_gather(const System &s, int k, hipStream_t st);
+hipError_t launch_cv_combine(const System &s, int W, int k, double2 *e_out, hipStream_t st);
+hipError_t launch_cv_ek(const System &s, int W, double2 *ek, hipStream_t st);
+hipError_t launch_cv_stats(const double *feat, const double2 *ek, long n, double *norm, hipStream_t st);
+hipError_t launch_cv_standardise(const double *feat, const double2 *ek, long n, const double *norm, float *X,
+                                 float *T, hipStream_t st);
+int cv_grad_workgroups(long nb);
+hipError_t launch_cv_grad(const float *P, const float *X, const float *T, long n0, long nb, float *part,
+                          double *lpart, float *grad, double loss_scale, double *loss, hipStream_t st);
+hipError_t launch_cv_adam(float *P, const float *grad, float *m, float *v, double lr, long t, hipStream_t st);
 
 // Exchange launch geometry for a spin block width.
 void exchange_geometry(int nmax, int *gb, size_t *lds);

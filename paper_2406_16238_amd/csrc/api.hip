@@ -236,6 +236,60 @@ int choose_fb_ksplit(int W, int G, long K) {
   return (int)std::max(1L, std::min(ks, 64L));
 }
 
+// Exchange energy of `W` walkers whose Theta is in `theta` (contiguous), into
+// the partial sums s.ekpart; vbpart as in launch_exchange.
+afqmc_status exchange_sys(afqmc_ctx *c, System &s, const double2 *theta, int W, double2 *vbpart, hipStream_t st) {
+  for (int spin = 0; spin < 2; ++spin) {
+    if (s.precision != AFQMC_FP64) {
+      {
+        Phase ph(c, AFQMC_PH_OPERANDS, st);
+        AFQMC_HIP(lp_prepare_rhs(s, theta, W, spin, st), "reduced-precision operand kernel");
+      }
+      Phase ph(c, AFQMC_PH_EXCHANGE, st);
+      AFQMC_HIP(launch_exchange_lp(s, W, spin, st, vbpart), "reduced-precision exchange kernel");
+    } else {
+      Phase ph(c, AFQMC_PH_EXCHANGE, st);
+      AFQMC_HIP(launch_exchange(s, theta, W, st, vbpart, spin), "exchange kernel");
+    }
+  }
+  return AFQMC_OK;
+}
+
+// Local energy in the control-variate mode (Theta of the walkers in s.theta,
+// overlaps in s.logo_new): vbias by its own contraction, E1, EJ, features,
+// network, subset draw, exact exchange of the subset, Horvitz-Thompson combine.
+afqmc_status cv_energy_sys(afqmc_ctx *c, System &s, int W, double2 *e_out, double *est, const double *weight,
+                           hipStream_t st) {
+  {
+    Phase ph(c, AFQMC_PH_FORCE_BIAS, st);
+    AFQMC_HIP(launch_force_bias_gemm(s, s.theta, W, st), "force-bias kernel");
+  }
+  s.fb_slices = s.fb_ksplit;
+  {
+    Phase ph(c, AFQMC_PH_ENERGY_1B, st);
+    AFQMC_HIP(launch_energy_e1(s, s.theta, W, st), "one-body energy kernel");
+  }
+  {
+    Phase ph(c, AFQMC_PH_FB_EPILOGUE, st);
+    AFQMC_HIP(launch_fb_energy_epilogue(s, W, nullptr, s.fb_slices, st), "Coulomb epilogue");
+  }
+  {
+    Phase ph(c, AFQMC_PH_CV, st);
+    AFQMC_HIP(launch_cv_features(s, W, s.cv_feat, st), "feature kernel");
+    AFQMC_HIP(launch_cv_predict(s, s.cv_feat, W, s.cv_f, st), "network kernel");
+    AFQMC_HIP(launch_cv_subset(s, W, s.cv_k, s.cv_seed, st), "subset kernel");
+    AFQMC_HIP(launch_cv_gather(s, s.cv_k, st), "gather kernel");
+  }
+  afqmc_status r = exchange_sys(c, s, s.cv_theta, s.cv_k, nullptr, st);
+  if (r != AFQMC_OK) return r;
+  {
+    Phase ph(c, AFQMC_PH_COMBINE, st);
+    AFQMC_HIP(launch_cv_combine(s, W, s.cv_k, e_out, st), "energy combine kernel");
+    if (est) AFQMC_HIP(launch_estimator(weight, e_out, W, est, st), "estimator kernel");
+  }
+  return AFQMC_OK;
+}
+
 // Local energy of W walkers of system s into e_out (device double2 [W][3]).
 // `c` may be NULL (set-up); it only supplies the phase timers.
 afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W, double2 *e_out, double *est,
@@ -245,6 +299,7 @@ afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W
     AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_new, s.stat_new, nullptr, st),
               "overlap kernel");
   }
+  if (s.ex_mode == AFQMC_EX_CV && W == s.W) return cv_energy_sys(c, s, W, e_out, est, weight, st);
   // vbias: as the trace of the exchange matrices (MFMA exchange), else by its own contraction
   const bool fused_vb = s.ex_mfma;
   if (!fused_vb) {
@@ -258,18 +313,9 @@ afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W
     Phase ph(c, AFQMC_PH_ENERGY_1B, st);
     AFQMC_HIP(launch_energy_e1(s, s.theta, W, st), "one-body energy kernel");
   }
-  for (int spin = 0; spin < 2; ++spin) {
-    if (s.precision != AFQMC_FP64) {
-      {
-        Phase ph(c, AFQMC_PH_OPERANDS, st);
-        AFQMC_HIP(lp_prepare_rhs(s, s.theta, W, spin, st), "reduced-precision operand kernel");
-      }
-      Phase ph(c, AFQMC_PH_EXCHANGE, st);
-      AFQMC_HIP(launch_exchange_lp(s, W, spin, st, s.fbpart), "reduced-precision exchange kernel");
-    } else {
-      Phase ph(c, AFQMC_PH_EXCHANGE, st);
-      AFQMC_HIP(launch_exchange(s, s.theta, W, st, fused_vb ? s.fbpart : nullptr, spin), "exchange kernel");
-    }
+  {
+    afqmc_status r = exchange_sys(c, s, s.theta, W, fused_vb ? s.fbpart : nullptr, st);
+    if (r != AFQMC_OK) return r;
   }
   if (fused_vb) s.fb_slices = 2;
   {
@@ -379,8 +425,26 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     s.lp_lhs[sp] = b0;
     s.lp_rhs[sp] = b1;
   }
+  // learned control variate: network state (small) always, Theta of the subset in EX_CV mode
+  s.cv_seed = c->opt.cv_seed;
+  s.cv_k = (int)std::min<double>(s.W, std::max(1.0, std::ceil(c->opt.cv_fraction * s.W - 1e-9)));
+  {
+    const size_t Wn = s.W;
+    ok = ok && dalloc(c, &s.cv_params, kCvParams) && dalloc(c, &s.cv_m, kCvParams) &&
+         dalloc(c, &s.cv_v, kCvParams) && dalloc(c, &s.cv_norm, kCvNorm) &&
+         dalloc(c, &s.cv_feat, Wn * kCvFeatures) && dalloc(c, &s.cv_f, Wn) && dalloc(c, &s.cv_sel, Wn) &&
+         dalloc(c, &s.cv_pos, Wn) && dalloc(c, &s.cv_counter, 2);
+    if (ok && c->opt.ex_mode == AFQMC_EX_CV) ok = dalloc(c, &s.cv_theta, (size_t)s.cv_k * M * Nt);
+    s.bytes += 4ull * 3 * kCvParams + 8ull * (kCvNorm + Wn * kCvFeatures) + 16ull * Wn + 8ull * Wn + 16 +
+               (c->opt.ex_mode == AFQMC_EX_CV ? 16ull * s.cv_k * M * Nt : 0);
+  }
   if (!ok) return fail(AFQMC_ERR_OOM, "device allocation failed");
   *bytes_used += s.bytes;
+  AFQMC_HIP(cv_enable_lds(), "network kernel LDS attribute");
+  AFQMC_HIP(launch_cv_init(s, 0x5EEDull, st), "network initialisation");
+  AFQMC_HIP(launch_cv_zero(s.cv_m, kCvParams * sizeof(float), st), "zero fill");
+  AFQMC_HIP(launch_cv_zero(s.cv_v, kCvParams * sizeof(float), st), "zero fill");
+  AFQMC_HIP(launch_cv_zero(s.cv_counter, 2 * sizeof(uint64_t), st), "zero fill");
   AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
   AFQMC_HIP(ovlp_enable_lds(nmax), "overlap kernel LDS attribute");
   if (s.precision != AFQMC_FP64) AFQMC_HIP(lp_enable_lds(s), "reduced-precision exchange LDS attribute");
@@ -489,6 +553,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     AFQMC_HIP(hipStreamSynchronize(st), "set-up synchronise");
     s.e_hf = he[0].x;
   }
+  s.ex_mode = c->opt.ex_mode;  // the trial energy above used the full exchange
   return AFQMC_OK;
 }
 
@@ -667,7 +732,11 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   if (o.streams < 0) return fail(AFQMC_ERR_ARG, "streams must be >= 0");
   if (o.ex_mode != AFQMC_EX_FULL && o.ex_mode != AFQMC_EX_CV) return fail(AFQMC_ERR_ARG, "unknown ex_mode");
   if (!(o.cv_fraction > 0.0 && o.cv_fraction <= 1.0)) return fail(AFQMC_ERR_ARG, "cv_fraction must be in (0, 1]");
-  if (o.ex_mode == AFQMC_EX_CV) return fail(AFQMC_ERR_UNSUPPORTED, "the control-variate exchange is not built yet");
+  if (o.ex_mode == AFQMC_EX_CV)
+    for (int i = 0; i < nsys; ++i)
+      if (sys[i].nwalkers > kCvMaxWalkers)
+        return fail(AFQMC_ERR_UNSUPPORTED, "the control-variate exchange supports at most " +
+                                               std::to_string(kCvMaxWalkers) + " walkers per system");
   for (int i = 0; i < nsys; ++i) {
     std::string why;
     if (!valid_desc(sys[i], why)) return fail(AFQMC_ERR_ARG, "system " + std::to_string(i) + ": " + why);
@@ -683,6 +752,9 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     { delete c; return fail(AFQMC_ERR_UNSUPPORTED, "reduced precision needs the MFMA exchange kernel"); }
   c->opt.taylor_order = o.taylor_order;
   c->opt.fb_cap = o.fb_cap;
+  c->opt.ex_mode = o.ex_mode;
+  c->opt.cv_fraction = o.cv_fraction;
+  c->opt.cv_seed = o.cv_seed;
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
@@ -1007,6 +1079,184 @@ afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w, void *cons
   return AFQMC_OK;
 }
 
+afqmc_status afqmc_cv_collect(afqmc_ctx *ctx, const afqmc_walkers *w, double *const *feat_out, void *const *ek_out,
+                              void *hip_stream) {
+  if (!ctx || !w || !feat_out || !ek_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers or outputs");
+  invalidate_caches(ctx);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    if (!w[i].phi || !feat_out[i] || !ek_out[i]) return fail(AFQMC_ERR_ARG, "NULL phi or output");
+  }
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
+    System &s = ctx->sys[i];
+    {
+      Phase ph(ctx, AFQMC_PH_OVERLAP, ls);
+      AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
+                                  s.logo_new, s.stat_new, nullptr, ls),
+                "overlap kernel");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_FORCE_BIAS, ls);
+      AFQMC_HIP(launch_force_bias_gemm(s, s.theta, s.W, ls), "force-bias kernel");
+    }
+    s.fb_slices = s.fb_ksplit;
+    {
+      Phase ph(ctx, AFQMC_PH_ENERGY_1B, ls);
+      AFQMC_HIP(launch_energy_e1(s, s.theta, s.W, ls), "one-body energy kernel");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_FB_EPILOGUE, ls);
+      AFQMC_HIP(launch_fb_energy_epilogue(s, s.W, nullptr, s.fb_slices, ls), "Coulomb epilogue");
+    }
+    {
+      Phase ph(ctx, AFQMC_PH_CV, ls);
+      AFQMC_HIP(launch_cv_features(s, s.W, feat_out[i], ls), "feature kernel");
+    }
+    afqmc_status r = exchange_sys(ctx, s, s.theta, s.W, nullptr, ls);
+    if (r != AFQMC_OK) return r;
+    AFQMC_HIP(launch_cv_ek(s, s.W, static_cast<double2 *>(ek_out[i]), ls), "exchange sum kernel");
+    return AFQMC_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+System *cv_system(afqmc_ctx *ctx, int32_t isys) {
+  if (!ctx || isys < 0 || isys >= (int)ctx->sys.size()) return nullptr;
+  return &ctx->sys[isys];
+}
+
+// Device workspace of a synchronous call: freed after the stream has finished.
+struct Workspace {
+  std::vector<void *> ptrs;
+  hipStream_t st = nullptr;
+  ~Workspace() {
+    if (!ptrs.empty()) (void)hipStreamSynchronize(st);
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  bool get(T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, (count ? count : 1) * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    ptrs.push_back(q);
+    *p = static_cast<T *>(q);
+    return true;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+afqmc_status afqmc_cv_train(afqmc_ctx *ctx, int32_t isys, const double *feat, const void *ek, int64_t n,
+                            int32_t epochs, int32_t batch, double lr, double *loss_out, void *hip_stream) {
+  System *sp = cv_system(ctx, isys);
+  if (!sp || !feat || !ek) return fail(AFQMC_ERR_ARG, "NULL context, inputs or bad system index");
+  if (n < 2 || epochs < 0 || batch < 1 || !(lr > 0.0) || n > (int64_t)1 << 30)
+    return fail(AFQMC_ERR_ARG, "need n >= 2, epochs >= 0, batch >= 1 and lr > 0");
+  System &s = *sp;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const long nb_max = std::min<long>(batch, n);
+  Workspace ws;
+  ws.st = st;
+  float *X = nullptr, *T = nullptr, *part = nullptr, *grad = nullptr;
+  double *lpart = nullptr, *loss = nullptr;
+  if (!ws.get(&X, (size_t)n * kCvFeatures) || !ws.get(&T, (size_t)n * 2) ||
+      !ws.get(&part, (size_t)cv_grad_workgroups(nb_max) * kCvParams) || !ws.get(&grad, kCvParams) ||
+      !ws.get(&lpart, (size_t)cv_grad_workgroups(nb_max)) || !ws.get(&loss, (size_t)std::max(1, epochs)))
+    return fail(AFQMC_ERR_OOM, "device allocation failed (training workspace)");
+  AFQMC_HIP(launch_cv_stats(feat, static_cast<const double2 *>(ek), n, s.cv_norm, st), "statistics kernel");
+  AFQMC_HIP(launch_cv_standardise(feat, static_cast<const double2 *>(ek), n, s.cv_norm, X, T, st),
+            "standardise kernel");
+  AFQMC_HIP(launch_cv_zero(s.cv_m, kCvParams * sizeof(float), st), "zero fill");
+  AFQMC_HIP(launch_cv_zero(s.cv_v, kCvParams * sizeof(float), st), "zero fill");
+  AFQMC_HIP(launch_cv_zero(loss, (size_t)std::max(1, epochs) * sizeof(double), st), "zero fill");
+  long t = 0;
+  for (int e = 0; e < epochs; ++e)
+    for (long b0 = 0; b0 < n; b0 += batch) {
+      const long nb = std::min<long>(batch, n - b0);
+      AFQMC_HIP(launch_cv_grad(s.cv_params, X, T, b0, nb, part, lpart, grad, (double)nb / (double)n, loss + e, st),
+                "network gradient kernel");
+      AFQMC_HIP(launch_cv_adam(s.cv_params, grad, s.cv_m, s.cv_v, lr, ++t, st), "Adam kernel");
+    }
+  if (loss_out && epochs > 0)
+    AFQMC_HIP(hipMemcpyAsync(loss_out, loss, (size_t)epochs * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  AFQMC_HIP(hipStreamSynchronize(st), "training");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_cv_set_params(afqmc_ctx *ctx, int32_t isys, const float *params, const double *norm,
+                                 void *hip_stream) {
+  System *sp = cv_system(ctx, isys);
+  if (!sp) return fail(AFQMC_ERR_ARG, "NULL context or bad system index");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (params)
+    AFQMC_HIP(hipMemcpyAsync(sp->cv_params, params, kCvParams * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+  if (norm) AFQMC_HIP(hipMemcpyAsync(sp->cv_norm, norm, kCvNorm * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  AFQMC_HIP(launch_cv_zero(sp->cv_m, kCvParams * sizeof(float), st), "zero fill");
+  AFQMC_HIP(launch_cv_zero(sp->cv_v, kCvParams * sizeof(float), st), "zero fill");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_cv_get_params(afqmc_ctx *ctx, int32_t isys, float *params, double *norm, void *hip_stream) {
+  System *sp = cv_system(ctx, isys);
+  if (!sp) return fail(AFQMC_ERR_ARG, "NULL context or bad system index");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (params)
+    AFQMC_HIP(hipMemcpyAsync(params, sp->cv_params, kCvParams * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+  if (norm) AFQMC_HIP(hipMemcpyAsync(norm, sp->cv_norm, kCvNorm * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_cv_predict(afqmc_ctx *ctx, int32_t isys, const double *feat, int64_t n, void *f_out,
+                              void *hip_stream) {
+  System *sp = cv_system(ctx, isys);
+  if (!sp || !feat || !f_out) return fail(AFQMC_ERR_ARG, "NULL context, inputs or bad system index");
+  if (n < 0 || n > (int64_t)1 << 30) return fail(AFQMC_ERR_ARG, "bad sample count");
+  AFQMC_HIP(launch_cv_predict(*sp, feat, n, static_cast<double2 *>(f_out), static_cast<hipStream_t>(hip_stream)),
+            "network kernel");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_cv_loss_grad(afqmc_ctx *ctx, int32_t isys, const float *x, const float *t, int64_t n,
+                                float *grad_out, double *loss_out, void *hip_stream) {
+  System *sp = cv_system(ctx, isys);
+  if (!sp || !x || !t || !grad_out || !loss_out) return fail(AFQMC_ERR_ARG, "NULL argument or bad system index");
+  if (n < 1 || n > (int64_t)1 << 30) return fail(AFQMC_ERR_ARG, "bad sample count");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  Workspace ws;
+  ws.st = st;
+  float *part = nullptr;
+  double *lpart = nullptr;
+  if (!ws.get(&part, (size_t)cv_grad_workgroups(n) * kCvParams) || !ws.get(&lpart, (size_t)cv_grad_workgroups(n)))
+    return fail(AFQMC_ERR_OOM, "device allocation failed (gradient workspace)");
+  AFQMC_HIP(launch_cv_zero(loss_out, sizeof(double), st), "zero fill");
+  AFQMC_HIP(launch_cv_grad(sp->cv_params, x, t, 0, n, part, lpart, grad_out, 1.0, loss_out, st),
+            "network gradient kernel");
+  AFQMC_HIP(hipStreamSynchronize(st), "gradient");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_cv_state(afqmc_ctx *ctx, int32_t isys, void *f_out, int32_t *subset_out, uint64_t *call_out,
+                            void *hip_stream) {
+  System *sp = cv_system(ctx, isys);
+  if (!sp) return fail(AFQMC_ERR_ARG, "NULL context or bad system index");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (f_out)
+    AFQMC_HIP(hipMemcpyAsync(f_out, sp->cv_f, (size_t)sp->W * sizeof(double2), hipMemcpyDeviceToDevice, st), "copy");
+  if (subset_out)
+    AFQMC_HIP(hipMemcpyAsync(subset_out, sp->cv_sel, (size_t)sp->cv_k * sizeof(int32_t), hipMemcpyDeviceToDevice, st),
+              "copy");
+  if (call_out)
+    AFQMC_HIP(hipMemcpyAsync(call_out, sp->cv_counter + 1, sizeof(uint64_t), hipMemcpyDeviceToDevice, st), "copy");
+  return AFQMC_OK;
+}
+
 afqmc_status afqmc_set_timing(afqmc_ctx *ctx, int32_t enable) {
   if (!ctx) return fail(AFQMC_ERR_ARG, "NULL context");
   fold_timings(ctx);
@@ -1042,6 +1292,8 @@ afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out)
   out->lane = ctx->lanes.empty() ? -1 : ctx->lane_of[isys];
   out->graph_captures = ctx->graph_captures;
   out->graph_replays = ctx->graph_replays;
+  out->cv_subset = s.ex_mode == AFQMC_EX_CV ? s.cv_k : 0;
+  out->reserved_info = 0;
   return AFQMC_OK;
 }
 

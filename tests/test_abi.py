@@ -102,6 +102,13 @@ def test_step_calls_reject_null_context(lib):
     assert lib.afqmc_get_info(None, 0, ctypes.byref(info)) == A.ERR_ARG
     assert lib.afqmc_set_timing(None, 1) == A.ERR_ARG
     assert lib.afqmc_get_timings(None, None) == A.ERR_ARG
+    assert lib.afqmc_cv_collect(None, None, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_cv_train(None, 0, None, None, 10, 1, 1, 1e-3, None, None) == A.ERR_ARG
+    assert lib.afqmc_cv_set_params(None, 0, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_cv_get_params(None, 0, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_cv_predict(None, 0, None, 1, None, None) == A.ERR_ARG
+    assert lib.afqmc_cv_loss_grad(None, 0, None, None, 1, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_cv_state(None, 0, None, None, None, None) == A.ERR_ARG
     lib.afqmc_destroy(None)  # no-op
 
 
@@ -115,7 +122,7 @@ def test_struct_layouts_match_header(tmp_path):
                                             "reserved"]),
               "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
               "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "exchange_order", "lane",
-                                      "graph_captures", "graph_replays"]),
+                                      "graph_captures", "graph_replays", "cv_subset", "reserved_info"]),
               "afqmc_timings": (A.Timings, ["ms", "count"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "afqmc.h"', "int main(void) {"]
     for cname, (_, fl) in fields.items():
