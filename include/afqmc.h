@@ -105,7 +105,8 @@ typedef struct {
   uint64_t cv_seed;         /* AFQMC_EX_CV: seed of the subset draws; default 7   */
   int32_t reserved[8];      /* reserved[0] bit 0: VALU (non-MFMA) exchange kernel;
                                bit 1: VALU kernels for the force bias, V_HS, B1
-                               and Taylor products (both for comparison runs);
+                               and Taylor products; bit 2: the generic MFMA GEMM
+                               for the Taylor terms (all for comparison runs);
                                reserved[1]: walkers per exchange workgroup (1, 2
                                or 4); reserved[2]: exchange tile order (1 = Cholesky
                                block fastest, g > 1 = groups of g walker blocks);

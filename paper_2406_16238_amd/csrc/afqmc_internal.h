@@ -63,6 +63,7 @@ struct System {
   int ex_ngb = 1;     // its number of workgroups along G
   size_t ex_lds = 0;  // its dynamic LDS
   bool use_mfma_gemm = true;   // MFMA kernels for force bias, V_HS, B1 and Taylor terms
+  bool taylor_kernel = true;   // the dedicated Taylor-term kernel (else the generic MFMA GEMM)
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans
   int ex_group = 0;            // tile order of the MFMA exchange launches (see tile_of)
@@ -181,6 +182,10 @@ hipError_t launch_add_identity(double *A, int M, double diag, hipStream_t st);
 hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, hipStream_t st);
 hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
 hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
+// dedicated Taylor-term kernel (k_taylor.hip)
+bool taylor_mfma_supported(int M, int Nt);
+hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
+                              hipStream_t st);
 
 // learned control variate (k_cv.hip)
 hipError_t cv_enable_lds();

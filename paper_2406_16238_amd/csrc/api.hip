@@ -41,6 +41,7 @@ struct afqmc_ctx {
   std::vector<void *> allocs;
   bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
+  int debug_bits = 0;                // reserved[0]
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
   int ex_group = 8;                  // exchange tile order (reserved[2]: 1 = plain, g > 1 = groups of g)
   bool ex_wx_forced = false;         // launch shape fixed by the caller: no tuning
@@ -384,6 +385,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     return fail(AFQMC_ERR_UNSUPPORTED, "a spin block wider than " + std::to_string(kMaxSpinOrbitals) +
                                            " orbitals is not supported");
   s.use_mfma_gemm = !c->force_valu_gemm;
+  s.taylor_kernel = !(c->debug_bits & 4);
   s.precision = c->opt.precision;
   s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
   exchange_geometry(nmax, &s.ex_gb, &s.ex_lds);
@@ -757,6 +759,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->opt.cv_seed = o.cv_seed;
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
+  c->debug_bits = o.reserved[0];
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
     c->ex_wx = o.reserved[1];
     c->ex_wx_forced = true;

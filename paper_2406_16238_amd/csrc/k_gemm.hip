@@ -200,6 +200,8 @@ __global__ __launch_bounds__(kThreads) void k_taylor_term(const double *__restri
 
 hipError_t launch_taylor_term(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
                               hipStream_t st) {
+  if (s.use_mfma_gemm && s.taylor_kernel && taylor_mfma_supported(s.M, s.Nt))
+    return launch_taylor_mfma(s, tin, tout, alpha, W, st);
   if (s.use_mfma_gemm) {
     // [Re A | Im A] (M x 2M) times [T ; iT] (2M x 2Nt) per walker
     const long n2 = 2L * s.Nt, MM = (long)s.M * s.M;

@@ -1,0 +1,188 @@
+// One term of the Taylor series of the two-body exponential applied to the
+// walker slabs (Sec. 2, eq. Bprop, exp(sqrt(dt) V_HS) phi by its series):
+//   T_out = alpha * A_w T_in,   tacc += T_out,
+// with A_w = sqrt(dt) V_HS of walker w held as real and imaginary M x M planes
+// and T complex M x Nt.  As one real product per walker: rows i, columns
+// c = (j, re/im) interleaved, contraction over the two planes times q,
+//   [Re A | Im A] (M x 2M)  x  [T ; iT] (2M x 2Nt),   iT = (-Im T, Re T).
+//
+// A workgroup owns BM = 8 TR rows and all BN = 32 TN >= 2 Nt columns of one
+// walker, on a 2 x 2 grid of waves (4 TR rows x 16 TN columns each), so the
+// walker's A rows are read from memory exactly once and its T (M x Nt, 16 M Nt
+// bytes) is shared by the M / BM row tiles, which the launch order places on
+// one XCD.  Each wave issues TR x TN v_mfma_f64_4x4x4_4b_f64 per 4 contraction
+// indices (lane 16k+4b+i supplies A_b[i][k], lane 16k+4b+j supplies B_b[k][j],
+// lane 16i+4b+j receives D_b[i][j]; the four blocks are the four 4-column
+// groups of one 16-column group).  The contraction is staged 16 indices at a
+// time in LDS (k-major, padded rows) with 16-byte global loads, double-buffered
+// through registers.  M must be even (16-byte loads of A never straddle the two
+// planes); other shapes use the generic GEMM.
+#include "afqmc_internal.h"
+#include "device_util.h"
+
+namespace afqmc {
+
+namespace {
+constexpr int TKC = 16;  // contraction indices per LDS stage
+}
+
+template <int TR, int TN>
+__global__ __launch_bounds__(kThreads) void k_taylor_mfma(const double *__restrict__ vhs,
+                                                         const double2 *__restrict__ tin, double2 *__restrict__ tout,
+                                                         double2 *__restrict__ tacc, int M, int Nt, int W, int nrt,
+                                                         double alpha) {
+  constexpr int BM = 8 * TR, BN = 32 * TN;
+  constexpr int LDA = BM + 1, LDB = BN + 1;
+  constexpr int AV = BM * TKC / 2;                 // double2 of A per stage
+  constexpr int BV = TKC * BN / 2;                 // double2 of B per stage
+  constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
+  extern __shared__ double tsm[];
+  double *sA = tsm;                    // [2][TKC][LDA]
+  double *sB = tsm + 2 * TKC * LDA;    // [2][TKC][LDB]
+
+  // contiguous stretch of (walker, row tile) per XCD (workgroups are dealt to
+  // the 8 XCDs round-robin), row tile fastest
+  const int ntiles = W * nrt;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int t = x * per + min(x, rem) + jx;
+  const int w = t / nrt, i0 = (t - w * nrt) * BM;
+
+  const size_t MM = (size_t)M * M;
+  const double *Aw = vhs + (size_t)w * 2 * MM;
+  const double2 *Tw = tin + (size_t)w * M * Nt;
+  const int K = 2 * M, cols = 2 * Nt;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
+
+  double2 ra[APT], rb[BPT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * kThreads;            // (row, k pair)
+      const int row = e / (TKC / 2), kp = e - row * (TKC / 2);
+      const int gi = i0 + row, gk = k0 + 2 * kp;
+      ra[r] = (e < AV && gi < M && gk < K)
+                  ? *reinterpret_cast<const double2 *>(Aw + (gk >= M ? MM : 0) + (size_t)gi * M + (gk >= M ? gk - M : gk))
+                  : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = tid + r * kThreads;            // (k, complex column j)
+      const int kk = e / (BN / 2), j = e - kk * (BN / 2);
+      const int gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (e < BV && j < Nt && gk < K) {
+        const double2 z = Tw[(size_t)(gk >= M ? gk - M : gk) * Nt + j];
+        v = gk >= M ? make_double2(-z.y, z.x) : z;
+      }
+      rb[r] = v;
+    }
+  };
+  auto store = [&](int buf) {
+    double *a = sA + buf * TKC * LDA;
+    double *b = sB + buf * TKC * LDB;
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * kThreads;
+      if (e < AV) {
+        const int row = e / (TKC / 2), kp = e - row * (TKC / 2);
+        a[(2 * kp) * LDA + row] = ra[r].x;
+        a[(2 * kp + 1) * LDA + row] = ra[r].y;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = tid + r * kThreads;
+      if (e < BV) {
+        const int kk = e / (BN / 2), j = e - kk * (BN / 2);
+        b[kk * LDB + 2 * j] = rb[r].x;
+        b[kk * LDB + 2 * j + 1] = rb[r].y;
+      }
+    }
+  };
+
+  constexpr int TRW = TR;  // 4-row slabs per wave
+  double acc[TRW][TN];
+#pragma unroll
+  for (int i = 0; i < TRW; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
+
+  const int nchunk = (K + TKC - 1) / TKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * TKC);
+    const double *a = sA + buf * TKC * LDA + wm * 4 * TR + l4;
+    const double *b = sB + buf * TKC * LDB + wn * 16 * TN + lr;
+#pragma unroll
+    for (int ks = 0; ks < TKC / 4; ++ks) {
+      double av[TRW], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TRW; ++i) av[i] = a[(ks * 4 + lk) * LDA + i * 4];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = b[(ks * 4 + lk) * LDB + j * 16];
+#pragma unroll
+      for (int i = 0; i < TRW; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  double *to = reinterpret_cast<double *>(tout + (size_t)w * M * Nt);
+  double *ta = reinterpret_cast<double *>(tacc + (size_t)w * M * Nt);
+#pragma unroll
+  for (int i = 0; i < TRW; ++i) {
+    const int gi = i0 + wm * 4 * TR + 4 * i + lk;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = wn * 16 * TN + 16 * j + lr;
+      if (gi < M && c < cols) {
+        const size_t off = (size_t)gi * cols + c;
+        const double v = alpha * acc[i][j];
+        to[off] = v;
+        ta[off] += v;
+      }
+    }
+  }
+}
+
+namespace {
+template <int TR, int TN>
+hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
+  constexpr int BM = 8 * TR, BN = 32 * TN;
+  const size_t lds = 2ull * TKC * ((BM + 1) + (BN + 1)) * sizeof(double);
+  auto k = k_taylor_mfma<TR, TN>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int nrt = (s.M + BM - 1) / BM;
+  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(kThreads), lds, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt, W,
+                     nrt, alpha);
+  return hipGetLastError();
+}
+}  // namespace
+
+bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <= 80; }
+
+hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
+                              hipStream_t st) {
+  if (s.Nt <= 16) return run_taylor<16, 1>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 32) return run_taylor<16, 2>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 48) return run_taylor<12, 3>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 64) return run_taylor<12, 4>(s, tin, tout, alpha, W, st);
+  return run_taylor<10, 5>(s, tin, tout, alpha, W, st);
+}
+
+}  // namespace afqmc

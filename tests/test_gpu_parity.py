@@ -211,12 +211,13 @@ def test_full_size_sampled(spec):
         p.close()
 
 
-@pytest.mark.parametrize("bits", [1, 2, 3], ids=["valu-exchange", "valu-gemm", "valu-all"])
+@pytest.mark.parametrize("bits", [1, 2, 3, 4], ids=["valu-exchange", "valu-gemm", "valu-all", "generic-taylor"])
 @pytest.mark.parametrize("spec,W", [(RAGGED, 7), (TILED, 70)], ids=["ragged", "tiled"])
 def test_valu_kernels_match_oracle(spec, W, bits):
     """The VALU kernels (kept for comparison runs and as the exchange fallback
-    where the MFMA tiling does not apply) stay at parity too; reserved[0]
-    selects them."""
+    where the MFMA tiling does not apply) and the generic MFMA GEMM for the
+    Taylor terms (the fallback of the dedicated kernel) stay at parity too;
+    reserved[0] selects them."""
     from paper_2406_16238_amd import afqmc as A
     o = A.default_options()
     o.reserved[0] = bits
