@@ -42,9 +42,11 @@ constexpr int BPAD = 8;     // bf16 padding of a staged row (row stride 40 eleme
 // Trace epilogue shared by both forms.  T of each wave (ROWW x CP floats) is in
 // LDS at row stride TSF; every lane pairs each accumulator entry with the
 // transposed entry of the same Cholesky vector and accumulates in FP64.
+// only >= 0 restricts the pass to that Cholesky vector of the wave (whose T
+// alone is then in LDS, at the addresses of the full layout minus its offset).
 template <int NR, int CT, int RT>
 __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *sT, int TSF, int lane,
-                                         double &pre, double &pim, double *dg) {
+                                         double &pre, double &pim, double *dg, int only) {
   const int lr = lane & 15, lk = lane >> 4;
   const bool odd = lr & 1;
 #pragma unroll
@@ -55,6 +57,7 @@ __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *
       for (int r = 0; r < 4; ++r) {
         const int row = rt * 16 + 4 * lk + r;
         const int gl = row / NR, i = row - gl * NR;
+        if (only >= 0 && gl != only) continue;
         const int col = ct * 16 + lr, j = col >> 1;
         const float2 t = *reinterpret_cast<const float2 *>(sT + (gl * NR + j) * TSF + 2 * i);
         const double v = (double)acc[rt][ct][r];
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
       for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
   __syncthreads();
   double pre = 0.0, pim = 0.0, dg[2] = {0.0, 0.0};
-  lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg);
+  lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg, -1);
   lp_finish<GC>(pre, pim, dg, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart, vbpart);
 }
 
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
 // terms; contraction index contiguous and zero-padded to Kp, a multiple of 32)
 // for one spin block.
 template <int NR, int NT>
-__global__ __launch_bounds__(kThreads) void k_exchange_bf16(const __bf16 *__restrict__ LtB,
+__global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(const __bf16 *__restrict__ LtB,
                                                              const __bf16 *__restrict__ ThB, int Kp, int N, int G,
                                                              int W, int stride, int spin,
                                                              double2 *__restrict__ ekpart,
@@ -210,8 +213,12 @@ __global__ __launch_bounds__(kThreads) void k_exchange_bf16(const __bf16 *__rest
   constexpr int AV = NT * ROWS * (LKC / 8), BV = NT * COLS * (LKC / 8);  // 16-byte vectors per stage
   constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
   constexpr int TSF = CP + 2;
+  // The two-term form keeps two workgroups per CU (registers for two waves per
+  // SIMD, under 80 KB of LDS): one staging buffer refilled between two
+  // barriers, and the trace epilogue one Cholesky vector of each wave at a time.
+  constexpr int NBUF = (NT == 2) ? 1 : 2;
   extern __shared__ __bf16 bsm[];
-  __bf16 *sA = bsm, *sB = bsm + 2 * ASZ;
+  __bf16 *sA = bsm, *sB = bsm + NBUF * ASZ;
 
   int gb, wb;
   tile_of(blockIdx.x, ngb * nwb, ngb, nwb, group, gb, wb);
@@ -276,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_exchange_bf16(const __bf16 *__rest
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
   for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = ch & 1;
+    const int buf = NBUF == 2 ? (ch & 1) : 0;
     if (ch + 1 < nchunk) load((ch + 1) * LKC);
     const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * lk;
     const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * lk;
@@ -310,20 +317,45 @@ __global__ __launch_bounds__(kThreads) void k_exchange_bf16(const __bf16 *__rest
     AFQMC_SWEEP(ah, bm)
     AFQMC_SWEEP(ah, bh)
 #undef AFQMC_SWEEP
-    if (ch + 1 < nchunk) store(buf ^ 1);
+    if (NBUF == 2) {
+      if (ch + 1 < nchunk) store(buf ^ 1);
+    } else if (ch + 1 < nchunk) {
+      __syncthreads();  // every wave is done reading the buffer
+      store(0);
+    }
     __syncthreads();
   }
 
-  float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * ROWW * TSF;
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
-  __syncthreads();
   double pre = 0.0, pim = 0.0, dg[2] = {0.0, 0.0};
-  lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg);
+  if constexpr (NT == 2) {
+    // one Cholesky vector of the wave at a time: T^g (NR x CP) per wave in LDS
+    float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * NR * TSF;
+#pragma unroll
+    for (int pass = 0; pass < GC; ++pass) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + 4 * lk + r;
+            if (row / NR == pass) sT[(row - pass * NR) * TSF + ct * 16 + lr] = acc[rt][ct][r];
+          }
+      __syncthreads();
+      lp_trace<NR, CT, RT>(acc, sT - pass * NR * TSF, TSF, lane, pre, pim, dg, pass);
+      if (pass + 1 < GC) __syncthreads();
+    }
+  } else {
+    float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * ROWW * TSF;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
+    __syncthreads();
+    lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg, -1);
+  }
   lp_finish<GC>(pre, pim, dg, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart, vbpart);
 }
 
@@ -450,8 +482,9 @@ size_t lds_f32(int nr) {
 }
 size_t lds_bf(int nr, int nt) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
-  const size_t stage = 2ull * nt * (LWY * roww + LWX * cp) * (LKC + BPAD) * sizeof(__bf16);
-  const size_t epi = 4ull * roww * (cp + 2) * sizeof(float);
+  const size_t nbuf = nt == 2 ? 1 : 2, erows = nt == 2 ? nr : roww;
+  const size_t stage = nbuf * nt * (LWY * roww + LWX * cp) * (LKC + BPAD) * sizeof(__bf16);
+  const size_t epi = 4ull * erows * (cp + 2) * sizeof(float);
   return stage > epi ? stage : epi;
 }
 }  // namespace
