@@ -106,11 +106,14 @@ typedef struct {
   int32_t reserved[8];      /* reserved[0] bit 0: VALU (non-MFMA) exchange kernel;
                                bit 1: VALU kernels for the force bias, V_HS, B1
                                and Taylor products; bit 2: the generic MFMA GEMM
-                               for the Taylor terms (all for comparison runs);
+                               for the Taylor terms; bit 3: V_HS from the full
+                               (unpacked) L^g (all for comparison runs);
                                reserved[1]: walkers per exchange workgroup (1, 2
                                or 4); reserved[2]: exchange tile order (1 = Cholesky
                                block fastest, g > 1 = groups of g walker blocks);
                                either one fixes the launch shape (no tuning);
+                               reserved[3]: tile shape of the V_HS product (0 =
+                               default, 1..4 alternatives for comparison runs);
                                other entries: zero                                */
 } afqmc_options;
 
@@ -209,6 +212,10 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void 
  * or when (flags & AFQMC_STEP_FRESH) says the walkers were changed elsewhere.
  * When they are reused, log<Psi_T|phi> of the walkers is taken from
  * walkers.log_ovlp (which propagation and re-orthogonalisation keep current).
+ * When they are recomputed, vbias is still taken as the trace of the exchange
+ * matrices (full exchange mode), as in every later step, so a run restarted
+ * from its walker state after a step without re-orthogonalisation repeats the
+ * uninterrupted run bit for bit.
  */
 enum { AFQMC_STEP_REORTHO = 1u, AFQMC_STEP_FRESH = 2u };
 afqmc_status afqmc_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,

@@ -53,6 +53,8 @@ struct System {
 
   double *L = nullptr, *LtT = nullptr, *htT = nullptr, *trial = nullptr, *B1 = nullptr, *lmf = nullptr;
   double *LtS[2] = {nullptr, nullptr};  // per spin [G][M][NR]: half-rotated, rows padded for the exchange
+  double *Lp = nullptr;                 // [G][M(M+1)/2] packed upper triangles of the L^g
+  double *vhsp = nullptr;               // [W][2][M(M+1)/2] packed V_HS planes
   double2 *theta = nullptr, *fbpart = nullptr, *tA = nullptr, *tB = nullptr, *tacc = nullptr;
   double *yp = nullptr, *vhs = nullptr, *wsc = nullptr;
   double2 *logo_now = nullptr, *logo_new = nullptr, *e1 = nullptr, *ej = nullptr, *ekpart = nullptr;
@@ -64,6 +66,8 @@ struct System {
   size_t ex_lds = 0;  // its dynamic LDS
   bool use_mfma_gemm = true;   // MFMA kernels for force bias, V_HS, B1 and Taylor terms
   bool taylor_kernel = true;   // the dedicated Taylor-term kernel (else the generic MFMA GEMM)
+  int vhs_variant = 0;         // tile shape of the V_HS GEMM
+  bool pack_chol = true;       // V_HS from the packed upper triangles of the L^g
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans
   int ex_group = 0;            // tile order of the MFMA exchange launches (see tile_of)
@@ -128,7 +132,7 @@ struct GemmArgs {
   int cplx_rows = 0;
 };
 hipError_t gemm_f64(const GemmArgs &a, hipStream_t st);
-hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st);
+hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st, int variant);
 hipError_t gemm_b1_mfma(const GemmArgs &a, hipStream_t st);
 hipError_t gemm_taylor_mfma(const GemmArgs &a, hipStream_t st);
 hipError_t gemm_fb_mfma(const GemmArgs &a, hipStream_t st);
@@ -182,6 +186,7 @@ hipError_t launch_add_identity(double *A, int M, double diag, hipStream_t st);
 hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, hipStream_t st);
 hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
 hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
+hipError_t launch_pack_upper(const System &s, hipStream_t st);
 // dedicated Taylor-term kernel (k_taylor.hip)
 bool taylor_mfma_supported(int M, int Nt);
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,

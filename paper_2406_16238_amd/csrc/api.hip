@@ -42,6 +42,7 @@ struct afqmc_ctx {
   bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   int debug_bits = 0;                // reserved[0]
+  int vhs_variant = 0;               // reserved[3]: tile shape of the V_HS GEMM (0 = default, 1..4 others)
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
   int ex_group = 8;                  // exchange tile order (reserved[2]: 1 = plain, g > 1 = groups of g)
   bool ex_wx_forced = false;         // launch shape fixed by the caller: no tuning
@@ -191,10 +192,10 @@ bool valid_desc(const afqmc_system_desc &d, std::string &why) {
 
 // Sizes of every buffer of one system (doubles, double2s, uint32s).
 struct Plan {
-  size_t L, LtT, htT, trial, B1, lmf, theta, fbpart, yp, vhs, tbuf, wsc, wvec2, ekpart, stat, LtS0, LtS1;
+  size_t L, LtT, htT, trial, B1, lmf, theta, fbpart, yp, vhs, tbuf, wsc, wvec2, ekpart, stat, LtS0, LtS1, Lp, vhsp;
   size_t lp_bytes[2][2];  // reduced-precision operands per spin: [lhs, rhs] in bytes
   uint64_t bytes() const {
-    return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc + LtS0 + LtS1) +
+    return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc + LtS0 + LtS1 + Lp + vhsp) +
            16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat + lp_bytes[0][0] +
            lp_bytes[0][1] + lp_bytes[1][0] + lp_bytes[1][1];
   }
@@ -213,6 +214,8 @@ Plan plan_for(const System &s) {
   p.fbpart = (size_t)std::max(s.fb_ksplit, 2) * W * G;
   p.yp = 2 * W * G;
   p.vhs = 2 * W * M * M;
+  p.Lp = s.pack_chol ? G * (M * (M + 1) / 2) : 0;
+  p.vhsp = s.pack_chol ? 2 * W * (M * (M + 1) / 2) : 0;
   p.tbuf = W * M * Nt;
   p.wsc = 6 * W;
   p.wvec2 = W;  // logo_now, logo_new, e1, ej (+1 spare)
@@ -386,6 +389,8 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
                                            " orbitals is not supported");
   s.use_mfma_gemm = !c->force_valu_gemm;
   s.taylor_kernel = !(c->debug_bits & 4);
+  s.vhs_variant = c->vhs_variant;
+  s.pack_chol = s.use_mfma_gemm && !(c->debug_bits & 8);
   s.precision = c->opt.precision;
   s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
   exchange_geometry(nmax, &s.ex_gb, &s.ex_lds);
@@ -420,7 +425,8 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
             dalloc(c, &s.tacc, p.tbuf) && dalloc(c, &s.wsc, p.wsc) && dalloc(c, &s.logo_now, p.wvec2) &&
             dalloc(c, &s.logo_new, p.wvec2) && dalloc(c, &s.e1, p.wvec2) && dalloc(c, &s.ej, p.wvec2) &&
             dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat) &&
-            (p.LtS0 == 0 || dalloc(c, &s.LtS[0], p.LtS0)) && (p.LtS1 == 0 || dalloc(c, &s.LtS[1], p.LtS1));
+            (p.LtS0 == 0 || dalloc(c, &s.LtS[0], p.LtS0)) && (p.LtS1 == 0 || dalloc(c, &s.LtS[1], p.LtS1)) &&
+            (p.Lp == 0 || (dalloc(c, &s.Lp, p.Lp) && dalloc(c, &s.vhsp, p.vhsp)));
   for (int sp = 0; sp < 2 && ok; ++sp) {
     unsigned char *b0 = nullptr, *b1 = nullptr;
     if (p.lp_bytes[sp][0]) ok = ok && dalloc(c, &b0, p.lp_bytes[sp][0]) && dalloc(c, &b1, p.lp_bytes[sp][1]);
@@ -453,6 +459,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
 
   const size_t mm = M * M;
   AFQMC_HIP(hipMemcpyAsync(s.L, d.chol, p.L * sizeof(double), hipMemcpyHostToDevice, st), "upload chol");
+  if (s.Lp) AFQMC_HIP(launch_pack_upper(s, st), "Cholesky packing");
   AFQMC_HIP(hipMemcpyAsync(s.trial, d.trial, p.trial * sizeof(double), hipMemcpyHostToDevice, st),
             "upload trial");
   // temporaries of set-up
@@ -760,6 +767,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   c->debug_bits = o.reserved[0];
+  if (o.reserved[3] >= 0 && o.reserved[3] <= 4) c->vhs_variant = o.reserved[3];
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
     c->ex_wx = o.reserved[1];
     c->ex_wx_forced = true;
@@ -808,10 +816,12 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
 // are taken from walkers.log_ovlp.  With `want_theta` the overlap pass after
 // the step also writes Theta of the new walkers (for a local energy next).
 static afqmc_status propagate_sys(afqmc_ctx *ctx, System &s, const afqmc_walkers &wk, const double *x, bool reuse,
-                                  bool want_theta, hipStream_t st) {
+                                  bool want_theta, hipStream_t st, bool ready = false) {
   double2 *phi = static_cast<double2 *>(wk.phi);
   const int W = s.W;
-  if (reuse) {
+  if (ready) {
+    // Theta, log-overlaps, singular markers and vbias partials already computed
+  } else if (reuse) {
     AFQMC_HIP(hipMemcpyAsync(s.logo_now, wk.log_ovlp, (size_t)W * sizeof(double2), hipMemcpyDeviceToDevice, st),
               "copy");
     AFQMC_HIP(hipMemcpyAsync(s.stat_now, s.stat_new, (size_t)W * sizeof(uint32_t), hipMemcpyDeviceToDevice, st),
@@ -902,7 +912,23 @@ afqmc_status step_body(afqmc_ctx *ctx, const afqmc_walkers *w, const double *con
     System &s = ctx->sys[i];
     const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
     s.cache_phi = nullptr;
-    afqmc_status r = propagate_sys(ctx, s, w[i], x[i], reuse, true, ls);
+    bool ready = false;
+    if (!reuse && s.ex_mfma && s.ex_mode == AFQMC_EX_FULL) {
+      // a fresh start takes vbias by the route every later step takes (the
+      // trace of the exchange matrices), so a run restarted from its walker
+      // state repeats the uninterrupted run bit for bit
+      {
+        Phase ph(ctx, AFQMC_PH_OVERLAP, ls);
+        AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
+                                    s.logo_now, s.stat_now, nullptr, ls),
+                  "overlap kernel");
+      }
+      afqmc_status r = exchange_sys(ctx, s, s.theta, s.W, s.fbpart, ls);
+      if (r != AFQMC_OK) return r;
+      s.fb_slices = 2;
+      ready = true;
+    }
+    afqmc_status r = propagate_sys(ctx, s, w[i], x[i], reuse, true, ls, ready);
     if (r != AFQMC_OK) return r;
     if (flags & AFQMC_STEP_REORTHO) {
       Phase ph(ctx, AFQMC_PH_REORTHO, ls);

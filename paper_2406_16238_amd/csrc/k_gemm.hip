@@ -119,14 +119,83 @@ hipError_t launch_force_bias_gemm(const System &s, const double2 *theta, int W, 
 }
 
 // ---- two-body generator: vhs[w][c][pq] = sum_g yp[w][c][g] L[g][pq] ----------
+// The L^g are symmetric, so is every V_HS: with the packed upper triangles
+// (Lp[g][t], t over p <= q row by row: the packed Cholesky vectors of Sec. 3.2)
+// the product runs over M(M+1)/2 columns instead of M^2, and a second kernel
+// writes each packed element to (p, q) and (q, p).  Each element is the same
+// sum over g in the same order as in the unpacked product.
+
+// t0(p) = index of element (p, p) in the packed rows: p M - p (p - 1) / 2.
+__device__ __forceinline__ long packed_row(long p, long M) { return p * M - p * (p - 1) / 2; }
+
+// Lp[g][t] = L[g][p][q] for p <= q.  Grid (rows p, G); block over q.
+__global__ void k_pack_upper(const double *__restrict__ L, int M, double *__restrict__ Lp) {
+  const int p = blockIdx.x, g = blockIdx.y;
+  const long Mp = (long)M * (M + 1) / 2;
+  const double *src = L + ((size_t)g * M + p) * M;
+  double *dst = Lp + (size_t)g * Mp + packed_row(p, M) - p;
+  for (int q = p + threadIdx.x; q < M; q += blockDim.x) dst[q] = src[q];
+}
+
+// full[m][p][q] = full[m][q][p] = packed[m][t(p, q)] for p <= q; one workgroup
+// per 32 x 32 tile (bi <= bj) of one matrix m, the transposed copy through LDS.
+__global__ __launch_bounds__(kThreads) void k_unpack_symmetric(const double *__restrict__ packed, int M, int ntile,
+                                                               double *__restrict__ full) {
+  __shared__ double tile[32][33];
+  const int m = blockIdx.y;
+  // tile index -> (bi, bj), bi <= bj, row-major over the upper triangle of tiles
+  int t = blockIdx.x, bi = 0;
+  while (t >= ntile - bi) {
+    t -= ntile - bi;
+    ++bi;
+  }
+  const int bj = bi + t;
+  const long Mp = (long)M * (M + 1) / 2;
+  const double *P = packed + (size_t)m * Mp;
+  double *F = full + (size_t)m * M * M;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int p = bi * 32 + r, q = bj * 32 + tx;
+    double v = 0.0;
+    if (p < M && q < M && p <= q) {
+      v = P[packed_row(p, M) + (q - p)];
+      F[(size_t)p * M + q] = v;
+    }
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int q = bj * 32 + r, p = bi * 32 + tx;  // write (q, p) from element (p, q)
+    if (p < M && q < M && p < q) F[(size_t)q * M + p] = tile[tx][r];
+  }
+}
+
+hipError_t launch_pack_upper(const System &s, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_upper, dim3(s.M, s.G), dim3(kThreads), 0, st, s.L, s.M, s.Lp);
+  return hipGetLastError();
+}
+
 hipError_t launch_vhs(const System &s, int W, hipStream_t st) {
   const long MM = (long)s.M * s.M;
   GemmArgs a;
-  a.m = 2 * W; a.n = (int)MM; a.k = s.G;
+  a.m = 2 * W; a.k = s.G;
   a.A = s.yp; a.sai = s.G; a.sak = 1;
+  if (s.use_mfma_gemm && s.Lp) {
+    const long Mp = (long)s.M * (s.M + 1) / 2;
+    a.n = (int)Mp;
+    a.B = s.Lp; a.sbk = Mp; a.sbj = 1;
+    a.C = s.vhsp; a.sci = Mp; a.scj = 1;
+    hipError_t e = gemm_vhs_mfma(a, st, s.vhs_variant);
+    if (e != hipSuccess) return e;
+    const int nt = (s.M + 31) / 32;
+    hipLaunchKernelGGL(k_unpack_symmetric, dim3(nt * (nt + 1) / 2, 2 * W), dim3(kThreads), 0, st, s.vhsp, s.M, nt,
+                       s.vhs);
+    return hipGetLastError();
+  }
+  a.n = (int)MM;
   a.B = s.L; a.sbk = MM; a.sbj = 1;
   a.C = s.vhs; a.sci = MM; a.scj = 1;
-  return s.use_mfma_gemm ? gemm_vhs_mfma(a, st) : gemm_f64(a, st);
+  return s.use_mfma_gemm ? gemm_vhs_mfma(a, st, s.vhs_variant) : gemm_f64(a, st);
 }
 
 // ---- one-body half step: out_w = B1 in_w (complex columns as real pairs) -----

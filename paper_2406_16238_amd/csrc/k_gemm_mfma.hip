@@ -38,8 +38,8 @@ namespace {
 constexpr int MKC = 16;
 }
 
-template <int WM, int WN, int TM, int TN, int AMODE, int BMODE>
-__global__ __launch_bounds__(kThreads) void k_gemm_mfma(GemmArgs a, int kchunk, int gx, int gy) {
+template <int WM, int WN, int TM, int TN, int AMODE, int BMODE, int MINB>
+__global__ __launch_bounds__(kThreads, MINB) void k_gemm_mfma(GemmArgs a, int kchunk, int gx, int gy) {
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
   constexpr int LDA = BM + 1, LDB = BN + 1;     // padded LDS rows
   constexpr int APT = (AMODE == 3) ? BM * MKC / (2 * kThreads) : BM * MKC / kThreads;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_mfma(GemmArgs a, int kchunk, 
 
 namespace {
 
-template <int WM, int WN, int TM, int TN, int AMODE, int BMODE>
+template <int WM, int WN, int TM, int TN, int AMODE, int BMODE, int MINB = 1>
 hipError_t run(const GemmArgs &a, hipStream_t st) {
   constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
   const int ks = a.ksplit < 1 ? 1 : a.ksplit;
@@ -220,7 +220,7 @@ hipError_t run(const GemmArgs &a, hipStream_t st) {
   g.ksplit = ks;
   const int gx = (a.m + BM - 1) / BM, gy = (a.n + BN - 1) / BN;
   const size_t lds = (size_t)2 * MKC * ((BM + 1) + (BN + 1)) * sizeof(double);
-  auto k = k_gemm_mfma<WM, WN, TM, TN, AMODE, BMODE>;
+  auto k = k_gemm_mfma<WM, WN, TM, TN, AMODE, BMODE, MINB>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -235,7 +235,18 @@ hipError_t run(const GemmArgs &a, hipStream_t st) {
 }  // namespace
 
 // V_HS planes: rows (w, c) = 2W, columns M^2, contraction over G.
-hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st) { return run<2, 2, 4, 4, 0, 0>(a, st); }
+// Default: 128 x 96 tiles, 64 x 48 per wave, two waves per SIMD (measured
+// 8 % faster at the headline shape than 128 x 128 tiles at one wave per
+// SIMD); the other shapes are kept for comparison runs.
+hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st, int variant) {
+  switch (variant) {
+    case 1: return run<2, 2, 4, 4, 0, 0, 1>(a, st);
+    case 2: return run<2, 2, 4, 4, 0, 0, 2>(a, st);
+    case 3: return run<2, 2, 2, 4, 0, 0, 2>(a, st);
+    case 4: return run<1, 4, 8, 2, 0, 0, 1>(a, st);
+    default: return run<2, 2, 4, 3, 0, 0, 2>(a, st);
+  }
+}
 // B1 times walker slabs: M rows, 2 Nt real columns, batched over walkers.
 hipError_t gemm_b1_mfma(const GemmArgs &a, hipStream_t st) { return run<4, 1, 1, 5, 0, 0>(a, st); }
 // Taylor term: [Re A | Im A] times [T ; iT], batched over walkers.

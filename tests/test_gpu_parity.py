@@ -211,7 +211,8 @@ def test_full_size_sampled(spec):
         p.close()
 
 
-@pytest.mark.parametrize("bits", [1, 2, 3, 4], ids=["valu-exchange", "valu-gemm", "valu-all", "generic-taylor"])
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 8], ids=["valu-exchange", "valu-gemm", "valu-all", "generic-taylor",
+                                                       "unpacked-vhs"])
 @pytest.mark.parametrize("spec,W", [(RAGGED, 7), (TILED, 70)], ids=["ragged", "tiled"])
 def test_valu_kernels_match_oracle(spec, W, bits):
     """The VALU kernels (kept for comparison runs and as the exchange fallback
