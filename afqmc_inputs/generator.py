@@ -24,6 +24,20 @@ synthetic systems stand in for them with the same shapes):
   [M][N_alpha + N_beta] with the alpha columns first.
 * Fields: x[step] of shape [W][Nchol], standard normal, from a separate
   ``default_rng(field_seed)`` drawn step by step.
+
+Counter recipe (``recipe="counter"``, for systems whose Cholesky tensor is too
+large to draw on the host; the library can generate the same tensor on the
+device, bit for bit):
+
+* L^gamma_pq = L^gamma_qp = sqrt(3) (u_{4i} + u_{4i+1} + u_{4i+2} + u_{4i+3} - 2)
+  * (exp(-gamma / tau) * scale) for p <= q, i = (gamma M + p) M + q, where u_n =
+  (SplitMix64 output n of the stream seeded with ``seed``) >> 11, times 2^-53
+  (a uniform on [0, 1) with 53 bits; the sum of four has mean 2 and variance
+  1/3, so the bracket has mean 0 and variance 1).  The four uniforms are added
+  left to right, then the bracket is multiplied by sqrt(3) and by the per-vector
+  factor (computed with the C library's exp).
+* h as in the default recipe (from ``default_rng(seed)``); the trial is the
+  lowest N eigenvectors of h alone (no pass over L on the host).
 """
 from __future__ import annotations
 
@@ -45,6 +59,7 @@ class SystemSpec:
     scale: str = "inv_m"       # "inv_m" | "literal" | "inv_sqrt_m"
     seed: int = 0              # Hamiltonian seed
     ecore: float = 0.0
+    recipe: str = "rng"        # "rng" (numpy default_rng) | "counter" (SplitMix64 counters)
 
     @property
     def nelec(self) -> int:
@@ -92,12 +107,63 @@ def make_chol(rng: np.random.Generator, m: int, nchol: int, tau: float,
     return chol
 
 
+GOLDEN = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def splitmix64_outputs(seed: int, n: np.ndarray) -> np.ndarray:
+    """Outputs n (uint64 array) of the SplitMix64 stream seeded with `seed`
+    (Steele, Lea and Flood 2014): state_n = seed + (n + 1) phi64, mixed."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _M64) + (n.astype(np.uint64) + np.uint64(1)) * np.uint64(GOLDEN)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def chol_factors(nchol: int, tau: float, scale: float) -> np.ndarray:
+    """exp(-gamma / tau) * scale per Cholesky vector, with the C library's exp."""
+    return np.array([math.exp(-g / tau) * scale for g in range(nchol)])
+
+
+def make_chol_counter(seed: int, m: int, nchol: int, tau: float, scale: float,
+                      gammas=None) -> np.ndarray:
+    """The counter recipe's L^gamma (all, or the listed gammas) as [len, M, M]."""
+    gammas = range(nchol) if gammas is None else list(gammas)
+    fac = chol_factors(nchol, tau, scale)
+    iu = np.triu_indices(m)
+    out = np.empty((len(gammas), m, m))
+    root3 = math.sqrt(3.0)
+    for k, g in enumerate(gammas):
+        i = (np.uint64(g) * np.uint64(m) + iu[0].astype(np.uint64)) * np.uint64(m) + iu[1].astype(np.uint64)
+        u = [(splitmix64_outputs(seed, np.uint64(4) * i + np.uint64(r)) >> np.uint64(11)).astype(np.float64)
+             * 2.0 ** -53 for r in range(4)]
+        z = (((u[0] + u[1]) + u[2]) + u[3]) - 2.0
+        v = (z * root3) * fac[g]
+        out[k][iu] = v
+        out[k][(iu[1], iu[0])] = v
+    return out
+
+
 def make_hamiltonian(spec: SystemSpec):
     """Return (h1 [M,M], chol [Nchol,M,M], ecore) as float64 numpy arrays."""
     rng = np.random.default_rng(spec.seed)
     h1 = make_h1(rng, spec.nbasis)
-    chol = make_chol(rng, spec.nbasis, spec.nchol, spec.tau, spec.scale_factor())
+    if spec.recipe == "counter":
+        chol = make_chol_counter(spec.seed, spec.nbasis, spec.nchol, spec.tau, spec.scale_factor())
+    else:
+        chol = make_chol(rng, spec.nbasis, spec.nchol, spec.tau, spec.scale_factor())
     return h1, chol, float(spec.ecore)
+
+
+def make_h1_only(spec: SystemSpec) -> np.ndarray:
+    return make_h1(np.random.default_rng(spec.seed), spec.nbasis)
+
+
+def make_trial_from_h(h1: np.ndarray, nalpha: int, nbeta: int) -> np.ndarray:
+    """Lowest eigenvectors of h alone (the counter recipe's trial)."""
+    _, vecs = np.linalg.eigh(0.5 * (h1 + h1.T))
+    return np.ascontiguousarray(np.hstack([vecs[:, :nalpha], vecs[:, :nbeta]]))
 
 
 def make_trial(h1: np.ndarray, chol: np.ndarray, nalpha: int, nbeta: int) -> np.ndarray:
@@ -115,8 +181,19 @@ def make_trial(h1: np.ndarray, chol: np.ndarray, nalpha: int, nbeta: int) -> np.
 def make_system(spec: SystemSpec):
     """Hamiltonian plus trial for one spec."""
     h1, chol, ecore = make_hamiltonian(spec)
-    trial = make_trial(h1, chol, spec.nalpha, spec.nbeta)
+    if spec.recipe == "counter":
+        trial = make_trial_from_h(h1, spec.nalpha, spec.nbeta)
+    else:
+        trial = make_trial(h1, chol, spec.nalpha, spec.nbeta)
     return h1, chol, ecore, trial
+
+
+def make_system_without_chol(spec: SystemSpec):
+    """(h1, ecore, trial) of a counter-recipe spec, whose L is generated on the device."""
+    if spec.recipe != "counter":
+        raise ValueError("only the counter recipe can leave L to the device")
+    h1 = make_h1_only(spec)
+    return h1, float(spec.ecore), make_trial_from_h(h1, spec.nalpha, spec.nbeta)
 
 
 def initial_walkers(trial: np.ndarray, nwalkers: int, noise: float = 0.0,
@@ -157,7 +234,7 @@ MEDIUM = RunSpec("medium-M200-N20-chol800",
 HEADLINE = RunSpec("headline-M400-N40-chol1600",
                    SystemSpec(400, 40, 40, 1600, tau=300.0), nwalkers=256, nsteps=20)
 BENZENE_SCALE = RunSpec("benzene-scale-M1512-N42-chol6000",
-                        SystemSpec(1512, 42, 42, 6000, tau=0.75 * 1512), nwalkers=64, nsteps=20)
+                        SystemSpec(1512, 42, 42, 6000, tau=0.75 * 1512, recipe="counter"), nwalkers=64, nsteps=20)
 
 
 def batching_specs() -> list[RunSpec]:

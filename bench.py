@@ -79,6 +79,9 @@ def parse_args(argv=None):
     ap.add_argument("--cv-train-steps", type=int, default=60, help="cv: trajectory steps whose walkers train the network")
     ap.add_argument("--cv-epochs", type=int, default=30, help="cv: training passes")
     ap.add_argument("--cv-draws", type=int, default=60, help="cv: subset draws at fixed walkers")
+    ap.add_argument("--cv-system", default="headline", choices=["headline", "benzene"],
+                    help="cv: the headline shape, or M=1512, N=42+42, 6000 Cholesky vectors, 64 walkers with the "
+                         "Cholesky tensor drawn on the device")
     ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
     ap.add_argument("--phases", action="store_true", help="print the per-phase tables to stderr")
@@ -271,18 +274,23 @@ def bench_batching(args):
 
 
 def bench_cv(args):
-    """Learned control variate at the headline shape: walker-steps/s with the
-    exact exchange on a 1/8 subset against full exchange, and the estimator's
-    bias and spread at fixed walkers against plain subsampling."""
+    """Learned control variate: walker-steps/s with the exact exchange on a 1/8
+    subset against full exchange, and the estimator's bias and spread at fixed
+    walkers against plain subsampling (f = 0).  Headline shape, or the
+    benzene-scale shape with its Cholesky tensor drawn on the device."""
     import numpy as np
     import torch
     import afqmc_inputs as gi
     from paper_2406_16238_amd import afqmc as A
 
-    spec = gi.HEADLINE
+    spec = gi.BENZENE_SCALE if args.cv_system == "benzene" else gi.HEADLINE
     s = spec.system
     W, G = spec.nwalkers, s.nchol
-    h1, chol, ecore, trial = gi.make_system(s)
+    if s.recipe == "counter":
+        h1, ecore, trial = gi.make_system_without_chol(s)
+        chol = A.CholGen(G, s.seed, s.tau, s.scale_factor())
+    else:
+        h1, chol, ecore, trial = gi.make_system(s)
     sysin = A.SystemInput(h1, chol, ecore, trial, s.nalpha, s.nbeta, W, spec.dt)
     prec = PRECISION_CODE[args.precision]
     gen = torch.Generator(device="cuda")
@@ -298,10 +306,20 @@ def bench_cv(args):
             if hook:
                 hook(k)
 
+    def timed(ctx, walkers):
+        run(ctx, walkers, args.warmup, 9000)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        run(ctx, walkers, args.steps, 9100)
+        ev1.record()
+        torch.cuda.synchronize()
+        return W * args.steps / (ev0.elapsed_time(ev1) * 1e-3)
+
     out = {}
+    t0 = time.time()
     ctx = A.setup_hamiltonian(sysin, A.default_options(precision=prec, ex_mode=A.EX_CV))
-    full = A.setup_hamiltonian(sysin, A.default_options(precision=prec))
-    del chol
+    setup_s = time.time() - t0
     # training samples: features and exact exchange along the path's own trajectory
     w = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
     A.overlap(ctx, w)
@@ -320,24 +338,14 @@ def bench_cv(args):
                        "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                        "seconds": round(time.time() - t0, 2)}
     del feats, eks
-    # throughput: the same trajectory continued with full exchange and with the control variate
-    rates = {}
-    for label, c in (("full_exchange", full), ("control_variate", ctx)):
-        wk = A.Walkers(w.phi.clone(), w.weight.clone(), w.log_ovlp.clone(), w.flags.clone())
-        A.overlap(c, wk)
-        run(c, wk, args.warmup, 9000)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        run(c, wk, args.steps, 9100)
-        ev1.record()
-        torch.cuda.synchronize()
-        rates[label] = W * args.steps / (ev0.elapsed_time(ev1) * 1e-3)
-    # estimator at fixed walkers: R subset draws, against the exact value and plain subsampling
+    saved = [t.clone() for t in (w.phi, w.weight, w.log_ovlp, w.flags)]
+    # estimator at fixed walkers: exact value from the full exchange, then R draws
     wt = w.weight.cpu().numpy()
     om = wt / wt.sum()
-    A.local_energy(full, w, e)
-    exact = float(np.sum(om * e.cpu().numpy()[:, 2].real))
+    fx = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+    ex = torch.empty(W, dtype=torch.complex128, device="cuda")
+    A.cv_collect(ctx, w, fx, ex)
+    exact = float(np.sum(om * (fx[:, 0].cpu().numpy() + ex.cpu().numpy().real)))   # Re EJ + Re EK
 
     def draws(R):
         v = []
@@ -346,20 +354,30 @@ def bench_cv(args):
             v.append(np.sum(om * e.cpu().numpy()[:, 2].real))
         return np.array(v)
     cvd = draws(args.cv_draws)
+    params, norm = A.cv_get_params(ctx)
     A.cv_set_params(ctx, torch.zeros(A.CV_NPARAMS, dtype=torch.float32, device="cuda"),
                     torch.tensor([0.0] * 8 + [1.0] * 8 + [0.0, 0.0, 1.0, 1.0], dtype=torch.float64, device="cuda"))
     pld = draws(args.cv_draws)
+    A.cv_set_params(ctx, params, norm)
+    # throughput from the same walker state: control variate, then full exchange
+    rates = {"control_variate": timed(ctx, A.Walkers(*[t.clone() for t in saved]))}
     ctx.close()
+    torch.cuda.empty_cache()
+    full = A.setup_hamiltonian(sysin, A.default_options(precision=prec))
+    rates["full_exchange"] = timed(full, A.Walkers(*[t.clone() for t in saved]))
     full.close()
     k = -(-W // 8)
     out.update({
-        "metric": "walker-steps/s (propagate+energy) at M=400,N=40 with the learned exchange control variate",
+        "metric": f"walker-steps/s (propagate+energy) at M={s.nbasis},N={s.nalpha} with the learned exchange "
+                  "control variate",
         "value": round(rates["control_variate"], 2), "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else f"{args.precision} (exchange, force bias) + f64 (rest)",
-        "data": "synthetic (seeded generator; network trained on the run's own trajectory)",
-        "config": {"workload": spec.name, "nwalkers": W, "exact_exchange_walkers_per_call": k,
-                   "precision": args.precision},
+        "data": "synthetic (seeded generator" + ("; Cholesky tensor drawn on the device" if s.recipe == "counter"
+                                                 else "") + "; network trained on the run's own trajectory)",
+        "config": {"workload": spec.name, "nbasis": s.nbasis, "nalpha": s.nalpha, "nchol": G, "nwalkers": W,
+                   "exact_exchange_walkers_per_call": k, "precision": args.precision,
+                   "setup_seconds": round(setup_s, 1)},
         "full_exchange_value": round(rates["full_exchange"], 2),
         "speedup_vs_full_exchange": round(rates["control_variate"] / rates["full_exchange"], 3),
         "estimator_at_fixed_walkers": {

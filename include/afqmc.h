@@ -71,6 +71,17 @@ typedef struct {
   double ecore;         /* constant energy (nuclear repulsion)                      */
   const double *trial;  /* host [M][Nt] real, orthonormal columns per spin block    */
   double dt;            /* imaginary time step (eq. afqmc), > 0                     */
+  int32_t chol_gen;     /* 0: chol is the host array above; 1: chol is NULL and the
+                           library draws the synthetic tensor on the device:
+                           L^g_pq = L^g_qp = sqrt(3) (u_{4i} + u_{4i+1} + u_{4i+2}
+                           + u_{4i+3} - 2) * (exp(-g / gen_tau) * gen_scale) for
+                           p <= q, i = (g M + p) M + q, u_n = (output n of the
+                           SplitMix64 stream seeded with gen_seed) >> 11, times
+                           2^-53 (sums left to right; exp from the C library)   */
+  int32_t reserved_desc;
+  uint64_t gen_seed;
+  double gen_tau;       /* > 0 */
+  double gen_scale;
 } afqmc_system_desc;
 
 /* Exchange-energy mode of afqmc_local_energy and afqmc_step. */

@@ -38,7 +38,9 @@ class SystemDesc(ctypes.Structure):
     _fields_ = [("nbasis", ctypes.c_int32), ("nalpha", ctypes.c_int32), ("nbeta", ctypes.c_int32),
                 ("nchol", ctypes.c_int32), ("nwalkers", ctypes.c_int32),
                 ("h1", ctypes.c_void_p), ("chol", ctypes.c_void_p), ("ecore", ctypes.c_double),
-                ("trial", ctypes.c_void_p), ("dt", ctypes.c_double)]
+                ("trial", ctypes.c_void_p), ("dt", ctypes.c_double), ("chol_gen", ctypes.c_int32),
+                ("reserved_desc", ctypes.c_int32), ("gen_seed", ctypes.c_uint64), ("gen_tau", ctypes.c_double),
+                ("gen_scale", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
@@ -152,11 +154,23 @@ def _stream_handle(stream) -> int:
 
 
 @dataclasses.dataclass
+class CholGen:
+    """The device-side synthetic Cholesky recipe (chol_gen = 1): seed, decay
+    length and scale, for G vectors."""
+
+    nchol: int
+    seed: int
+    tau: float
+    scale: float
+
+
+@dataclasses.dataclass
 class SystemInput:
-    """Host-side description of one system (float64 numpy arrays)."""
+    """Host-side description of one system (float64 numpy arrays).  `chol` is
+    either the [G, M, M] array or a CholGen (the library draws L on the device)."""
 
     h1: np.ndarray
-    chol: np.ndarray
+    chol: "np.ndarray | CholGen"
     ecore: float
     trial: np.ndarray
     nalpha: int
@@ -170,7 +184,7 @@ class SystemInput:
 
     @property
     def nchol(self):
-        return self.chol.shape[0]
+        return self.chol.nchol if isinstance(self.chol, CholGen) else self.chol.shape[0]
 
 
 @dataclasses.dataclass
@@ -241,15 +255,21 @@ def setup_hamiltonian(systems: Sequence[SystemInput] | SystemInput, options: Opt
     descs = (SystemDesc * len(systems))()
     for i, s in enumerate(systems):
         h1 = np.ascontiguousarray(s.h1, np.float64)
-        chol = np.ascontiguousarray(s.chol, np.float64)
         trial = np.ascontiguousarray(s.trial, np.float64)
         m = h1.shape[0]
-        if h1.shape != (m, m) or chol.ndim != 3 or chol.shape[1:] != (m, m) \
-                or trial.shape != (m, s.nalpha + s.nbeta):
+        gen = s.chol if isinstance(s.chol, CholGen) else None
+        if gen is None:
+            chol = np.ascontiguousarray(s.chol, np.float64)
+            if chol.ndim != 3 or chol.shape[1:] != (m, m):
+                raise ValueError(f"system {i}: inconsistent array shapes")
+            keep.append(chol)
+        if h1.shape != (m, m) or trial.shape != (m, s.nalpha + s.nbeta):
             raise ValueError(f"system {i}: inconsistent array shapes")
-        keep += [h1, chol, trial]
-        descs[i] = SystemDesc(m, s.nalpha, s.nbeta, chol.shape[0], s.nwalkers,
-                              h1.ctypes.data, chol.ctypes.data, float(s.ecore), trial.ctypes.data, float(s.dt))
+        keep += [h1, trial]
+        descs[i] = SystemDesc(m, s.nalpha, s.nbeta, s.nchol, s.nwalkers, h1.ctypes.data,
+                              None if gen else chol.ctypes.data, float(s.ecore), trial.ctypes.data, float(s.dt),
+                              1 if gen else 0, 0, gen.seed if gen else 0, gen.tau if gen else 0.0,
+                              gen.scale if gen else 0.0)
     opt = options if options is not None else default_options()
     handle = ctypes.c_void_p()
     st = _stream_handle(stream) if stream is not False else 0

@@ -187,6 +187,8 @@ hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, 
 hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
 hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
 hipError_t launch_pack_upper(const System &s, hipStream_t st);
+// the synthetic Cholesky tensor of the counter recipe (see afqmc_system_desc)
+hipError_t launch_gen_chol(const System &s, uint64_t seed, const double *fac, double root3, hipStream_t st);
 // dedicated Taylor-term kernel (k_taylor.hip)
 bool taylor_mfma_supported(int M, int Nt);
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,

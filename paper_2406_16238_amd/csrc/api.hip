@@ -123,6 +123,16 @@ void free_all(afqmc_ctx *c) {
   c->allocs.clear();
 }
 
+// Frees one allocation of the context (the device must be done with it).
+void free_one(afqmc_ctx *c, void *p) {
+  for (size_t i = 0; i < c->allocs.size(); ++i)
+    if (c->allocs[i] == p) {
+      (void)hipFree(p);
+      c->allocs.erase(c->allocs.begin() + (long)i);
+      return;
+    }
+}
+
 // Releases everything the context holds (after the device has finished with it).
 void release(afqmc_ctx *c) {
   (void)hipDeviceSynchronize();
@@ -181,7 +191,15 @@ struct Temps {
 };
 
 bool valid_desc(const afqmc_system_desc &d, std::string &why) {
-  if (!d.h1 || !d.chol || !d.trial) { why = "h1, chol and trial must be non-NULL host pointers"; return false; }
+  if (d.chol_gen != 0 && d.chol_gen != 1) { why = "chol_gen must be 0 or 1"; return false; }
+  if (!d.h1 || !d.trial || (d.chol_gen == 0 && !d.chol)) {
+    why = "h1, trial and (unless chol_gen = 1) chol must be non-NULL host pointers";
+    return false;
+  }
+  if (d.chol_gen == 1 && !(d.gen_tau > 0.0 && std::isfinite(d.gen_tau) && std::isfinite(d.gen_scale))) {
+    why = "gen_tau must be positive and finite, gen_scale finite";
+    return false;
+  }
   if (d.nbasis <= 0 || d.nchol <= 0 || d.nwalkers <= 0) { why = "nbasis, nchol and nwalkers must be positive"; return false; }
   if (d.nalpha < 0 || d.nbeta < 0 || d.nalpha + d.nbeta <= 0) { why = "need at least one electron"; return false; }
   if (d.nalpha > d.nbasis || d.nbeta > d.nbasis) { why = "more electrons of one spin than orbitals"; return false; }
@@ -458,7 +476,18 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   if (s.precision != AFQMC_FP64) AFQMC_HIP(lp_enable_lds(s), "reduced-precision exchange LDS attribute");
 
   const size_t mm = M * M;
-  AFQMC_HIP(hipMemcpyAsync(s.L, d.chol, p.L * sizeof(double), hipMemcpyHostToDevice, st), "upload chol");
+  if (d.chol_gen == 1) {
+    std::vector<double> fac(G);
+    for (size_t g = 0; g < G; ++g) fac[g] = std::exp(-(double)g / d.gen_tau) * d.gen_scale;
+    double *dfac = nullptr;
+    Temps gt;
+    gt.st = st;
+    if (!gt.get(&dfac, G)) return fail(AFQMC_ERR_OOM, "device allocation failed (generator factors)");
+    AFQMC_HIP(hipMemcpyAsync(dfac, fac.data(), G * sizeof(double), hipMemcpyHostToDevice, st), "upload factors");
+    AFQMC_HIP(launch_gen_chol(s, d.gen_seed, dfac, std::sqrt(3.0), st), "Cholesky generator");
+  } else {
+    AFQMC_HIP(hipMemcpyAsync(s.L, d.chol, p.L * sizeof(double), hipMemcpyHostToDevice, st), "upload chol");
+  }
   if (s.Lp) AFQMC_HIP(launch_pack_upper(s, st), "Cholesky packing");
   AFQMC_HIP(hipMemcpyAsync(s.trial, d.trial, p.trial * sizeof(double), hipMemcpyHostToDevice, st),
             "upload trial");
@@ -786,6 +815,15 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     afqmc_status r = setup_one(c, sys[i], c->sys[i], st, &used, o.mem_limit_bytes);
     System &sy = c->sys[i];
     if (r == AFQMC_OK && c->tune && sy.ex_mfma) r = tune_exchange(sy, st);
+    if (r == AFQMC_OK && sy.Lp && sy.L) {
+      // after set-up only the packed triangles are read: give the full tensor back
+      if (hipStreamSynchronize(st) != hipSuccess) r = fail(AFQMC_ERR_HIP, "set-up failed on the device");
+      else {
+        free_one(c, sy.L);
+        sy.L = nullptr;
+        sy.bytes -= 8ull * sy.G * sy.M * sy.M;
+      }
+    }
     if (r != AFQMC_OK) {
       (void)hipStreamSynchronize(st);
       release(c);

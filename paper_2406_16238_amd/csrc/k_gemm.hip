@@ -170,6 +170,37 @@ __global__ __launch_bounds__(kThreads) void k_unpack_symmetric(const double *__r
   }
 }
 
+// Synthetic Cholesky vectors by counters (the input recipe documented with
+// afqmc_system_desc): every element from four SplitMix64 outputs, so the
+// tensor needs no host memory and equals its host twin bit for bit.
+__global__ void k_gen_chol(double *__restrict__ L, int M, unsigned long long seed, const double *__restrict__ fac,
+                           double root3) {
+  const int p = blockIdx.x, g = blockIdx.y;
+  const unsigned long long golden = 0x9E3779B97F4A7C15ull;
+  for (int q = p + threadIdx.x; q < M; q += blockDim.x) {
+    const unsigned long long i = ((unsigned long long)g * M + p) * M + q;
+    double u[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      unsigned long long z = seed + (4 * i + r + 1) * golden;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z ^= z >> 31;
+      u[r] = (double)(z >> 11) * 0x1p-53;
+    }
+    const double zsum = ((u[0] + u[1]) + u[2]) + u[3] - 2.0;
+    const double v = (zsum * root3) * fac[g];
+    L[((size_t)g * M + p) * M + q] = v;
+    L[((size_t)g * M + q) * M + p] = v;
+  }
+}
+
+hipError_t launch_gen_chol(const System &s, uint64_t seed, const double *fac, double root3, hipStream_t st) {
+  hipLaunchKernelGGL(k_gen_chol, dim3(s.M, s.G), dim3(kThreads), 0, st, s.L, s.M, (unsigned long long)seed, fac,
+                     root3);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_upper(const System &s, hipStream_t st) {
   hipLaunchKernelGGL(k_pack_upper, dim3(s.M, s.G), dim3(kThreads), 0, st, s.L, s.M, s.Lp);
   return hipGetLastError();

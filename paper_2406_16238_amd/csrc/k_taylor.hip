@@ -16,7 +16,7 @@
 // groups of one 16-column group).  The contraction is staged 16 indices at a
 // time in LDS (k-major, padded rows) with 16-byte global loads, double-buffered
 // through registers.  M must be even (16-byte loads of A never straddle the two
-// planes); other shapes use the generic GEMM.
+// planes) and Nt at most 96; other shapes use the generic GEMM.
 #include "afqmc_internal.h"
 #include "device_util.h"
 
@@ -174,7 +174,7 @@ hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double
 }
 }  // namespace
 
-bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <= 80; }
+bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <= 96; }
 
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
                               hipStream_t st) {
@@ -182,7 +182,8 @@ hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout
   if (s.Nt <= 32) return run_taylor<16, 2>(s, tin, tout, alpha, W, st);
   if (s.Nt <= 48) return run_taylor<12, 3>(s, tin, tout, alpha, W, st);
   if (s.Nt <= 64) return run_taylor<12, 4>(s, tin, tout, alpha, W, st);
-  return run_taylor<10, 5>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 80) return run_taylor<10, 5>(s, tin, tout, alpha, W, st);
+  return run_taylor<8, 6>(s, tin, tout, alpha, W, st);
 }
 
 }  // namespace afqmc

@@ -57,6 +57,7 @@ def _desc(m=6, na=2, nb=2, g=4, w=3, dt=0.01):
     ("nbasis", 0, A.ERR_ARG), ("nchol", -1, A.ERR_ARG), ("nwalkers", 0, A.ERR_ARG),
     ("nalpha", 7, A.ERR_ARG), ("dt", 0.0, A.ERR_ARG), ("dt", float("nan"), A.ERR_ARG),
     ("ecore", float("inf"), A.ERR_ARG), ("h1", None, A.ERR_ARG), ("trial", None, A.ERR_ARG),
+    ("chol", None, A.ERR_ARG), ("chol_gen", 2, A.ERR_ARG),
 ])
 def test_setup_rejects_bad_descriptions(lib, field, value, status):
     d, keep = _desc()
@@ -66,6 +67,14 @@ def test_setup_rejects_bad_descriptions(lib, field, value, status):
     assert r == status
     assert out.value is None
     assert len(A.last_error()) > 0
+
+
+def test_setup_rejects_bad_generator(lib):
+    for tau, scale in ((0.0, 1.0), (float("nan"), 1.0), (1.0, float("inf"))):
+        d, keep = _desc()
+        d.chol, d.chol_gen, d.gen_tau, d.gen_scale = None, 1, tau, scale
+        out = ctypes.c_void_p()
+        assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, None, None, ctypes.byref(out)) == A.ERR_ARG
 
 
 def test_setup_rejects_wide_spin_blocks(lib):
@@ -116,7 +125,8 @@ def test_struct_layouts_match_header(tmp_path):
     """ctypes layouts equal what a C compiler makes of include/afqmc.h."""
     import subprocess
     fields = {"afqmc_system_desc": (A.SystemDesc, ["nbasis", "nalpha", "nbeta", "nchol", "nwalkers", "h1", "chol",
-                                                   "ecore", "trial", "dt"]),
+                                                   "ecore", "trial", "dt", "chol_gen", "reserved_desc", "gen_seed",
+                                                   "gen_tau", "gen_scale"]),
               "afqmc_options": (A.Options, ["precision", "taylor_order", "fb_cap", "e_shift", "mem_limit_bytes",
                                             "streams", "use_graph", "tune", "ex_mode", "cv_fraction", "cv_seed",
                                             "reserved"]),

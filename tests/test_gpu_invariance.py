@@ -118,3 +118,30 @@ def test_packed_cholesky_vhs_is_bitwise_the_full_product():
             ctx.close()
     for a, b, name in zip(outs[0], outs[1], ("phi", "weight", "log_ovlp", "flags", "energies")):
         assert a.tobytes() == b.tobytes(), name
+
+
+def test_device_generated_cholesky_equals_host_twin():
+    """chol_gen = 1 (the library draws the counter recipe's L on the device)
+    gives the same trajectory, bit for bit, as the host-drawn twin array."""
+    A, torch = _lib()
+    spec = gi.SystemSpec(60, 6, 5, 240, tau=45.0, seed=5, recipe="counter")
+    Wg = 24
+    h1, chol, ecore, trial = gi.make_system(spec)
+    gen = A.CholGen(spec.nchol, spec.seed, spec.tau, spec.scale_factor())
+    outs = []
+    for src in (chol, gen):
+        ctx = A.setup_hamiltonian(A.SystemInput(h1, src, ecore, trial, spec.nalpha, spec.nbeta, Wg, 0.005))
+        try:
+            info = A.get_info(ctx, 0)
+            w = A.Walkers.from_numpy(gi.initial_walkers(trial, Wg, noise=0.05, seed=6))
+            A.overlap(ctx, w)
+            e = torch.empty((Wg, 3), dtype=torch.complex128, device="cuda")
+            fs = gi.FieldStream(8, Wg, spec.nchol)
+            for k in range(1, 7):
+                A.step(ctx, w, torch.as_tensor(fs.next(), device="cuda"), e, reortho=(k == 5))
+            torch.cuda.synchronize()
+            outs.append(_host(w, e) + [np.array([info.e_hf, info.const_c])])
+        finally:
+            ctx.close()
+    for a, b, name in zip(outs[0], outs[1], ("phi", "weight", "log_ovlp", "flags", "energies", "scalars")):
+        assert a.tobytes() == b.tobytes(), name

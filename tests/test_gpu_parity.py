@@ -168,6 +168,37 @@ def test_tiled_sizes_parity():
         p.close()
 
 
+WIDE = gi.SystemSpec(96, 42, 41, 192, tau=70.0, seed=13)  # 48-row padded spin blocks, 83 columns
+
+
+@pytest.mark.parametrize("api", ["separate", "step"])
+def test_wide_spin_blocks_parity(api):
+    """N = 42 + 41 (the benzene-scale electron count): padded spin blocks of 48
+    rows in the exchange and the widest Taylor tile, against the oracle."""
+    p = Pair(WIDE, 9, 0.005)
+    try:
+        phis = gi.initial_walkers(p.trial, 9, noise=0.02, seed=4)
+        if api == "separate":
+            worst, g, o = run_both(p, 3, phis, reortho_every=2)
+            assert worst["e"] < TOL and worst["w"] < TOL and worst["logo"] < TOL and worst["phi"] < TOL, worst
+            return
+        fields = gi.FieldStream(0, 9, WIDE.nchol)
+        w = p.walkers(phis)
+        e = p.torch.empty((9, 3), dtype=p.torch.complex128, device="cuda")
+        ophi, ow, ologo = phis.copy(), np.ones(9), O.initial_logo(p.ham, phis)
+        for step in range(1, 4):
+            x = fields.next()
+            p.A.step(p.ctx, w, p.torch.as_tensor(x, device="cuda"), e, reortho=(step == 2))
+            ophi, ow, ologo, _ = O.propagate(p.ham, ophi, ow, ologo, x)
+            if step == 2:
+                ophi, ologo = O.reorthogonalize(p.ham, ophi, ologo)
+        gphi, gw, glogo, _ = p.to_host(w)
+        assert cmp_rel(e.cpu().numpy(), O.local_energies(p.ham, ophi)) < TOL
+        assert cmp_rel(gw, ow) < TOL and cmp_rel(gphi, ophi, np.abs(ophi).max()) < TOL
+    finally:
+        p.close()
+
+
 def test_deterministic_replay(small):
     outs = []
     for _ in range(2):

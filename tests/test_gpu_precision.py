@@ -37,7 +37,8 @@ def energies(p, ctx, phis):
 
 @pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("spec,W", [(gi.SMALL.system, 10), (gi.SystemSpec(100, 10, 10, 200, tau=75.0, seed=11), 70),
-                                    (gi.HEADLINE.system, 256)], ids=["small", "tiled", "headline"])
+                                    (gi.SystemSpec(96, 42, 41, 192, tau=70.0, seed=13), 9),
+                                    (gi.HEADLINE.system, 256)], ids=["small", "tiled", "wide", "headline"])
 def test_energy_error_on_identical_walkers(form, spec, W):
     p = Pair(spec, W, 0.005)
     ctx = ctx_for(p, FORMS[form])

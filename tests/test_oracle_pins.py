@@ -357,3 +357,23 @@ def test_generator_recipe():
     assert np.allclose(trial[:, :4].T @ trial[:, :4], np.eye(4), atol=1e-12)
     assert gi.batching_walker_counts() == [428, 102, 144, 170, 145, 423, 454, 325,
                                            81, 106, 213, 258, 342, 279, 182, 135]
+
+
+def test_counter_recipe_generator():
+    """The counter recipe's Cholesky vectors: symmetric, standardised bracket of
+    mean 0 and variance 1, scaled by exp(-g/tau) * scale, the same entries
+    whatever subset of vectors is drawn, and SplitMix64's published first output."""
+    import math
+    m, g, tau, scale = 30, 40, 12.0, 1.0 / 30
+    L = gi.make_chol_counter(11, m, g, tau, scale)
+    assert np.array_equal(L, L.transpose(0, 2, 1))
+    z = np.concatenate([L[k][np.triu_indices(m)] / (math.exp(-k / tau) * scale) for k in range(g)])
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 1.0) < 0.02 and np.abs(z).max() <= 2 * math.sqrt(3) + 1e-12
+    sub = gi.make_chol_counter(11, m, g, tau, scale, gammas=[3, 17])
+    assert np.array_equal(sub[0], L[3]) and np.array_equal(sub[1], L[17])
+    assert int(gi.splitmix64_outputs(0, np.array([0], dtype=np.uint64))[0]) == 0xE220A8397B1DCDAF
+    spec = gi.SystemSpec(m, 3, 3, g, tau=tau, seed=11, recipe="counter")
+    h1, chol, ecore, trial = gi.make_system(spec)
+    assert np.array_equal(chol, L)
+    h1b, ecb, trb = gi.make_system_without_chol(spec)
+    assert np.array_equal(h1, h1b) and np.array_equal(trial, trb)
