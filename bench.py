@@ -82,8 +82,8 @@ def parse_args(argv=None):
     ap.add_argument("--cv-system", default="headline", choices=["headline", "benzene"],
                     help="cv: the headline shape, or M=1512, N=42+42, 6000 Cholesky vectors, 64 walkers with the "
                          "Cholesky tensor drawn on the device")
-    ap.add_argument("--cpu-walkers", type=int, default=16, help="walkers in the CPU oracle sample")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="steps in the CPU oracle sample")
+    ap.add_argument("--cpu-walkers", type=int, default=32, help="walkers in the CPU oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=6, help="steps in the CPU oracle sample")
     ap.add_argument("--phases", action="store_true", help="print the per-phase tables to stderr")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the run, copy a device buffer of this many MiB (a plain copy kernel of known "

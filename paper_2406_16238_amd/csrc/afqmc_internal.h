@@ -67,6 +67,7 @@ struct System {
   bool use_mfma_gemm = true;   // MFMA kernels for force bias, V_HS, B1 and Taylor terms
   bool taylor_kernel = true;   // the dedicated Taylor-term kernel (else the generic MFMA GEMM)
   int vhs_variant = 0;         // tile shape of the V_HS GEMM
+  int taylor_variant = 0;      // tile shape of the Taylor-term kernel
   bool pack_chol = true;       // V_HS from the packed upper triangles of the L^g
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans

@@ -43,6 +43,7 @@ struct afqmc_ctx {
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   int debug_bits = 0;                // reserved[0]
   int vhs_variant = 0;               // reserved[3]: tile shape of the V_HS GEMM (0 = default, 1..4 others)
+  int taylor_variant = 0;            // reserved[4]: tile shape of the Taylor kernel (0 = default, 1..4 others)
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
   int ex_group = 8;                  // exchange tile order (reserved[2]: 1 = plain, g > 1 = groups of g)
   bool ex_wx_forced = false;         // launch shape fixed by the caller: no tuning
@@ -408,6 +409,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   s.use_mfma_gemm = !c->force_valu_gemm;
   s.taylor_kernel = !(c->debug_bits & 4);
   s.vhs_variant = c->vhs_variant;
+  s.taylor_variant = c->taylor_variant;
   s.pack_chol = s.use_mfma_gemm && !(c->debug_bits & 8);
   s.precision = c->opt.precision;
   s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
@@ -797,6 +799,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   c->debug_bits = o.reserved[0];
   if (o.reserved[3] >= 0 && o.reserved[3] <= 4) c->vhs_variant = o.reserved[3];
+  if (o.reserved[4] >= 0 && o.reserved[4] <= 4) c->taylor_variant = o.reserved[4];
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
     c->ex_wx = o.reserved[1];
     c->ex_wx_forced = true;

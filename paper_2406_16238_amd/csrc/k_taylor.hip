@@ -6,8 +6,8 @@
 // c = (j, re/im) interleaved, contraction over the two planes times q,
 //   [Re A | Im A] (M x 2M)  x  [T ; iT] (2M x 2Nt),   iT = (-Im T, Re T).
 //
-// A workgroup owns BM = 8 TR rows and all BN = 32 TN >= 2 Nt columns of one
-// walker, on a 2 x 2 grid of waves (4 TR rows x 16 TN columns each), so the
+// A workgroup owns BM = 4 WM TR rows and all BN = 16 WN TN >= 2 Nt columns of
+// one walker, on a WM x WN grid of waves (4 TR rows x 16 TN columns each), so the
 // walker's A rows are read from memory exactly once and its T (M x Nt, 16 M Nt
 // bytes) is shared by the M / BM row tiles, which the launch order places on
 // one XCD.  Each wave issues TR x TN v_mfma_f64_4x4x4_4b_f64 per 4 contraction
@@ -26,16 +26,17 @@ namespace {
 constexpr int TKC = 16;  // contraction indices per LDS stage
 }
 
-template <int TR, int TN>
-__global__ __launch_bounds__(kThreads) void k_taylor_mfma(const double *__restrict__ vhs,
-                                                         const double2 *__restrict__ tin, double2 *__restrict__ tout,
-                                                         double2 *__restrict__ tacc, int M, int Nt, int W, int nrt,
-                                                         double alpha) {
-  constexpr int BM = 8 * TR, BN = 32 * TN;
+template <int WM, int WN, int TR, int TN>
+__global__ __launch_bounds__(64 * WM * WN) void k_taylor_mfma(const double *__restrict__ vhs,
+                                                             const double2 *__restrict__ tin,
+                                                             double2 *__restrict__ tout, double2 *__restrict__ tacc,
+                                                             int M, int Nt, int W, int nrt, double alpha) {
+  constexpr int NTH = 64 * WM * WN;
+  constexpr int BM = WM * 4 * TR, BN = WN * 16 * TN;
   constexpr int LDA = BM + 1, LDB = BN + 1;
   constexpr int AV = BM * TKC / 2;                 // double2 of A per stage
   constexpr int BV = TKC * BN / 2;                 // double2 of B per stage
-  constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
+  constexpr int APT = (AV + NTH - 1) / NTH, BPT = (BV + NTH - 1) / NTH;
   extern __shared__ double tsm[];
   double *sA = tsm;                    // [2][TKC][LDA]
   double *sB = tsm + 2 * TKC * LDA;    // [2][TKC][LDB]
@@ -54,14 +55,14 @@ __global__ __launch_bounds__(kThreads) void k_taylor_mfma(const double *__restri
   const int K = 2 * M, cols = 2 * Nt;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
+  const int wm = wv / WN, wn = wv - (wv / WN) * WN;
   const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
 
   double2 ra[APT], rb[BPT];
   auto load = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * kThreads;            // (row, k pair)
+      const int e = tid + r * NTH;                 // (row, k pair)
       const int row = e / (TKC / 2), kp = e - row * (TKC / 2);
       const int gi = i0 + row, gk = k0 + 2 * kp;
       ra[r] = (e < AV && gi < M && gk < K)
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_taylor_mfma(const double *__restri
     }
 #pragma unroll
     for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * kThreads;            // (k, complex column j)
+      const int e = tid + r * NTH;                 // (k, complex column j)
       const int kk = e / (BN / 2), j = e - kk * (BN / 2);
       const int gk = k0 + kk;
       double2 v = make_double2(0.0, 0.0);
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void k_taylor_mfma(const double *__restri
     double *b = sB + buf * TKC * LDB;
 #pragma unroll
     for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * kThreads;
+      const int e = tid + r * NTH;
       if (e < AV) {
         const int row = e / (TKC / 2), kp = e - row * (TKC / 2);
         a[(2 * kp) * LDA + row] = ra[r].x;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void k_taylor_mfma(const double *__restri
     }
 #pragma unroll
     for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * kThreads;
+      const int e = tid + r * NTH;
       if (e < BV) {
         const int kk = e / (BN / 2), j = e - kk * (BN / 2);
         b[kk * LDB + 2 * j] = rb[r].x;
@@ -155,11 +156,12 @@ __global__ __launch_bounds__(kThreads) void k_taylor_mfma(const double *__restri
 }
 
 namespace {
-template <int TR, int TN>
+template <int WM, int WN, int TR, int TN>
 hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
-  constexpr int BM = 8 * TR, BN = 32 * TN;
+  constexpr int BM = WM * 4 * TR, BN = WN * 16 * TN;
+  static_assert(BN >= 2, "columns");
   const size_t lds = 2ull * TKC * ((BM + 1) + (BN + 1)) * sizeof(double);
-  auto k = k_taylor_mfma<TR, TN>;
+  auto k = k_taylor_mfma<WM, WN, TR, TN>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -168,8 +170,8 @@ hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double
     attr = true;
   }
   const int nrt = (s.M + BM - 1) / BM;
-  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(kThreads), lds, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt, W,
-                     nrt, alpha);
+  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * WM * WN), lds, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt,
+                     W, nrt, alpha);
   return hipGetLastError();
 }
 }  // namespace
@@ -178,12 +180,20 @@ bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <
 
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
                               hipStream_t st) {
-  if (s.Nt <= 16) return run_taylor<16, 1>(s, tin, tout, alpha, W, st);
-  if (s.Nt <= 32) return run_taylor<16, 2>(s, tin, tout, alpha, W, st);
-  if (s.Nt <= 48) return run_taylor<12, 3>(s, tin, tout, alpha, W, st);
-  if (s.Nt <= 64) return run_taylor<12, 4>(s, tin, tout, alpha, W, st);
-  if (s.Nt <= 80) return run_taylor<10, 5>(s, tin, tout, alpha, W, st);
-  return run_taylor<8, 6>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 16) return run_taylor<2, 2, 16, 1>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 32) return run_taylor<2, 2, 16, 2>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 48) return run_taylor<2, 2, 12, 3>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 64) return run_taylor<2, 2, 12, 4>(s, tin, tout, alpha, W, st);
+  if (s.Nt <= 80) {
+    switch (s.taylor_variant) {
+      case 1: return run_taylor<2, 1, 10, 10>(s, tin, tout, alpha, W, st);
+      case 2: return run_taylor<1, 2, 20, 5>(s, tin, tout, alpha, W, st);
+      case 3: return run_taylor<2, 2, 20, 5>(s, tin, tout, alpha, W, st);
+      case 4: return run_taylor<4, 1, 5, 10>(s, tin, tout, alpha, W, st);
+      default: return run_taylor<2, 2, 10, 5>(s, tin, tout, alpha, W, st);
+    }
+  }
+  return run_taylor<2, 2, 8, 6>(s, tin, tout, alpha, W, st);
 }
 
 }  // namespace afqmc
