@@ -309,6 +309,25 @@ afqmc_status afqmc_cv_loss_grad(afqmc_ctx *ctx, int32_t isys, const float *x, co
 afqmc_status afqmc_cv_state(afqmc_ctx *ctx, int32_t isys, void *f_out, int32_t *subset_out, uint64_t *call_out,
                             void *hip_stream);
 
+/*
+ * Population control (the driver step of Sec. 3.1 that keeps the walker
+ * weights from spreading; the paper does not fix the method, this is the comb
+ * of Calandra Buonaura and Sorella): with cumulative weights C_i summed in
+ * walker order and total Wt, W teeth at (u + k) Wt / W for k = 0..W-1; new
+ * walker k is a copy (orbitals, log-overlap, flags) of the first walker i with
+ * C_i > tooth k, and every weight becomes Wt / W.  Zero-weight walkers are never
+ * copied; with Wt = 0 nothing changes.  `u`: nsys device pointers to one double
+ * in [0, 1) each.  `parents_out`: NULL, or nsys device int32 [W] receiving the
+ * parent of each new walker.  Cached Theta/vbias of afqmc_step are dropped.
+ */
+afqmc_status afqmc_population_control(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *u,
+                                      int32_t *const *parents_out, void *hip_stream);
+
+/* Sets E_T (the energy shift of the weight update, eq. weight_update) of
+ * system `isys`, e.g. for feedback from the running estimate; drops recorded
+ * step graphs (they hold the old factor).  Synchronises the device. */
+afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift);
+
 /* Set-up scalars of system `isys`.  AFQMC_ERR_ARG on NULL or bad index. */
 afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out);
 

@@ -44,6 +44,8 @@ R9  Re-orthogonalisation: modified Gram-Schmidt per spin block with positive
 R10 The overlap is carried as a complex logarithm; S is formed from the
     logarithms of the walker's overlap before and after the step, both
     recomputed from the determinants.
+R11 Population control (named, not specified): a comb over the cumulative
+    weights with one uniform offset; every new walker carries the mean weight.
 """
 from __future__ import annotations
 
@@ -330,6 +332,32 @@ def reorthogonalize(ham: OracleHamiltonian, phis, logos):
             phis[w][:, sl] = q
             logos[w] -= np.sum(np.log(np.diag(r).real))
     return phis, logos
+
+
+# ---- population control ----------------------------------------------------------
+
+def comb(weights, u: float):
+    """Population control by a comb (the paper names population control among the
+    driver's steps, Sec. 3.1, without fixing the method; reading R11: the comb of
+    Calandra Buonaura and Sorella, 1998).  With cumulative weights C_i (summed in
+    walker order) and total Wt, W teeth sit at (u + k) Wt / W, k = 0..W-1, for one
+    uniform u in [0, 1); tooth k selects the first walker i with C_i > tooth.
+    Returns the parent of every new walker and the new weights, all Wt / W."""
+    w = np.asarray(weights, dtype=float)
+    W = len(w)
+    c = np.cumsum(w)
+    total = c[-1]
+    if not total > 0.0:
+        return np.arange(W), w.copy()
+    step = total / W
+    parents = np.empty(W, dtype=int)
+    i = 0
+    for k in range(W):
+        tooth = (u + k) * step
+        while i < W - 1 and c[i] <= tooth:
+            i += 1
+        parents[k] = i
+    return parents, np.full(W, step)
 
 
 # ---- driver ----------------------------------------------------------------------

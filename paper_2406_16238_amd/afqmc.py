@@ -79,7 +79,8 @@ EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate"
            "afqmc_greens_function", "afqmc_force_bias", "afqmc_get_info",
            "afqmc_set_timing", "afqmc_get_timings", "afqmc_destroy", "afqmc_last_error",
            "afqmc_cv_collect", "afqmc_cv_train", "afqmc_cv_set_params", "afqmc_cv_get_params",
-           "afqmc_cv_predict", "afqmc_cv_loss_grad", "afqmc_cv_state")
+           "afqmc_cv_predict", "afqmc_cv_loss_grad", "afqmc_cv_state", "afqmc_population_control",
+           "afqmc_set_e_shift")
 CV_NFEAT, CV_NPARAMS, CV_NNORM = 8, 17922, 20
 
 _lib = None
@@ -120,6 +121,8 @@ def load_library() -> ctypes.CDLL:
         "afqmc_cv_predict": ([P, ctypes.c_int32, P, ctypes.c_int64, P, P], ctypes.c_int),
         "afqmc_cv_loss_grad": ([P, ctypes.c_int32, P, P, ctypes.c_int64, P, P, P], ctypes.c_int),
         "afqmc_cv_state": ([P, ctypes.c_int32, P, P, P, P], ctypes.c_int),
+        "afqmc_population_control": ([P, ctypes.POINTER(CWalkers), pp, pp, P], ctypes.c_int),
+        "afqmc_set_e_shift": ([P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -389,6 +392,22 @@ def get_timings(ctx: Context) -> dict:
 
 def destroy(ctx: Context):
     ctx.close()
+
+
+def population_control(ctx: Context, walkers, u, parents_out=None, stream=None):
+    """afqmc_population_control: comb resampling; u float64 [1] per system (device), in [0, 1)."""
+    import torch
+    w = _walker_array(ctx, walkers)
+    us = _ptr_array(ctx, u, [(1,)] * ctx.nsys, torch.float64)
+    ps = None
+    if parents_out is not None:
+        ps = _ptr_array(ctx, parents_out, [(s.nwalkers,) for s in ctx.systems], torch.int32)
+    _check(load_library().afqmc_population_control(ctx.handle, w, us, ps, _stream_handle(stream)))
+
+
+def set_e_shift(ctx: Context, e_shift: float, isys: int = 0):
+    """afqmc_set_e_shift: the energy shift E_T of the weight update."""
+    _check(load_library().afqmc_set_e_shift(ctx.handle, isys, float(e_shift)))
 
 
 # ---- learned control variate ---------------------------------------------------------

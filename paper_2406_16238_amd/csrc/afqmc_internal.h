@@ -188,6 +188,9 @@ hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, 
 hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
 hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
 hipError_t launch_pack_upper(const System &s, hipStream_t st);
+// comb population control (k_popctl.hip); parents_out may be NULL
+hipError_t launch_comb(const System &s, double *weight, double2 *phi, double2 *logo, uint32_t *flags, const double *u,
+                       int *parents_out, hipStream_t st);
 // the synthetic Cholesky tensor of the counter recipe (see afqmc_system_desc)
 hipError_t launch_gen_chol(const System &s, uint64_t seed, const double *fac, double root3, hipStream_t st);
 // dedicated Taylor-term kernel (k_taylor.hip)

@@ -1327,6 +1327,36 @@ afqmc_status afqmc_cv_state(afqmc_ctx *ctx, int32_t isys, void *f_out, int32_t *
   return AFQMC_OK;
 }
 
+afqmc_status afqmc_population_control(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *u,
+                                      int32_t *const *parents_out, void *hip_stream) {
+  if (!ctx || !w || !u) return fail(AFQMC_ERR_ARG, "NULL context, walkers or offsets");
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+    if (!u[i]) return fail(AFQMC_ERR_ARG, "offset of system " + std::to_string(i) + " is NULL");
+  }
+  invalidate_caches(ctx);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
+    System &s = ctx->sys[i];
+    AFQMC_HIP(launch_comb(s, w[i].weight, static_cast<double2 *>(w[i].phi), static_cast<double2 *>(w[i].log_ovlp),
+                          w[i].flags, u[i], parents_out ? parents_out[i] : nullptr, ls),
+              "population control kernels");
+    return AFQMC_OK;
+  });
+}
+
+afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift) {
+  if (!ctx || isys < 0 || isys >= (int)ctx->sys.size()) return fail(AFQMC_ERR_ARG, "NULL context or bad index");
+  if (!std::isfinite(e_shift)) return fail(AFQMC_ERR_ARG, "e_shift must be finite");
+  ctx->sys[isys].e_shift = e_shift;
+  // recorded steps hold the old weight factor
+  (void)hipDeviceSynchronize();
+  for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+  return AFQMC_OK;
+}
+
 afqmc_status afqmc_set_timing(afqmc_ctx *ctx, int32_t enable) {
   if (!ctx) return fail(AFQMC_ERR_ARG, "NULL context");
   fold_timings(ctx);

@@ -118,6 +118,8 @@ def test_step_calls_reject_null_context(lib):
     assert lib.afqmc_cv_predict(None, 0, None, 1, None, None) == A.ERR_ARG
     assert lib.afqmc_cv_loss_grad(None, 0, None, None, 1, None, None, None) == A.ERR_ARG
     assert lib.afqmc_cv_state(None, 0, None, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_population_control(None, None, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_set_e_shift(None, 0, 0.0) == A.ERR_ARG
     lib.afqmc_destroy(None)  # no-op
 
 

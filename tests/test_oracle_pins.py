@@ -377,3 +377,25 @@ def test_counter_recipe_generator():
     assert np.array_equal(chol, L)
     h1b, ecb, trb = gi.make_system_without_chol(spec)
     assert np.array_equal(h1, h1b) and np.array_equal(trial, trb)
+
+
+def test_comb_population_control():
+    """The comb keeps W walkers and the total weight; each walker gets floor or
+    ceil of W w_i / Wt copies, zero-weight walkers none, and averaged over the
+    offset u the copies are exactly W w_i / Wt."""
+    rng = np.random.default_rng(8)
+    W = 37
+    w = rng.exponential(1.0, W)
+    w[[3, 11]] = 0.0
+    total = np.cumsum(w)[-1]
+    mean = np.zeros(W)
+    grid = (np.arange(4000) + 0.5) / 4000
+    for u in grid:
+        parents, nw = O.comb(w, u)
+        n = np.bincount(parents, minlength=W)
+        assert n.sum() == W and np.allclose(nw, total / W)
+        assert np.all(n >= np.floor(W * w / total) - 1e-12) and np.all(n <= np.ceil(W * w / total) + 1e-12)
+        assert n[3] == 0 and n[11] == 0
+        assert np.all(np.diff(parents) >= 0)
+        mean += n / len(grid)
+    assert np.max(np.abs(mean - W * w / total)) < 2e-3
