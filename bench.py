@@ -72,6 +72,8 @@ def parse_args(argv=None):
                          "(training on the path's own trajectory, then full exchange vs the 1/8 subset)")
     ap.add_argument("--precision", default="bf16x2", choices=["fp64", "fp32", "bf16x3", "bf16x2"],
                     help="path reported in the JSON line (the FP64 path is timed too, for the speed-up)")
+    ap.add_argument("--prop-precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the propagation (V_HS planes and Taylor terms) of the reported path")
     ap.add_argument("--api", default="step", choices=["step", "separate"],
                     help="step: afqmc_step (one overlap/LU and one force bias per step); separate: "
                          "afqmc_propagate + afqmc_reorthogonalize + afqmc_local_energy")
@@ -425,15 +427,20 @@ def main(argv=None):
     gen.manual_seed(spec.field_seed)
     xs = torch.randn((args.warmup + args.steps, W, G), dtype=torch.float64, device="cuda", generator=gen)
 
-    forms = ["fp64"] if args.precision == "fp64" else ["fp64", args.precision]
+    prop32 = args.prop_precision == "fp32"
+    rep_key = args.precision + ("+fp32prop" if prop32 else "")
+    forms = ["fp64"] if rep_key == "fp64" else ["fp64", rep_key]
     ctxs, runs = {}, {}
     for form in forms:
-        ctxs[form] = A.setup_hamiltonian(sysin, A.default_options(precision=PRECISION_CODE[form]))
+        opt = A.default_options(precision=PRECISION_CODE[args.precision if form == rep_key else "fp64"])
+        if form == rep_key and prop32:
+            opt.prop_precision = A.FP32_CONTRACT
+        ctxs[form] = A.setup_hamiltonian(sysin, opt)
         runs[form] = time_path(A, torch, ctxs[form], spec, trial, xs, args)
     del chol
 
     rep = args.precision
-    r = runs[rep]
+    r = runs[rep_key]
     ms_per_step = r["total_ms"] / args.steps
     value = W * args.steps / (r["total_ms"] * 1e-3)
     # one exchange launch = one spin block of every walker (the phase timer
@@ -455,24 +462,25 @@ def main(argv=None):
     out = {"metric": METRIC, "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if rep == "fp64" else f"{rep} (exchange, force bias) + f64 (rest)",
+           "dtype": ("f64" if rep == "fp64" else f"{rep} (exchange, force bias)") +
+                    (" + f32 (V_HS, Taylor terms)" if prop32 else "") + ("" if rep_key == "fp64" else " + f64 (rest)"),
            "data": "synthetic (seeded generator: random symmetric h and Cholesky vectors scaled by "
                    "exp(-g/tau)/M, trial = lowest orbitals of a Fock-like matrix, N(0,1) fields)",
            "config": {"workload": spec.name, "nbasis": M, "nalpha": s.nalpha, "nbeta": s.nbeta, "nchol": G,
                       "nwalkers": W, "dt": spec.dt, "reortho_every": spec.reortho_every,
-                      "precision": rep, "taylor_order": 6, "api": args.api},
+                      "precision": rep, "propagation": args.prop_precision, "taylor_order": 6, "api": args.api},
            "roofline": roofline,
            "step_algorithmic_tflops": round(step_tf, 3),
            "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
            "mixed_energy": round(r["mixed_energy"], 8), "walkers_flagged": r["flagged"]}
-    if rep != "fp64":
+    if rep_key != "fp64":
         f = runs["fp64"]
         fp64_value = W * args.steps / (f["total_ms"] * 1e-3)
         # energy error of the reduced form on identical walker states: its own
         # final walkers evaluated by both paths
         e_lp = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
         e_64 = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
-        A.local_energy(ctxs[rep], r["walkers"], e_lp)
+        A.local_energy(ctxs[rep_key], r["walkers"], e_lp)
         A.local_energy(ctxs["fp64"], r["walkers"], e_64)
         torch.cuda.synchronize()
         d = np.abs(e_lp.cpu().numpy()[:, 0] - e_64.cpu().numpy()[:, 0])
@@ -482,6 +490,8 @@ def main(argv=None):
                             "mixed_energy": round(f["mixed_energy"], 8)}
         out["energy_error_vs_fp64_ha"] = {"max": float(d.max()), "rms": float(np.sqrt((d ** 2).mean())),
                                           "bar": 1e-4, "within_bar": bool(d.max() <= 1e-4)}
+        # the same fields from the same walkers: the mixed estimators of the two trajectories
+        out["mixed_energy_difference_vs_fp64_ha"] = abs(r["mixed_energy"] - f["mixed_energy"])
     if args.phases:
         for form in forms:
             print(f"-- {form}", file=sys.stderr)

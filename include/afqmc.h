@@ -114,6 +114,12 @@ typedef struct {
                                is computed per call, k = ceil(cv_fraction W);
                                default 0.125, in (0, 1]                           */
   uint64_t cv_seed;         /* AFQMC_EX_CV: seed of the subset draws; default 7   */
+  int32_t prop_precision;   /* AFQMC_FP64 (default) or AFQMC_FP32_CONTRACT: V_HS
+                               planes and the Taylor terms of the propagation in
+                               FP32 (the series sum, B1, overlaps and energies
+                               stay FP64; the mixed precision the paper mentions
+                               in Sec. 6).  Needs M a multiple of 4, Nt <= 96.    */
+  int32_t reserved_opt;
   int32_t reserved[8];      /* reserved[0] bit 0: VALU (non-MFMA) exchange kernel;
                                bit 1: VALU kernels for the force bias, V_HS, B1
                                and Taylor products; bit 2: the generic MFMA GEMM
@@ -125,6 +131,8 @@ typedef struct {
                                either one fixes the launch shape (no tuning);
                                reserved[3]: tile shape of the V_HS product (0 =
                                default, 1..4 alternatives for comparison runs);
+                               reserved[4]: tile shape of the Taylor-term kernels
+                               (0 = default, 1..8 alternatives);
                                other entries: zero                                */
 } afqmc_options;
 

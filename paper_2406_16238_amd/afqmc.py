@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
                 ("fb_cap", ctypes.c_double), ("e_shift", ctypes.c_double),
                 ("mem_limit_bytes", ctypes.c_uint64), ("streams", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("tune", ctypes.c_int32), ("ex_mode", ctypes.c_int32), ("cv_fraction", ctypes.c_double),
-                ("cv_seed", ctypes.c_uint64), ("reserved", ctypes.c_int32 * 8)]
+                ("cv_seed", ctypes.c_uint64), ("prop_precision", ctypes.c_int32), ("reserved_opt", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class CWalkers(ctypes.Structure):

@@ -55,6 +55,10 @@ struct System {
   double *LtS[2] = {nullptr, nullptr};  // per spin [G][M][NR]: half-rotated, rows padded for the exchange
   double *Lp = nullptr;                 // [G][M(M+1)/2] packed upper triangles of the L^g
   double *vhsp = nullptr;               // [W][2][M(M+1)/2] packed V_HS planes
+  // FP32 propagation: V_HS planes and Taylor terms in single precision
+  bool prop32 = false;
+  float *vhs32 = nullptr;                // [W][2][M][M]
+  float2 *tA32 = nullptr, *tB32 = nullptr;  // [W][M][Nt]
   double2 *theta = nullptr, *fbpart = nullptr, *tA = nullptr, *tB = nullptr, *tacc = nullptr;
   double *yp = nullptr, *vhs = nullptr, *wsc = nullptr;
   double2 *logo_now = nullptr, *logo_new = nullptr, *e1 = nullptr, *ej = nullptr, *ekpart = nullptr;
@@ -111,6 +115,7 @@ struct Options {
   int ex_mode = AFQMC_EX_FULL;
   double cv_fraction = 0.125;
   uint64_t cv_seed = 7;
+  int prop_precision = AFQMC_FP64;
 };
 
 // ---- kernel launchers (each returns the hipGetLastError() of its launch) ----
@@ -188,6 +193,11 @@ hipError_t launch_axpby(const double *x, double a, double *y, double b, long n, 
 hipError_t launch_zero2(double2 *p, long n, hipStream_t st);
 hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
 hipError_t launch_pack_upper(const System &s, hipStream_t st);
+// FP32 propagation (k_taylor32.hip)
+bool prop32_supported(int M, int Nt);
+hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st);
+hipError_t launch_c128_to_c64(const double2 *in, long n, float2 *out, hipStream_t st);
+hipError_t launch_unpack_f32(const System &s, int W, hipStream_t st);
 // comb population control (k_popctl.hip); parents_out may be NULL
 hipError_t launch_comb(const System &s, double *weight, double2 *phi, double2 *logo, uint32_t *flags, const double *u,
                        int *parents_out, hipStream_t st);

@@ -43,7 +43,7 @@ struct afqmc_ctx {
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   int debug_bits = 0;                // reserved[0]
   int vhs_variant = 0;               // reserved[3]: tile shape of the V_HS GEMM (0 = default, 1..4 others)
-  int taylor_variant = 0;            // reserved[4]: tile shape of the Taylor kernel (0 = default, 1..4 others)
+  int taylor_variant = 0;            // reserved[4]: tile shape of the Taylor kernels (0 = default, others 1..8)
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
   int ex_group = 8;                  // exchange tile order (reserved[2]: 1 = plain, g > 1 = groups of g)
   bool ex_wx_forced = false;         // launch shape fixed by the caller: no tuning
@@ -212,10 +212,12 @@ bool valid_desc(const afqmc_system_desc &d, std::string &why) {
 // Sizes of every buffer of one system (doubles, double2s, uint32s).
 struct Plan {
   size_t L, LtT, htT, trial, B1, lmf, theta, fbpart, yp, vhs, tbuf, wsc, wvec2, ekpart, stat, LtS0, LtS1, Lp, vhsp;
+  size_t vhs32, t32;  // FP32 propagation: floats, complex floats
   size_t lp_bytes[2][2];  // reduced-precision operands per spin: [lhs, rhs] in bytes
   uint64_t bytes() const {
     return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc + LtS0 + LtS1 + Lp + vhsp) +
-           16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat + lp_bytes[0][0] +
+           16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat + 4ull * vhs32 + 16ull * t32 +
+           lp_bytes[0][0] +
            lp_bytes[0][1] + lp_bytes[1][0] + lp_bytes[1][1];
   }
 };
@@ -232,7 +234,9 @@ Plan plan_for(const System &s) {
   p.theta = W * M * Nt;
   p.fbpart = (size_t)std::max(s.fb_ksplit, 2) * W * G;
   p.yp = 2 * W * G;
-  p.vhs = 2 * W * M * M;
+  p.vhs = s.prop32 ? 0 : 2 * W * M * M;
+  p.vhs32 = s.prop32 ? 2 * W * M * M : 0;
+  p.t32 = s.prop32 ? W * M * Nt : 0;
   p.Lp = s.pack_chol ? G * (M * (M + 1) / 2) : 0;
   p.vhsp = s.pack_chol ? 2 * W * (M * (M + 1) / 2) : 0;
   p.tbuf = W * M * Nt;
@@ -411,6 +415,10 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   s.vhs_variant = c->vhs_variant;
   s.taylor_variant = c->taylor_variant;
   s.pack_chol = s.use_mfma_gemm && !(c->debug_bits & 8);
+  s.prop32 = c->opt.prop_precision == AFQMC_FP32_CONTRACT;
+  if (s.prop32 && !(s.pack_chol && prop32_supported(s.M, s.Nt)))
+    return fail(AFQMC_ERR_UNSUPPORTED, "FP32 propagation needs the MFMA path, M a multiple of 4 and at most 96 "
+                                       "electrons");
   s.precision = c->opt.precision;
   s.fb_ksplit = choose_fb_ksplit(s.W, s.G, (long)s.M * s.Nt);
   exchange_geometry(nmax, &s.ex_gb, &s.ex_lds);
@@ -441,7 +449,9 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   bool ok = dalloc(c, &s.L, p.L) && dalloc(c, &s.LtT, p.LtT) && dalloc(c, &s.htT, p.htT) &&
             dalloc(c, &s.trial, p.trial) && dalloc(c, &s.B1, p.B1) && dalloc(c, &s.lmf, p.lmf) &&
             dalloc(c, &s.theta, p.theta) && dalloc(c, &s.fbpart, p.fbpart) && dalloc(c, &s.yp, p.yp) &&
-            dalloc(c, &s.vhs, p.vhs) && dalloc(c, &s.tA, p.tbuf) && dalloc(c, &s.tB, p.tbuf) &&
+            (p.vhs == 0 || dalloc(c, &s.vhs, p.vhs)) && dalloc(c, &s.tA, p.tbuf) && dalloc(c, &s.tB, p.tbuf) &&
+            (p.vhs32 == 0 || (dalloc(c, &s.vhs32, p.vhs32) && dalloc(c, &s.tA32, p.t32) &&
+                              dalloc(c, &s.tB32, p.t32))) &&
             dalloc(c, &s.tacc, p.tbuf) && dalloc(c, &s.wsc, p.wsc) && dalloc(c, &s.logo_now, p.wvec2) &&
             dalloc(c, &s.logo_new, p.wvec2) && dalloc(c, &s.e1, p.wvec2) && dalloc(c, &s.ej, p.wvec2) &&
             dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat) &&
@@ -770,6 +780,8 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   if (o.taylor_order < 1 || o.taylor_order > 16) return fail(AFQMC_ERR_ARG, "taylor_order must be in 1..16");
   if (std::isnan(o.fb_cap) || std::isinf(o.fb_cap)) return fail(AFQMC_ERR_ARG, "fb_cap must be finite");
   if (o.streams < 0) return fail(AFQMC_ERR_ARG, "streams must be >= 0");
+  if (o.prop_precision != AFQMC_FP64 && o.prop_precision != AFQMC_FP32_CONTRACT)
+    return fail(AFQMC_ERR_ARG, "prop_precision must be AFQMC_FP64 or AFQMC_FP32_CONTRACT");
   if (o.ex_mode != AFQMC_EX_FULL && o.ex_mode != AFQMC_EX_CV) return fail(AFQMC_ERR_ARG, "unknown ex_mode");
   if (!(o.cv_fraction > 0.0 && o.cv_fraction <= 1.0)) return fail(AFQMC_ERR_ARG, "cv_fraction must be in (0, 1]");
   if (o.ex_mode == AFQMC_EX_CV)
@@ -795,11 +807,12 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->opt.ex_mode = o.ex_mode;
   c->opt.cv_fraction = o.cv_fraction;
   c->opt.cv_seed = o.cv_seed;
+  c->opt.prop_precision = o.prop_precision;
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   c->debug_bits = o.reserved[0];
   if (o.reserved[3] >= 0 && o.reserved[3] <= 4) c->vhs_variant = o.reserved[3];
-  if (o.reserved[4] >= 0 && o.reserved[4] <= 4) c->taylor_variant = o.reserved[4];
+  if (o.reserved[4] >= 0 && o.reserved[4] <= 8) c->taylor_variant = o.reserved[4];
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
     c->ex_wx = o.reserved[1];
     c->ex_wx_forced = true;
@@ -890,15 +903,26 @@ static afqmc_status propagate_sys(afqmc_ctx *ctx, System &s, const afqmc_walkers
   {
     Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
     AFQMC_HIP(launch_b1(s, phi, s.tacc, W, st), "one-body kernel");
-    AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice, st),
-              "copy");
+    if (!s.prop32)
+      AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice, st),
+                "copy");
   }
   {
     Phase ph(ctx, AFQMC_PH_TAYLOR, st);
-    double2 *tin = s.tA, *tout = s.tB;
-    for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
-      AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st), "Taylor kernel");
-      std::swap(tin, tout);
+    if (s.prop32) {
+      // terms in FP32 from an FP32 copy of B1 phi; the series accumulates in FP64 (tacc)
+      AFQMC_HIP(launch_c128_to_c64(s.tacc, (long)W * s.M * s.Nt, s.tA32, st), "conversion kernel");
+      float2 *tin = s.tA32, *tout = s.tB32;
+      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
+        AFQMC_HIP(launch_taylor_f32(s, tin, tout, 1.0 / n, W, st), "FP32 Taylor kernel");
+        std::swap(tin, tout);
+      }
+    } else {
+      double2 *tin = s.tA, *tout = s.tB;
+      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
+        AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st), "Taylor kernel");
+        std::swap(tin, tout);
+      }
     }
   }
   {

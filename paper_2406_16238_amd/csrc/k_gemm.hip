@@ -218,6 +218,7 @@ hipError_t launch_vhs(const System &s, int W, hipStream_t st) {
     a.C = s.vhsp; a.sci = Mp; a.scj = 1;
     hipError_t e = gemm_vhs_mfma(a, st, s.vhs_variant);
     if (e != hipSuccess) return e;
+    if (s.prop32) return launch_unpack_f32(s, W, st);
     const int nt = (s.M + 31) / 32;
     hipLaunchKernelGGL(k_unpack_symmetric, dim3(nt * (nt + 1) / 2, 2 * W), dim3(kThreads), 0, st, s.vhsp, s.M, nt,
                        s.vhs);

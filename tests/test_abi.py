@@ -88,7 +88,7 @@ def test_setup_rejects_bad_options(lib):
     out = ctypes.c_void_p()
     for field, value in (("taylor_order", 0), ("taylor_order", 17), ("precision", 9), ("fb_cap", float("nan")),
                          ("streams", -1), ("ex_mode", 2), ("cv_fraction", 0.0), ("cv_fraction", 1.5),
-                         ("cv_fraction", float("nan"))):
+                         ("cv_fraction", float("nan")), ("prop_precision", 2)):
         o = A.default_options()
         setattr(o, field, value)
         assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, ctypes.byref(o), None, ctypes.byref(out)) \
@@ -131,7 +131,7 @@ def test_struct_layouts_match_header(tmp_path):
                                                    "gen_tau", "gen_scale"]),
               "afqmc_options": (A.Options, ["precision", "taylor_order", "fb_cap", "e_shift", "mem_limit_bytes",
                                             "streams", "use_graph", "tune", "ex_mode", "cv_fraction", "cv_seed",
-                                            "reserved"]),
+                                            "prop_precision", "reserved_opt", "reserved"]),
               "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
               "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "exchange_order", "lane",
                                       "graph_captures", "graph_replays", "cv_subset", "reserved_info"]),
