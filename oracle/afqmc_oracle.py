@@ -46,6 +46,16 @@ R10 The overlap is carried as a complex logarithm; S is formed from the
     recomputed from the determinants.
 R11 Population control (named, not specified): a comb over the cumulative
     weights with one uniform offset; every new walker carries the mean weight.
+R12 Free projection (the fp-AFQMC section): fields from the plain Gaussian,
+    mean-field subtraction only.  A walker stands for c |phi> with c the scalar
+    the shifted propagator accumulates; it carries the complex logarithm
+    a = log(c <Psi_T|phi>).  A step adds log S - dt (C - E_T) to a (S as in
+    eq. ovlp_ratio with y = x); re-orthogonalisation changes phi and
+    log<Psi_T|phi> but not a.  E(tau) = sum_w w_w e^{a_w} E_loc,w /
+    sum_w w_w e^{a_w} (complex), summed with the reference shift
+    r = max Re a_w over the walkers that count (w_w > 0, no singular or
+    non-finite flag); E_T = E_HF only keeps the amplitudes of order one.  No
+    walker is killed, capped or resampled.
 """
 from __future__ import annotations
 
@@ -332,6 +342,73 @@ def reorthogonalize(ham: OracleHamiltonian, phis, logos):
             phis[w][:, sl] = q
             logos[w] -= np.sum(np.log(np.diag(r).real))
     return phis, logos
+
+
+# ---- free projection ---------------------------------------------------------------
+
+def wrap_phase(t: float) -> float:
+    """The angle t mapped to (-pi, pi]."""
+    return float(np.angle(np.exp(1j * t)))
+
+
+def free_step_walker(ham: OracleHamiltonian, phi, logo, log_amp, x, taylor_order=6):
+    """One free-projection step of one walker (the fp-AFQMC section, reading
+    R12): phi' = B(x) phi with the mean-field-shifted propagator of eq. Bprop
+    and no force bias; a' = a + log S - dt (C - E_T), with S the overlap ratio of
+    eq. ovlp_ratio (its scalar exp(i sqrt(dt) x.l) included).  `logo` is
+    log<Psi_T|phi> of the walker as carried.  Returns a dict with the new phi,
+    logo, log-amplitude and flags; a walker whose new overlap vanishes keeps
+    its logo and amplitude and is flagged singular."""
+    flags = 0
+    x = np.asarray(x, dtype=float)
+    if not np.all(np.isfinite(x)):
+        flags |= W_NONFINITE
+        x = np.zeros_like(x)
+    phi3, logo1, log_s, sing1 = overlap_ratio(ham, phi, logo, x + 0j, taylor_order)
+    if sing1:
+        return {"phi": phi3, "logo": logo, "log_amp": log_amp, "flags": flags | W_SINGULAR}
+    a = log_amp + log_s - ham.dt * (ham.const - ham.e_trial)
+    a = complex(a.real, wrap_phase(a.imag))
+    return {"phi": phi3, "logo": logo1, "log_amp": a, "flags": flags}
+
+
+def free_propagate(ham: OracleHamiltonian, phis, logos, amps, x, taylor_order=6):
+    """One free-projection step for every walker.  x: [W, G] real fields.
+    Returns new (phis, logos, amps, flags)."""
+    W = phis.shape[0]
+    out_phi = np.empty_like(phis)
+    out_l = np.empty(W, dtype=np.complex128)
+    out_a = np.empty(W, dtype=np.complex128)
+    flags = np.zeros(W, dtype=np.uint32)
+    for w in range(W):
+        r = free_step_walker(ham, phis[w], logos[w], amps[w], x[w], taylor_order)
+        out_phi[w], out_l[w], out_a[w], flags[w] = r["phi"], r["logo"], r["log_amp"], r["flags"]
+    return out_phi, out_l, out_a, flags
+
+
+def free_estimator(weights, amps, energies, flags) -> dict:
+    """The fp-AFQMC energy estimate of one set of walkers (reading R12):
+    sums N = sum w e^{a - r} E, D = sum w e^{a - r}, N1, N2 (with E1, E2) over
+    the walkers that count, r = their largest Re a (0 if none), E = N / D."""
+    w = np.asarray(weights, dtype=float)
+    a = np.asarray(amps, dtype=np.complex128)
+    f = np.asarray(flags, dtype=np.int64)
+    use = (w > 0) & ((f & (W_SINGULAR | W_NONFINITE)) == 0) & np.isfinite(a)
+    if not use.any():
+        return {"N": 0j, "D": 0j, "N1": 0j, "N2": 0j, "r": 0.0, "n": 0, "E": complex(np.nan, np.nan)}
+    r = float(np.max(a[use].real))
+    z = w[use] * np.exp(a[use] - r)
+    e = np.asarray(energies)[use]
+    out = {"N": complex(np.sum(z * e[:, 0])), "D": complex(np.sum(z)),
+           "N1": complex(np.sum(z * e[:, 1])), "N2": complex(np.sum(z * e[:, 2])),
+           "r": r, "n": int(use.sum())}
+    out["E"] = out["N"] / out["D"]
+    return out
+
+
+def initial_amplitudes(logos) -> np.ndarray:
+    """a = log<Psi_T|phi> for walkers that start with c = 1."""
+    return np.array(logos, dtype=np.complex128).copy()
 
 
 # ---- population control ----------------------------------------------------------
