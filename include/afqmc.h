@@ -336,6 +336,54 @@ afqmc_status afqmc_population_control(afqmc_ctx *ctx, const afqmc_walkers *w, co
  * step graphs (they hold the old factor).  Synchronises the device. */
 afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift);
 
+/*
+ * Free-projection AFQMC (the fp-AFQMC section): the walker step with the
+ * mean-field shift only, no force bias, no phaseless projection and no
+ * population control.  A walker stands for c |phi>, c the scalar the shifted
+ * propagator accumulates, and carries besides phi and log_ovlp the complex
+ * log-amplitude a = log(c <Psi_T|phi>) in `log_amp` (nsys device pointers,
+ * each double2 [W], updated in place; start with a = log_ovlp for c = 1):
+ *   phi <- B1 T(sqrt(dt) V_HS) B1 phi, V_HS = -i sum_g x_g L^g (bare fields x),
+ *   a <- a + log<Psi_T|phi'> - log<Psi_T|phi> + i sqrt(dt) x.l - dt (C - E_T),
+ *   Im a reduced to [-pi, pi], log_ovlp <- log<Psi_T|phi'>.
+ * log<Psi_T|phi> is read from walkers.log_ovlp.  weight is neither read nor
+ * written.  A walker whose new overlap vanishes is flagged AFQMC_W_SINGULAR and
+ * keeps a and log_ovlp; non-finite fields are flagged AFQMC_W_NONFINITE and
+ * taken as 0.  afqmc_reorthogonalize applies unchanged (a is invariant under
+ * it).  Because V_HS is purely imaginary here, only its imaginary plane is
+ * formed and contracted when the MFMA Taylor kernels are in use.
+ * `x`: nsys device pointers, each [W][G] standard-normal fields.
+ * Errors: AFQMC_ERR_ARG on NULL pointers; AFQMC_ERR_HIP on launch failure.
+ */
+afqmc_status afqmc_free_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x,
+                                  void *const *log_amp, void *hip_stream);
+
+/*
+ * Energy estimate of free projection, E(tau) = N / D with
+ *   z_w = weight_w exp(a_w - r),  N = sum z E,  D = sum z,  N1 = sum z E1,
+ *   N2 = sum z E2,  r = max Re a_w,
+ * over the walkers that count (weight > 0, neither AFQMC_W_SINGULAR nor
+ * AFQMC_W_NONFINITE set, finite a; r = 0 when none does).  `e_in`: nsys device
+ * pointers, each double2 [W][3] = (E, E1, E2) as afqmc_local_energy writes.
+ * `est_out`: device double [nsys][AFQMC_FREE_EST] =
+ *   (Re N, Im N, Re D, Im D, Re N1, Im N1, Re N2, Im N2, r, n counted).
+ * The reduction order is fixed (bitwise reproducible).
+ */
+#define AFQMC_FREE_EST 10
+afqmc_status afqmc_free_estimator(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *log_amp,
+                                  void *const *e_in, double *est_out, void *hip_stream);
+
+/*
+ * One free-projection step: afqmc_free_propagate, then afqmc_reorthogonalize if
+ * (flags & AFQMC_STEP_REORTHO), then the local energy of the new walkers into
+ * e_out (as afqmc_local_energy) and, when est_out is not NULL, the estimate of
+ * afqmc_free_estimator into est_out [nsys][AFQMC_FREE_EST].  Theta of the new
+ * walkers comes from the overlap pass of the propagation (one LU per step).
+ * Runs eagerly (options.use_graph does not apply).  Other flags: AFQMC_ERR_ARG.
+ */
+afqmc_status afqmc_free_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *log_amp,
+                             void *const *e_out, double *est_out, uint32_t flags, void *hip_stream);
+
 /* Set-up scalars of system `isys`.  AFQMC_ERR_ARG on NULL or bad index. */
 afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out);
 

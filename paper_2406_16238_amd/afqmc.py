@@ -81,8 +81,9 @@ EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate"
            "afqmc_set_timing", "afqmc_get_timings", "afqmc_destroy", "afqmc_last_error",
            "afqmc_cv_collect", "afqmc_cv_train", "afqmc_cv_set_params", "afqmc_cv_get_params",
            "afqmc_cv_predict", "afqmc_cv_loss_grad", "afqmc_cv_state", "afqmc_population_control",
-           "afqmc_set_e_shift")
+           "afqmc_set_e_shift", "afqmc_free_propagate", "afqmc_free_estimator", "afqmc_free_step")
 CV_NFEAT, CV_NPARAMS, CV_NNORM = 8, 17922, 20
+FREE_EST = 10
 
 _lib = None
 
@@ -124,6 +125,9 @@ def load_library() -> ctypes.CDLL:
         "afqmc_cv_state": ([P, ctypes.c_int32, P, P, P, P], ctypes.c_int),
         "afqmc_population_control": ([P, ctypes.POINTER(CWalkers), pp, pp, P], ctypes.c_int),
         "afqmc_set_e_shift": ([P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+        "afqmc_free_propagate": ([P, ctypes.POINTER(CWalkers), pp, pp, P], ctypes.c_int),
+        "afqmc_free_estimator": ([P, ctypes.POINTER(CWalkers), pp, pp, P, P], ctypes.c_int),
+        "afqmc_free_step": ([P, ctypes.POINTER(CWalkers), pp, pp, pp, P, ctypes.c_uint32, P], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -409,6 +413,57 @@ def population_control(ctx: Context, walkers, u, parents_out=None, stream=None):
 def set_e_shift(ctx: Context, e_shift: float, isys: int = 0):
     """afqmc_set_e_shift: the energy shift E_T of the weight update."""
     _check(load_library().afqmc_set_e_shift(ctx.handle, isys, float(e_shift)))
+
+
+# ---- free projection --------------------------------------------------------------------
+
+def _free_est(ctx: Context, est_out):
+    import torch
+    if est_out is None:
+        return None
+    if est_out.dtype != torch.float64 or not est_out.is_cuda or not est_out.is_contiguous() \
+            or tuple(est_out.shape) != (ctx.nsys, FREE_EST):
+        raise ValueError(f"est_out must be a contiguous float64 CUDA tensor of shape ({ctx.nsys}, {FREE_EST})")
+    return est_out.data_ptr()
+
+
+def free_propagate(ctx: Context, walkers, x, log_amp, stream=None):
+    """afqmc_free_propagate: one free-projection step; x float64 [W, G], log_amp
+    complex128 [W] (log of c <Psi_T|phi>, updated in place) per system."""
+    import torch
+    w = _walker_array(ctx, walkers)
+    xs = _ptr_array(ctx, x, [(s.nwalkers, s.nchol) for s in ctx.systems], torch.float64)
+    am = _ptr_array(ctx, log_amp, [(s.nwalkers,) for s in ctx.systems], torch.complex128)
+    _check(load_library().afqmc_free_propagate(ctx.handle, w, xs, am, _stream_handle(stream)))
+
+
+def free_estimator(ctx: Context, walkers, log_amp, e_in, est_out, stream=None):
+    """afqmc_free_estimator: est_out float64 [nsys, 10] = (N, D, N1, N2 as
+    re/im pairs, r, n); E(tau) = N / D."""
+    import torch
+    w = _walker_array(ctx, walkers)
+    am = _ptr_array(ctx, log_amp, [(s.nwalkers,) for s in ctx.systems], torch.complex128)
+    es = _ptr_array(ctx, e_in, [(s.nwalkers, 3) for s in ctx.systems], torch.complex128)
+    _check(load_library().afqmc_free_estimator(ctx.handle, w, am, es, _free_est(ctx, est_out),
+                                               _stream_handle(stream)))
+
+
+def free_step(ctx: Context, walkers, x, log_amp, e_out, est_out=None, reortho=False, stream=None):
+    """afqmc_free_step: free propagation, optional re-orthogonalisation, local
+    energy and (with est_out) the free-projection estimate."""
+    import torch
+    w = _walker_array(ctx, walkers)
+    xs = _ptr_array(ctx, x, [(s.nwalkers, s.nchol) for s in ctx.systems], torch.float64)
+    am = _ptr_array(ctx, log_amp, [(s.nwalkers,) for s in ctx.systems], torch.complex128)
+    es = _ptr_array(ctx, e_out, [(s.nwalkers, 3) for s in ctx.systems], torch.complex128)
+    _check(load_library().afqmc_free_step(ctx.handle, w, xs, am, es, _free_est(ctx, est_out),
+                                          STEP_REORTHO if reortho else 0, _stream_handle(stream)))
+
+
+def free_energy(est_row) -> complex:
+    """E(tau) = N / D from one row of a free-projection estimate."""
+    r = [float(v) for v in est_row]
+    return complex(r[0], r[1]) / complex(r[2], r[3])
 
 
 # ---- learned control variate ---------------------------------------------------------

@@ -73,6 +73,7 @@ struct System {
   int vhs_variant = 0;         // tile shape of the V_HS GEMM
   int taylor_variant = 0;      // tile shape of the Taylor-term kernel
   bool pack_chol = true;       // V_HS from the packed upper triangles of the L^g
+  bool free_full = false;      // free projection through both V_HS planes (comparison runs)
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans
   int ex_group = 0;            // tile order of the MFMA exchange launches (see tile_of)
@@ -161,12 +162,17 @@ hipError_t launch_fb_propagate_epilogue(const System &s, const Options &o, const
 hipError_t launch_fb_energy_epilogue(const System &s, int W, double2 *vbias_out, int nslices, hipStream_t st);
 
 // Two-body generator A = sqrt(dt) V_HS for every walker.
-hipError_t launch_vhs(const System &s, int W, hipStream_t st);
+// imag_only: form only the imaginary planes (rows (w, 1)); the real planes are
+// left as they are and must not be read (a purely imaginary V_HS)
+hipError_t launch_vhs(const System &s, int W, hipStream_t st, bool imag_only = false);
 // out_w = B1 in_w for every walker (real M x M times complex M x Nt).
 hipError_t launch_b1(const System &s, const double2 *in, double2 *out, int W, hipStream_t st);
 // Taylor term: tout = alpha * A_w tin; tacc += tout.
+// kbeg = M skips the real plane of V_HS (zero for free projection); only the
+// MFMA Taylor kernels take kbeg != 0 (free_half_supported)
 hipError_t launch_taylor_term(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st);
+                              hipStream_t st, int kbeg = 0);
+bool free_half_supported(const System &s);
 // Weight update of the phaseless step.
 hipError_t launch_weight_update(const System &s, const afqmc_walkers &w, int W, hipStream_t st);
 
@@ -195,10 +201,16 @@ hipError_t launch_fill_pattern2(double2 *p, long n, hipStream_t st);
 hipError_t launch_pack_upper(const System &s, hipStream_t st);
 // FP32 propagation (k_taylor32.hip)
 bool prop32_supported(int M, int Nt);
-hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st);
+hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
+                             int kbeg = 0);
 hipError_t launch_c128_to_c64(const double2 *in, long n, float2 *out, hipStream_t st);
-hipError_t launch_unpack_f32(const System &s, int W, hipStream_t st);
+hipError_t launch_unpack_f32(const System &s, int W, hipStream_t st, bool imag_only = false);
 // comb population control (k_popctl.hip); parents_out may be NULL
+// free projection
+hipError_t launch_free_fields(const System &s, const double *x, int W, uint32_t *flags, hipStream_t st);
+hipError_t launch_free_amplitude(const System &s, const afqmc_walkers &wk, double2 *amp, int W, hipStream_t st);
+hipError_t launch_free_estimator(const double *weight, const uint32_t *flags, const double2 *amp, const double2 *e,
+                                 int W, double *est, hipStream_t st);
 hipError_t launch_comb(const System &s, double *weight, double2 *phi, double2 *logo, uint32_t *flags, const double *u,
                        int *parents_out, hipStream_t st);
 // the synthetic Cholesky tensor of the counter recipe (see afqmc_system_desc)
@@ -206,7 +218,7 @@ hipError_t launch_gen_chol(const System &s, uint64_t seed, const double *fac, do
 // dedicated Taylor-term kernel (k_taylor.hip)
 bool taylor_mfma_supported(int M, int Nt);
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st);
+                              hipStream_t st, int kbeg = 0);
 
 // learned control variate (k_cv.hip)
 hipError_t cv_enable_lds();

@@ -415,6 +415,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   s.vhs_variant = c->vhs_variant;
   s.taylor_variant = c->taylor_variant;
   s.pack_chol = s.use_mfma_gemm && !(c->debug_bits & 8);
+  s.free_full = (c->debug_bits & 16) != 0;
   s.prop32 = c->opt.prop_precision == AFQMC_FP32_CONTRACT;
   if (s.prop32 && !(s.pack_chol && prop32_supported(s.M, s.Nt)))
     return fail(AFQMC_ERR_UNSUPPORTED, "FP32 propagation needs the MFMA path, M a multiple of 4 and at most 96 "
@@ -865,6 +866,58 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   return AFQMC_OK;
 }
 
+// phi <- B1 T(sqrt(dt) V_HS) B1 phi from the rows already in s.yp, then the
+// overlap pass of the new walkers (log-overlaps into s.logo_new, Theta into
+// s.theta with `want_theta`).  `imag` says V_HS is purely imaginary (free
+// projection): only its imaginary plane is formed and contracted where the
+// Taylor kernels allow it.
+static afqmc_status apply_propagator(afqmc_ctx *ctx, System &s, double2 *phi, bool want_theta, bool imag,
+                                     hipStream_t st) {
+  const int W = s.W;
+  const bool half = imag && free_half_supported(s);
+  const int kbeg = half ? s.M : 0;
+  {
+    Phase ph(ctx, AFQMC_PH_VHS, st);
+    AFQMC_HIP(launch_vhs(s, W, st, half), "V_HS kernel");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
+    AFQMC_HIP(launch_b1(s, phi, s.tacc, W, st), "one-body kernel");
+    if (!s.prop32)
+      AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice, st),
+                "copy");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_TAYLOR, st);
+    if (s.prop32) {
+      // terms in FP32 from an FP32 copy of B1 phi; the series accumulates in FP64 (tacc)
+      AFQMC_HIP(launch_c128_to_c64(s.tacc, (long)W * s.M * s.Nt, s.tA32, st), "conversion kernel");
+      float2 *tin = s.tA32, *tout = s.tB32;
+      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
+        AFQMC_HIP(launch_taylor_f32(s, tin, tout, 1.0 / n, W, st, kbeg), "FP32 Taylor kernel");
+        std::swap(tin, tout);
+      }
+    } else {
+      double2 *tin = s.tA, *tout = s.tB;
+      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
+        AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st, kbeg), "Taylor kernel");
+        std::swap(tin, tout);
+      }
+    }
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
+    AFQMC_HIP(launch_b1(s, s.tacc, phi, W, st), "one-body kernel");
+  }
+  {
+    Phase ph(ctx, AFQMC_PH_OVERLAP, st);
+    AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, want_theta ? s.theta : nullptr, s.logo_new,
+                                s.stat_new, nullptr, st),
+              "overlap kernel");
+  }
+  return AFQMC_OK;
+}
+
 // One propagation step of system s.  With `reuse`, theta / fbpart already hold
 // Theta and the vbias partials of the current walkers, and their log-overlaps
 // are taken from walkers.log_ovlp.  With `want_theta` the overlap pass after
@@ -896,48 +949,27 @@ static afqmc_status propagate_sys(afqmc_ctx *ctx, System &s, const afqmc_walkers
     Phase ph(ctx, AFQMC_PH_FB_EPILOGUE, st);
     AFQMC_HIP(launch_fb_propagate_epilogue(s, ctx->opt, x, W, wk.flags, s.fb_slices, st), "force-bias epilogue");
   }
-  {
-    Phase ph(ctx, AFQMC_PH_VHS, st);
-    AFQMC_HIP(launch_vhs(s, W, st), "V_HS kernel");
-  }
-  {
-    Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
-    AFQMC_HIP(launch_b1(s, phi, s.tacc, W, st), "one-body kernel");
-    if (!s.prop32)
-      AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice, st),
-                "copy");
-  }
-  {
-    Phase ph(ctx, AFQMC_PH_TAYLOR, st);
-    if (s.prop32) {
-      // terms in FP32 from an FP32 copy of B1 phi; the series accumulates in FP64 (tacc)
-      AFQMC_HIP(launch_c128_to_c64(s.tacc, (long)W * s.M * s.Nt, s.tA32, st), "conversion kernel");
-      float2 *tin = s.tA32, *tout = s.tB32;
-      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
-        AFQMC_HIP(launch_taylor_f32(s, tin, tout, 1.0 / n, W, st), "FP32 Taylor kernel");
-        std::swap(tin, tout);
-      }
-    } else {
-      double2 *tin = s.tA, *tout = s.tB;
-      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
-        AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st), "Taylor kernel");
-        std::swap(tin, tout);
-      }
-    }
-  }
-  {
-    Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
-    AFQMC_HIP(launch_b1(s, s.tacc, phi, W, st), "one-body kernel");
-  }
-  {
-    Phase ph(ctx, AFQMC_PH_OVERLAP, st);
-    AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, want_theta ? s.theta : nullptr, s.logo_new,
-                                s.stat_new, nullptr, st),
-              "overlap kernel");
-  }
+  afqmc_status r = apply_propagator(ctx, s, phi, want_theta, false, st);
+  if (r != AFQMC_OK) return r;
   {
     Phase ph(ctx, AFQMC_PH_WEIGHT, st);
     AFQMC_HIP(launch_weight_update(s, wk, W, st), "weight kernel");
+  }
+  return AFQMC_OK;
+}
+
+// One free-projection step of system s (fields, propagator, amplitude update).
+static afqmc_status free_propagate_sys(afqmc_ctx *ctx, System &s, const afqmc_walkers &wk, const double *x,
+                                       double2 *amp, bool want_theta, hipStream_t st) {
+  {
+    Phase ph(ctx, AFQMC_PH_FB_EPILOGUE, st);
+    AFQMC_HIP(launch_free_fields(s, x, s.W, wk.flags, st), "field kernel");
+  }
+  afqmc_status r = apply_propagator(ctx, s, static_cast<double2 *>(wk.phi), want_theta, true, st);
+  if (r != AFQMC_OK) return r;
+  {
+    Phase ph(ctx, AFQMC_PH_WEIGHT, st);
+    AFQMC_HIP(launch_free_amplitude(s, wk, amp, s.W, st), "amplitude kernel");
   }
   return AFQMC_OK;
 }
@@ -1379,6 +1411,78 @@ afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift) {
   for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
   ctx->graphs.clear();
   return AFQMC_OK;
+}
+
+static afqmc_status check_amplitudes(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *log_amp) {
+  if (!log_amp) return fail(AFQMC_ERR_ARG, "NULL log-amplitudes");
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+    if (!log_amp[i]) return fail(AFQMC_ERR_ARG, "log-amplitudes of system " + std::to_string(i) + " are NULL");
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_free_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x,
+                                  void *const *log_amp, void *hip_stream) {
+  if (!ctx || !w || !x) return fail(AFQMC_ERR_ARG, "NULL context, walkers or fields");
+  afqmc_status r = check_amplitudes(ctx, w, log_amp);
+  if (r != AFQMC_OK) return r;
+  for (size_t i = 0; i < ctx->sys.size(); ++i)
+    if (!x[i]) return fail(AFQMC_ERR_ARG, "fields of system " + std::to_string(i) + " are NULL");
+  invalidate_caches(ctx);
+  return for_each_system(ctx, static_cast<hipStream_t>(hip_stream), [&](int i, hipStream_t ls) {
+    return free_propagate_sys(ctx, ctx->sys[i], w[i], x[i], static_cast<double2 *>(log_amp[i]), false, ls);
+  });
+}
+
+afqmc_status afqmc_free_estimator(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *log_amp, void *const *e_in,
+                                  double *est_out, void *hip_stream) {
+  if (!ctx || !w || !e_in || !est_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers, energies or est_out");
+  afqmc_status r = check_amplitudes(ctx, w, log_amp);
+  if (r != AFQMC_OK) return r;
+  for (size_t i = 0; i < ctx->sys.size(); ++i)
+    if (!e_in[i]) return fail(AFQMC_ERR_ARG, "energies of system " + std::to_string(i) + " are NULL");
+  return for_each_system(ctx, static_cast<hipStream_t>(hip_stream), [&](int i, hipStream_t ls) {
+    Phase ph(ctx, AFQMC_PH_COMBINE, ls);
+    AFQMC_HIP(launch_free_estimator(w[i].weight, w[i].flags, static_cast<const double2 *>(log_amp[i]),
+                                    static_cast<const double2 *>(e_in[i]), ctx->sys[i].W,
+                                    est_out + (size_t)AFQMC_FREE_EST * i, ls),
+              "estimator kernel");
+    return AFQMC_OK;
+  });
+}
+
+afqmc_status afqmc_free_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *log_amp,
+                             void *const *e_out, double *est_out, uint32_t flags, void *hip_stream) {
+  if (!ctx || !w || !x || !e_out) return fail(AFQMC_ERR_ARG, "NULL context, walkers, fields or e_out");
+  if (flags & ~(uint32_t)AFQMC_STEP_REORTHO) return fail(AFQMC_ERR_ARG, "unknown free-step flags");
+  afqmc_status r = check_amplitudes(ctx, w, log_amp);
+  if (r != AFQMC_OK) return r;
+  for (size_t i = 0; i < ctx->sys.size(); ++i)
+    if (!x[i] || !e_out[i]) return fail(AFQMC_ERR_ARG, "NULL fields or e_out of system " + std::to_string(i));
+  invalidate_caches(ctx);
+  return for_each_system(ctx, static_cast<hipStream_t>(hip_stream), [&](int i, hipStream_t ls) {
+    System &s = ctx->sys[i];
+    double2 *amp = static_cast<double2 *>(log_amp[i]);
+    double2 *e = static_cast<double2 *>(e_out[i]);
+    afqmc_status rr = free_propagate_sys(ctx, s, w[i], x[i], amp, true, ls);
+    if (rr != AFQMC_OK) return rr;
+    if (flags & AFQMC_STEP_REORTHO) {
+      Phase ph(ctx, AFQMC_PH_REORTHO, ls);
+      AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
+                           static_cast<double2 *>(w[i].log_ovlp), ls),
+                "Gram-Schmidt kernel");
+    }
+    rr = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, e, nullptr, w[i].weight, ls, true);
+    if (rr != AFQMC_OK) return rr;
+    if (est_out) {
+      Phase ph(ctx, AFQMC_PH_COMBINE, ls);
+      AFQMC_HIP(launch_free_estimator(w[i].weight, w[i].flags, amp, e, s.W, est_out + (size_t)AFQMC_FREE_EST * i, ls),
+                "estimator kernel");
+    }
+    return AFQMC_OK;
+  });
 }
 
 afqmc_status afqmc_set_timing(afqmc_ctx *ctx, int32_t enable) {

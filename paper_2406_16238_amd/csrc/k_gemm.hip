@@ -140,9 +140,9 @@ __global__ void k_pack_upper(const double *__restrict__ L, int M, double *__rest
 // full[m][p][q] = full[m][q][p] = packed[m][t(p, q)] for p <= q; one workgroup
 // per 32 x 32 tile (bi <= bj) of one matrix m, the transposed copy through LDS.
 __global__ __launch_bounds__(kThreads) void k_unpack_symmetric(const double *__restrict__ packed, int M, int ntile,
-                                                               double *__restrict__ full) {
+                                                               int pstride, int poff, double *__restrict__ full) {
   __shared__ double tile[32][33];
-  const int m = blockIdx.y;
+  const int m = blockIdx.y * pstride + poff;
   // tile index -> (bi, bj), bi <= bj, row-major over the upper triangle of tiles
   int t = blockIdx.x, bi = 0;
   while (t >= ntile - bi) {
@@ -206,27 +206,29 @@ hipError_t launch_pack_upper(const System &s, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_vhs(const System &s, int W, hipStream_t st) {
+hipError_t launch_vhs(const System &s, int W, hipStream_t st, bool imag_only) {
   const long MM = (long)s.M * s.M;
+  // rows (w, c) of yp; with imag_only the rows (w, 1) alone, into planes (w, 1)
+  const int rows = imag_only ? W : 2 * W, rstride = imag_only ? 2 : 1, roff = imag_only ? 1 : 0;
   GemmArgs a;
-  a.m = 2 * W; a.k = s.G;
-  a.A = s.yp; a.sai = s.G; a.sak = 1;
+  a.m = rows; a.k = s.G;
+  a.A = s.yp + (size_t)roff * s.G; a.sai = (long)rstride * s.G; a.sak = 1;
   if (s.use_mfma_gemm && s.Lp) {
     const long Mp = (long)s.M * (s.M + 1) / 2;
     a.n = (int)Mp;
     a.B = s.Lp; a.sbk = Mp; a.sbj = 1;
-    a.C = s.vhsp; a.sci = Mp; a.scj = 1;
+    a.C = s.vhsp + (size_t)roff * Mp; a.sci = rstride * Mp; a.scj = 1;
     hipError_t e = gemm_vhs_mfma(a, st, s.vhs_variant);
     if (e != hipSuccess) return e;
-    if (s.prop32) return launch_unpack_f32(s, W, st);
+    if (s.prop32) return launch_unpack_f32(s, W, st, imag_only);
     const int nt = (s.M + 31) / 32;
-    hipLaunchKernelGGL(k_unpack_symmetric, dim3(nt * (nt + 1) / 2, 2 * W), dim3(kThreads), 0, st, s.vhsp, s.M, nt,
-                       s.vhs);
+    hipLaunchKernelGGL(k_unpack_symmetric, dim3(nt * (nt + 1) / 2, rows), dim3(kThreads), 0, st, s.vhsp, s.M, nt,
+                       rstride, roff, s.vhs);
     return hipGetLastError();
   }
   a.n = (int)MM;
   a.B = s.L; a.sbk = MM; a.sbj = 1;
-  a.C = s.vhs; a.sci = MM; a.scj = 1;
+  a.C = s.vhs + (size_t)roff * MM; a.sci = rstride * MM; a.scj = 1;
   return s.use_mfma_gemm ? gemm_vhs_mfma(a, st, s.vhs_variant) : gemm_f64(a, st);
 }
 
@@ -299,10 +301,16 @@ __global__ __launch_bounds__(kThreads) void k_taylor_term(const double *__restri
   }
 }
 
+bool free_half_supported(const System &s) {
+  if (s.free_full || !s.use_mfma_gemm) return false;
+  return s.prop32 || (s.taylor_kernel && taylor_mfma_supported(s.M, s.Nt));
+}
+
 hipError_t launch_taylor_term(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st) {
+                              hipStream_t st, int kbeg) {
   if (s.use_mfma_gemm && s.taylor_kernel && taylor_mfma_supported(s.M, s.Nt))
-    return launch_taylor_mfma(s, tin, tout, alpha, W, st);
+    return launch_taylor_mfma(s, tin, tout, alpha, W, st, kbeg);
+  if (kbeg != 0) return hipErrorInvalidValue;
   if (s.use_mfma_gemm) {
     // [Re A | Im A] (M x 2M) times [T ; iT] (2M x 2Nt) per walker
     const long n2 = 2L * s.Nt, MM = (long)s.M * s.M;

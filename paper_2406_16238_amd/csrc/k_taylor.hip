@@ -16,7 +16,9 @@
 // groups of one 16-column group).  The contraction is staged 16 indices at a
 // time in LDS (k-major, padded rows) with 16-byte global loads, double-buffered
 // through registers.  M must be even (16-byte loads of A never straddle the two
-// planes) and Nt at most 96; other shapes use the generic GEMM.
+// planes) and Nt at most 96; other shapes use the generic GEMM.  The contraction
+// starts at kbeg: 0, or M to skip a real plane that is zero (free projection,
+// where V_HS is purely imaginary).
 #include "afqmc_internal.h"
 #include "device_util.h"
 
@@ -30,7 +32,8 @@ template <int WM, int WN, int TR, int TN>
 __global__ __launch_bounds__(64 * WM * WN) void k_taylor_mfma(const double *__restrict__ vhs,
                                                              const double2 *__restrict__ tin,
                                                              double2 *__restrict__ tout, double2 *__restrict__ tacc,
-                                                             int M, int Nt, int W, int nrt, double alpha) {
+                                                             int M, int Nt, int W, int nrt, double alpha,
+                                                             int kbeg) {
   constexpr int NTH = 64 * WM * WN;
   constexpr int BM = WM * 4 * TR, BN = WN * 16 * TN;
   constexpr int LDA = BM + 1, LDB = BN + 1;
@@ -112,13 +115,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_taylor_mfma(const double *__re
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
 
-  const int nchunk = (K + TKC - 1) / TKC;
-  load(0);
+  const int nchunk = (K - kbeg + TKC - 1) / TKC;
+  load(kbeg);
   store(0);
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nchunk) load((ch + 1) * TKC);
+    if (ch + 1 < nchunk) load(kbeg + (ch + 1) * TKC);
     const double *a = sA + buf * TKC * LDA + wm * 4 * TR + l4;
     const double *b = sB + buf * TKC * LDB + wn * 16 * TN + lr;
 #pragma unroll
@@ -157,7 +160,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_taylor_mfma(const double *__re
 
 namespace {
 template <int WM, int WN, int TR, int TN>
-hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
+hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
+                      int kbeg) {
   constexpr int BM = WM * 4 * TR, BN = WN * 16 * TN;
   static_assert(BN >= 2, "columns");
   const size_t lds = 2ull * TKC * ((BM + 1) + (BN + 1)) * sizeof(double);
@@ -171,7 +175,7 @@ hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double
   }
   const int nrt = (s.M + BM - 1) / BM;
   hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * WM * WN), lds, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt,
-                     W, nrt, alpha);
+                     W, nrt, alpha, kbeg);
   return hipGetLastError();
 }
 }  // namespace
@@ -179,27 +183,27 @@ hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double
 bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <= 96; }
 
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st) {
-  if (s.Nt <= 16) return run_taylor<2, 2, 16, 1>(s, tin, tout, alpha, W, st);
-  if (s.Nt <= 32) return run_taylor<2, 2, 16, 2>(s, tin, tout, alpha, W, st);
-  if (s.Nt <= 48) return run_taylor<2, 2, 12, 3>(s, tin, tout, alpha, W, st);
-  if (s.Nt <= 64) return run_taylor<2, 2, 12, 4>(s, tin, tout, alpha, W, st);
+                              hipStream_t st, int kbeg) {
+  if (s.Nt <= 16) return run_taylor<2, 2, 16, 1>(s, tin, tout, alpha, W, st, kbeg);
+  if (s.Nt <= 32) return run_taylor<2, 2, 16, 2>(s, tin, tout, alpha, W, st, kbeg);
+  if (s.Nt <= 48) return run_taylor<2, 2, 12, 3>(s, tin, tout, alpha, W, st, kbeg);
+  if (s.Nt <= 64) return run_taylor<2, 2, 12, 4>(s, tin, tout, alpha, W, st, kbeg);
   if (s.Nt <= 80) {
     switch (s.taylor_variant) {
-      case 1: return run_taylor<2, 1, 10, 10>(s, tin, tout, alpha, W, st);
-      case 2: return run_taylor<1, 2, 20, 5>(s, tin, tout, alpha, W, st);
-      case 3: return run_taylor<2, 2, 20, 5>(s, tin, tout, alpha, W, st);
-      case 4: return run_taylor<4, 1, 5, 10>(s, tin, tout, alpha, W, st);
-      case 5: return run_taylor<2, 2, 10, 5>(s, tin, tout, alpha, W, st);
-      case 6: return run_taylor<2, 2, 4, 5>(s, tin, tout, alpha, W, st);
-      case 7: return run_taylor<2, 2, 7, 5>(s, tin, tout, alpha, W, st);
-      case 8: return run_taylor<2, 2, 8, 5>(s, tin, tout, alpha, W, st);
+      case 1: return run_taylor<2, 1, 10, 10>(s, tin, tout, alpha, W, st, kbeg);
+      case 2: return run_taylor<1, 2, 20, 5>(s, tin, tout, alpha, W, st, kbeg);
+      case 3: return run_taylor<2, 2, 20, 5>(s, tin, tout, alpha, W, st, kbeg);
+      case 4: return run_taylor<4, 1, 5, 10>(s, tin, tout, alpha, W, st, kbeg);
+      case 5: return run_taylor<2, 2, 10, 5>(s, tin, tout, alpha, W, st, kbeg);
+      case 6: return run_taylor<2, 2, 4, 5>(s, tin, tout, alpha, W, st, kbeg);
+      case 7: return run_taylor<2, 2, 7, 5>(s, tin, tout, alpha, W, st, kbeg);
+      case 8: return run_taylor<2, 2, 8, 5>(s, tin, tout, alpha, W, st, kbeg);
       // default 48-row tiles: at the headline shape 0.82 ms per term against
       // 0.93 for 80 rows (a shorter grid tail at three waves per SIMD)
-      default: return run_taylor<2, 2, 6, 5>(s, tin, tout, alpha, W, st);
+      default: return run_taylor<2, 2, 6, 5>(s, tin, tout, alpha, W, st, kbeg);
     }
   }
-  return run_taylor<2, 2, 8, 6>(s, tin, tout, alpha, W, st);
+  return run_taylor<2, 2, 8, 6>(s, tin, tout, alpha, W, st, kbeg);
 }
 
 }  // namespace afqmc

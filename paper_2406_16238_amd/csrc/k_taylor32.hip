@@ -12,7 +12,8 @@
 // B[l / 16][l % 16], accumulator item r of lane l is D[4 (l / 16) + r][l % 16].
 // The contraction is staged 16 indices at a time in LDS (k-major) with 16-byte
 // global loads, double-buffered through registers.  M must be a multiple of 4
-// (16-byte loads of A never straddle the planes); Nt at most 96.
+// (16-byte loads of A never straddle the planes); Nt at most 96.  The
+// contraction starts at kbeg (0, or M when the real plane is zero).
 #include "afqmc_internal.h"
 #include "device_util.h"
 
@@ -29,7 +30,7 @@ constexpr int QTH = 128;  // two waves
 template <int QRT, int CT>
 __global__ __launch_bounds__(QTH) void k_taylor_f32(const float *__restrict__ A32, const float2 *__restrict__ tin,
                                                     float2 *__restrict__ tout, double2 *__restrict__ tacc, int M,
-                                                    int Nt, int W, int nrt, float alpha) {
+                                                    int Nt, int W, int nrt, float alpha, int kbeg) {
   constexpr int BM = 16 * QRT, BN = 32 * CT;
   constexpr int LDA = BM + 4, LDB = BN + 16;  // LDB = 16 mod 32 banks: conflict-free B reads
   constexpr int AV = BM * QKC / 4;   // float4 of A per stage
@@ -109,13 +110,13 @@ __global__ __launch_bounds__(QTH) void k_taylor_f32(const float *__restrict__ A3
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = f4t{0.f, 0.f, 0.f, 0.f};
 
-  const int nchunk = (K + QKC - 1) / QKC;
-  load(0);
+  const int nchunk = (K - kbeg + QKC - 1) / QKC;
+  load(kbeg);
   store(0);
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nchunk) load((ch + 1) * QKC);
+    if (ch + 1 < nchunk) load(kbeg + (ch + 1) * QKC);
     const float *a = sA + buf * QKC * LDA + lr;
     const float *b = sB + buf * QKC * LDB + wn * 16 * CT + lr;
 #pragma unroll
@@ -162,9 +163,10 @@ __global__ void k_c128_to_c64(const double2 *__restrict__ in, long n, float2 *__
 // full32[m][p][q] = full32[m][q][p] = float(packed[m][t(p, q)]) for p <= q (as
 // the FP64 unpacking, writing FP32 planes)
 __global__ __launch_bounds__(kThreads) void k_unpack_symmetric_f32(const double *__restrict__ packed, int M,
-                                                                   int ntile, float *__restrict__ full) {
+                                                                   int ntile, int pstride, int poff,
+                                                                   float *__restrict__ full) {
   __shared__ float tile[32][33];
-  const int m = blockIdx.y;
+  const int m = blockIdx.y * pstride + poff;
   int t = blockIdx.x, bi = 0;
   while (t >= ntile - bi) {
     t -= ntile - bi;
@@ -193,39 +195,42 @@ __global__ __launch_bounds__(kThreads) void k_unpack_symmetric_f32(const double 
 
 namespace {
 template <int QRT, int CT>
-hipError_t run_taylor32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st) {
+hipError_t run_taylor32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
+                        int kbeg) {
   constexpr int BM = 16 * QRT, BN = 32 * CT;
   const size_t lds = 2ull * QKC * ((BM + 4) + (BN + 16)) * sizeof(float);
   const int nrt = (s.M + BM - 1) / BM;
   hipLaunchKernelGGL((k_taylor_f32<QRT, CT>), dim3((unsigned)(W * nrt)), dim3(QTH), lds, st, s.vhs32, tin, tout,
-                     s.tacc, s.M, s.Nt, W, nrt, (float)alpha);
+                     s.tacc, s.M, s.Nt, W, nrt, (float)alpha, kbeg);
   return hipGetLastError();
 }
 
 template <int QRT>
-hipError_t run_taylor32_ct(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st) {
+hipError_t run_taylor32_ct(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
+                           int kbeg) {
   switch ((2 * s.Nt + 31) / 32) {
-    case 1: return run_taylor32<QRT, 1>(s, tin, tout, alpha, W, st);
-    case 2: return run_taylor32<QRT, 2>(s, tin, tout, alpha, W, st);
-    case 3: return run_taylor32<QRT, 3>(s, tin, tout, alpha, W, st);
-    case 4: return run_taylor32<QRT, 4>(s, tin, tout, alpha, W, st);
-    case 5: return run_taylor32<QRT, 5>(s, tin, tout, alpha, W, st);
-    default: return run_taylor32<QRT, 6>(s, tin, tout, alpha, W, st);
+    case 1: return run_taylor32<QRT, 1>(s, tin, tout, alpha, W, st, kbeg);
+    case 2: return run_taylor32<QRT, 2>(s, tin, tout, alpha, W, st, kbeg);
+    case 3: return run_taylor32<QRT, 3>(s, tin, tout, alpha, W, st, kbeg);
+    case 4: return run_taylor32<QRT, 4>(s, tin, tout, alpha, W, st, kbeg);
+    case 5: return run_taylor32<QRT, 5>(s, tin, tout, alpha, W, st, kbeg);
+    default: return run_taylor32<QRT, 6>(s, tin, tout, alpha, W, st, kbeg);
   }
 }
 }  // namespace
 
 bool prop32_supported(int M, int Nt) { return M % 4 == 0 && Nt >= 1 && Nt <= 96; }
 
-hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st) {
+hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
+                             int kbeg) {
   // default 48-row tiles (measured at the headline shape: 3.51 ms per step
   // against 4.14 for 80 rows, 4.02 for 32 and 3.60 for 64: the smaller grid
   // tail outweighs the extra re-reads of T)
   switch (s.taylor_variant) {
-    case 1: return run_taylor32_ct<2>(s, tin, tout, alpha, W, st);
-    case 2: return run_taylor32_ct<5>(s, tin, tout, alpha, W, st);
-    case 3: return run_taylor32_ct<4>(s, tin, tout, alpha, W, st);
-    default: return run_taylor32_ct<3>(s, tin, tout, alpha, W, st);
+    case 1: return run_taylor32_ct<2>(s, tin, tout, alpha, W, st, kbeg);
+    case 2: return run_taylor32_ct<5>(s, tin, tout, alpha, W, st, kbeg);
+    case 3: return run_taylor32_ct<4>(s, tin, tout, alpha, W, st, kbeg);
+    default: return run_taylor32_ct<3>(s, tin, tout, alpha, W, st, kbeg);
   }
 }
 
@@ -235,10 +240,11 @@ hipError_t launch_c128_to_c64(const double2 *in, long n, float2 *out, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_unpack_f32(const System &s, int W, hipStream_t st) {
+hipError_t launch_unpack_f32(const System &s, int W, hipStream_t st, bool imag_only) {
   const int nt = (s.M + 31) / 32;
-  hipLaunchKernelGGL(k_unpack_symmetric_f32, dim3(nt * (nt + 1) / 2, 2 * W), dim3(kThreads), 0, st, s.vhsp, s.M, nt,
-                     s.vhs32);
+  const int pstride = imag_only ? 2 : 1, poff = imag_only ? 1 : 0;
+  hipLaunchKernelGGL(k_unpack_symmetric_f32, dim3(nt * (nt + 1) / 2, imag_only ? W : 2 * W), dim3(kThreads), 0, st,
+                     s.vhsp, s.M, nt, pstride, poff, s.vhs32);
   return hipGetLastError();
 }
 

@@ -120,6 +120,9 @@ def test_step_calls_reject_null_context(lib):
     assert lib.afqmc_cv_state(None, 0, None, None, None, None) == A.ERR_ARG
     assert lib.afqmc_population_control(None, None, None, None, None) == A.ERR_ARG
     assert lib.afqmc_set_e_shift(None, 0, 0.0) == A.ERR_ARG
+    assert lib.afqmc_free_propagate(None, ctypes.byref(w), None, None, None) == A.ERR_ARG
+    assert lib.afqmc_free_estimator(None, ctypes.byref(w), None, None, None, None) == A.ERR_ARG
+    assert lib.afqmc_free_step(None, ctypes.byref(w), None, None, None, None, 0, None) == A.ERR_ARG
     lib.afqmc_destroy(None)  # no-op
 
 

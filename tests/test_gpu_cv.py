@@ -259,3 +259,36 @@ def test_unbiased_and_variance_gain(precision):
     finally:
         ctx.close()
         p.close()
+
+
+def test_cv_in_a_system_set():
+    """Each system of a set has its own network and subset draws; the set's
+    energies equal those of separate single-system contexts bit for bit."""
+    from test_gpu_batching import small_set, make_inputs, assert_bitwise
+    import torch
+    from paper_2406_16238_amd import afqmc as A
+    inputs = make_inputs(A, small_set(4))
+    opts = dict(ex_mode=A.EX_CV)
+    walkers = [gi.initial_walkers(t, s.nwalkers, noise=0.03, seed=50 + i) for i, (s, t) in enumerate(inputs)]
+
+    together = A.setup_hamiltonian([s for s, _ in inputs], A.default_options(**opts))
+    try:
+        ws = [A.Walkers.from_numpy(p) for p in walkers]
+        es = [torch.empty((s.nwalkers, 3), dtype=torch.complex128, device="cuda") for s, _ in inputs]
+        for _ in range(2):
+            A.local_energy(together, ws, es)
+        torch.cuda.synchronize()
+        got = [e.cpu().numpy() for e in es]
+    finally:
+        together.close()
+    for i, (s, _) in enumerate(inputs):
+        one = A.setup_hamiltonian(s, A.default_options(**opts))
+        try:
+            w = A.Walkers.from_numpy(walkers[i])
+            e = torch.empty((s.nwalkers, 3), dtype=torch.complex128, device="cuda")
+            for _ in range(2):
+                A.local_energy(one, w, e)
+            torch.cuda.synchronize()
+            assert_bitwise({"e": e.cpu().numpy()}, {"e": got[i]}, f"system {i}")
+        finally:
+            one.close()

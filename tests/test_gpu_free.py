@@ -1,0 +1,240 @@
+"""Free projection (the fp-AFQMC section) through the C ABI against the
+oracle's free step and estimator (pinned on the CPU against Fock space and
+Gauss-Hermite quadrature).
+
+Bar: orbitals, log-overlaps, log-amplitudes (modulo 2 pi i), local energies
+and the estimate E(tau) = N / D within 1e-10 relative of the oracle after
+several steps with re-orthogonalisation; walker flags bit for bit.
+"""
+import numpy as np
+import pytest
+
+import afqmc_inputs as gi
+from oracle import afqmc_oracle as O
+from pairs import Pair, cmp_rel, phase_diff
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+RAGGED = gi.SystemSpec(37, 5, 3, 70, tau=30.0, seed=7)          # odd M: generic Taylor GEMM, both planes
+OPEN = gi.SystemSpec(100, 10, 9, 200, tau=75.0, seed=11)
+WIDE = gi.SystemSpec(96, 42, 41, 192, tau=70.0, seed=13)
+
+
+def _est_host(est_row):
+    r = est_row
+    return {"N": complex(r[0], r[1]), "D": complex(r[2], r[3]), "N1": complex(r[4], r[5]),
+            "N2": complex(r[6], r[7]), "r": r[8], "n": int(r[9])}
+
+
+def _cmp_est(g, o):
+    """Relative distance of two estimates (sums compared after undoing r)."""
+    assert g["n"] == o["n"]
+    if o["n"] == 0:
+        return 0.0
+    sc = np.exp(g["r"] - o["r"])
+    d = abs(g["r"] - o["r"])
+    for k in ("N", "D", "N1", "N2"):
+        d = max(d, abs(g[k] * sc - o[k]) / max(abs(o[k]), abs(o["D"]) * 1e-3, 1e-300))
+    return d
+
+
+def _free_run(p, W, nsteps, reortho_every, seed_w=5, seed_f=3, api="step", noise=0.03):
+    A, torch = p.A, p.torch
+    phis = gi.initial_walkers(p.trial, W, noise=noise, seed=seed_w)
+    fields = gi.FieldStream(seed_f, W, p.ham.nchol)
+    w = p.walkers(phis)
+    amp = w.log_ovlp.clone()
+    e = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+    est = torch.empty((1, A.FREE_EST), dtype=torch.float64, device="cuda")
+    ophi, ologo = phis.copy(), O.initial_logo(p.ham, phis)
+    oamp = O.initial_amplitudes(ologo)
+    oflags = np.zeros(W, np.uint32)
+    worst = {"phi": 0.0, "logo": 0.0, "amp": 0.0, "e": 0.0, "est": 0.0}
+    for step in range(1, nsteps + 1):
+        x = fields.next()
+        reo = bool(reortho_every) and step % reortho_every == 0
+        xt = torch.as_tensor(x, device="cuda")
+        if api == "step":
+            A.free_step(p.ctx, w, xt, amp, e, est, reortho=reo)
+        else:
+            A.free_propagate(p.ctx, w, xt, amp)
+            if reo:
+                A.reorthogonalize(p.ctx, w)
+            A.local_energy(p.ctx, w, e)
+            A.free_estimator(p.ctx, w, amp, e, est)
+        ophi, ologo, oamp, fl = O.free_propagate(p.ham, ophi, ologo, oamp, x)
+        oflags |= fl
+        if reo:
+            ophi, ologo = O.reorthogonalize(p.ham, ophi, ologo)
+        oe = O.local_energies(p.ham, ophi)
+        oest = O.free_estimator(np.ones(W), oamp, oe, oflags)
+        gphi, _, glogo, gflags = p.to_host(w)
+        assert np.array_equal(gflags, oflags), step
+        worst["phi"] = max(worst["phi"], cmp_rel(gphi, ophi, np.abs(ophi).max()))
+        worst["logo"] = max(worst["logo"], phase_diff(glogo, ologo))
+        worst["amp"] = max(worst["amp"], phase_diff(amp.cpu().numpy(), oamp))
+        worst["e"] = max(worst["e"], cmp_rel(e.cpu().numpy(), oe))
+        worst["est"] = max(worst["est"], _cmp_est(_est_host(est.cpu().numpy()[0]), oest))
+    return worst, (w, amp, e, est)
+
+
+@pytest.mark.parametrize("spec,W", [(gi.SMALL.system, 10), (RAGGED, 7), (OPEN, 37), (WIDE, 9)],
+                         ids=["small", "ragged", "open-shell", "wide"])
+@pytest.mark.parametrize("api", ["step", "separate"])
+def test_free_projection_matches_oracle(spec, W, api):
+    p = Pair(spec, W, 0.01)
+    try:
+        worst, _ = _free_run(p, W, 8, 4, api=api)
+        print(spec, api, worst)
+        assert max(worst.values()) < TOL, worst
+    finally:
+        p.close()
+
+
+def test_free_projection_medium_tiled():
+    """A walker count that spans several tiles of every kernel (M = 200)."""
+    p = Pair(gi.MEDIUM.system, 70, 0.005)
+    try:
+        worst, _ = _free_run(p, 70, 3, 3)
+        assert max(worst.values()) < TOL, worst
+    finally:
+        p.close()
+
+
+def test_imaginary_plane_path_equals_both_planes():
+    """Free projection contracts only the imaginary plane of V_HS; reserved[0]
+    bit 4 forces both planes (the real one zero).  Same walkers either way, to
+    rounding."""
+    from paper_2406_16238_amd import afqmc as A
+    o = A.default_options()
+    o.reserved[0] = 16
+    outs = []
+    for opts in (None, o):
+        p = Pair(gi.SMALL.system, 10, 0.01, options=opts)
+        try:
+            worst, (w, amp, e, est) = _free_run(p, 10, 6, 3)
+            assert max(worst.values()) < TOL, worst
+            outs.append((w.phi.cpu().numpy(), amp.cpu().numpy(), e.cpu().numpy()))
+        finally:
+            p.close()
+    (a, aa, ea), (b, ab, eb) = outs
+    assert cmp_rel(a, b, np.abs(b).max()) < 1e-13
+    assert phase_diff(aa, ab) < 1e-12
+    assert cmp_rel(ea, eb) < 1e-12
+
+
+def test_free_estimator_flags_and_weights():
+    """The estimate over chosen amplitudes, weights and flags (zero weights,
+    singular and non-finite walkers excluded) against the oracle."""
+    p = Pair(gi.SMALL.system, 12, 0.01)
+    A, torch = p.A, p.torch
+    try:
+        W = 12
+        rng = np.random.default_rng(4)
+        phis = gi.initial_walkers(p.trial, W, noise=0.05, seed=6)
+        w = p.walkers(phis)
+        wt = rng.uniform(0.2, 2.0, W)
+        wt[3] = 0.0
+        fl = np.zeros(W, np.uint32)
+        fl[5] = O.W_SINGULAR
+        fl[8] = O.W_NONFINITE
+        fl[9] = O.W_DEAD          # not an exclusion in free projection
+        a = rng.normal(0, 4, W) + 1j * rng.uniform(-np.pi, np.pi, W)
+        a[0] = 40.0 + 0.5j        # the reference shift keeps large amplitudes finite
+        w.weight.copy_(torch.as_tensor(wt))
+        w.flags.copy_(torch.as_tensor(fl.astype(np.int32)))
+        amp = torch.as_tensor(a, device="cuda")
+        e = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        A.local_energy(p.ctx, w, e)
+        est = torch.empty((1, A.FREE_EST), dtype=torch.float64, device="cuda")
+        A.free_estimator(p.ctx, w, amp, e, est)
+        g = _est_host(est.cpu().numpy()[0])
+        o = O.free_estimator(wt, a, e.cpu().numpy(), fl)
+        assert g["n"] == 9 and _cmp_est(g, o) < 1e-13
+        assert abs(g["r"] - 40.0) == 0.0
+        assert abs(A.free_energy(est.cpu().numpy()[0]) - o["E"]) < 1e-12 * abs(o["E"])
+        # nothing counts: zeros and r = 0
+        w.weight.zero_()
+        A.free_estimator(p.ctx, w, amp, e, est)
+        assert not est.cpu().numpy().any()
+    finally:
+        p.close()
+
+
+def test_nonfinite_field_flags_the_walker():
+    p = Pair(gi.SMALL.system, 6, 0.01)
+    A, torch = p.A, p.torch
+    try:
+        W = 6
+        phis = gi.initial_walkers(p.trial, W, noise=0.03, seed=2)
+        x = gi.FieldStream(1, W, p.ham.nchol).next()
+        x[2, 5] = np.nan
+        w = p.walkers(phis)
+        amp = w.log_ovlp.clone()
+        A.free_propagate(p.ctx, w, torch.as_tensor(x, device="cuda"), amp)
+        ologo = O.initial_logo(p.ham, phis)
+        ophi, ologo, oamp, ofl = O.free_propagate(p.ham, phis, ologo, O.initial_amplitudes(ologo), x)
+        gphi, _, glogo, gfl = p.to_host(w)
+        assert np.array_equal(gfl, ofl) and gfl[2] == O.W_NONFINITE
+        assert cmp_rel(gphi, ophi, np.abs(ophi).max()) < TOL
+        assert phase_diff(amp.cpu().numpy(), oamp) < TOL
+    finally:
+        p.close()
+
+
+def test_free_projection_fp32_propagation():
+    """FP32 propagation in free projection (imaginary plane in FP32) tracks the
+    FP64 free path to single-precision tolerances."""
+    from paper_2406_16238_amd import afqmc as A
+    spec, W = gi.MEDIUM.system, 32
+    res = []
+    for prec in (A.FP64, A.FP32_CONTRACT):
+        p = Pair(spec, W, 0.005, options=A.default_options(prop_precision=prec))
+        try:
+            phis = gi.initial_walkers(p.trial, W, noise=0.02, seed=5)
+            fields = gi.FieldStream(7, W, spec.nchol)
+            w = p.walkers(phis)
+            amp = w.log_ovlp.clone()
+            e = p.torch.empty((W, 3), dtype=p.torch.complex128, device="cuda")
+            est = p.torch.empty((1, A.FREE_EST), dtype=p.torch.float64, device="cuda")
+            for step in range(1, 7):
+                A.free_step(p.ctx, w, p.torch.as_tensor(fields.next(), device="cuda"), amp, e, est,
+                            reortho=step % 3 == 0)
+            p.torch.cuda.synchronize()
+            res.append((w.phi.cpu().numpy(), amp.cpu().numpy(), A.free_energy(est.cpu().numpy()[0])))
+        finally:
+            p.close()
+    (a, aa, ea), (b, ab, eb) = res
+    d = cmp_rel(b, a, np.abs(a).max())
+    assert 0.0 < d < 1e-5
+    assert phase_diff(ab, aa) < 1e-4
+    assert abs(eb - ea) < 1e-4
+
+
+def test_full_size_sampled():
+    """The M = 400 workload in the benchmark's launch configuration: one free
+    step for every walker on the GPU, a sample recomputed by the oracle."""
+    spec = gi.HEADLINE
+    p = Pair(spec.system, spec.nwalkers, spec.dt)
+    A, torch = p.A, p.torch
+    try:
+        W = spec.nwalkers
+        phis = gi.initial_walkers(p.trial, W, noise=0.01, seed=12)
+        x = gi.FieldStream(0, W, spec.system.nchol).next()
+        w = p.walkers(phis)
+        amp = w.log_ovlp.clone()
+        e = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        A.free_step(p.ctx, w, torch.as_tensor(x, device="cuda"), amp, e)
+        gphi, _, glogo, gfl = p.to_host(w)
+        assert not gfl.any()
+        ge, ga = e.cpu().numpy(), amp.cpu().numpy()
+        for k in np.unique(np.linspace(0, W - 1, 5).astype(int)):
+            logo0 = O.overlap_theta(p.ham, phis[k])[0]
+            r = O.free_step_walker(p.ham, phis[k], logo0, logo0, x[k])
+            assert cmp_rel(gphi[k], r["phi"], np.max(np.abs(r["phi"]))) < TOL
+            assert phase_diff(glogo[k], r["logo"]) < TOL
+            assert phase_diff(ga[k], r["log_amp"]) < TOL
+            assert cmp_rel(ge[k], np.array(O.local_energy(p.ham, r["phi"]))) < TOL
+    finally:
+        p.close()
