@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "walker-steps/s (propagate+energy) at M=400,N=40; speed-up vs FP64 at 0.1 mHa"
+METRIC_FREE = "free-projection walker-steps/s (propagate+energy) at M=400,N=40; speed-up vs FP64"
 # dense MI355X peaks per arithmetic type (TFLOP/s)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
 PRECISION_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
@@ -74,6 +75,9 @@ def parse_args(argv=None):
                     help="path reported in the JSON line (the FP64 path is timed too, for the speed-up)")
     ap.add_argument("--prop-precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the propagation (V_HS planes and Taylor terms) of the reported path")
+    ap.add_argument("--projection", default="phaseless", choices=["phaseless", "free"],
+                    help="phaseless AFQMC (the headline) or free projection (same kernels, bare fields, "
+                         "complex amplitudes)")
     ap.add_argument("--api", default="step", choices=["step", "separate"],
                     help="step: afqmc_step (one overlap/LU and one force bias per step); separate: "
                          "afqmc_propagate + afqmc_reorthogonalize + afqmc_local_energy")
@@ -100,17 +104,19 @@ def exchange_flops(M, na, nb, G, W):
     return float(W) * (4.0 * n2 * M * G + 8.0 * n2 * G)
 
 
-def step_flops(M, na, nb, G):
+def step_flops(M, na, nb, G, free=False):
     """Algorithmic flops of one walker-step (both spins, real L and trial,
     complex walkers): exchange + trace + V_HS + Taylor(6) + B1 (twice) + force
-    bias + overlaps and solves."""
+    bias + overlaps and solves.  Free projection: real fields, so V_HS is a
+    real combination of the L^g and each Taylor term a real-by-complex product."""
     n2 = na * na + nb * nb
     nt = na + nb
-    return (4.0 * n2 * M * G + 8.0 * n2 * G + 4.0 * G * M * M + 6 * 8.0 * M * M * nt + 2 * 4.0 * M * M * nt
-            + 4.0 * G * M * nt + 2 * 16.0 * M * n2)
+    f = 0.5 if free else 1.0
+    return (4.0 * n2 * M * G + 8.0 * n2 * G + f * 4.0 * G * M * M + f * 6 * 8.0 * M * M * nt
+            + 2 * 4.0 * M * M * nt + 4.0 * G * M * nt + 2 * 16.0 * M * n2)
 
 
-def cpu_baseline(spec, n_walkers, n_steps):
+def cpu_baseline(spec, n_walkers, n_steps, free=False):
     """The CPU oracle, as it stands, on a bounded sample of the same workload."""
     import numpy as np
     import afqmc_inputs as gi
@@ -128,15 +134,20 @@ def cpu_baseline(spec, n_walkers, n_steps):
     fields = gi.FieldStream(spec.field_seed, n_walkers, s.nchol)
     w = np.ones(n_walkers)
     logo = O.initial_logo(ham, phis)
+    amp = O.initial_amplitudes(logo)
     t0 = time.perf_counter()
     for k in range(1, n_steps + 1):
-        phis, w, logo, _ = O.propagate(ham, phis, w, logo, fields.next())
+        if free:
+            phis, logo, amp, _ = O.free_propagate(ham, phis, logo, amp, fields.next())
+        else:
+            phis, w, logo, _ = O.propagate(ham, phis, w, logo, fields.next())
         if k % spec.reortho_every == 0:
             phis, logo = O.reorthogonalize(ham, phis, logo)
         O.local_energies(ham, phis)
     dt = time.perf_counter() - t0
     return {"value": n_walkers * n_steps / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_walkers} walkers x {n_steps} steps (propagate + local energy, FP64) of {spec.name}, "
+            "sample": f"{n_walkers} walkers x {n_steps} {'free-projection ' if free else ''}steps "
+                      f"(propagate + local energy, FP64) of {spec.name}, "
                       f"{dt:.1f} s on the host CPU, numpy complex128"}
 
 
@@ -147,10 +158,22 @@ def time_path(A, torch, ctx, spec, trial, xs, args):
     walkers = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
     A.overlap(ctx, walkers)
     e_out = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
-    est = torch.empty((1, 4), dtype=torch.float64, device="cuda")
+    free = args.projection == "free"
+    est = torch.empty((1, A.FREE_EST if free else 4), dtype=torch.float64, device="cuda")
+    amp = walkers.log_ovlp.clone()
 
     def step(k):
         reo = (k + 1) % spec.reortho_every == 0
+        if free:
+            if args.api == "step":
+                A.free_step(ctx, walkers, xs[k], amp, e_out, est, reortho=reo)
+                return
+            A.free_propagate(ctx, walkers, xs[k], amp)
+            if reo:
+                A.reorthogonalize(ctx, walkers)
+            A.local_energy(ctx, walkers, e_out)
+            A.free_estimator(ctx, walkers, amp, e_out, est)
+            return
         if args.api == "step":
             A.step(ctx, walkers, xs[k], e_out, est, reortho=reo)
             return
@@ -176,8 +199,11 @@ def time_path(A, torch, ctx, spec, trial, xs, args):
     phases = A.get_timings(ctx)
     A.set_timing(ctx, False)
     h = est.cpu().numpy()[0]
-    return {"total_ms": total_ms, "phases": phases, "walkers": walkers,
-            "mixed_energy": float(h[0] / h[1]) if h[1] > 0 else float("nan"),
+    if free:
+        energy = A.free_energy(h).real if h[9] > 0 else float("nan")
+    else:
+        energy = float(h[0] / h[1]) if h[1] > 0 else float("nan")
+    return {"total_ms": total_ms, "phases": phases, "walkers": walkers, "mixed_energy": energy,
             "flagged": int((walkers.flags.cpu().numpy() != 0).sum())}
 
 
@@ -457,9 +483,10 @@ def main(argv=None):
                 "kernel": f"{kernel} (one spin block of {W} walkers per launch)", "avg_launch_ms": round(avg_ms, 4),
                 "flops_per_launch": ex_flops,
                 "executed_tflops": round(achieved * PRODUCTS[rep], 3)}
-    step_tf = step_flops(M, s.nalpha, s.nbeta, G) * W / (ms_per_step * 1e-3) / 1e12
+    free = args.projection == "free"
+    step_tf = step_flops(M, s.nalpha, s.nbeta, G, free) * W / (ms_per_step * 1e-3) / 1e12
 
-    out = {"metric": METRIC, "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
+    out = {"metric": METRIC_FREE if free else METRIC, "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": ("f64" if rep == "fp64" else f"{rep} (exchange, force bias)") +
@@ -468,7 +495,8 @@ def main(argv=None):
                    "exp(-g/tau)/M, trial = lowest orbitals of a Fock-like matrix, N(0,1) fields)",
            "config": {"workload": spec.name, "nbasis": M, "nalpha": s.nalpha, "nbeta": s.nbeta, "nchol": G,
                       "nwalkers": W, "dt": spec.dt, "reortho_every": spec.reortho_every,
-                      "precision": rep, "propagation": args.prop_precision, "taylor_order": 6, "api": args.api},
+                      "precision": rep, "propagation": args.prop_precision, "taylor_order": 6, "api": args.api,
+                      "projection": args.projection},
            "roofline": roofline,
            "step_algorithmic_tflops": round(step_tf, 3),
            "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
@@ -502,7 +530,7 @@ def main(argv=None):
     del xs, runs
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_walkers, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_walkers, args.cpu_steps, free)
     print(json.dumps(out), flush=True)
     return 0
 
