@@ -124,7 +124,10 @@ typedef struct {
                                bit 1: VALU kernels for the force bias, V_HS, B1
                                and Taylor products; bit 2: the generic MFMA GEMM
                                for the Taylor terms; bit 3: V_HS from the full
-                               (unpacked) L^g (all for comparison runs);
+                               (unpacked) L^g; bit 4: free projection through
+                               both V_HS planes; bit 5: four real products per
+                               Taylor term instead of three (all for comparison
+                               runs);
                                reserved[1]: walkers per exchange workgroup (1, 2
                                or 4); reserved[2]: exchange tile order (1 = Cholesky
                                block fastest, g > 1 = groups of g walker blocks);
@@ -132,7 +135,8 @@ typedef struct {
                                reserved[3]: tile shape of the V_HS product (0 =
                                default, 1..4 alternatives for comparison runs);
                                reserved[4]: tile shape of the Taylor-term kernels
-                               (0 = default, 1..8 alternatives);
+                               (0 = default, 1..8 four-product alternatives,
+                               9..10 three-product alternatives);
                                other entries: zero                                */
 } afqmc_options;
 

@@ -74,6 +74,7 @@ struct System {
   int taylor_variant = 0;      // tile shape of the Taylor-term kernel
   bool pack_chol = true;       // V_HS from the packed upper triangles of the L^g
   bool free_full = false;      // free projection through both V_HS planes (comparison runs)
+  bool taylor4 = false;        // four real products per Taylor term (comparison runs)
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans
   int ex_group = 0;            // tile order of the MFMA exchange launches (see tile_of)

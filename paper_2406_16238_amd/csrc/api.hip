@@ -416,6 +416,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   s.taylor_variant = c->taylor_variant;
   s.pack_chol = s.use_mfma_gemm && !(c->debug_bits & 8);
   s.free_full = (c->debug_bits & 16) != 0;
+  s.taylor4 = (c->debug_bits & 32) != 0;
   s.prop32 = c->opt.prop_precision == AFQMC_FP32_CONTRACT;
   if (s.prop32 && !(s.pack_chol && prop32_supported(s.M, s.Nt)))
     return fail(AFQMC_ERR_UNSUPPORTED, "FP32 propagation needs the MFMA path, M a multiple of 4 and at most 96 "
@@ -813,7 +814,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   c->debug_bits = o.reserved[0];
   if (o.reserved[3] >= 0 && o.reserved[3] <= 4) c->vhs_variant = o.reserved[3];
-  if (o.reserved[4] >= 0 && o.reserved[4] <= 8) c->taylor_variant = o.reserved[4];
+  if (o.reserved[4] >= 0 && o.reserved[4] <= 10) c->taylor_variant = o.reserved[4];
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
     c->ex_wx = o.reserved[1];
     c->ex_wx_forced = true;

@@ -158,6 +158,163 @@ __global__ __launch_bounds__(64 * WM * WN) void k_taylor_mfma(const double *__re
   }
 }
 
+// The same term with three real products instead of four (the 3M form of a
+// complex product): with A = Ar + i Ai and T = Tr + i Ti,
+//   P1 = Ar Tr,  P2 = Ai Ti,  P3 = (Ar + Ai)(Tr + Ti),
+//   A T = (P1 - P2) + i (P3 - P1 - P2),
+// each an M x M by M x Nt real product, so a term costs 6 M^2 Nt flops instead
+// of 8.  A workgroup owns BM = 4 WM TR rows and BNC = 16 WN TN >= Nt complex
+// columns of one walker; wave (wm, wn) holds the three products of its
+// 4 TR x 16 TN block, so the combination happens in registers and each lane
+// writes whole complex entries.  Ar + Ai and Tr + Ti are formed from the
+// staged operands in registers.  LDS per stage: the Ar and Ai rows (k-major)
+// and the Tr and Ti planes of 16 contraction indices.
+template <int WM, int WN, int TR, int TN>
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__restrict__ vhs,
+                                                             const double2 *__restrict__ tin,
+                                                             double2 *__restrict__ tout,
+                                                             double2 *__restrict__ tacc, int M, int Nt, int W,
+                                                             int nrt, double alpha) {
+  constexpr int NTH = 64 * WM * WN;
+  constexpr int BM = WM * 4 * TR, BNC = WN * 16 * TN;
+  constexpr int LDA = BM + 1, LDB = BNC + 1;
+  constexpr int AV = 2 * BM * TKC / 2;              // double2 (k pairs) of Ar and Ai per stage
+  constexpr int BV = TKC * BNC;                     // complex entries of T per stage
+  constexpr int APT = (AV + NTH - 1) / NTH, BPT = (BV + NTH - 1) / NTH;
+  extern __shared__ double tsm[];
+  double *sA = tsm;                        // [2 buf][2 plane][TKC][LDA]
+  double *sB = tsm + 2 * 2 * TKC * LDA;    // [2 buf][2 plane][TKC][LDB]
+
+  const int ntiles = W * nrt;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int t = x * per + min(x, rem) + jx;
+  const int w = t / nrt, i0 = (t - w * nrt) * BM;
+
+  const size_t MM = (size_t)M * M;
+  const double *Aw = vhs + (size_t)w * 2 * MM;
+  const double2 *Tw = tin + (size_t)w * M * Nt;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv / WN, wn = wv - (wv / WN) * WN;
+  const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
+
+  double2 ra[APT], rb[BPT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * NTH;                 // (plane, row, k pair)
+      const int pr = e / (TKC / 2), kp = e - pr * (TKC / 2);
+      const int pl = pr / BM, row = pr - pl * BM;
+      const int gi = i0 + row, gk = k0 + 2 * kp;
+      ra[r] = (e < AV && gi < M && gk < M)
+                  ? *reinterpret_cast<const double2 *>(Aw + pl * MM + (size_t)gi * M + gk)
+                  : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = tid + r * NTH;                 // (k, complex column j)
+      const int kk = e / BNC, j = e - kk * BNC;
+      const int gk = k0 + kk;
+      rb[r] = (e < BV && j < Nt && gk < M) ? Tw[(size_t)gk * Nt + j] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int buf) {
+    double *a = sA + buf * 2 * TKC * LDA;
+    double *b = sB + buf * 2 * TKC * LDB;
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * NTH;
+      if (e < AV) {
+        const int pr = e / (TKC / 2), kp = e - pr * (TKC / 2);
+        const int pl = pr / BM, row = pr - pl * BM;
+        a[(pl * TKC + 2 * kp) * LDA + row] = ra[r].x;
+        a[(pl * TKC + 2 * kp + 1) * LDA + row] = ra[r].y;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = tid + r * NTH;
+      if (e < BV) {
+        const int kk = e / BNC, j = e - kk * BNC;
+        b[kk * LDB + j] = rb[r].x;
+        b[(TKC + kk) * LDB + j] = rb[r].y;
+      }
+    }
+  };
+
+  double p1[TR][TN], p2[TR][TN], p3[TR][TN];
+#pragma unroll
+  for (int i = 0; i < TR; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = 0.0;
+
+  const int nchunk = (M + TKC - 1) / TKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * TKC);
+    const double *ar = sA + buf * 2 * TKC * LDA + wm * 4 * TR + l4;
+    const double *ai = ar + TKC * LDA;
+    const double *br = sB + buf * 2 * TKC * LDB + wn * 16 * TN + lr;
+    const double *bi = br + TKC * LDB;
+#pragma unroll
+    for (int ks = 0; ks < TKC / 4; ++ks) {
+      const int kr = ks * 4 + lk;
+      double xr[TR], xi[TR], yr[TN], yi[TN];
+#pragma unroll
+      for (int i = 0; i < TR; ++i) {
+        xr[i] = ar[kr * LDA + i * 4];
+        xi[i] = ai[kr * LDA + i * 4];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        yr[j] = br[kr * LDB + j * 16];
+        yi[j] = bi[kr * LDB + j * 16];
+      }
+#pragma unroll
+      for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p1[i][j], 0, 0, 0);
+          p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < TR; ++i) xr[i] += xi[i];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) yr[j] += yi[j];
+#pragma unroll
+      for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) p3[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p3[i][j], 0, 0, 0);
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  double2 *to = tout + (size_t)w * M * Nt;
+  double2 *ta = tacc + (size_t)w * M * Nt;
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    const int gi = i0 + wm * 4 * TR + 4 * i + lk;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = wn * 16 * TN + 16 * j + lr;
+      if (gi < M && c < Nt) {
+        const size_t off = (size_t)gi * Nt + c;
+        const double re = p1[i][j] - p2[i][j];
+        const double im = (p3[i][j] - p1[i][j]) - p2[i][j];
+        const double2 v = make_double2(alpha * re, alpha * im);
+        to[off] = v;
+        const double2 o = ta[off];
+        ta[off] = make_double2(o.x + v.x, o.y + v.y);
+      }
+    }
+  }
+}
+
 namespace {
 template <int WM, int WN, int TR, int TN>
 hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
@@ -180,10 +337,52 @@ hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double
 }
 }  // namespace
 
+namespace {
+template <int WM, int WN, int TR, int TN>
+hipError_t run_taylor3m(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
+  constexpr int BM = WM * 4 * TR, BNC = WN * 16 * TN;
+  const size_t lds = 2ull * 2 * TKC * ((BM + 1) + (BNC + 1)) * sizeof(double);
+  auto k = k_taylor3m<WM, WN, TR, TN>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int nrt = (s.M + BM - 1) / BM;
+  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * WM * WN), lds, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt,
+                     W, nrt, alpha);
+  return hipGetLastError();
+}
+
+template <int TR>
+hipError_t run_taylor3m_tn(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
+  switch ((s.Nt + 15) / 16) {
+    case 1: return run_taylor3m<4, 1, TR, 1>(s, tin, tout, alpha, W, st);
+    case 2: return run_taylor3m<4, 1, TR, 2>(s, tin, tout, alpha, W, st);
+    case 3: return run_taylor3m<4, 1, TR, 3>(s, tin, tout, alpha, W, st);
+    case 4: return run_taylor3m<4, 1, TR, 4>(s, tin, tout, alpha, W, st);
+    case 5: return run_taylor3m<4, 1, TR, 5>(s, tin, tout, alpha, W, st);
+    // 96 columns: 32-row tiles keep the three accumulator sets in registers
+    default: return run_taylor3m<4, 1, 2, 6>(s, tin, tout, alpha, W, st);
+  }
+}
+}  // namespace
+
 bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <= 96; }
 
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
                               hipStream_t st, int kbeg) {
+  // a complex V_HS: three real products per term (taylor4, or variants 1..8,
+  // keep the four-product kernel for comparison runs; 9..10 other 3M row tiles)
+  if (kbeg == 0 && !s.taylor4 && (s.taylor_variant == 0 || s.taylor_variant >= 9)) {
+    switch (s.taylor_variant) {
+      case 9: return run_taylor3m_tn<2>(s, tin, tout, alpha, W, st);
+      case 10: return run_taylor3m_tn<4>(s, tin, tout, alpha, W, st);
+      default: return run_taylor3m_tn<3>(s, tin, tout, alpha, W, st);
+    }
+  }
   if (s.Nt <= 16) return run_taylor<2, 2, 16, 1>(s, tin, tout, alpha, W, st, kbeg);
   if (s.Nt <= 32) return run_taylor<2, 2, 16, 2>(s, tin, tout, alpha, W, st, kbeg);
   if (s.Nt <= 48) return run_taylor<2, 2, 12, 3>(s, tin, tout, alpha, W, st, kbeg);
