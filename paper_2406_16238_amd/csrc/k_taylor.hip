@@ -169,7 +169,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_taylor_mfma(const double *__re
 // writes whole complex entries.  Ar + Ai and Tr + Ti are formed from the
 // staged operands in registers.  LDS per stage: the Ar and Ai rows (k-major)
 // and the Tr and Ti planes of 16 contraction indices.
-template <int WM, int WN, int TR, int TN>
+// IMAG: A = i Ai (free projection, a real-field V_HS): A T = -Ai Ti + i Ai Tr,
+// two products P1 = Ai Tr, P2 = Ai Ti and only the Ai rows staged.
+template <int WM, int WN, int TR, int TN, bool IMAG = false>
 __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__restrict__ vhs,
                                                              const double2 *__restrict__ tin,
                                                              double2 *__restrict__ tout,
@@ -178,12 +180,13 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
   constexpr int NTH = 64 * WM * WN;
   constexpr int BM = WM * 4 * TR, BNC = WN * 16 * TN;
   constexpr int LDA = BM + 1, LDB = BNC + 1;
-  constexpr int AV = 2 * BM * TKC / 2;              // double2 (k pairs) of Ar and Ai per stage
+  constexpr int NPL = IMAG ? 1 : 2;                 // staged planes of A
+  constexpr int AV = NPL * BM * TKC / 2;            // double2 (k pairs) of A per stage
   constexpr int BV = TKC * BNC;                     // complex entries of T per stage
   constexpr int APT = (AV + NTH - 1) / NTH, BPT = (BV + NTH - 1) / NTH;
   extern __shared__ double tsm[];
-  double *sA = tsm;                        // [2 buf][2 plane][TKC][LDA]
-  double *sB = tsm + 2 * 2 * TKC * LDA;    // [2 buf][2 plane][TKC][LDB]
+  double *sA = tsm;                          // [2 buf][NPL plane][TKC][LDA]
+  double *sB = tsm + 2 * NPL * TKC * LDA;    // [2 buf][2 plane][TKC][LDB]
 
   const int ntiles = W * nrt;
   const int per = ntiles >> 3, rem = ntiles & 7;
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
       const int pl = pr / BM, row = pr - pl * BM;
       const int gi = i0 + row, gk = k0 + 2 * kp;
       ra[r] = (e < AV && gi < M && gk < M)
-                  ? *reinterpret_cast<const double2 *>(Aw + pl * MM + (size_t)gi * M + gk)
+                  ? *reinterpret_cast<const double2 *>(Aw + (IMAG ? 1 : pl) * MM + (size_t)gi * M + gk)
                   : make_double2(0.0, 0.0);
     }
 #pragma unroll
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
     }
   };
   auto store = [&](int buf) {
-    double *a = sA + buf * 2 * TKC * LDA;
+    double *a = sA + buf * NPL * TKC * LDA;
     double *b = sB + buf * 2 * TKC * LDB;
 #pragma unroll
     for (int r = 0; r < APT; ++r) {
@@ -256,8 +259,8 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nchunk) load((ch + 1) * TKC);
-    const double *ar = sA + buf * 2 * TKC * LDA + wm * 4 * TR + l4;
-    const double *ai = ar + TKC * LDA;
+    const double *ar = sA + buf * NPL * TKC * LDA + wm * 4 * TR + l4;
+    const double *ai = IMAG ? ar : ar + TKC * LDA;
     const double *br = sB + buf * 2 * TKC * LDB + wn * 16 * TN + lr;
     const double *bi = br + TKC * LDB;
 #pragma unroll
@@ -266,13 +269,23 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
       double xr[TR], xi[TR], yr[TN], yi[TN];
 #pragma unroll
       for (int i = 0; i < TR; ++i) {
-        xr[i] = ar[kr * LDA + i * 4];
         xi[i] = ai[kr * LDA + i * 4];
+        xr[i] = IMAG ? 0.0 : ar[kr * LDA + i * 4];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         yr[j] = br[kr * LDB + j * 16];
         yi[j] = bi[kr * LDB + j * 16];
+      }
+      if constexpr (IMAG) {
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi[i], yr[j], p1[i][j], 0, 0, 0);
+            p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
+          }
+        continue;
       }
 #pragma unroll
       for (int i = 0; i < TR; ++i)
@@ -304,8 +317,8 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
       const int c = wn * 16 * TN + 16 * j + lr;
       if (gi < M && c < Nt) {
         const size_t off = (size_t)gi * Nt + c;
-        const double re = p1[i][j] - p2[i][j];
-        const double im = (p3[i][j] - p1[i][j]) - p2[i][j];
+        const double re = IMAG ? -p2[i][j] : p1[i][j] - p2[i][j];
+        const double im = IMAG ? p1[i][j] : (p3[i][j] - p1[i][j]) - p2[i][j];
         const double2 v = make_double2(alpha * re, alpha * im);
         to[off] = v;
         const double2 o = ta[off];
@@ -338,11 +351,11 @@ hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double
 }  // namespace
 
 namespace {
-template <int WM, int WN, int TR, int TN>
+template <int WM, int WN, int TR, int TN, bool IMAG = false>
 hipError_t run_taylor3m(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
   constexpr int BM = WM * 4 * TR, BNC = WN * 16 * TN;
-  const size_t lds = 2ull * 2 * TKC * ((BM + 1) + (BNC + 1)) * sizeof(double);
-  auto k = k_taylor3m<WM, WN, TR, TN>;
+  const size_t lds = 2ull * TKC * ((IMAG ? 1 : 2) * (BM + 1) + 2 * (BNC + 1)) * sizeof(double);
+  auto k = k_taylor3m<WM, WN, TR, TN, IMAG>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -356,16 +369,16 @@ hipError_t run_taylor3m(const System &s, const double2 *tin, double2 *tout, doub
   return hipGetLastError();
 }
 
-template <int TR>
+template <int TR, bool IMAG = false>
 hipError_t run_taylor3m_tn(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
   switch ((s.Nt + 15) / 16) {
-    case 1: return run_taylor3m<4, 1, TR, 1>(s, tin, tout, alpha, W, st);
-    case 2: return run_taylor3m<4, 1, TR, 2>(s, tin, tout, alpha, W, st);
-    case 3: return run_taylor3m<4, 1, TR, 3>(s, tin, tout, alpha, W, st);
-    case 4: return run_taylor3m<4, 1, TR, 4>(s, tin, tout, alpha, W, st);
-    case 5: return run_taylor3m<4, 1, TR, 5>(s, tin, tout, alpha, W, st);
+    case 1: return run_taylor3m<4, 1, TR, 1, IMAG>(s, tin, tout, alpha, W, st);
+    case 2: return run_taylor3m<4, 1, TR, 2, IMAG>(s, tin, tout, alpha, W, st);
+    case 3: return run_taylor3m<4, 1, TR, 3, IMAG>(s, tin, tout, alpha, W, st);
+    case 4: return run_taylor3m<4, 1, TR, 4, IMAG>(s, tin, tout, alpha, W, st);
+    case 5: return run_taylor3m<4, 1, TR, 5, IMAG>(s, tin, tout, alpha, W, st);
     // 96 columns: 32-row tiles keep the three accumulator sets in registers
-    default: return run_taylor3m<4, 1, 2, 6>(s, tin, tout, alpha, W, st);
+    default: return run_taylor3m<4, 1, 2, 6, IMAG>(s, tin, tout, alpha, W, st);
   }
 }
 }  // namespace
@@ -376,7 +389,13 @@ hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout
                               hipStream_t st, int kbeg) {
   // a complex V_HS: three real products per term (taylor4, or variants 1..8,
   // keep the four-product kernel for comparison runs; 9..10 other 3M row tiles)
-  if (kbeg == 0 && !s.taylor4 && (s.taylor_variant == 0 || s.taylor_variant >= 9)) {
+  if (!s.taylor4 && (s.taylor_variant == 0 || s.taylor_variant >= 9)) {
+    if (kbeg != 0) {
+      // purely imaginary V_HS (its real plane is not formed): two products
+      if (kbeg != s.M) return hipErrorInvalidValue;
+      return s.taylor_variant == 10 ? run_taylor3m_tn<4, true>(s, tin, tout, alpha, W, st)
+                                    : run_taylor3m_tn<3, true>(s, tin, tout, alpha, W, st);
+    }
     switch (s.taylor_variant) {
       case 9: return run_taylor3m_tn<2>(s, tin, tout, alpha, W, st);
       case 10: return run_taylor3m_tn<4>(s, tin, tout, alpha, W, st);
