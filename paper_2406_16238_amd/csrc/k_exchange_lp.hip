@@ -36,7 +36,6 @@ namespace {
 constexpr int LWX = 2;      // walkers per workgroup
 constexpr int LWY = 2;      // Cholesky-vector groups per workgroup
 constexpr int LKC = 32;     // contraction rows per LDS stage
-constexpr int BPAD = 8;     // bf16 padding of a staged row (row stride 40 elements = 80 bytes)
 }  // namespace
 
 // Trace epilogue shared by both forms.  T of each wave (ROWW x CP floats) is in
@@ -208,15 +207,21 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   constexpr int CP = 2 * NR, CT = CP / 16;
   constexpr int ROWS = LWY * ROWW;
   constexpr int COLS = LWX * CP;
-  constexpr int RS = LKC + BPAD;                 // staged row stride (bf16)
+  // Staged rows are LKC = 32 bf16 (64 bytes) with no padding; the four 16-byte
+  // k groups of row r sit in slots k8 ^ swz(r), so the 16 rows one MFMA operand
+  // read touches at one k group fall in distinct banks, and a row is still one
+  // 64-byte run for the stores.
+  constexpr int RS = LKC;                        // staged row stride (bf16)
   constexpr int ASZ = NT * ROWS * RS, BSZ = NT * COLS * RS;   // bf16 per stage
   constexpr int AV = NT * ROWS * (LKC / 8), BV = NT * COLS * (LKC / 8);  // 16-byte vectors per stage
   constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
   constexpr int TSF = CP + 2;
-  // The two-term form keeps two workgroups per CU (registers for two waves per
-  // SIMD, under 80 KB of LDS): one staging buffer refilled between two
-  // barriers, and the trace epilogue one Cholesky vector of each wave at a time.
-  constexpr int NBUF = (NT == 2) ? 1 : 2;
+  static_assert(ROWW % 16 == 0 && CP % 16 == 0 && LKC == 32, "row bases keep the swizzle of the lane's row");
+  // Two staging buffers (one barrier per chunk).  The two-term form fits two
+  // workgroups per CU (80 KB of LDS, registers for two waves per SIMD) and does
+  // the trace epilogue one Cholesky vector of each wave at a time.
+  constexpr int NBUF = 2;
+  auto swz = [](int r) { return ((r >> 1) ^ (r >> 2)) & 3; };
   extern __shared__ __bf16 bsm[];
   __bf16 *sA = bsm, *sB = bsm + NBUF * ASZ;
 
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
       const int v = tid + r * kThreads;
       if (v < AV) {
         const int k8 = v % (LKC / 8), t = v / (LKC / 8);
-        *reinterpret_cast<uint4 *>(a + t * RS + 8 * k8) = ra[r];
+        *reinterpret_cast<uint4 *>(a + t * RS + 8 * (k8 ^ swz(t))) = ra[r];
       }
     }
 #pragma unroll
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
       const int v = tid + r * kThreads;
       if (v < BV) {
         const int k8 = v % (LKC / 8), t = v / (LKC / 8);
-        *reinterpret_cast<uint4 *>(b + t * RS + 8 * k8) = rb[r];
+        *reinterpret_cast<uint4 *>(b + t * RS + 8 * (k8 ^ swz(t))) = rb[r];
       }
     }
   };
@@ -285,8 +290,8 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = NBUF == 2 ? (ch & 1) : 0;
     if (ch + 1 < nchunk) load((ch + 1) * LKC);
-    const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * lk;
-    const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * lk;
+    const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * (lk ^ swz(lr));
+    const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * (lk ^ swz(lr));
     bf8v ah[RT], am[RT], bh[CT], bm[CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
@@ -482,8 +487,8 @@ size_t lds_f32(int nr) {
 }
 size_t lds_bf(int nr, int nt) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
-  const size_t nbuf = nt == 2 ? 1 : 2, erows = nt == 2 ? nr : roww;
-  const size_t stage = nbuf * nt * (LWY * roww + LWX * cp) * (LKC + BPAD) * sizeof(__bf16);
+  const size_t nbuf = 2, erows = nt == 2 ? nr : roww;
+  const size_t stage = nbuf * nt * (LWY * roww + LWX * cp) * LKC * sizeof(__bf16);
   const size_t epi = 4ull * erows * (cp + 2) * sizeof(float);
   return stage > epi ? stage : epi;
 }
