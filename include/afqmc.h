@@ -133,7 +133,7 @@ typedef struct {
                                block fastest, g > 1 = groups of g walker blocks);
                                either one fixes the launch shape (no tuning);
                                reserved[3]: tile shape of the V_HS product (0 =
-                               default, 1..4 alternatives for comparison runs);
+                               default, 1..8 alternatives for comparison runs);
                                reserved[4]: tile shape of the Taylor-term kernels
                                (0 = default, 1..8 four-product alternatives,
                                9..10 three-product alternatives);

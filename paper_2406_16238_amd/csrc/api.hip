@@ -42,7 +42,7 @@ struct afqmc_ctx {
   bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   int debug_bits = 0;                // reserved[0]
-  int vhs_variant = 0;               // reserved[3]: tile shape of the V_HS GEMM (0 = default, 1..4 others)
+  int vhs_variant = 0;               // reserved[3]: tile shape of the V_HS GEMM (0 = default, 1..8 others)
   int taylor_variant = 0;            // reserved[4]: tile shape of the Taylor kernels (0 = default, others 1..8)
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
   int ex_group = 8;                  // exchange tile order (reserved[2]: 1 = plain, g > 1 = groups of g)
@@ -813,7 +813,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   c->debug_bits = o.reserved[0];
-  if (o.reserved[3] >= 0 && o.reserved[3] <= 4) c->vhs_variant = o.reserved[3];
+  if (o.reserved[3] >= 0 && o.reserved[3] <= 8) c->vhs_variant = o.reserved[3];
   if (o.reserved[4] >= 0 && o.reserved[4] <= 10) c->taylor_variant = o.reserved[4];
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
     c->ex_wx = o.reserved[1];

@@ -244,6 +244,10 @@ hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st, int variant) {
     case 2: return run<2, 2, 4, 4, 0, 0, 2>(a, st);
     case 3: return run<2, 2, 2, 4, 0, 0, 2>(a, st);
     case 4: return run<1, 4, 8, 2, 0, 0, 1>(a, st);
+    case 5: return run<4, 1, 2, 6, 0, 0, 2>(a, st);
+    case 6: return run<4, 1, 2, 5, 0, 0, 2>(a, st);
+    case 7: return run<4, 1, 2, 4, 0, 0, 2>(a, st);
+    case 8: return run<4, 1, 1, 8, 0, 0, 2>(a, st);
     default: return run<2, 2, 4, 3, 0, 0, 2>(a, st);
   }
 }
