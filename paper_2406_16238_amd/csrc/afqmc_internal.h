@@ -63,6 +63,8 @@ struct System {
   double *yp = nullptr, *vhs = nullptr, *wsc = nullptr;
   double2 *logo_now = nullptr, *logo_new = nullptr, *e1 = nullptr, *ej = nullptr, *ekpart = nullptr;
   uint32_t *stat_now = nullptr, *stat_new = nullptr;
+  double2 *opart = nullptr;    // per-spin-block scratch of the overlap and Gram-Schmidt kernels, [W][2]
+  uint32_t *ospart = nullptr;   // [W][2]
 
   int fb_ksplit = 1;  // split-K slices of the force-bias contraction
   int ex_gb = 1;      // Cholesky vectors per workgroup of the VALU exchange kernel
@@ -147,12 +149,14 @@ hipError_t gemm_fb_mfma(const GemmArgs &a, hipStream_t st);
 hipError_t gemm_nn_mfma(const GemmArgs &a, hipStream_t st);
 
 // Overlap, log-determinant and (optionally) Theta for every walker.
+// part: [W][2] double2 and spart: [W][2] uint32 scratch (per spin block)
 hipError_t launch_ovlp_theta(const double2 *phi, const double *trial, int M, int Na, int Nb, int W,
-                             double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or,
-                             hipStream_t st);
+                             double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or, hipStream_t st,
+                             double2 *part, uint32_t *spart);
 hipError_t ovlp_enable_lds(int nmax);
 // Modified Gram-Schmidt per spin block, log_ovlp -= sum log R_ii.
-hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st);
+// scratch: [W][2] doubles
+hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st, double *scratch);
 
 // Force bias: split-K contraction into fbpart, then the epilogues.
 hipError_t launch_force_bias_gemm(const System &s, const double2 *theta, int W, hipStream_t st);

@@ -216,7 +216,8 @@ struct Plan {
   size_t lp_bytes[2][2];  // reduced-precision operands per spin: [lhs, rhs] in bytes
   uint64_t bytes() const {
     return 8ull * (L + LtT + htT + trial + B1 + lmf + yp + vhs + wsc + LtS0 + LtS1 + Lp + vhsp) +
-           16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart) + 4ull * 2 * stat + 4ull * vhs32 + 16ull * t32 +
+           16ull * (theta + fbpart + 3 * tbuf + 5 * wvec2 + ekpart + 2 * stat) + 4ull * 4 * stat + 4ull * vhs32 +
+           16ull * t32 +
            lp_bytes[0][0] +
            lp_bytes[0][1] + lp_bytes[1][0] + lp_bytes[1][1];
   }
@@ -323,7 +324,7 @@ afqmc_status local_energy_sys(afqmc_ctx *c, System &s, const double2 *phi, int W
                               const double *weight, hipStream_t st, bool have_theta = false) {
   if (!have_theta) {
     Phase ph(c, AFQMC_PH_OVERLAP, st);
-    AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_new, s.stat_new, nullptr, st),
+    AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_new, s.stat_new, nullptr, st, s.opart, s.ospart),
               "overlap kernel");
   }
   if (s.ex_mode == AFQMC_EX_CV && W == s.W) return cv_energy_sys(c, s, W, e_out, est, weight, st);
@@ -457,6 +458,7 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
             dalloc(c, &s.tacc, p.tbuf) && dalloc(c, &s.wsc, p.wsc) && dalloc(c, &s.logo_now, p.wvec2) &&
             dalloc(c, &s.logo_new, p.wvec2) && dalloc(c, &s.e1, p.wvec2) && dalloc(c, &s.ej, p.wvec2) &&
             dalloc(c, &s.ekpart, p.ekpart) && dalloc(c, &s.stat_now, p.stat) && dalloc(c, &s.stat_new, p.stat) &&
+            dalloc(c, &s.opart, 2 * p.stat) && dalloc(c, &s.ospart, 2 * p.stat) &&
             (p.LtS0 == 0 || dalloc(c, &s.LtS[0], p.LtS0)) && (p.LtS1 == 0 || dalloc(c, &s.LtS[1], p.LtS1)) &&
             (p.Lp == 0 || (dalloc(c, &s.Lp, p.Lp) && dalloc(c, &s.vhsp, p.vhsp)));
   for (int sp = 0; sp < 2 && ok; ++sp) {
@@ -913,7 +915,7 @@ static afqmc_status apply_propagator(afqmc_ctx *ctx, System &s, double2 *phi, bo
   {
     Phase ph(ctx, AFQMC_PH_OVERLAP, st);
     AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, want_theta ? s.theta : nullptr, s.logo_new,
-                                s.stat_new, nullptr, st),
+                                s.stat_new, nullptr, st, s.opart, s.ospart),
               "overlap kernel");
   }
   return AFQMC_OK;
@@ -937,7 +939,7 @@ static afqmc_status propagate_sys(afqmc_ctx *ctx, System &s, const afqmc_walkers
   } else {
     {
       Phase ph(ctx, AFQMC_PH_OVERLAP, st);
-      AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_now, s.stat_now, nullptr, st),
+      AFQMC_HIP(launch_ovlp_theta(phi, s.trial, s.M, s.Na, s.Nb, W, s.theta, s.logo_now, s.stat_now, nullptr, st, s.opart, s.ospart),
                 "overlap kernel");
     }
     {
@@ -1018,7 +1020,7 @@ afqmc_status step_body(afqmc_ctx *ctx, const afqmc_walkers *w, const double *con
       {
         Phase ph(ctx, AFQMC_PH_OVERLAP, ls);
         AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
-                                    s.logo_now, s.stat_now, nullptr, ls),
+                                    s.logo_now, s.stat_now, nullptr, ls, s.opart, s.ospart),
                   "overlap kernel");
       }
       afqmc_status r = exchange_sys(ctx, s, s.theta, s.W, s.fbpart, ls);
@@ -1031,7 +1033,7 @@ afqmc_status step_body(afqmc_ctx *ctx, const afqmc_walkers *w, const double *con
     if (flags & AFQMC_STEP_REORTHO) {
       Phase ph(ctx, AFQMC_PH_REORTHO, ls);
       AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
-                           static_cast<double2 *>(w[i].log_ovlp), ls),
+                           static_cast<double2 *>(w[i].log_ovlp), ls, reinterpret_cast<double *>(s.opart)),
                 "Gram-Schmidt kernel");
     }
     r = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, static_cast<double2 *>(e_out[i]),
@@ -1146,7 +1148,7 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void 
     System &s = ctx->sys[i];
     Phase ph(ctx, AFQMC_PH_REORTHO, ls);
     AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
-                         static_cast<double2 *>(w[i].log_ovlp), ls),
+                         static_cast<double2 *>(w[i].log_ovlp), ls, reinterpret_cast<double *>(s.opart)),
               "Gram-Schmidt kernel");
     return AFQMC_OK;
   });
@@ -1163,7 +1165,7 @@ afqmc_status afqmc_overlap(afqmc_ctx *ctx, const afqmc_walkers *w, void *hip_str
   return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
     System &s = ctx->sys[i];
     AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, nullptr,
-                                static_cast<double2 *>(w[i].log_ovlp), s.stat_new, w[i].flags, ls),
+                                static_cast<double2 *>(w[i].log_ovlp), s.stat_new, w[i].flags, ls, s.opart, s.ospart),
               "overlap kernel");
     return AFQMC_OK;
   });
@@ -1180,7 +1182,7 @@ afqmc_status afqmc_greens_function(afqmc_ctx *ctx, const afqmc_walkers *w, void 
   for (size_t i = 0; i < ctx->sys.size(); ++i) {
     System &s = ctx->sys[i];
     AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W,
-                                static_cast<double2 *>(theta_out[i]), s.logo_new, s.stat_new, nullptr, st),
+                                static_cast<double2 *>(theta_out[i]), s.logo_new, s.stat_new, nullptr, st, s.opart, s.ospart),
               "overlap kernel");
   }
   return AFQMC_OK;
@@ -1196,7 +1198,7 @@ afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w, void *cons
   for (size_t i = 0; i < ctx->sys.size(); ++i) {
     System &s = ctx->sys[i];
     AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
-                                s.logo_new, s.stat_new, nullptr, st),
+                                s.logo_new, s.stat_new, nullptr, st, s.opart, s.ospart),
               "overlap kernel");
     AFQMC_HIP(launch_force_bias_gemm(s, s.theta, s.W, st), "force-bias kernel");
     s.fb_slices = s.fb_ksplit;
@@ -1219,7 +1221,7 @@ afqmc_status afqmc_cv_collect(afqmc_ctx *ctx, const afqmc_walkers *w, double *co
     {
       Phase ph(ctx, AFQMC_PH_OVERLAP, ls);
       AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
-                                  s.logo_new, s.stat_new, nullptr, ls),
+                                  s.logo_new, s.stat_new, nullptr, ls, s.opart, s.ospart),
                 "overlap kernel");
     }
     {
@@ -1472,7 +1474,7 @@ afqmc_status afqmc_free_step(afqmc_ctx *ctx, const afqmc_walkers *w, const doubl
     if (flags & AFQMC_STEP_REORTHO) {
       Phase ph(ctx, AFQMC_PH_REORTHO, ls);
       AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
-                           static_cast<double2 *>(w[i].log_ovlp), ls),
+                           static_cast<double2 *>(w[i].log_ovlp), ls, reinterpret_cast<double *>(s.opart)),
                 "Gram-Schmidt kernel");
     }
     rr = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, e, nullptr, w[i].weight, ls, true);

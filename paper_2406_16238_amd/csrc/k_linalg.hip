@@ -6,7 +6,8 @@
 // Green's function G^s_pq = <a+_p a_q> = sum_i Psi_pi Theta_qi with
 // Theta_s = phi_s O_s^-1.  One workgroup per walker holds O_s in LDS and inverts
 // it in place by Gauss-Jordan elimination with partial (row) pivoting; the
-// pivots give the determinant.
+// pivots give the determinant.  The two spin blocks of a walker run in separate
+// workgroups; a second small kernel adds their log-determinants.
 #include "afqmc_internal.h"
 #include "device_util.h"
 
@@ -17,21 +18,22 @@ constexpr int OKQ = 32;                                   // rows of phi / Psi s
 constexpr int OMAXE = (kMaxSpinOrbitals * kMaxSpinOrbitals + kThreads - 1) / kThreads;  // O entries per thread
 }  // namespace
 
-// One workgroup per walker, spin blocks in turn.  LDS: O (N x N complex, inverted
-// in place), plus staging for OKQ rows of Psi_s (real) and phi_s (complex).
+// One workgroup per (walker, spin block).  LDS: O (N x N complex, inverted in
+// place), plus staging for OKQ rows of Psi_s (real) and phi_s (complex).
+// part[w][s] = (log |det O_s|, sum of pivot phases, not reduced), spart[w][s] = 1
+// when O_s is singular (then Theta_s is not written).
 __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restrict__ phi,
                                                         const double *__restrict__ trial, int M, int Na,
                                                         int Nb, double2 *__restrict__ theta,
-                                                        double2 *__restrict__ logo,
-                                                        uint32_t *__restrict__ stat,
-                                                        uint32_t *__restrict__ flags_or) {
+                                                        double2 *__restrict__ part,
+                                                        uint32_t *__restrict__ spart) {
   extern __shared__ double2 sdyn[];
   __shared__ double2 scol[kMaxSpinOrbitals];
   __shared__ int spiv[kMaxSpinOrbitals];
   __shared__ double2 spivval;
   __shared__ int ssing;
 
-  const int w = blockIdx.x;
+  const int w = blockIdx.x, s = blockIdx.y;
   const int tid = threadIdx.x;
   const int Nt = Na + Nb;
   const int nmax = Na > Nb ? Na : Nb;
@@ -40,12 +42,17 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
   double *sPs = reinterpret_cast<double *>(sPh + OKQ * nmax);  // [OKQ][N]
   const double2 *ph = phi + (size_t)w * M * Nt;
   double lre = 0.0, lim = 0.0;  // log det accumulated by thread 0
-  int singular = 0;
 
-  for (int s = 0; s < 2 && !singular; ++s) {
+  {
     const int N = s ? Nb : Na;
     const int off = s ? Na : 0;
-    if (N == 0) continue;
+    if (N == 0) {
+      if (tid == 0) {
+        part[(size_t)w * 2 + s] = make_double2(0.0, 0.0);
+        spart[(size_t)w * 2 + s] = 0u;
+      }
+      return;
+    }
     const int NN = N * N;
     // O = Psi_s^T phi_s, OKQ rows at a time through LDS
     double2 o[OMAXE];
@@ -142,8 +149,11 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       __syncthreads();
     }
     if (ssing) {
-      singular = 1;
-      break;
+      if (tid == 0) {
+        part[(size_t)w * 2 + s] = make_double2(0.0, 0.0);
+        spart[(size_t)w * 2 + s] = 1u;
+      }
+      return;
     }
     // undo the row interchanges as column interchanges, last first
     for (int k = N - 1; k >= 0; --k) {
@@ -181,18 +191,35 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
         __syncthreads();
       }
     }
-    __syncthreads();
-  }
-
-  if (singular && theta) {
-    double2 *th = theta + (size_t)w * M * Nt;
-    for (int e = tid; e < M * Nt; e += blockDim.x) th[e] = make_double2(0.0, 0.0);
   }
   if (tid == 0) {
-    logo[w] = singular ? make_double2(0.0, 0.0) : make_double2(lre, wrap_phase(lim));
-    if (stat) stat[w] = singular ? (uint32_t)AFQMC_W_SINGULAR : 0u;
-    if (flags_or && singular) flags_or[w] |= AFQMC_W_SINGULAR;
+    part[(size_t)w * 2 + s] = make_double2(lre, lim);
+    spart[(size_t)w * 2 + s] = 0u;
   }
+}
+
+// log<Psi_T|phi> = sum of the two spin blocks' log-determinants (phase reduced
+// to (-pi, pi]); a walker with a singular block gets log-overlap 0 and the
+// singular flag.
+__global__ void k_ovlp_finish(const double2 *__restrict__ part, const uint32_t *__restrict__ spart, int W,
+                              double2 *__restrict__ logo, uint32_t *__restrict__ stat,
+                              uint32_t *__restrict__ flags_or) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const bool singular = (spart[2 * w] | spart[2 * w + 1]) != 0u;
+  const double2 a = part[2 * w], b = part[2 * w + 1];
+  logo[w] = singular ? make_double2(0.0, 0.0) : make_double2(a.x + b.x, wrap_phase(a.y + b.y));
+  if (stat) stat[w] = singular ? (uint32_t)AFQMC_W_SINGULAR : 0u;
+  if (flags_or && singular) flags_or[w] |= AFQMC_W_SINGULAR;
+}
+
+// Theta of a walker with a singular block is all zero.
+__global__ __launch_bounds__(kThreads) void k_theta_zero_singular(const uint32_t *__restrict__ spart, long per,
+                                                                 double2 *__restrict__ theta) {
+  const int w = blockIdx.x;
+  if (!(spart[2 * w] | spart[2 * w + 1])) return;
+  double2 *th = theta + (size_t)w * per;
+  for (long e = threadIdx.x; e < per; e += blockDim.x) th[e] = make_double2(0.0, 0.0);
 }
 
 size_t ovlp_lds_bytes(int nmax) {
@@ -205,27 +232,33 @@ hipError_t ovlp_enable_lds(int nmax) {
 }
 
 hipError_t launch_ovlp_theta(const double2 *phi, const double *trial, int M, int Na, int Nb, int W,
-                             double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or,
-                             hipStream_t st) {
+                             double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or, hipStream_t st,
+                             double2 *part, uint32_t *spart) {
   const int nmax = Na > Nb ? Na : Nb;
-  hipLaunchKernelGGL(k_ovlp_theta, dim3(W), dim3(kThreads), ovlp_lds_bytes(nmax), st, phi, trial, M, Na, Nb, theta,
-                     logo, stat, flags_or);
+  hipLaunchKernelGGL(k_ovlp_theta, dim3(W, 2), dim3(kThreads), ovlp_lds_bytes(nmax), st, phi, trial, M, Na, Nb, theta,
+                     part, spart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ovlp_finish, dim3((W + 255) / 256), dim3(256), 0, st, part, spart, W, logo, stat, flags_or);
+  if ((e = hipGetLastError()) != hipSuccess || !theta) return e;
+  hipLaunchKernelGGL(k_theta_zero_singular, dim3(W), dim3(kThreads), 0, st, spart, (long)M * (Na + Nb), theta);
   return hipGetLastError();
 }
 
 // Modified Gram-Schmidt of each spin block: for k = 0..N-1, r_kk = |phi_k|,
 // phi_k /= r_kk, r_kj = phi_k^H phi_j and phi_j -= r_kj phi_k for j > k.
 // One workgroup per walker; wave v handles columns j = k+1+v, k+1+v+4, ...
+// One workgroup per (walker, spin block); logr[w][s] = sum_i log R_ii of the block.
 __global__ __launch_bounds__(kThreads) void k_mgs(double2 *__restrict__ phi, int M, int Na, int Nb,
-                                                 double2 *__restrict__ logo) {
+                                                 double *__restrict__ logr_out) {
   __shared__ double2 sr[kMaxSpinOrbitals];
   __shared__ double snorm;
-  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int w = blockIdx.x, s = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int nw = blockDim.x >> 6;
   const int Nt = Na + Nb;
   double2 *ph = phi + (size_t)w * M * Nt;
   double logr = 0.0;
-  for (int s = 0; s < 2; ++s) {
+  {
     const int N = s ? Nb : Na;
     const int off = s ? Na : 0;
     for (int k = 0; k < N; ++k) {
@@ -268,11 +301,20 @@ __global__ __launch_bounds__(kThreads) void k_mgs(double2 *__restrict__ phi, int
       __syncthreads();
     }
   }
-  if (tid == 0) logo[w].x -= logr;
+  if (tid == 0) logr_out[(size_t)w * 2 + s] = logr;
 }
 
-hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st) {
-  hipLaunchKernelGGL(k_mgs, dim3(W), dim3(kThreads), 0, st, phi, M, Na, Nb, logo);
+// log<Psi_T|phi> -= sum over both blocks of log R_ii
+__global__ void k_mgs_finish(const double *__restrict__ logr, int W, double2 *__restrict__ logo) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < W) logo[w].x -= logr[2 * w] + logr[2 * w + 1];
+}
+
+hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st, double *scratch) {
+  hipLaunchKernelGGL(k_mgs, dim3(W, 2), dim3(kThreads), 0, st, phi, M, Na, Nb, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mgs_finish, dim3((W + 255) / 256), dim3(256), 0, st, scratch, W, logo);
   return hipGetLastError();
 }
 
