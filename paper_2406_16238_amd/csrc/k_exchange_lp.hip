@@ -11,7 +11,9 @@
 //           dropped ml + lm + ll are below FP32 rounding);
 //   BF16x2: the three terms hh + hm + mh (x is kept to about 2^-17 relative and
 //           the dropped mm is of order 2^-18 of the product).
-// In both forms T is kept in LDS as FP32 and the traces are accumulated in FP64.
+// In both forms T is kept in LDS as FP32; the FP32 form accumulates the traces in
+// FP64, the split forms each lane's partial traces (at most 100 products) in FP32
+// and the sums over lanes and Cholesky vectors in FP64.
 // Overlaps, LU, propagation, weights and re-orthogonalisation stay FP64.
 //
 // Work decomposition as in the FP64 kernel: one GEMM per spin block with rows
@@ -40,12 +42,12 @@ constexpr int LKC = 32;     // contraction rows per LDS stage
 
 // Trace epilogue shared by both forms.  T of each wave (ROWW x CP floats) is in
 // LDS at row stride TSF; every lane pairs each accumulator entry with the
-// transposed entry of the same Cholesky vector and accumulates in FP64.
+// transposed entry of the same Cholesky vector and accumulates in R (FP64 or FP32).
 // only >= 0 restricts the pass to that Cholesky vector of the wave (whose T
 // alone is then in LDS, at the addresses of the full layout minus its offset).
-template <int NR, int CT, int RT>
+template <int NR, int CT, int RT, typename R = double>
 __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *sT, int TSF, int lane,
-                                         double &pre, double &pim, double *dg, int only) {
+                                         R &pre, R &pim, R *dg, int only) {
   const int lr = lane & 15, lk = lane >> 4;
   const bool odd = lr & 1;
 #pragma unroll
@@ -59,10 +61,10 @@ __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *
         if (only >= 0 && gl != only) continue;
         const int col = ct * 16 + lr, j = col >> 1;
         const float2 t = *reinterpret_cast<const float2 *>(sT + (gl * NR + j) * TSF + 2 * i);
-        const double v = (double)acc[rt][ct][r];
-        pre = fma(v, odd ? -(double)t.y : (double)t.x, pre);
-        pim = fma(v, odd ? (double)t.x : (double)t.y, pim);
-        const double d = (j == i) ? v : 0.0;
+        const R v = (R)acc[rt][ct][r];
+        pre = fma(v, odd ? -(R)t.y : (R)t.x, pre);
+        pim = fma(v, odd ? (R)t.x : (R)t.y, pim);
+        const R d = (j == i) ? v : (R)0;
         if (gl == 0) dg[0] += d;
         else dg[1] += d;
       }
@@ -331,7 +333,9 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     __syncthreads();
   }
 
-  double pre = 0.0, pim = 0.0, dg[2] = {0.0, 0.0};
+  // each lane's partial traces (at most ROWW CP / 64 products) in FP32, the
+  // sums over lanes and Cholesky vectors in FP64
+  float pre = 0.f, pim = 0.f, dg[2] = {0.f, 0.f};
   if constexpr (NT == 2) {
     // one Cholesky vector of the wave at a time: T^g (NR x CP) per wave in LDS
     float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * NR * TSF;
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
             if (row / NR == pass) sT[(row - pass * NR) * TSF + ct * 16 + lr] = acc[rt][ct][r];
           }
       __syncthreads();
-      lp_trace<NR, CT, RT>(acc, sT - pass * NR * TSF, TSF, lane, pre, pim, dg, pass);
+      lp_trace<NR, CT, RT, float>(acc, sT - pass * NR * TSF, TSF, lane, pre, pim, dg, pass);
       if (pass + 1 < GC) __syncthreads();
     }
   } else {
@@ -359,9 +363,11 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
 #pragma unroll
         for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
     __syncthreads();
-    lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg, -1);
+    lp_trace<NR, CT, RT, float>(acc, sT, TSF, lane, pre, pim, dg, -1);
   }
-  lp_finish<GC>(pre, pim, dg, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart, vbpart);
+  const double dgd[2] = {(double)dg[0], (double)dg[1]};
+  lp_finish<GC>((double)pre, (double)pim, dgd, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart,
+                vbpart);
 }
 
 // ---- operand preparation -------------------------------------------------------
