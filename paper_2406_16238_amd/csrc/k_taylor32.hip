@@ -154,6 +154,160 @@ __global__ __launch_bounds__(QTH) void k_taylor_f32(const float *__restrict__ A3
       }
 }
 
+// The FP32 term with three real products (the 3M form of the complex product,
+// as in the FP64 kernel): P1 = Ar Tr, P2 = Ai Ti, P3 = (Ar + Ai)(Tr + Ti),
+// A T = (P1 - P2) + i (P3 - P1 - P2); IMAG (A = i Ai): P1 = Ai Tr, P2 = Ai Ti,
+// A T = -P2 + i P1.  WM waves, each 16 rows of one walker by all 16 TNC >= Nt
+// complex columns, so the combination stays in registers.  LDS per stage: the
+// A planes k-major and the Tr and Ti planes of 16 contraction indices.
+template <int WM, int TNC, bool IMAG>
+__global__ __launch_bounds__(64 * WM) void k_taylor3m_f32(const float *__restrict__ A32,
+                                                        const float2 *__restrict__ tin, float2 *__restrict__ tout,
+                                                        double2 *__restrict__ tacc, int M, int Nt, int W, int nrt,
+                                                        float alpha) {
+  constexpr int NTH = 64 * WM;
+  constexpr int BM = 16 * WM, BNC = 16 * TNC;
+  constexpr int NPL = IMAG ? 1 : 2;
+  constexpr int LDA = BM + 4, LDB = BNC + 4;
+  constexpr int AV = NPL * BM * QKC / 4;            // float4 (4 k) of A per stage
+  constexpr int BV = QKC * BNC / 2;                 // float4 (2 complex) of T per stage
+  constexpr int APT = (AV + NTH - 1) / NTH, BPT = (BV + NTH - 1) / NTH;
+  extern __shared__ float qsm[];
+  float *sA = qsm;                          // [2 buf][NPL][QKC][LDA]
+  float *sB = qsm + 2 * NPL * QKC * LDA;    // [2 buf][2][QKC][LDB]
+
+  const int ntiles = W * nrt;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int t = x * per + min(x, rem) + jx;
+  const int w = t / nrt, i0 = (t - w * nrt) * BM;
+
+  const size_t MM = (size_t)M * M;
+  const float *Aw = A32 + (size_t)w * 2 * MM;
+  const float2 *Tw = tin + (size_t)w * M * Nt;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  float4 ra[APT], rb[BPT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * NTH;                 // (plane, row, k quad)
+      const int pr = e / (QKC / 4), kq = e - pr * (QKC / 4);
+      const int pl = pr / BM, row = pr - pl * BM;
+      const int gi = i0 + row, gk = k0 + 4 * kq;
+      ra[r] = (e < AV && gi < M && gk < M)
+                  ? *reinterpret_cast<const float4 *>(Aw + (IMAG ? 1 : pl) * MM + (size_t)gi * M + gk)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = tid + r * NTH;                 // (k, complex column pair)
+      const int kk = e / (BNC / 2), jp = e - kk * (BNC / 2);
+      const int gk = k0 + kk, j = 2 * jp;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < BV && gk < M && j < Nt) {
+        const float2 *src = Tw + (size_t)gk * Nt + j;
+        const float2 z0 = src[0];
+        const float2 z1 = (j + 1 < Nt) ? src[1] : make_float2(0.f, 0.f);
+        v = make_float4(z0.x, z0.y, z1.x, z1.y);
+      }
+      rb[r] = v;
+    }
+  };
+  auto store = [&](int buf) {
+    float *a = sA + buf * NPL * QKC * LDA;
+    float *b = sB + buf * 2 * QKC * LDB;
+#pragma unroll
+    for (int r = 0; r < APT; ++r) {
+      const int e = tid + r * NTH;
+      if (e < AV) {
+        const int pr = e / (QKC / 4), kq = e - pr * (QKC / 4);
+        const int pl = pr / BM, row = pr - pl * BM;
+        float *ap = a + (pl * QKC + 4 * kq) * LDA + row;
+        ap[0 * LDA] = ra[r].x;
+        ap[1 * LDA] = ra[r].y;
+        ap[2 * LDA] = ra[r].z;
+        ap[3 * LDA] = ra[r].w;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+      const int e = tid + r * NTH;
+      if (e < BV) {
+        const int kk = e / (BNC / 2), jp = e - kk * (BNC / 2);
+        *reinterpret_cast<float2 *>(b + kk * LDB + 2 * jp) = make_float2(rb[r].x, rb[r].z);
+        *reinterpret_cast<float2 *>(b + (QKC + kk) * LDB + 2 * jp) = make_float2(rb[r].y, rb[r].w);
+      }
+    }
+  };
+
+  f4t p1[TNC], p2[TNC], p3[TNC];
+#pragma unroll
+  for (int j = 0; j < TNC; ++j) p1[j] = p2[j] = p3[j] = f4t{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunk = (M + QKC - 1) / QKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * QKC);
+    const float *a0 = sA + buf * NPL * QKC * LDA + wv * 16 + lr;
+    const float *br = sB + buf * 2 * QKC * LDB + lr;
+    const float *bi = br + QKC * LDB;
+#pragma unroll
+    for (int ks = 0; ks < QKC / 4; ++ks) {
+      const int kr = ks * 4 + lk;
+      float yr[TNC], yi[TNC];
+#pragma unroll
+      for (int j = 0; j < TNC; ++j) {
+        yr[j] = br[kr * LDB + j * 16];
+        yi[j] = bi[kr * LDB + j * 16];
+      }
+      if constexpr (IMAG) {
+        const float xi = a0[kr * LDA];
+#pragma unroll
+        for (int j = 0; j < TNC; ++j) {
+          p1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yr[j], p1[j], 0, 0, 0);
+          p2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yi[j], p2[j], 0, 0, 0);
+        }
+      } else {
+        const float xr = a0[kr * LDA], xi = a0[(QKC + kr) * LDA];
+#pragma unroll
+        for (int j = 0; j < TNC; ++j) {
+          p1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, yr[j], p1[j], 0, 0, 0);
+          p2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yi[j], p2[j], 0, 0, 0);
+        }
+        const float xs = xr + xi;
+#pragma unroll
+        for (int j = 0; j < TNC; ++j) p3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs, yr[j] + yi[j], p3[j], 0, 0, 0);
+      }
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  float2 *to = tout + (size_t)w * M * Nt;
+  double2 *ta = tacc + (size_t)w * M * Nt;
+#pragma unroll
+  for (int j = 0; j < TNC; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gi = i0 + wv * 16 + 4 * lk + r;
+      const int c = 16 * j + lr;
+      if (gi < M && c < Nt) {
+        const size_t off = (size_t)gi * Nt + c;
+        const float re = IMAG ? -p2[j][r] : p1[j][r] - p2[j][r];
+        const float im = IMAG ? p1[j][r] : (p3[j][r] - p1[j][r]) - p2[j][r];
+        const float2 v = make_float2(alpha * re, alpha * im);
+        to[off] = v;
+        const double2 o = ta[off];
+        ta[off] = make_double2(o.x + (double)v.x, o.y + (double)v.y);
+      }
+    }
+}
+
 // out[i] = float(in[i]) for n complex values
 __global__ void k_c128_to_c64(const double2 *__restrict__ in, long n, float2 *__restrict__ out) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,10 +373,50 @@ hipError_t run_taylor32_ct(const System &s, const float2 *tin, float2 *tout, dou
 }
 }  // namespace
 
+namespace {
+template <int WM, int TNC, bool IMAG>
+hipError_t run_taylor3m_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st) {
+  constexpr int BM = 16 * WM, BNC = 16 * TNC;
+  const size_t lds = 2ull * QKC * ((IMAG ? 1 : 2) * (BM + 4) + 2 * (BNC + 4)) * sizeof(float);
+  const int nrt = (s.M + BM - 1) / BM;
+  hipLaunchKernelGGL((k_taylor3m_f32<WM, TNC, IMAG>), dim3((unsigned)(W * nrt)), dim3(64 * WM), lds, st, s.vhs32,
+                     tin, tout, s.tacc, s.M, s.Nt, W, nrt, (float)alpha);
+  return hipGetLastError();
+}
+
+template <int WM, bool IMAG>
+hipError_t run_taylor3m_f32_tn(const System &s, const float2 *tin, float2 *tout, double alpha, int W,
+                               hipStream_t st) {
+  switch ((s.Nt + 15) / 16) {
+    case 1: return run_taylor3m_f32<WM, 1, IMAG>(s, tin, tout, alpha, W, st);
+    case 2: return run_taylor3m_f32<WM, 2, IMAG>(s, tin, tout, alpha, W, st);
+    case 3: return run_taylor3m_f32<WM, 3, IMAG>(s, tin, tout, alpha, W, st);
+    case 4: return run_taylor3m_f32<WM, 4, IMAG>(s, tin, tout, alpha, W, st);
+    case 5: return run_taylor3m_f32<WM, 5, IMAG>(s, tin, tout, alpha, W, st);
+    default: return run_taylor3m_f32<WM, 6, IMAG>(s, tin, tout, alpha, W, st);
+  }
+}
+}  // namespace
+
 bool prop32_supported(int M, int Nt) { return M % 4 == 0 && Nt >= 1 && Nt <= 96; }
 
 hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
                              int kbeg) {
+  // three real products (two for a purely imaginary V_HS, kbeg = M); taylor4 or
+  // variants 1..3 keep the four-product kernel for comparison runs, 9 and 10
+  // are other row tiles
+  if (!s.taylor4 && (s.taylor_variant == 0 || s.taylor_variant >= 9)) {
+    if (kbeg != 0 && kbeg != s.M) return hipErrorInvalidValue;
+    const bool imag = kbeg != 0;
+    switch (s.taylor_variant) {
+      case 9: return imag ? run_taylor3m_f32_tn<2, true>(s, tin, tout, alpha, W, st)
+                          : run_taylor3m_f32_tn<2, false>(s, tin, tout, alpha, W, st);
+      case 10: return imag ? run_taylor3m_f32_tn<4, true>(s, tin, tout, alpha, W, st)
+                           : run_taylor3m_f32_tn<4, false>(s, tin, tout, alpha, W, st);
+      default: return imag ? run_taylor3m_f32_tn<3, true>(s, tin, tout, alpha, W, st)
+                           : run_taylor3m_f32_tn<3, false>(s, tin, tout, alpha, W, st);
+    }
+  }
   // default 48-row tiles (measured at the headline shape: 3.51 ms per step
   // against 4.14 for 80 rows, 4.02 for 32 and 3.60 for 64: the smaller grid
   // tail outweighs the extra re-reads of T)

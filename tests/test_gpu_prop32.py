@@ -91,3 +91,31 @@ def test_fp32_propagation_rejects_unsupported_shapes():
         A.setup_hamiltonian(A.SystemInput(h1, chol, ecore, trial, 5, 3, 4, 0.01),
                             A.default_options(prop_precision=A.FP32_CONTRACT))
     assert err.value.status == A.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("variant", [0, 9, 10])
+def test_fp32_three_products_match_four(variant):
+    """The FP32 Taylor terms with three real products (row tiles of 48, 32 and
+    64 rows) against the four-product FP32 kernel (reserved[0] bit 5) on the
+    same fields: the same walkers to FP32 rounding."""
+    from paper_2406_16238_amd import afqmc as A
+    spec, W = gi.SystemSpec(100, 10, 9, 200, tau=75.0, seed=11), 37
+    outs = []
+    for bits, var in ((0, variant), (32, 0)):
+        o = A.default_options(prop_precision=A.FP32_CONTRACT)
+        o.reserved[0] = bits
+        o.reserved[4] = var
+        p = Pair(spec, W, 0.005, options=o)
+        try:
+            phis = gi.initial_walkers(p.trial, W, noise=0.03, seed=4)
+            w = p.walkers(phis)
+            fields = gi.FieldStream(6, W, spec.nchol)
+            for _ in range(3):
+                p.propagate(w, fields.next())
+            outs.append(p.to_host(w))
+        finally:
+            p.close()
+    (a, wa, _, _), (b, wb, _, _) = outs
+    d = cmp_rel(a, b, np.abs(b).max())
+    assert d < 2e-6, d
+    assert cmp_rel(wa, wb) < 2e-6
