@@ -238,3 +238,68 @@ def test_full_size_sampled():
             assert cmp_rel(ge[k], np.array(O.local_energy(p.ham, r["phi"]))) < TOL
     finally:
         p.close()
+
+
+def _free_run_set(A, torch, ctx, inputs, idx, nsteps):
+    """Free steps of the systems `idx` of `inputs` in ctx (all of its systems);
+    returns every system's walkers, amplitudes, energies and estimates."""
+    walkers, amps, xs, es, fields = [], [], [], [], []
+    for i in idx:
+        sysin, trial = inputs[i]
+        w = A.Walkers.from_numpy(gi.initial_walkers(trial, sysin.nwalkers, noise=0.03, seed=40 + i))
+        walkers.append(w)
+        xs.append(torch.empty((sysin.nwalkers, sysin.nchol), dtype=torch.float64, device="cuda"))
+        es.append(torch.empty((sysin.nwalkers, 3), dtype=torch.complex128, device="cuda"))
+        fields.append(gi.FieldStream(70 + i, sysin.nwalkers, sysin.nchol))
+    A.overlap(ctx, walkers)
+    amps = [w.log_ovlp.clone() for w in walkers]
+    est = torch.empty((len(idx), A.FREE_EST), dtype=torch.float64, device="cuda")
+    for step in range(1, nsteps + 1):
+        for x, f in zip(xs, fields):
+            x.copy_(torch.as_tensor(f.next()))
+        A.free_step(ctx, walkers, xs, amps, es, est, reortho=(step % 3 == 0))
+    torch.cuda.synchronize()
+    return [{"phi": w.phi.cpu().numpy(), "logo": w.log_ovlp.cpu().numpy(), "amp": a.cpu().numpy(),
+             "e": e.cpu().numpy(), "est": est.cpu().numpy()[k]} for k, (w, a, e) in enumerate(zip(walkers, amps, es))]
+
+
+def test_free_projection_in_a_system_set():
+    """afqmc_free_step on a context holding several uneven systems (internal
+    streams) equals separate single-system contexts bit for bit."""
+    from paper_2406_16238_amd import afqmc as A
+    import torch
+    from test_gpu_batching import assert_bitwise, make_inputs, small_set
+    specs = small_set(5)
+    inputs = make_inputs(A, specs)
+    ctx = A.setup_hamiltonian([s for s, _ in inputs])
+    try:
+        together = _free_run_set(A, torch, ctx, inputs, list(range(len(inputs))), 5)
+    finally:
+        ctx.close()
+    for i in range(len(inputs)):
+        c1 = A.setup_hamiltonian([inputs[i][0]])
+        try:
+            alone = _free_run_set(A, torch, c1, inputs, [i], 5)[0]
+        finally:
+            c1.close()
+        assert_bitwise(together[i], alone, f"system {i}")
+
+
+def test_free_step_rejects_unknown_flags():
+    p = Pair(gi.SMALL.system, 4, 0.01)
+    A, torch = p.A, p.torch
+    try:
+        w = p.walkers(gi.initial_walkers(p.trial, 4, noise=0.02, seed=1))
+        amp = w.log_ovlp.clone()
+        x = torch.zeros((4, p.ham.nchol), dtype=torch.float64, device="cuda")
+        e = torch.empty((4, 3), dtype=torch.complex128, device="cuda")
+        lib = A.load_library()
+        wa = A._walker_array(p.ctx, w)
+        xs = A._ptr_array(p.ctx, x, [(4, p.ham.nchol)], torch.float64)
+        am = A._ptr_array(p.ctx, amp, [(4,)], torch.complex128)
+        es = A._ptr_array(p.ctx, e, [(4, 3)], torch.complex128)
+        assert lib.afqmc_free_step(p.ctx.handle, wa, xs, am, es, None, A.STEP_FRESH, None) == A.ERR_ARG
+        assert lib.afqmc_free_step(p.ctx.handle, wa, xs, None, es, None, 0, None) == A.ERR_ARG
+        assert lib.afqmc_free_step(p.ctx.handle, wa, xs, am, es, None, 0, None) == A.OK
+    finally:
+        p.close()
