@@ -31,6 +31,9 @@
 
 namespace afqmc {
 
+// 16 zero bytes: the source of LDS DMA lanes whose rows lie past the operands
+__device__ const uint4 kZero16 = {0u, 0u, 0u, 0u};
+
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
@@ -38,6 +41,10 @@ namespace {
 constexpr int LWX = 2;      // walkers per workgroup
 constexpr int LWY = 2;      // Cholesky-vector groups per workgroup
 constexpr int LKC = 32;     // contraction rows per LDS stage
+#ifndef AFQMC_EXCHANGE_DMA
+#define AFQMC_EXCHANGE_DMA 1
+#endif
+constexpr bool kExchangeDma = AFQMC_EXCHANGE_DMA;  // stage the split-BF16 operands by LDS DMA
 }  // namespace
 
 // Trace epilogue shared by both forms.  T of each wave (ROWW x CP floats) is in
@@ -226,6 +233,11 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   auto swz = [](int r) { return ((r >> 1) ^ (r >> 2)) & 3; };
   extern __shared__ __bf16 bsm[];
   __bf16 *sA = bsm, *sB = bsm + NBUF * ASZ;
+  // With LDS DMA (global_load_lds_dwordx4: lane L's 16 bytes land at the wave's
+  // LDS base + 16 L) a stage is filled straight from memory, 1 KB (16 staged
+  // rows) per wave instruction; rows past G or W read a zero block.
+  constexpr bool DMA = kExchangeDma;
+  static_assert(AV % 64 == 0 && BV % 64 == 0, "whole 1 KB blocks");
 
   int gb, wb;
   tile_of(blockIdx.x, ngb * nwb, ngb, nwb, group, gb, wb);
@@ -278,6 +290,32 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     }
   };
 
+  auto issue = [&](int q0, int buf) {
+    __bf16 *a = sA + buf * ASZ;
+    __bf16 *b = sB + buf * BSZ;
+    const int t4 = lane >> 2, slot = lane & 3;
+#pragma unroll
+    for (int r = 0; r < (AV / 64 + 3) / 4; ++r) {
+      const int blk = wv + 4 * r, t = 16 * blk + t4;          // staged row (p, row)
+      if (blk >= AV / 64) break;                              // uniform in the wave
+      const int row = t % ROWS, p = t / ROWS;
+      const int gl = row / NR, i = row - gl * NR, g = g0 + gl;
+      const __bf16 *src = g < G ? LtB + p * aplane + ((size_t)g * NR + i) * Kp + q0 + 8 * (slot ^ swz(t))
+                                : reinterpret_cast<const __bf16 *>(&kZero16);
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(a + blk * 512), 16, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < (BV / 64 + 3) / 4; ++r) {
+      const int blk = wv + 4 * r, t = 16 * blk + t4;          // staged column (p, col)
+      if (blk >= BV / 64) break;                              // uniform in the wave
+      const int col = t % COLS, p = t / COLS;
+      const int wl = col / CP, c = col - wl * CP, w = w0 + wl;
+      const __bf16 *src = w < W ? ThB + p * bplane + ((size_t)w * CP + c) * Kp + q0 + 8 * (slot ^ swz(t))
+                                : reinterpret_cast<const __bf16 *>(&kZero16);
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(b + blk * 512), 16, 0, 0);
+    }
+  };
+
   f4v acc[RT][CT];
 #pragma unroll
   for (int i = 0; i < RT; ++i)
@@ -285,13 +323,22 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     for (int j = 0; j < CT; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 
   const int nchunk = Kp / LKC;
-  load(0);
-  store(0);
+  if constexpr (DMA) {
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+  } else {
+    load(0);
+    store(0);
+  }
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = NBUF == 2 ? (ch & 1) : 0;
-    if (ch + 1 < nchunk) load((ch + 1) * LKC);
+    if constexpr (DMA) {
+      if (ch + 1 < nchunk) issue((ch + 1) * LKC, buf ^ 1);
+    } else if (ch + 1 < nchunk) {
+      load((ch + 1) * LKC);
+    }
     const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * (lk ^ swz(lr));
     const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * (lk ^ swz(lr));
     bf8v ah[RT], am[RT], bh[CT], bm[CT];
@@ -324,11 +371,10 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     AFQMC_SWEEP(ah, bm)
     AFQMC_SWEEP(ah, bh)
 #undef AFQMC_SWEEP
-    if (NBUF == 2) {
-      if (ch + 1 < nchunk) store(buf ^ 1);
+    if constexpr (DMA) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into the other buffer have landed
     } else if (ch + 1 < nchunk) {
-      __syncthreads();  // every wave is done reading the buffer
-      store(0);
+      store(buf ^ 1);
     }
     __syncthreads();
   }
