@@ -88,6 +88,9 @@ def parse_args(argv=None):
     ap.add_argument("--cv-system", default="headline", choices=["headline", "benzene"],
                     help="cv: the headline shape, or M=1512, N=42+42, 6000 Cholesky vectors, 64 walkers with the "
                          "Cholesky tensor drawn on the device")
+    ap.add_argument("--repeats", type=int, default=4,
+                    help="further timed blocks of --steps steps after the reported one (their walker-steps/s and "
+                         "the median of all blocks are reported beside value)")
     ap.add_argument("--cpu-walkers", type=int, default=32, help="walkers in the CPU oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=6, help="steps in the CPU oracle sample")
     ap.add_argument("--phases", action="store_true", help="print the per-phase tables to stderr")
@@ -145,7 +148,27 @@ def cpu_baseline(spec, n_walkers, n_steps, free=False):
             phis, logo = O.reorthogonalize(ham, phis, logo)
         O.local_energies(ham, phis)
     dt = time.perf_counter() - t0
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            p1 = gi.initial_walkers(trial, 8)
+            w1, l1 = np.ones(8), O.initial_logo(ham, p1)
+            a1 = O.initial_amplitudes(l1)
+            f1 = gi.FieldStream(spec.field_seed, 8, s.nchol)
+            t1 = time.perf_counter()
+            for _ in range(2):
+                if free:
+                    p1, l1, a1, _ = O.free_propagate(ham, p1, l1, a1, f1.next())
+                else:
+                    p1, w1, l1, _ = O.propagate(ham, p1, w1, l1, f1.next())
+                O.local_energies(ham, p1)
+            d1 = time.perf_counter() - t1
+        single = {"value": 16 / d1, "cores": 1, "sample": f"8 walkers x 2 steps, {d1:.1f} s, BLAS limited to 1 thread"}
+    except ImportError:
+        pass
     return {"value": n_walkers * n_steps / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+            "single_thread": single,
             "sample": f"{n_walkers} walkers x {n_steps} {'free-projection ' if free else ''}steps "
                       f"(propagate + local energy, FP64) of {spec.name}, "
                       f"{dt:.1f} s on the host CPU, numpy complex128"}
@@ -203,8 +226,19 @@ def time_path(A, torch, ctx, spec, trial, xs, args):
         energy = A.free_energy(h).real if h[9] > 0 else float("nan")
     else:
         energy = float(h[0] / h[1]) if h[1] > 0 else float("nan")
+    flagged = int((walkers.flags.cpu().numpy() != 0).sum())
+    # further timed blocks (the same fields again), for the spread of the rate
+    blocks = [total_ms]
+    for _ in range(max(0, args.repeats)):
+        torch.cuda.synchronize()
+        ev0.record()
+        for k in range(args.warmup, nsteps):
+            step(k)
+        ev1.record()
+        torch.cuda.synchronize()
+        blocks.append(ev0.elapsed_time(ev1))
     return {"total_ms": total_ms, "phases": phases, "walkers": walkers, "mixed_energy": energy,
-            "flagged": int((walkers.flags.cpu().numpy() != 0).sum())}
+            "flagged": flagged, "blocks_ms": blocks}
 
 
 def bench_batching(args):
@@ -500,7 +534,12 @@ def main(argv=None):
            "roofline": roofline,
            "step_algorithmic_tflops": round(step_tf, 3),
            "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in r["phases"].items()},
-           "mixed_energy": round(r["mixed_energy"], 8), "walkers_flagged": r["flagged"]}
+           "mixed_energy": round(r["mixed_energy"], 8), "walkers_flagged": r["flagged"],
+           "repeat_blocks_walker_steps_per_s": [round(W * args.steps / (b * 1e-3), 1) for b in r["blocks_ms"]],
+           "median_walker_steps_per_s": round(float(np.median([W * args.steps / (b * 1e-3) for b in r["blocks_ms"]])),
+                                              2),
+           "device": {"name": torch.cuda.get_device_name(0),
+                      "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", "")}}
     if rep_key != "fp64":
         f = runs["fp64"]
         fp64_value = W * args.steps / (f["total_ms"] * 1e-3)

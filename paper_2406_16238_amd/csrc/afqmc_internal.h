@@ -55,6 +55,8 @@ struct System {
   double *LtS[2] = {nullptr, nullptr};  // per spin [G][M][NR]: half-rotated, rows padded for the exchange
   double *Lp = nullptr;                 // [G][M(M+1)/2] packed upper triangles of the L^g
   double *vhsp = nullptr;               // [W][2][M(M+1)/2] packed V_HS planes
+  float *Lp32 = nullptr;                // FP32 propagation: packed L^g in FP32, [G][ldlp32]
+  long ldlp32 = 0;                      // M(M+1)/2 rounded up to a multiple of 4
   // FP32 propagation: V_HS planes and Taylor terms in single precision
   bool prop32 = false;
   float *vhs32 = nullptr;                // [W][2][M][M]
@@ -210,6 +212,9 @@ hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, d
                              int kbeg = 0);
 hipError_t launch_c128_to_c64(const double2 *in, long n, float2 *out, hipStream_t st);
 hipError_t launch_unpack_f32(const System &s, int W, hipStream_t st, bool imag_only = false);
+hipError_t launch_pack_to_f32(const double *in, long n, long rows, long ldo, float *out, hipStream_t st);
+// V_HS of FP32 propagation from Lp32 (FP32 GEMM), unpacked into the FP32 planes
+hipError_t launch_vhs_f32(const System &s, int W, hipStream_t st, bool imag_only);
 // comb population control (k_popctl.hip); parents_out may be NULL
 // free projection
 hipError_t launch_free_fields(const System &s, const double *x, int W, uint32_t *flags, hipStream_t st);

@@ -505,6 +505,14 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     AFQMC_HIP(hipMemcpyAsync(s.L, d.chol, p.L * sizeof(double), hipMemcpyHostToDevice, st), "upload chol");
   }
   if (s.Lp) AFQMC_HIP(launch_pack_upper(s, st), "Cholesky packing");
+  if (s.prop32) {
+    // FP32 propagation forms V_HS in FP32 from an FP32 copy of the packed vectors
+    const long Mp = (long)M * (M + 1) / 2;
+    s.ldlp32 = (Mp + 3) / 4 * 4;
+    if (!dalloc(c, &s.Lp32, (size_t)G * s.ldlp32)) return fail(AFQMC_ERR_OOM, "device allocation failed (FP32 L)");
+    s.bytes += 4ull * G * s.ldlp32;
+    AFQMC_HIP(launch_pack_to_f32(s.Lp, Mp, G, s.ldlp32, s.Lp32, st), "FP32 packed Cholesky vectors");
+  }
   AFQMC_HIP(hipMemcpyAsync(s.trial, d.trial, p.trial * sizeof(double), hipMemcpyHostToDevice, st),
             "upload trial");
   // temporaries of set-up
@@ -842,6 +850,12 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
         free_one(c, sy.L);
         sy.L = nullptr;
         sy.bytes -= 8ull * sy.G * sy.M * sy.M;
+        if (sy.Lp32) {
+          // FP32 propagation reads only the FP32 copy
+          free_one(c, sy.Lp);
+          sy.Lp = nullptr;
+          sy.bytes -= 4ull * sy.G * sy.M * (sy.M + 1);
+        }
       }
     }
     if (r != AFQMC_OK) {

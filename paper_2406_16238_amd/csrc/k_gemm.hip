@@ -207,6 +207,7 @@ hipError_t launch_pack_upper(const System &s, hipStream_t st) {
 }
 
 hipError_t launch_vhs(const System &s, int W, hipStream_t st, bool imag_only) {
+  if (s.prop32 && s.Lp32) return launch_vhs_f32(s, W, st, imag_only);
   const long MM = (long)s.M * s.M;
   // rows (w, c) of yp; with imag_only the rows (w, 1) alone, into planes (w, 1)
   const int rows = imag_only ? W : 2 * W, rstride = imag_only ? 2 : 1, roff = imag_only ? 1 : 0;

@@ -316,7 +316,8 @@ __global__ void k_c128_to_c64(const double2 *__restrict__ in, long n, float2 *__
 
 // full32[m][p][q] = full32[m][q][p] = float(packed[m][t(p, q)]) for p <= q (as
 // the FP64 unpacking, writing FP32 planes)
-__global__ __launch_bounds__(kThreads) void k_unpack_symmetric_f32(const double *__restrict__ packed, int M,
+template <typename P>
+__global__ __launch_bounds__(kThreads) void k_unpack_symmetric_f32(const P *__restrict__ packed, long ldp, int M,
                                                                    int ntile, int pstride, int poff,
                                                                    float *__restrict__ full) {
   __shared__ float tile[32][33];
@@ -327,15 +328,14 @@ __global__ __launch_bounds__(kThreads) void k_unpack_symmetric_f32(const double 
     ++bi;
   }
   const int bj = bi + t;
-  const long Mp = (long)M * (M + 1) / 2;
-  const double *P = packed + (size_t)m * Mp;
+  const P *Pm = packed + (size_t)m * ldp;
   float *F = full + (size_t)m * M * M;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int r = ty; r < 32; r += 8) {
     const int p = bi * 32 + r, q = bj * 32 + tx;
     float v = 0.f;
     if (p < M && q < M && p <= q) {
-      v = (float)P[(long)p * M - (long)p * (p - 1) / 2 + (q - p)];
+      v = (float)Pm[(long)p * M - (long)p * (p - 1) / 2 + (q - p)];
       F[(size_t)p * M + q] = v;
     }
     tile[r][tx] = v;
@@ -345,6 +345,141 @@ __global__ __launch_bounds__(kThreads) void k_unpack_symmetric_f32(const double 
     const int q = bj * 32 + r, p = bi * 32 + tx;
     if (p < M && q < M && p < q) F[(size_t)q * M + p] = tile[tx][r];
   }
+}
+
+// FP32 propagation: the V_HS product in FP32 as well,
+//   C[r][c] = sum_g Y[r][g] Lp32[g][c]  (Y read as FP64 rows and rounded),
+// rows r = the field rows (w, re/im) or (w, im), columns the packed upper
+// triangle (ldb >= M(M+1)/2, a multiple of 4, zero-padded).  128 x 128 tiles,
+// 2 x 2 waves of 64 x 64 on v_mfma_f32_16x16x4f32, 16 contraction indices per
+// LDS stage double-buffered through registers; workgroups remapped so that
+// each XCD walks a contiguous range of tiles, row tiles fastest.
+namespace {
+constexpr int VBM = 128, VBN = 128, VKC = 16;
+}
+__global__ __launch_bounds__(kThreads) void k_vhs_f32(const double *__restrict__ Y, long lda, int R, int K,
+                                                     const float *__restrict__ B, long ldb, int N,
+                                                     float *__restrict__ C, long ldc, int gx, int gy) {
+  constexpr int LDA = VBM + 4, LDB = VBN + 4;
+  __shared__ __attribute__((aligned(16))) float sA[2][VKC][LDA];
+  __shared__ __attribute__((aligned(16))) float sB[2][VKC][LDB];
+  const int nb = gx * gy;
+  int lin = blockIdx.x;
+  const int per = nb / 8;
+  if (lin < per * 8) lin = (lin % 8) * per + lin / 8;
+  const int bx = lin % gx, by = lin / gx;
+  const int r0 = bx * VBM, c0 = by * VBN;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  double2 ra[4];
+  float4 rb[2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * kThreads;             // (row, k pair): 128 x 8
+      const int row = e >> 3, kp = e & 7;
+      const int gr = r0 + row, gk = k0 + 2 * kp;
+      double2 v = make_double2(0.0, 0.0);
+      if (gr < R) {
+        if (gk + 1 < K) v = make_double2(Y[(size_t)gr * lda + gk], Y[(size_t)gr * lda + gk + 1]);
+        else if (gk < K) v.x = Y[(size_t)gr * lda + gk];
+      }
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = tid + r * kThreads;             // (k, column quad): 16 x 32
+      const int kk = e >> 5, cq = e & 31;
+      const int gk = k0 + kk, gc = c0 + 4 * cq;
+      rb[r] = (gk < K && gc < ldb) ? *reinterpret_cast<const float4 *>(B + (size_t)gk * ldb + gc)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * kThreads;
+      const int row = e >> 3, kp = e & 7;
+      sA[buf][2 * kp][row] = (float)ra[r].x;
+      sA[buf][2 * kp + 1][row] = (float)ra[r].y;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = tid + r * kThreads;
+      const int kk = e >> 5, cq = e & 31;
+      *reinterpret_cast<float4 *>(&sB[buf][kk][4 * cq]) = rb[r];
+    }
+  };
+
+  f4t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4t{0.f, 0.f, 0.f, 0.f};
+  const int nchunk = (K + VKC - 1) / VKC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) load((ch + 1) * VKC);
+#pragma unroll
+    for (int ks = 0; ks < VKC / 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      float av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sA[buf][kk][wm * 64 + 16 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sB[buf][kk][wn * 64 + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (ch + 1 < nchunk) store(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = r0 + wm * 64 + 16 * i + 4 * lk + r, gc = c0 + wn * 64 + 16 * j + lr;
+        if (gr < R && gc < N) C[(size_t)gr * ldc + gc] = acc[i][j][r];
+      }
+}
+
+// out[i] = float(in[i]) for a [rows][n] array into [rows][ldo] (pad columns zeroed)
+__global__ void k_pack_to_f32(const double *__restrict__ in, long n, long rows, long ldo, float *__restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * ldo) return;
+  const long r = e / ldo, c = e - r * ldo;
+  out[e] = c < n ? (float)in[r * n + c] : 0.f;
+}
+
+hipError_t launch_pack_to_f32(const double *in, long n, long rows, long ldo, float *out, hipStream_t st) {
+  const long tot = rows * ldo;
+  hipLaunchKernelGGL(k_pack_to_f32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, in, n, rows, ldo, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_vhs_f32(const System &s, int W, hipStream_t st, bool imag_only) {
+  const long Mp = (long)s.M * (s.M + 1) / 2;
+  const int rows = imag_only ? W : 2 * W, rstride = imag_only ? 2 : 1, roff = imag_only ? 1 : 0;
+  const int gx = (rows + VBM - 1) / VBM, gy = (int)((Mp + VBN - 1) / VBN);
+  float *packed = reinterpret_cast<float *>(s.vhsp);      // [2W][Mp] floats in the FP64 packed buffer
+  hipLaunchKernelGGL(k_vhs_f32, dim3((unsigned)(gx * gy)), dim3(kThreads), 0, st, s.yp + (size_t)roff * s.G,
+                     (long)rstride * s.G, rows, s.G, s.Lp32, s.ldlp32, (int)Mp, packed + (size_t)roff * Mp,
+                     (long)rstride * Mp, gx, gy);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nt = (s.M + 31) / 32;
+  hipLaunchKernelGGL(k_unpack_symmetric_f32<float>, dim3(nt * (nt + 1) / 2, imag_only ? W : 2 * W), dim3(kThreads),
+                     0, st, packed, Mp, s.M, nt, rstride, roff, s.vhs32);
+  return hipGetLastError();
 }
 
 namespace {
@@ -437,8 +572,8 @@ hipError_t launch_c128_to_c64(const double2 *in, long n, float2 *out, hipStream_
 hipError_t launch_unpack_f32(const System &s, int W, hipStream_t st, bool imag_only) {
   const int nt = (s.M + 31) / 32;
   const int pstride = imag_only ? 2 : 1, poff = imag_only ? 1 : 0;
-  hipLaunchKernelGGL(k_unpack_symmetric_f32, dim3(nt * (nt + 1) / 2, imag_only ? W : 2 * W), dim3(kThreads), 0, st,
-                     s.vhsp, s.M, nt, pstride, poff, s.vhs32);
+  hipLaunchKernelGGL(k_unpack_symmetric_f32<double>, dim3(nt * (nt + 1) / 2, imag_only ? W : 2 * W), dim3(kThreads),
+                     0, st, s.vhsp, (long)s.M * (s.M + 1) / 2, s.M, nt, pstride, poff, s.vhs32);
   return hipGetLastError();
 }
 
