@@ -304,6 +304,71 @@ __global__ __launch_bounds__(kThreads) void k_mgs(double2 *__restrict__ phi, int
   if (tid == 0) logr_out[(size_t)w * 2 + s] = logr;
 }
 
+// The same modified Gram-Schmidt with the spin block held in registers: one
+// workgroup of 512 threads per (walker, spin block), thread q holding row q
+// (M <= 512) of the block's NMAX >= N columns (N <= 48: the row fits the
+// registers of two waves per SIMD), so phi is read and written once.
+// Norms and the dot products of column k with the later columns are summed
+// over the rows by butterfly shuffles within each wave and then over the eight
+// waves through LDS in a fixed order; the loops over columns are unrolled so
+// the row stays in registers.
+template <int NMAX>
+__global__ __launch_bounds__(512) void k_mgs_reg(double2 *__restrict__ phi, int M, int Na, int Nb,
+                                                double *__restrict__ logr_out) {
+  __shared__ double2 sdot[8][NMAX];
+  const int w = blockIdx.x, s = blockIdx.y, q = threadIdx.x, lane = q & 63, wv = q >> 6;
+  const int Nt = Na + Nb, N = s ? Nb : Na, off = s ? Na : 0;
+  double2 *row = phi + ((size_t)w * M + q) * Nt + off;
+  double2 c[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) c[j] = (q < M && j < N) ? row[j] : make_double2(0.0, 0.0);
+  double logr = 0.0;
+#pragma clang loop unroll(full)
+  for (int k = 0; k < NMAX; ++k) {
+    if (k >= N) continue;  // uniform in the workgroup
+    // |column k|^2
+    double n2 = cabs2(c[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n2 += __shfl_xor(n2, o, 64);
+    if (lane == 0) sdot[wv][0] = make_double2(n2, 0.0);
+    __syncthreads();
+    double nn = sdot[0][0].x;
+#pragma unroll
+    for (int v = 1; v < 8; ++v) nn += sdot[v][0].x;
+    const double r = sqrt(nn);
+    c[k] = cscale(c[k], 1.0 / r);
+    logr += log(r);
+    __syncthreads();
+    // r_kj = sum_q conj(c_qk) c_qj for j > k, then c_j -= r_kj c_k
+#pragma clang loop unroll(full)
+    for (int j = k + 1; j < NMAX; ++j) {
+      double re = c[k].x * c[j].x + c[k].y * c[j].y;
+      double im = c[k].x * c[j].y - c[k].y * c[j].x;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o, 64);
+        im += __shfl_xor(im, o, 64);
+      }
+      if (lane == 0) sdot[wv][j] = make_double2(re, im);
+    }
+    __syncthreads();
+#pragma clang loop unroll(full)
+    for (int j = k + 1; j < NMAX; ++j) {
+      double2 d = sdot[0][j];
+#pragma unroll
+      for (int v = 1; v < 8; ++v) d = cadd(d, sdot[v][j]);
+      c[j] = csub(c[j], cmul(d, c[k]));
+    }
+    __syncthreads();
+  }
+  if (q < M) {
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+      if (j < N) row[j] = c[j];
+  }
+  if (q == 0) logr_out[(size_t)w * 2 + s] = logr;
+}
+
 // log<Psi_T|phi> -= sum over both blocks of log R_ii
 __global__ void k_mgs_finish(const double *__restrict__ logr, int W, double2 *__restrict__ logo) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,7 +376,18 @@ __global__ void k_mgs_finish(const double *__restrict__ logr, int W, double2 *__
 }
 
 hipError_t launch_mgs(double2 *phi, int M, int Na, int Nb, int W, double2 *logo, hipStream_t st, double *scratch) {
-  hipLaunchKernelGGL(k_mgs, dim3(W, 2), dim3(kThreads), 0, st, phi, M, Na, Nb, scratch);
+  const int n = Na > Nb ? Na : Nb;
+  if (M <= 512 && n <= 48) {
+    const dim3 g(W, 2), b(512);
+    if (n <= 8) hipLaunchKernelGGL(k_mgs_reg<8>, g, b, 0, st, phi, M, Na, Nb, scratch);
+    else if (n <= 16) hipLaunchKernelGGL(k_mgs_reg<16>, g, b, 0, st, phi, M, Na, Nb, scratch);
+    else if (n <= 24) hipLaunchKernelGGL(k_mgs_reg<24>, g, b, 0, st, phi, M, Na, Nb, scratch);
+    else if (n <= 32) hipLaunchKernelGGL(k_mgs_reg<32>, g, b, 0, st, phi, M, Na, Nb, scratch);
+    else if (n <= 40) hipLaunchKernelGGL(k_mgs_reg<40>, g, b, 0, st, phi, M, Na, Nb, scratch);
+    else hipLaunchKernelGGL(k_mgs_reg<48>, g, b, 0, st, phi, M, Na, Nb, scratch);
+  } else {
+    hipLaunchKernelGGL(k_mgs, dim3(W, 2), dim3(kThreads), 0, st, phi, M, Na, Nb, scratch);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mgs_finish, dim3((W + 255) / 256), dim3(256), 0, st, scratch, W, logo);
