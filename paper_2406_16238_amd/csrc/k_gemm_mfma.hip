@@ -26,9 +26,10 @@
 //             multiplied by i, (re, im) -> (-im, re)  ([T ; iT] for [Re A | Im A])
 // With cplx_rows set, output row i goes to C[(i/2)*sci + i%2 + j*scj] (the two
 // rows of one complex vector interleave).
-// Workgroups are remapped so that each XCD (every 8th workgroup id) walks a
-// contiguous range of tiles, row tiles fastest, which keeps a B column panel in
-// one XCD's L2 while all row tiles consume it.
+// The launch is 1-D over (tile, batch, K slice) and remapped so that each XCD
+// (every 8th workgroup id) walks one contiguous stretch of that order, row tiles
+// fastest: a B column panel stays in one XCD's L2 while all row tiles consume
+// it, and the tiles of one batch entry (one walker's slab) share an XCD.
 #include "afqmc_internal.h"
 #include "device_util.h"
 
@@ -49,14 +50,15 @@ __global__ __launch_bounds__(kThreads, MINB) void k_gemm_mfma(GemmArgs a, int kc
   double *sA = smem;                        // [2][MKC][LDA]
   double *sB = smem + 2 * MKC * LDA;        // [2][MKC][LDB]
 
-  // XCD-aware tile order
+  // XCD-aware order over (tile, batch entry and K slice)
   const int nb = gx * gy;
-  int lin = blockIdx.x;
-  const int per = nb / 8;
-  if (lin < per * 8) lin = (lin % 8) * per + lin / 8;
-  const int bx = lin % gx, by = lin / gx;
+  const int ntot = gridDim.x;
+  const int per = ntot >> 3, rem = ntot & 7;
+  const int xcd = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int lin = xcd * per + min(xcd, rem) + jx;
+  const int tile = lin % nb, bz = lin / nb;
+  const int bx = tile % gx, by = tile / gx;
   const int i0 = bx * BM, j0 = by * BN;
-  const int bz = blockIdx.z;
   const int b = bz / a.ksplit, s = bz - b * a.ksplit;
   const int kbeg = s * kchunk;
   const int kend = min(a.k, kbeg + kchunk);
@@ -228,7 +230,7 @@ hipError_t run(const GemmArgs &a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k, dim3(gx * gy, 1, a.batch * ks), dim3(kThreads), lds, st, g, kchunk, gx, gy);
+  hipLaunchKernelGGL(k, dim3((unsigned)((long)gx * gy * a.batch * ks)), dim3(kThreads), lds, st, g, kchunk, gx, gy);
   return hipGetLastError();
 }
 
