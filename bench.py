@@ -88,6 +88,8 @@ def parse_args(argv=None):
     ap.add_argument("--cv-system", default="headline", choices=["headline", "benzene"],
                     help="cv: the headline shape, or M=1512, N=42+42, 6000 Cholesky vectors, 64 walkers with the "
                          "Cholesky tensor drawn on the device")
+    ap.add_argument("--no-prop32-leg", action="store_true",
+                    help="skip timing the reported form with FP32 propagation as well")
     ap.add_argument("--repeats", type=int, default=4,
                     help="further timed blocks of --steps steps after the reported one (their walker-steps/s and "
                          "the median of all blocks are reported beside value)")
@@ -490,10 +492,15 @@ def main(argv=None):
     prop32 = args.prop_precision == "fp32"
     rep_key = args.precision + ("+fp32prop" if prop32 else "")
     forms = ["fp64"] if rep_key == "fp64" else ["fp64", rep_key]
+    # the reported form with FP32 propagation too (the paper's mixed precision on top of it)
+    p32_key = args.precision + "+fp32prop"
+    p32_ok = s.nbasis % 4 == 0 and s.nalpha + s.nbeta <= 96
+    if rep_key != "fp64" and not prop32 and not args.no_prop32_leg and p32_ok:
+        forms.append(p32_key)
     ctxs, runs = {}, {}
     for form in forms:
-        opt = A.default_options(precision=PRECISION_CODE[args.precision if form == rep_key else "fp64"])
-        if form == rep_key and prop32:
+        opt = A.default_options(precision=PRECISION_CODE[args.precision if form in (rep_key, p32_key) else "fp64"])
+        if form == p32_key:
             opt.prop_precision = A.FP32_CONTRACT
         ctxs[form] = A.setup_hamiltonian(sysin, opt)
         runs[form] = time_path(A, torch, ctxs[form], spec, trial, xs, args)
@@ -559,6 +566,21 @@ def main(argv=None):
                                           "bar": 1e-4, "within_bar": bool(d.max() <= 1e-4)}
         # the same fields from the same walkers: the mixed estimators of the two trajectories
         out["mixed_energy_difference_vs_fp64_ha"] = abs(r["mixed_energy"] - f["mixed_energy"])
+    if p32_key in runs and p32_key != rep_key:
+        q = runs[p32_key]
+        e_q = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        e_64 = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        A.local_energy(ctxs[p32_key], q["walkers"], e_q)
+        A.local_energy(ctxs["fp64"], q["walkers"], e_64)
+        torch.cuda.synchronize()
+        dq = np.abs(e_q.cpu().numpy()[:, 0] - e_64.cpu().numpy()[:, 0])
+        qv = W * args.steps / (q["total_ms"] * 1e-3)
+        out["fp32_propagation_path"] = {
+            "value": round(qv, 2), "ms_per_step": round(q["total_ms"] / args.steps, 4),
+            "speedup_vs_fp64": round(qv / (W * args.steps / (runs["fp64"]["total_ms"] * 1e-3)), 3),
+            "energy_error_vs_fp64_ha": {"max": float(dq.max()), "bar": 1e-4, "within_bar": bool(dq.max() <= 1e-4)},
+            "mixed_energy_difference_vs_fp64_ha": abs(q["mixed_energy"] - runs["fp64"]["mixed_energy"]),
+            "note": "the reported form with V_HS and the Taylor terms in FP32 as well (the paper's mixed precision)"}
     if args.phases:
         for form in forms:
             print(f"-- {form}", file=sys.stderr)
