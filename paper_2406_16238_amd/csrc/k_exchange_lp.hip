@@ -47,14 +47,13 @@ constexpr int LKC = 32;     // contraction rows per LDS stage
 constexpr bool kExchangeDma = AFQMC_EXCHANGE_DMA;  // stage the split-BF16 operands by LDS DMA
 }  // namespace
 
-// Trace epilogue shared by both forms.  T of each wave (ROWW x CP floats) is in
-// LDS at row stride TSF; every lane pairs each accumulator entry with the
-// transposed entry of the same Cholesky vector and accumulates in R (FP64 or FP32).
-// only >= 0 restricts the pass to that Cholesky vector of the wave (whose T
-// alone is then in LDS, at the addresses of the full layout minus its offset).
+// Trace epilogue of the FP32 and three-term forms.  T of each wave (ROWW x CP
+// floats) is in LDS at row stride TSF; every lane pairs each accumulator entry
+// with the transposed entry of the same Cholesky vector and accumulates in R
+// (FP64 or FP32).
 template <int NR, int CT, int RT, typename R = double>
 __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *sT, int TSF, int lane,
-                                         R &pre, R &pim, R *dg, int only) {
+                                         R &pre, R &pim, R *dg) {
   const int lr = lane & 15, lk = lane >> 4;
   const bool odd = lr & 1;
 #pragma unroll
@@ -65,7 +64,6 @@ __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *
       for (int r = 0; r < 4; ++r) {
         const int row = rt * 16 + 4 * lk + r;
         const int gl = row / NR, i = row - gl * NR;
-        if (only >= 0 && gl != only) continue;
         const int col = ct * 16 + lr, j = col >> 1;
         const float2 t = *reinterpret_cast<const float2 *>(sT + (gl * NR + j) * TSF + 2 * i);
         const R v = (R)acc[rt][ct][r];
@@ -75,6 +73,65 @@ __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *
         if (gl == 0) dg[0] += d;
         else dg[1] += d;
       }
+}
+
+// Trace epilogue of the two-term form, one Cholesky vector (pass) of the wave
+// at a time.  T^g goes to LDS as two planes, Re and Im, of U[j][i] = T^g_ij at
+// row stride NR + 4: a lane's four accumulator rows i0..i0+3 of column (j, re|im)
+// are one 16-byte store, and the partner T^g_ji of an entry is two 4-byte reads
+// at offsets fixed at compile time, so the epilogue is almost free of VALU work
+// (a wave64 VALU instruction costs four cycles of the SIMD).  Rows of one tile
+// belong to one Cholesky vector unless the tile straddles two (NR % 16 != 0);
+// in that tile each lane's four rows still share one.
+template <int NR, int CT, int RT>
+__device__ __forceinline__ void lp_store_u(const f4v (&acc)[RT][CT], float *sU, int lane, int pass) {
+  constexpr int CS = NR + 4;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int sidx = (lr & 1) * NR * CS + (lr >> 1) * CS + 4 * lk - pass * NR;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
+    if (glo == ghi && glo != pass) continue;
+    const bool mine = glo == ghi || (rt * 16 + 4 * lk) / NR == pass;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      if (mine) *reinterpret_cast<f4v *>(sU + sidx + ct * 8 * CS + rt * 16) = acc[rt][ct];
+  }
+}
+
+template <int NR, int CT, int RT>
+__device__ __forceinline__ void lp_trace_u(const f4v (&acc)[RT][CT], const float *sU, int lane, float &pre,
+                                           float &pim, float *dg, int pass) {
+  constexpr int CS = NR + 4;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool odd = lr & 1;
+  const int bidx = (4 * lk - pass * NR) * CS + (lr >> 1);   // + (rt 16 + r) CS + 8 ct: U[i][j], row i of the pass
+  float a0 = 0.f, a1 = 0.f;                                 // sum of v Re T_ji, sum of v Im T_ji
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
+    if (glo == ghi && glo != pass) continue;
+    const bool mine = glo == ghi || (rt * 16 + 4 * lk) / NR == pass;
+    if (!mine) continue;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int off = bidx + (rt * 16 + r) * CS + ct * 8;
+        const float v = acc[rt][ct][r];
+        a0 = fmaf(v, sU[off], a0);
+        a1 = fmaf(v, sU[NR * CS + off], a1);
+      }
+  }
+  // the lane holds Re T_ij (even lr) or Im T_ij (odd lr)
+  pre += odd ? -a1 : a0;
+  pim += odd ? a0 : a1;
+  // diagonal, in the parity convention of lp_finish: lane l adds Re (l even)
+  // or Im (l odd) of T_ii, i = l / 2
+  for (int l = lane; l < 2 * NR; l += 64) {
+    const int i = l >> 1;
+    dg[pass] += sU[(l & 1) * NR * CS + i * CS + i];
+  }
 }
 
 template <int GC>
@@ -196,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
       for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
   __syncthreads();
   double pre = 0.0, pim = 0.0, dg[2] = {0.0, 0.0};
-  lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg, -1);
+  lp_trace<NR, CT, RT>(acc, sT, TSF, lane, pre, pim, dg);
   lp_finish<GC>(pre, pim, dg, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart, vbpart);
 }
 
@@ -371,6 +428,10 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     AFQMC_SWEEP(ah, bm)
     AFQMC_SWEEP(ah, bh)
 #undef AFQMC_SWEEP
+    // keep every MFMA of the chunk ahead of the wait for the next stage (the
+    // scheduler would otherwise sink most of them below the barrier, leaving
+    // the copies a fraction of the chunk to land in)
+    __builtin_amdgcn_sched_barrier(0);
     if constexpr (DMA) {
       __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into the other buffer have landed
     } else if (ch + 1 < nchunk) {
@@ -383,21 +444,13 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   // sums over lanes and Cholesky vectors in FP64
   float pre = 0.f, pim = 0.f, dg[2] = {0.f, 0.f};
   if constexpr (NT == 2) {
-    // one Cholesky vector of the wave at a time: T^g (NR x CP) per wave in LDS
-    float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * NR * TSF;
+    // one Cholesky vector of the wave at a time: U (two NR x (NR + 4) planes) per wave in LDS
+    float *sU = reinterpret_cast<float *>(bsm) + (size_t)wv * NR * (NR + 4) * 2;
 #pragma unroll
     for (int pass = 0; pass < GC; ++pass) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = rt * 16 + 4 * lk + r;
-            if (row / NR == pass) sT[(row - pass * NR) * TSF + ct * 16 + lr] = acc[rt][ct][r];
-          }
+      lp_store_u<NR, CT, RT>(acc, sU, lane, pass);
       __syncthreads();
-      lp_trace<NR, CT, RT, float>(acc, sT - pass * NR * TSF, TSF, lane, pre, pim, dg, pass);
+      lp_trace_u<NR, CT, RT>(acc, sU, lane, pre, pim, dg, pass);
       if (pass + 1 < GC) __syncthreads();
     }
   } else {
@@ -409,7 +462,7 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
 #pragma unroll
         for (int r = 0; r < 4; ++r) sT[(rt * 16 + 4 * lk + r) * TSF + ct * 16 + lr] = acc[rt][ct][r];
     __syncthreads();
-    lp_trace<NR, CT, RT, float>(acc, sT, TSF, lane, pre, pim, dg, -1);
+    lp_trace<NR, CT, RT, float>(acc, sT, TSF, lane, pre, pim, dg);
   }
   const double dgd[2] = {(double)dg[0], (double)dg[1]};
   lp_finish<GC>((double)pre, (double)pim, dgd, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride, gb * LWY + wy, ekpart,
@@ -539,9 +592,9 @@ size_t lds_f32(int nr) {
 }
 size_t lds_bf(int nr, int nt) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
-  const size_t nbuf = 2, erows = nt == 2 ? nr : roww;
+  const size_t nbuf = 2;
   const size_t stage = nbuf * nt * (LWY * roww + LWX * cp) * LKC * sizeof(__bf16);
-  const size_t epi = 4ull * erows * (cp + 2) * sizeof(float);
+  const size_t epi = nt == 2 ? 4ull * nr * (nr + 4) * 2 * sizeof(float) : 4ull * roww * (cp + 2) * sizeof(float);
   return stage > epi ? stage : epi;
 }
 }  // namespace
