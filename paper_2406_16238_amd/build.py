@@ -41,6 +41,19 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _check_defined(lib: str) -> None:
+    """Fail when the library references a symbol of its own namespace that no
+    object defines: the host pass can drop a kernel's launch stub without a
+    diagnostic, which would otherwise surface only when the library is loaded."""
+    nm = shutil.which("nm") or "/usr/bin/nm"
+    r = subprocess.run([nm, "-D", "--undefined-only", lib], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"nm failed on {lib}:\n{r.stderr}")
+    missing = [ln.split()[-1] for ln in r.stdout.splitlines() if "_ZN5afqmc" in ln]
+    if missing:
+        raise RuntimeError("libafqmc.so leaves its own symbols undefined:\n  " + "\n  ".join(missing))
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
@@ -51,6 +64,7 @@ def build(verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    _check_defined(tmp)
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

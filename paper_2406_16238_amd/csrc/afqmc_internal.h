@@ -106,6 +106,8 @@ struct System {
 
 // Reduced-precision exchange (k_exchange_lp.hip).
 bool lp_exchange_supported(int precision, int nr);
+// the split-BF16 kernels address their operand planes with 32-bit element offsets
+bool lp_operands_addressable(int precision, int G, int M, int W, int nr);
 size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs);
 hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st);
 hipError_t lp_enable_lds(const System &s);

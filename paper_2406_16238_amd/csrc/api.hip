@@ -434,6 +434,9 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     const bool ok = s.ex_mfma && (s.Na == 0 || lp_exchange_supported(s.precision, s.ex_plan[0].NR)) &&
                     (s.Nb == 0 || lp_exchange_supported(s.precision, s.ex_plan[1].NR));
     if (!ok) return fail(AFQMC_ERR_UNSUPPORTED, "reduced precision is built for spin blocks of up to 48 orbitals");
+    for (int sp = 0; sp < 2; ++sp)
+      if ((sp ? s.Nb : s.Na) > 0 && !lp_operands_addressable(s.precision, s.G, s.M, s.W, s.ex_plan[sp].NR))
+        return fail(AFQMC_ERR_UNSUPPORTED, "reduced-precision exchange operands exceed 2^32 elements");
   }
   if (s.ex_mfma) {
     s.ex_nparts[0] = s.ex_plan[0].ngroups;

@@ -31,9 +31,6 @@
 
 namespace afqmc {
 
-// 16 zero bytes: the source of LDS DMA lanes whose rows lie past the operands
-__device__ const uint4 kZero16 = {0u, 0u, 0u, 0u};
-
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
@@ -45,6 +42,10 @@ constexpr int LKC = 32;     // contraction rows per LDS stage
 #define AFQMC_EXCHANGE_DMA 1
 #endif
 constexpr bool kExchangeDma = AFQMC_EXCHANGE_DMA;  // stage the split-BF16 operands by LDS DMA
+// Cholesky vectors per plane of the split-BF16 half rotation: G rounded up to
+// whole workgroup rows (LWY groups of at most two vectors), the extra vectors
+// zero, so every staged row a workgroup reads lies inside the planes.
+__host__ __device__ constexpr int lp_padded_g(int G) { return (G + 2 * LWY - 1) / (2 * LWY) * (2 * LWY); }
 }  // namespace
 
 // Trace epilogue of the FP32 and three-term forms.  T of each wave (ROWW x CP
@@ -298,10 +299,11 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
 
   int gb, wb;
   tile_of(blockIdx.x, ngb * nwb, ngb, nwb, group, gb, wb);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: LDS stage addresses stay scalar
   const int wy = wv / LWX, wx = wv - (wv / LWX) * LWX;
   const int g0 = gb * LWY * GC, w0 = wb * LWX;
-  const size_t aplane = (size_t)G * NR * Kp, bplane = (size_t)W * CP * Kp;
+  const size_t aplane = (size_t)lp_padded_g(G) * NR * Kp, bplane = (size_t)W * CP * Kp;
 
   uint4 ra[APT], rb[BPT];
   auto load = [&](int q0) {
@@ -347,28 +349,45 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     }
   };
 
+  // LDS DMA sources: this lane's 16 bytes of every staged row it fills, as
+  // element offsets at k = 0 (loop-invariant; a chunk adds q0 to the uniform
+  // base).  Rows past G are the zero vectors of the padded planes; columns of
+  // walkers past W repeat walker W - 1 (their results are never written).
+  constexpr int NIA = (AV / 64 + 3) / 4, NIB = (BV / 64 + 3) / 4;
+  uint32_t offa[NIA], offb[NIB];
+  {
+    const int t4 = lane >> 2, slot = lane & 3;
+#pragma unroll
+    for (int r = 0; r < NIA; ++r) {
+      const int blk = wv + 4 * r, t = 16 * blk + t4;          // staged row (p, row)
+      const int row = t % ROWS, p = t / ROWS;
+      const int gl = row / NR, i = row - gl * NR, g = g0 + gl;
+      offa[r] = (uint32_t)(p * aplane + ((size_t)g * NR + i) * Kp + 8 * (slot ^ swz(t)));
+    }
+#pragma unroll
+    for (int r = 0; r < NIB; ++r) {
+      const int blk = wv + 4 * r, t = 16 * blk + t4;          // staged column (p, col)
+      const int col = t % COLS, p = t / COLS;
+      const int wl = col / CP, c = col - wl * CP, w = min(w0 + wl, W - 1);
+      offb[r] = (uint32_t)(p * bplane + ((size_t)w * CP + c) * Kp + 8 * (slot ^ swz(t)));
+    }
+  }
   auto issue = [&](int q0, int buf) {
     __bf16 *a = sA + buf * ASZ;
     __bf16 *b = sB + buf * BSZ;
-    const int t4 = lane >> 2, slot = lane & 3;
+    const __bf16 *la = LtB + q0, *tb = ThB + q0;
 #pragma unroll
-    for (int r = 0; r < (AV / 64 + 3) / 4; ++r) {
-      const int blk = wv + 4 * r, t = 16 * blk + t4;          // staged row (p, row)
-      if (blk >= AV / 64) break;                              // uniform in the wave
-      const int row = t % ROWS, p = t / ROWS;
-      const int gl = row / NR, i = row - gl * NR, g = g0 + gl;
-      const __bf16 *src = g < G ? LtB + p * aplane + ((size_t)g * NR + i) * Kp + q0 + 8 * (slot ^ swz(t))
-                                : reinterpret_cast<const __bf16 *>(&kZero16);
+    for (int r = 0; r < NIA; ++r) {
+      const int blk = wv + 4 * r;
+      if ((AV / 64) % 4 != 0 && blk >= AV / 64) break;       // uniform in the wave
+      const __bf16 *src = la + offa[r];
       __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(a + blk * 512), 16, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < (BV / 64 + 3) / 4; ++r) {
-      const int blk = wv + 4 * r, t = 16 * blk + t4;          // staged column (p, col)
-      if (blk >= BV / 64) break;                              // uniform in the wave
-      const int col = t % COLS, p = t / COLS;
-      const int wl = col / CP, c = col - wl * CP, w = w0 + wl;
-      const __bf16 *src = w < W ? ThB + p * bplane + ((size_t)w * CP + c) * Kp + q0 + 8 * (slot ^ swz(t))
-                                : reinterpret_cast<const __bf16 *>(&kZero16);
+    for (int r = 0; r < NIB; ++r) {
+      const int blk = wv + 4 * r;
+      if ((BV / 64) % 4 != 0 && blk >= BV / 64) break;       // uniform in the wave
+      const __bf16 *src = tb + offb[r];
       __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(b + blk * 512), 16, 0, 0);
     }
   };
@@ -486,14 +505,14 @@ __global__ void k_lt_to_f32(const double *__restrict__ LtS, long n, float *__res
 // LtB[p][g][i][q] (p < NT) from LtS[g][q][i] (rows i < NR, q < Kp, zero for q >= M)
 template <int NT>
 __global__ void k_lt_to_bf16(const double *__restrict__ LtS, int G, int M, int NR, int Kp, __bf16 *__restrict__ LtB) {
-  const long n = (long)G * NR * Kp;
+  const long n = (long)lp_padded_g(G) * NR * Kp;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int q = (int)(e % Kp);
   const long t = e / Kp;
   const int i = (int)(t % NR);
   const int g = (int)(t / NR);
-  const float x = (q < M) ? (float)LtS[((size_t)g * M + q) * NR + i] : 0.f;
+  const float x = (q < M && g < G) ? (float)LtS[((size_t)g * M + q) * NR + i] : 0.f;
   __bf16 h, m, l;
   split3(x, h, m, l);
   LtB[e] = h;
@@ -610,7 +629,13 @@ size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs) {
   const int kp = ((M + LKC - 1) / LKC) * LKC;
   if (precision == AFQMC_FP32_CONTRACT) return lhs ? (size_t)G * M * nr : (size_t)W * M * 2 * nr;
   const size_t nt = bf_terms(precision);
-  return lhs ? nt * G * nr * kp : nt * W * 2 * nr * kp;
+  return lhs ? nt * lp_padded_g(G) * nr * kp : nt * W * 2 * nr * kp;
+}
+
+bool lp_operands_addressable(int precision, int G, int M, int W, int nr) {
+  if (!bf_terms(precision)) return true;
+  const size_t lim = (size_t)1 << 32;
+  return lp_operand_elems(precision, G, M, W, nr, true) < lim && lp_operand_elems(precision, G, M, W, nr, false) < lim;
 }
 
 hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st) {
@@ -622,7 +647,7 @@ hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st) {
                        static_cast<float *>(s.lp_lhs[spin]));
   } else {
     const int kp = ((s.M + LKC - 1) / LKC) * LKC;
-    const long n = (long)s.G * p.NR * kp;
+    const long n = (long)lp_padded_g(s.G) * p.NR * kp;
     hipLaunchKernelGGL(bf_terms(s.precision) == 3 ? k_lt_to_bf16<3> : k_lt_to_bf16<2>,
                        dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtS[spin], s.G, s.M, p.NR, kp,
                        static_cast<__bf16 *>(s.lp_lhs[spin]));
