@@ -46,6 +46,8 @@ __global__ __launch_bounds__(kThreads, MINB) void k_gemm_mfma(GemmArgs a, int kc
   constexpr int APT = (AMODE == 3) ? BM * MKC / (2 * kThreads) : BM * MKC / kThreads;
   constexpr int BPT = BN * MKC / kThreads;
   static_assert(WM * WN == 4, "four waves");
+  static_assert(!(AMODE == 0 && BMODE == 0) || (MKC == 16 && kThreads == 256 && APT * 16 == BM && BPT * 16 == BN),
+                "load00 covers the tiles");
   extern __shared__ double smem[];
   double *sA = smem;                        // [2][MKC][LDA]
   double *sB = smem + 2 * MKC * LDA;        // [2][MKC][LDB]
@@ -71,7 +73,32 @@ __global__ __launch_bounds__(kThreads, MINB) void k_gemm_mfma(GemmArgs a, int kc
 
   double ra[(AMODE == 3) ? 2 * APT : APT];
   double rb[BPT];
+  // Modes 0/0 (row-major A and B): thread t loads A rows t/16 + 16r at k = t%16
+  // and B columns t%16 + 16c at k row t/16, so every address is a per-thread
+  // base plus a uniform step; interior chunks skip the bounds tests.
+  const int tq = tid >> 4, tl = tid & 15;
+  auto load00 = [&](int k0) {
+    const double *pa = A + (size_t)(i0 + tq) * a.sai + k0 + tl;
+    const double *pb = B + (size_t)(k0 + tq) * a.sbk + j0 + tl;
+    const size_t astep = (size_t)16 * a.sai;
+    if (i0 + BM <= a.m && j0 + BN <= a.n && k0 + MKC <= kend) {
+#pragma unroll
+      for (int r = 0; r < APT; ++r) ra[r] = pa[r * astep];
+#pragma unroll
+      for (int c = 0; c < BPT; ++c) rb[c] = pb[16 * c];
+    } else {
+      const bool ka = k0 + tl < kend, kb = k0 + tq < kend;
+#pragma unroll
+      for (int r = 0; r < APT; ++r) ra[r] = (ka && i0 + tq + 16 * r < a.m) ? pa[r * astep] : 0.0;
+#pragma unroll
+      for (int c = 0; c < BPT; ++c) rb[c] = (kb && j0 + tl + 16 * c < a.n) ? pb[16 * c] : 0.0;
+    }
+  };
   auto load = [&](int k0) {
+    if constexpr (AMODE == 0 && BMODE == 0) {
+      load00(k0);
+      return;
+    }
     if (AMODE == 3) {
 #pragma unroll
       for (int r = 0; r < APT; ++r) {
@@ -126,6 +153,13 @@ __global__ __launch_bounds__(kThreads, MINB) void k_gemm_mfma(GemmArgs a, int kc
   auto store = [&](int buf) {
     double *sa = sA + buf * MKC * LDA;
     double *sb = sB + buf * MKC * LDB;
+    if constexpr (AMODE == 0 && BMODE == 0) {
+#pragma unroll
+      for (int r = 0; r < APT; ++r) sa[tl * LDA + tq + 16 * r] = ra[r];
+#pragma unroll
+      for (int c = 0; c < BPT; ++c) sb[tq * LDB + tl + 16 * c] = rb[c];
+      return;
+    }
     if (AMODE == 3) {
 #pragma unroll
       for (int r = 0; r < APT; ++r) {
