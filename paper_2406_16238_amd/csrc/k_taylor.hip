@@ -202,24 +202,41 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
   const int wm = wv / WN, wn = wv - (wv / WN) * WN;
   const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
 
+  // Loop-invariant addressing: A element (plane, row, k pair) e = tid + NTH r
+  // keeps its source offset at k = 0 and its LDS slot; T is loaded as columns
+  // t%16 + 16c of contraction row t/16.  Interior chunks skip the bounds tests.
+  static_assert(BPT * NTH == BV && NTH == 16 * TKC, "T staged as t%16 + 16c, row t/16");
+  const int tq = tid >> 4, tl = tid & 15;
+  size_t offa[APT];
+  int sla[APT];
+  bool rowa[APT];
+#pragma unroll
+  for (int r = 0; r < APT; ++r) {
+    const int e = tid + r * NTH;                   // (plane, row, k pair)
+    const int pr = e / (TKC / 2), kp = e - pr * (TKC / 2);
+    const int pl = pr / BM, row = pr - pl * BM;
+    offa[r] = (IMAG ? 1 : pl) * MM + (size_t)(i0 + row) * M + 2 * kp;
+    sla[r] = (pl * TKC + 2 * kp) * LDA + row;
+    rowa[r] = e < AV && i0 + row < M;
+  }
+  const bool rows_in = i0 + BM <= M && AV % NTH == 0, cols_in = BNC <= Nt;
+  const int kpl = 2 * ((tid % (TKC / 2)));         // the k pair of every A element of this thread
+
   double2 ra[APT], rb[BPT];
   auto load = [&](int k0) {
+    const double2 *pb = Tw + (size_t)(k0 + tq) * Nt + tl;
+    if (rows_in && cols_in && k0 + TKC <= M) {
 #pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * NTH;                 // (plane, row, k pair)
-      const int pr = e / (TKC / 2), kp = e - pr * (TKC / 2);
-      const int pl = pr / BM, row = pr - pl * BM;
-      const int gi = i0 + row, gk = k0 + 2 * kp;
-      ra[r] = (e < AV && gi < M && gk < M)
-                  ? *reinterpret_cast<const double2 *>(Aw + (IMAG ? 1 : pl) * MM + (size_t)gi * M + gk)
-                  : make_double2(0.0, 0.0);
-    }
+      for (int r = 0; r < APT; ++r) ra[r] = *reinterpret_cast<const double2 *>(Aw + offa[r] + k0);
 #pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * NTH;                 // (k, complex column j)
-      const int kk = e / BNC, j = e - kk * BNC;
-      const int gk = k0 + kk;
-      rb[r] = (e < BV && j < Nt && gk < M) ? Tw[(size_t)gk * Nt + j] : make_double2(0.0, 0.0);
+      for (int c = 0; c < BPT; ++c) rb[c] = pb[16 * c];
+    } else {
+      const bool ka = k0 + kpl < M, kb = k0 + tq < M;
+#pragma unroll
+      for (int r = 0; r < APT; ++r)
+        ra[r] = (rowa[r] && ka) ? *reinterpret_cast<const double2 *>(Aw + offa[r] + k0) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < BPT; ++c) rb[c] = (kb && tl + 16 * c < Nt) ? pb[16 * c] : make_double2(0.0, 0.0);
     }
   };
   auto store = [&](int buf) {
@@ -227,22 +244,15 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
     double *b = sB + buf * 2 * TKC * LDB;
 #pragma unroll
     for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * NTH;
-      if (e < AV) {
-        const int pr = e / (TKC / 2), kp = e - pr * (TKC / 2);
-        const int pl = pr / BM, row = pr - pl * BM;
-        a[(pl * TKC + 2 * kp) * LDA + row] = ra[r].x;
-        a[(pl * TKC + 2 * kp + 1) * LDA + row] = ra[r].y;
+      if (AV % NTH == 0 || tid + r * NTH < AV) {
+        a[sla[r]] = ra[r].x;
+        a[sla[r] + LDA] = ra[r].y;
       }
     }
 #pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * NTH;
-      if (e < BV) {
-        const int kk = e / BNC, j = e - kk * BNC;
-        b[kk * LDB + j] = rb[r].x;
-        b[(TKC + kk) * LDB + j] = rb[r].y;
-      }
+    for (int c = 0; c < BPT; ++c) {
+      b[tq * LDB + tl + 16 * c] = rb[c].x;
+      b[(TKC + tq) * LDB + tl + 16 * c] = rb[c].y;
     }
   };
 
