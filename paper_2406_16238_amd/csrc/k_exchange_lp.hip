@@ -418,16 +418,19 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * (lk ^ swz(lr));
     const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * (lk ^ swz(lr));
     bf8v ah[RT], am[RT], bh[CT], bm[CT];
+    // the fragments of the first sweep (am x bh) are read first; the other
+    // RT + CT reads are spread over that sweep's MFMAs (the group barriers
+    // below), so an MFMA waits only on the reads it uses
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-      ah[i] = *reinterpret_cast<const bf8v *>(a + (0 * ROWS + i * 16) * RS);
-      am[i] = *reinterpret_cast<const bf8v *>(a + (1 * ROWS + i * 16) * RS);
+    for (int i = 0; i < (RT > CT ? RT : CT); ++i) {
+      if (i < RT) am[i] = *reinterpret_cast<const bf8v *>(a + (1 * ROWS + i * 16) * RS);
+      if (i < CT) bh[i] = *reinterpret_cast<const bf8v *>(b + (0 * COLS + i * 16) * RS);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < CT; ++j) {
-      bh[j] = *reinterpret_cast<const bf8v *>(b + (0 * COLS + j * 16) * RS);
-      bm[j] = *reinterpret_cast<const bf8v *>(b + (1 * COLS + j * 16) * RS);
-    }
+    for (int j = 0; j < CT; ++j) bm[j] = *reinterpret_cast<const bf8v *>(b + (1 * COLS + j * 16) * RS);
+#pragma unroll
+    for (int i = 0; i < RT; ++i) ah[i] = *reinterpret_cast<const bf8v *>(a + (0 * ROWS + i * 16) * RS);
     // one sweep over all accumulators per term, so dependent MFMAs are far
     // apart; the smallest terms first
 #define AFQMC_SWEEP(X, Y)                                                                         \
@@ -447,6 +450,14 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     AFQMC_SWEEP(ah, bm)
     AFQMC_SWEEP(ah, bh)
 #undef AFQMC_SWEEP
+    if constexpr (NT == 2 && 3 * RT * CT > 2 * (RT + CT)) {
+#pragma unroll
+      for (int q = 0; q < RT + CT; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // two MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * RT * CT - 2 * (RT + CT), 0);
+    }
     // keep every MFMA of the chunk ahead of the wait for the next stage (the
     // scheduler would otherwise sink most of them below the barrier, leaving
     // the copies a fraction of the chunk to land in)
