@@ -15,7 +15,10 @@ namespace afqmc {
 
 namespace {
 constexpr int OKQ = 32;                                   // rows of phi / Psi staged per pass
-constexpr int OMAXE = (kMaxSpinOrbitals * kMaxSpinOrbitals + kThreads - 1) / kThreads;  // O entries per thread
+constexpr int OBI = 2, OBJ = 4;                           // O entries per thread block: rows x columns
+constexpr int OBLK = ((kMaxSpinOrbitals + OBI - 1) / OBI * ((kMaxSpinOrbitals + OBJ - 1) / OBJ) + kThreads - 1) /
+                     kThreads;                             // O blocks per thread
+constexpr int TBQ = 2, TBJ = 4;                           // Theta entries per thread block: rows x columns
 }  // namespace
 
 // One workgroup per (walker, spin block).  LDS: O (N x N complex, inverted in
@@ -54,10 +57,25 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       return;
     }
     const int NN = N * N;
-    // O = Psi_s^T phi_s, OKQ rows at a time through LDS
-    double2 o[OMAXE];
+    // O = Psi_s^T phi_s, OKQ rows at a time through LDS.  Each thread owns
+    // blocks of OBI x OBJ entries, so a staged row costs OBI + OBJ LDS reads
+    // for OBI OBJ complex updates (indices past N are clamped on read and
+    // dropped on write); every entry sums over q in the same order.
+    const int nbj = (N + OBJ - 1) / OBJ, nob = ((N + OBI - 1) / OBI) * nbj;
+    int oi0[OBLK], oj0[OBLK];
 #pragma unroll
-    for (int r = 0; r < OMAXE; ++r) o[r] = make_double2(0.0, 0.0);
+    for (int b = 0; b < OBLK; ++b) {
+      const int bid = tid + b * kThreads;
+      oi0[b] = (bid / nbj) * OBI;
+      oj0[b] = (bid - (bid / nbj) * nbj) * OBJ;
+    }
+    double2 o[OBLK][OBI][OBJ];
+#pragma unroll
+    for (int b = 0; b < OBLK; ++b)
+#pragma unroll
+      for (int r = 0; r < OBI; ++r)
+#pragma unroll
+        for (int c = 0; c < OBJ; ++c) o[b][r][c] = make_double2(0.0, 0.0);
     for (int q0 = 0; q0 < M; q0 += OKQ) {
       const int nq = min(OKQ, M - q0);
       for (int e = tid; e < nq * N; e += blockDim.x) {
@@ -67,26 +85,39 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < OMAXE; ++r) {
-        const int e = tid + r * kThreads;
-        if (e < NN) {
-          const int i = e / N, j = e - (e / N) * N;
-          double re = o[r].x, im = o[r].y;
-          for (int qq = 0; qq < nq; ++qq) {
-            const double t = sPs[qq * N + i];
-            const double2 p = sPh[qq * N + j];
-            re = fma(t, p.x, re);
-            im = fma(t, p.y, im);
-          }
-          o[r] = make_double2(re, im);
+      for (int b = 0; b < OBLK; ++b) {
+        if (tid + b * kThreads >= nob) continue;
+        int ic[OBI], jc[OBJ];
+#pragma unroll
+        for (int r = 0; r < OBI; ++r) ic[r] = min(oi0[b] + r, N - 1);
+#pragma unroll
+        for (int c = 0; c < OBJ; ++c) jc[c] = min(oj0[b] + c, N - 1);
+        for (int qq = 0; qq < nq; ++qq) {
+          double t[OBI];
+          double2 pv[OBJ];
+#pragma unroll
+          for (int r = 0; r < OBI; ++r) t[r] = sPs[qq * N + ic[r]];
+#pragma unroll
+          for (int c = 0; c < OBJ; ++c) pv[c] = sPh[qq * N + jc[c]];
+#pragma unroll
+          for (int r = 0; r < OBI; ++r)
+#pragma unroll
+            for (int c = 0; c < OBJ; ++c)
+              o[b][r][c] = make_double2(fma(t[r], pv[c].x, o[b][r][c].x), fma(t[r], pv[c].y, o[b][r][c].y));
         }
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < OMAXE; ++r) {
-      const int e = tid + r * kThreads;
-      if (e < NN) sA[e] = o[r];
+    for (int b = 0; b < OBLK; ++b) {
+      if (tid + b * kThreads >= nob) continue;
+#pragma unroll
+      for (int r = 0; r < OBI; ++r)
+#pragma unroll
+        for (int c = 0; c < OBJ; ++c) {
+          const int i = oi0[b] + r, j = oj0[b] + c;
+          if (i < N && j < N) sA[i * N + j] = o[b][r][c];
+        }
     }
     if (tid == 0) ssing = 0;
     __syncthreads();
@@ -167,9 +198,11 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       }
       __syncthreads();
     }
-    // Theta_s = phi_s O_s^-1, OKQ rows of phi_s at a time through LDS
+    // Theta_s = phi_s O_s^-1, OKQ rows of phi_s at a time through LDS; each
+    // thread owns TBQ rows x TBJ columns, every entry summed over k in order
     if (theta) {
       double2 *th = theta + (size_t)w * M * Nt;
+      const int tnbj = (N + TBJ - 1) / TBJ;
       for (int q0 = 0; q0 < M; q0 += OKQ) {
         const int nq = min(OKQ, M - q0);
         for (int e = tid; e < nq * N; e += blockDim.x) {
@@ -177,16 +210,39 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
           sPh[qq * N + j] = ph[(size_t)(q0 + qq) * Nt + off + j];
         }
         __syncthreads();
-        for (int e = tid; e < nq * N; e += blockDim.x) {
-          const int qq = e / N, j = e - (e / N) * N;
-          double re = 0.0, im = 0.0;
+        const int tnb = ((nq + TBQ - 1) / TBQ) * tnbj;
+        for (int bid = tid; bid < tnb; bid += blockDim.x) {
+          const int qb = (bid / tnbj) * TBQ, jb = (bid - (bid / tnbj) * tnbj) * TBJ;
+          int qc[TBQ], jc[TBJ];
+#pragma unroll
+          for (int r = 0; r < TBQ; ++r) qc[r] = min(qb + r, nq - 1);
+#pragma unroll
+          for (int c = 0; c < TBJ; ++c) jc[c] = min(jb + c, N - 1);
+          double re[TBQ][TBJ], im[TBQ][TBJ];
+#pragma unroll
+          for (int r = 0; r < TBQ; ++r)
+#pragma unroll
+            for (int c = 0; c < TBJ; ++c) re[r][c] = im[r][c] = 0.0;
           for (int k = 0; k < N; ++k) {
-            const double2 p = sPh[qq * N + k];
-            const double2 x = sA[k * N + j];
-            re += p.x * x.x - p.y * x.y;
-            im += p.x * x.y + p.y * x.x;
+            double2 pv[TBQ], xv[TBJ];
+#pragma unroll
+            for (int r = 0; r < TBQ; ++r) pv[r] = sPh[qc[r] * N + k];
+#pragma unroll
+            for (int c = 0; c < TBJ; ++c) xv[c] = sA[k * N + jc[c]];
+#pragma unroll
+            for (int r = 0; r < TBQ; ++r)
+#pragma unroll
+              for (int c = 0; c < TBJ; ++c) {
+                re[r][c] += pv[r].x * xv[c].x - pv[r].y * xv[c].y;
+                im[r][c] += pv[r].x * xv[c].y + pv[r].y * xv[c].x;
+              }
           }
-          th[(size_t)(q0 + qq) * Nt + off + j] = make_double2(re, im);
+#pragma unroll
+          for (int r = 0; r < TBQ; ++r)
+#pragma unroll
+            for (int c = 0; c < TBJ; ++c)
+              if (qb + r < nq && jb + c < N)
+                th[(size_t)(q0 + qb + r) * Nt + off + jb + c] = make_double2(re[r][c], im[r][c]);
         }
         __syncthreads();
       }
