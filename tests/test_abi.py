@@ -35,6 +35,20 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(A.EXPORTS)
 
 
+def test_library_defines_every_kernel_it_launches(lib):
+    """Every symbol of the library's own namespace that it references is
+    defined in it: a kernel whose host launch stub went missing would only
+    fail when the library is loaded on a GPU machine."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--undefined-only", A.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    missing = [ln.split()[-1] for ln in out.splitlines() if "_ZN5afqmc" in ln]
+    assert not missing, missing
+
+
 def test_default_options(lib):
     o = A.default_options()
     assert o.precision == A.FP64 and o.taylor_order == 6 and o.fb_cap == 1.0
