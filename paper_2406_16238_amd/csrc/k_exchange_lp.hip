@@ -283,9 +283,9 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
 }
 
 // ---- split-BF16 forms ----------------------------------------------------------
-// LtB[p][g][NR][Kp], ThB[p][w][CP][Kp] (bf16, p = h, m (, l) for NT = 2 (3)
-// terms; contraction index contiguous and zero-padded to Kp, a multiple of 32)
-// for one spin block.
+// LtB[p][g][NR][Kp] (g over lp_padded_g(G), the extra vectors zero),
+// ThB[p][w][CP][Kp] (bf16, p = h, m (, l) for NT = 2 (3) terms; contraction
+// index contiguous and zero-padded to Kp, a multiple of 32) for one spin block.
 template <int NR, int NT>
 __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(const __bf16 *__restrict__ LtB,
                                                              const __bf16 *__restrict__ ThB, int Kp, int N, int G,
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   __bf16 *sA = bsm, *sB = bsm + NBUF * ASZ;
   // With LDS DMA (global_load_lds_dwordx4: lane L's 16 bytes land at the wave's
   // LDS base + 16 L) a stage is filled straight from memory, 1 KB (16 staged
-  // rows) per wave instruction; rows past G or W read a zero block.
+  // rows) per wave instruction (sources below).
   constexpr bool DMA = kExchangeDma;
   static_assert(AV % 64 == 0 && BV % 64 == 0, "whole 1 KB blocks");
 
