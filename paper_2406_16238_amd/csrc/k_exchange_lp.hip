@@ -135,29 +135,6 @@ __device__ __forceinline__ void lp_trace_u(const f4v (&acc)[RT][CT], const float
   }
 }
 
-// One DPP step of a wave reduction on a double (both 32-bit halves moved by
-// the same control); lanes that the row mask leaves out read 0.
-template <int CTRL, int ROWS = 0xF>
-__device__ __forceinline__ double dpp_double(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the 64 lanes, valid in lane 63: quad swaps and the row mirrors
-// give every lane its row's sum, the row broadcasts of lanes 15 and 31 add
-// the rows up.  A fixed order, and no LDS traffic (unlike a shuffle tree).
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v += dpp_double<0xB1>(v);         // quad_perm [1,0,3,2]
-  v += dpp_double<0x4E>(v);         // quad_perm [2,3,0,1]
-  v += dpp_double<0x141>(v);        // row_half_mirror
-  v += dpp_double<0x140>(v);        // row_mirror
-  v += dpp_double<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-  v += dpp_double<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-  return v;
-}
-
 template <int GC>
 __device__ __forceinline__ void lp_finish(double pre, double pim, const double *dg, int lane, int w, int W, int g0w,
                                           int G, int spin, int stride, int part, double2 *ekpart,

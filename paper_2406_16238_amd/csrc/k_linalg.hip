@@ -365,8 +365,8 @@ __global__ __launch_bounds__(kThreads) void k_mgs(double2 *__restrict__ phi, int
 // (M <= 512) of the block's NMAX >= N columns (N <= 48: the row fits the
 // registers of two waves per SIMD), so phi is read and written once.
 // Norms and the dot products of column k with the later columns are summed
-// over the rows by butterfly shuffles within each wave and then over the eight
-// waves through LDS in a fixed order; the loops over columns are unrolled so
+// over the rows by DPP steps within each wave (no LDS traffic) and then over
+// the eight waves through LDS in a fixed order; the loops over columns are unrolled so
 // the row stays in registers.
 template <int NMAX>
 __global__ __launch_bounds__(512) void k_mgs_reg(double2 *__restrict__ phi, int M, int Na, int Nb,
@@ -383,10 +383,8 @@ __global__ __launch_bounds__(512) void k_mgs_reg(double2 *__restrict__ phi, int 
   for (int k = 0; k < NMAX; ++k) {
     if (k >= N) continue;  // uniform in the workgroup
     // |column k|^2
-    double n2 = cabs2(c[k]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) n2 += __shfl_xor(n2, o, 64);
-    if (lane == 0) sdot[wv][0] = make_double2(n2, 0.0);
+    const double n2 = wave_sum_dpp(cabs2(c[k]));   // valid in lane 63
+    if (lane == 63) sdot[wv][0] = make_double2(n2, 0.0);
     __syncthreads();
     double nn = sdot[0][0].x;
 #pragma unroll
@@ -398,14 +396,9 @@ __global__ __launch_bounds__(512) void k_mgs_reg(double2 *__restrict__ phi, int 
     // r_kj = sum_q conj(c_qk) c_qj for j > k, then c_j -= r_kj c_k
 #pragma clang loop unroll(full)
     for (int j = k + 1; j < NMAX; ++j) {
-      double re = c[k].x * c[j].x + c[k].y * c[j].y;
-      double im = c[k].x * c[j].y - c[k].y * c[j].x;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_xor(re, o, 64);
-        im += __shfl_xor(im, o, 64);
-      }
-      if (lane == 0) sdot[wv][j] = make_double2(re, im);
+      const double re = wave_sum_dpp(c[k].x * c[j].x + c[k].y * c[j].y);
+      const double im = wave_sum_dpp(c[k].x * c[j].y - c[k].y * c[j].x);
+      if (lane == 63) sdot[wv][j] = make_double2(re, im);
     }
     __syncthreads();
 #pragma clang loop unroll(full)
