@@ -52,6 +52,30 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return v;
 }
 
+// Largest value over the 64 lanes with its index, ties to the smaller index
+// (values >= 0; lanes with nothing hold -1), valid in lane 63; the same DPP
+// steps as wave_sum_dpp, lanes the row mask leaves out reading (-1, INT_MAX).
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ void dpp_argmax_step(double &best, int &bi) {
+  const long long b = __double_as_longlong(best), none = __double_as_longlong(-1.0);
+  const int lo = __builtin_amdgcn_update_dpp((int)none, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(none >> 32), (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  const double ob = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  const int oi = __builtin_amdgcn_update_dpp(0x7fffffff, bi, CTRL, ROWS, 0xF, false);
+  if (ob > best || (ob == best && oi < bi)) {
+    best = ob;
+    bi = oi;
+  }
+}
+__device__ __forceinline__ void wave_argmax_dpp(double &best, int &bi) {
+  dpp_argmax_step<0xB1>(best, bi);
+  dpp_argmax_step<0x4E>(best, bi);
+  dpp_argmax_step<0x141>(best, bi);
+  dpp_argmax_step<0x140>(best, bi);
+  dpp_argmax_step<0x142, 0xA>(best, bi);
+  dpp_argmax_step<0x143, 0xC>(best, bi);
+}
+
 // Sum over a workgroup of kThreads threads (4 waves); result valid in thread 0.
 // Fixed shuffle tree, so the result is bitwise reproducible.
 template <int NV>

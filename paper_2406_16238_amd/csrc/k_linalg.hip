@@ -124,6 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
 
     for (int k = 0; k < N; ++k) {
       // pivot: largest |A_ik| for i >= k (first index on ties), found by wave 0
+      // (the arg-max over its lanes by DPP steps lands in lane 63)
       if (tid < 64) {
         double best = -1.0;
         int bi = k;
@@ -131,13 +132,8 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
           const double a = cabs2(sA[i * N + k]);
           if (a > best) { best = a; bi = i; }
         }
-#pragma unroll
-        for (int o2 = 32; o2 > 0; o2 >>= 1) {
-          const double ob = __shfl_down(best, o2, 64);
-          const int oi = __shfl_down(bi, o2, 64);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (tid == 0) {
+        wave_argmax_dpp(best, bi);
+        if (tid == 63) {
           spiv[k] = bi;
           const double2 pv = sA[bi * N + k];
           spivval = pv;
