@@ -458,8 +458,8 @@ def main(argv=None):
     args = parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures the walker step on one GPU only; multi-GPU runs are not part of this "
-              "build (walkers shard across GPUs with a 32-byte all-reduce per step).", file=sys.stderr)
+        print("bench.py measures the walker step on one GPU only; it offers no run on several GPUs "
+              "(walkers would shard across GPUs with a 32-byte all-reduce per step).", file=sys.stderr)
         return 2
 
     if args.workload == "batching":

@@ -47,7 +47,7 @@ typedef enum {
   AFQMC_ERR_ARG = 1,          /* invalid argument; nothing was launched       */
   AFQMC_ERR_OOM = 2,          /* device memory (or mem_limit_bytes) exhausted */
   AFQMC_ERR_HIP = 3,          /* a HIP runtime call or launch failed          */
-  AFQMC_ERR_UNSUPPORTED = 4   /* valid but outside what this build supports   */
+  AFQMC_ERR_UNSUPPORTED = 4   /* valid but outside what the library supports */
 } afqmc_status;
 
 /* Precision of the force-bias and exchange contractions (overlap LU,
@@ -322,7 +322,7 @@ afqmc_status afqmc_cv_state(afqmc_ctx *ctx, int32_t isys, void *f_out, int32_t *
                             void *hip_stream);
 
 /*
- * Population control (the driver step of Sec. 3.1 that keeps the walker
+ * Population control (the step of the simulation loop of Sec. 3.1 that keeps the walker
  * weights from spreading; the paper does not fix the method, this is the comb
  * of Calandra Buonaura and Sorella): with cumulative weights C_i summed in
  * walker order and total Wt, W teeth at (u + k) Wt / W for k = 0..W-1; new

@@ -415,7 +415,7 @@ def initial_amplitudes(logos) -> np.ndarray:
 
 def comb(weights, u: float):
     """Population control by a comb (the paper names population control among the
-    driver's steps, Sec. 3.1, without fixing the method; reading R11: the comb of
+    steps of the simulation loop, Sec. 3.1, without fixing the method; reading R11: the comb of
     Calandra Buonaura and Sorella, 1998).  With cumulative weights C_i (summed in
     walker order) and total Wt, W teeth sit at (u + k) Wt / W, k = 0..W-1, for one
     uniform u in [0, 1); tooth k selects the first walker i with C_i > tooth.
@@ -437,7 +437,7 @@ def comb(weights, u: float):
     return parents, np.full(W, step)
 
 
-# ---- driver ----------------------------------------------------------------------
+# ---- step loop -------------------------------------------------------------------
 
 def initial_logo(ham: OracleHamiltonian, phis) -> np.ndarray:
     return np.array([overlap_theta(ham, p)[0] for p in phis], dtype=np.complex128)

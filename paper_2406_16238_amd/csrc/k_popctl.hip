@@ -1,5 +1,5 @@
-// Population control by a comb (the driver's population-control step of
-// Sec. 3.1; the paper does not fix the method): with cumulative weights C_i
+// Population control by a comb (the population-control step of the
+// simulation loop of Sec. 3.1; the paper does not fix the method): with cumulative weights C_i
 // summed in walker order and total Wt, W teeth at (u + k) Wt / W for one
 // uniform u in [0, 1); tooth k selects the first walker i with C_i > tooth, new
 // walker k is a copy of it (orbitals, log-overlap, flags) and every weight

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_library_defines_every_kernel_it_launches(lib):
     """Every symbol of the library's own namespace that it references is
     defined in it: a kernel whose host launch stub went missing would only
-    fail when the library is loaded on a GPU machine."""
+    fail when the library is loaded on a machine with a GPU."""
     import shutil
     import subprocess
     nm = shutil.which("nm")
