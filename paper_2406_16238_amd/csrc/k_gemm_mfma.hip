@@ -204,13 +204,16 @@ __global__ __launch_bounds__(kThreads, MINB) void k_gemm_mfma(GemmArgs a, int kc
     store(0);
   }
   __syncthreads();
+  // a wave whose rows (or columns) all lie past the edge of C stages operands
+  // with the others but issues no MFMA
+  const bool live = i0 + wm * TM * 16 < a.m && j0 + wn * TN * 16 < a.n;
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch & 1;
     if (ch + 1 < nchunk) load(kbeg + (ch + 1) * MKC);
     const double *sa = sA + buf * MKC * LDA + wm * TM * 16 + l4;
     const double *sb = sB + buf * MKC * LDB + wn * TN * 16 + lr;
 #pragma unroll
-    for (int ks = 0; ks < MKC / 4; ++ks) {
+    for (int ks = 0; ks < (live ? MKC / 4 : 0); ++ks) {
       double av[TR], bv[TN];
 #pragma unroll
       for (int i = 0; i < TR; ++i) av[i] = sa[(ks * 4 + lk) * LDA + i * 4];

@@ -263,6 +263,9 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
     for (int j = 0; j < TN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = 0.0;
 
   const int nchunk = (M + TKC - 1) / TKC;
+  // a wave of the last row tile whose rows all lie past M stages operands with
+  // the others but issues no MFMA
+  const bool live = i0 + wm * 4 * TR < M;
   load(0);
   store(0);
   __syncthreads();
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
     const double *br = sB + buf * 2 * TKC * LDB + wn * 16 * TN + lr;
     const double *bi = br + TKC * LDB;
 #pragma unroll
-    for (int ks = 0; ks < TKC / 4; ++ks) {
+    for (int ks = 0; ks < (live ? TKC / 4 : 0); ++ks) {
       const int kr = ks * 4 + lk;
       double xr[TR], xi[TR], yr[TN], yi[TN];
 #pragma unroll
