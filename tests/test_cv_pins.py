@@ -90,3 +90,31 @@ def test_features_at_the_trial():
     assert abs(f[6] - 1.0) < 1e-15 and abs(f[7]) < 1e-15     # <Psi|Psi> = 1
     ek = CV.exchange_energy(ham, trial.astype(complex), O)
     assert abs(ham.e_trial - (f[2] + f[0] + ek.real)) < 1e-12
+
+
+def test_adam_first_two_updates_in_closed_form():
+    """Adam (Kingma & Ba 2015, Algorithm 1) from zero moments: with bias
+    correction the first update is -lr g1 / (|g1| + eps) per component, and the
+    second uses the corrected moments (b1 g1 + g2) / (1 + b1) and
+    (b2 g1^2 + g2^2) / (1 + b2).  Gradients of very different scales (down to
+    1e-9, where eps matters) separate eps outside the square root from eps
+    inside it, and a missing bias correction moves the first step by ~3x."""
+    rng = np.random.default_rng(5)
+    p0 = CV.init_params(seed=6)
+    scales = 10.0 ** rng.integers(-9, 2, size=CV.flatten(p0).size)
+    g1 = CV.unflatten(rng.standard_normal(scales.size) * scales)
+    g2 = CV.unflatten(rng.standard_normal(scales.size) * scales)
+    lr, b1, b2, eps = 2e-3, 0.9, 0.999, 1e-8
+    p = {k: v.copy() for k, v in p0.items()}
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(x) for k, x in p.items()}
+    CV.adam_step(p, g1, m, v, 1, lr)
+    a, ga = CV.flatten(p0), CV.flatten(g1)
+    step1 = a - lr * ga / (np.abs(ga) + eps)
+    assert np.allclose(CV.flatten(p), step1, rtol=1e-14, atol=1e-16)
+    CV.adam_step(p, g2, m, v, 2, lr)
+    gb = CV.flatten(g2)
+    mh = (b1 * ga + gb) / (1 + b1)
+    vh = (b2 * ga ** 2 + gb ** 2) / (1 + b2)
+    step2 = step1 - lr * mh / (np.sqrt(vh) + eps)
+    assert np.allclose(CV.flatten(p), step2, rtol=1e-12, atol=1e-16)

@@ -399,3 +399,120 @@ def test_comb_population_control():
         assert np.all(np.diff(parents) >= 0)
         mean += n / len(grid)
     assert np.max(np.abs(mean - W * w / total)) < 2e-3
+
+
+# P18 / P19: the phaseless projection and the force-bias cap ---------------------------
+class FockReference:
+    """Everything the weight update needs, built in Fock space only: the
+    Hamiltonian from the 4-index ERI, the mean-field shift and E_T as trial
+    expectations, the one-body operator of the shifted split as
+    H - C + 1/2 sum_g (v_g - m_g)^2, the force bias as the mixed expectation of
+    the bare two-body generator, and the overlap ratio S of eq. ovlp_ratio from
+    dense exponentials (no Green's function, no Thouless, no Taylor series)."""
+
+    def __init__(self, h1, chol, ecore, trial, na, nb, dt):
+        m = h1.shape[0]
+        self.sec = sec = FockSector(m, na, nb)
+        self.dt = dt
+        self.G = chol.shape[0]
+        H = sec.hamiltonian(h1, eri_from_chol(chol), ecore)
+        self.ct = sec.slater(trial, na)
+        nrm = self.ct @ self.ct
+        self.V = [sec.one_body(1j * chol[g]) for g in range(self.G)]
+        self.l = np.array([(self.ct @ sec.one_body(chol[g]) @ self.ct) / nrm for g in range(self.G)])
+        self.e_trial = float((self.ct @ H @ self.ct) / nrm)
+        self.C = ecore - 0.5 * float(np.sum(self.l ** 2))
+        Id = np.eye(sec.dim)
+        self.D = [self.V[g] - 1j * self.l[g] * Id for g in range(self.G)]
+        H1 = H - self.C * Id + 0.5 * sum(d @ d for d in self.D)
+        self.half = scipy.linalg.expm(-0.5 * dt * H1)
+
+    def xbar(self, phi, na):
+        cp = self.sec.slater(phi, na)
+        den = np.vdot(self.ct, cp)
+        return np.array([math.sqrt(self.dt) * np.vdot(self.ct, d @ cp) / den for d in self.D])
+
+    def S(self, phi, na, y):
+        cp = self.sec.slater(phi, na)
+        two = scipy.linalg.expm(-math.sqrt(self.dt) * sum(y[g] * self.D[g] for g in range(self.G)))
+        return np.vdot(self.ct, self.half @ two @ self.half @ cp) / np.vdot(self.ct, cp)
+
+
+@pytest.fixture(scope="module")
+def phase_case():
+    """Strong coupling (literal scale, dt = 0.3), two Cholesky vectors, an open
+    shell with different alpha and beta trials, a complex walker."""
+    m, na, nb, g, seed = 4, 2, 1, 2, 5
+    h1, chol, ecore, trial = tiny_system(m=m, na=na, nb=nb, nchol=g, seed=seed, uhf=True)
+    dt = 0.3
+    ham = O.build(h1, chol, ecore, trial, na, nb, dt)
+    ref = FockReference(h1, chol, ecore, trial, na, nb, dt)
+    rng = np.random.default_rng(seed)
+    phi = trial.astype(complex) + 0.5 * (rng.standard_normal((m, na + nb)) + 1j * rng.standard_normal((m, na + nb)))
+    return ham, ref, phi
+
+
+def _fock_weight(ref, phi, na, x, xbar, w0):
+    """w0 |I| max(0, cos arg S) exp(-dt (C - E_T)) with S and I from Fock space,
+    I = S exp(x.xbar - xbar.xbar / 2) (bilinear, eq. of the importance function)."""
+    S = ref.S(phi, na, x - xbar)
+    I = S * np.exp(np.sum(x * xbar) - 0.5 * np.sum(xbar * xbar))
+    return w0 * abs(I) * max(0.0, math.cos(np.angle(S))) * math.exp(-ref.dt * (ref.C - ref.e_trial)), S, I
+
+
+def test_p18_phaseless_projection_uses_the_phase_of_S(phase_case):
+    """theta = arg S (Sec. 2: the phaseless projection of the overlap ratio),
+    not arg I: one field where cos(arg S) < 0 < cos(arg I) must kill the walker
+    (weight exactly 0, W_DEAD), one where both are positive must give
+    w |I| cos(arg S) exp(-dt (C - E_T)), and the S, I the oracle reports must be
+    the Fock-space ones.  The Taylor order is raised so that the truncated
+    series equals the exponential to rounding."""
+    ham, ref, phi = phase_case
+    na = ham.nalpha
+    xb = ref.xbar(phi, na)
+    assert np.max(np.abs(xb.real)) > 0.05 and np.max(np.abs(xb.imag)) > 0.05  # arg I != arg S
+    rng = np.random.default_rng(17)
+    killed = kept = None
+    for _ in range(400):
+        x = 2.0 * rng.standard_normal(ham.nchol)
+        wref, S, I = _fock_weight(ref, phi, na, x, xb, 0.75)
+        cs, ci = math.cos(np.angle(S)), math.cos(np.angle(I))
+        if killed is None and cs < -0.2 and ci > 0.2:
+            killed = (x, S, I)
+        if kept is None and cs > 0.2 and ci > 0.2 and abs(cs - ci) > 0.3:
+            kept = (x, S, I, wref)
+        if killed is not None and kept is not None:
+            break
+    assert killed is not None and kept is not None
+    x, S, I = killed
+    r = O.step_walker(ham, phi, 0.75, x, fb_cap=0.0, taylor_order=40)
+    assert np.max(np.abs(r["xbar"] - xb)) < 1e-12
+    assert abs(r["S"] - S) < 1e-10 * abs(S) and abs(r["I"] - I) < 1e-10 * abs(I)
+    assert r["weight"] == 0.0 and r["flags"] & O.W_DEAD
+    x, S, I, wref = kept
+    r = O.step_walker(ham, phi, 0.75, x, fb_cap=0.0, taylor_order=40)
+    assert not r["flags"] & O.W_DEAD
+    assert abs(r["theta"] - np.angle(S)) < 1e-10
+    assert abs(r["weight"] - wref) < 1e-10 * wref
+
+
+def test_p19_force_bias_cap_rescales_the_modulus(phase_case):
+    """The cap (reading R4): a component whose modulus exceeds c is rescaled to
+    modulus c with its phase unchanged, the others are untouched, and the capped
+    force bias is the one that shifts the field and enters I."""
+    ham, ref, phi = phase_case
+    na = ham.nalpha
+    xb = ref.xbar(phi, na)
+    mags = np.abs(xb)
+    c = 0.5 * (mags.min() + mags.max())
+    assert mags.min() < c < mags.max()
+    xc = np.where(mags > c, c * xb / mags, xb)
+    x = np.array([0.3, -0.4])
+    r = O.step_walker(ham, phi, 1.0, x, fb_cap=c, taylor_order=40)
+    assert np.max(np.abs(r["xbar"] - xc)) < 1e-12
+    big = mags > c
+    assert np.allclose(np.abs(r["xbar"][big]), c, rtol=1e-13, atol=0)
+    assert np.allclose(np.angle(r["xbar"][big]), np.angle(xb[big]), rtol=0, atol=1e-12)
+    wref, S, I = _fock_weight(ref, phi, na, x, xc, 1.0)
+    assert abs(r["S"] - S) < 1e-10 * abs(S) and abs(r["I"] - I) < 1e-10 * abs(I)
+    assert abs(r["weight"] - wref) < 1e-10 * wref
