@@ -35,9 +35,10 @@ R3  theta = arg S (not arg I).
 R4  Force-bias cap: |xbar_g| > c  =>  xbar_g <- c xbar_g / |xbar_g|, c = 1 by
     default; c <= 0 disables it.
 R5  The two-body exponential is a Taylor series of order 6.
-R6  Energy shift E_T = E_HF (the trial's own local energy), fixed.
-R7  No hybrid-energy capping, no population control; a walker with
-    cos(theta) <= 0 gets weight exactly 0 and keeps propagating.
+R6  Energy shift E_T = E_HF (the trial's own local energy) unless the block
+    loop (R13) moves it.
+R7  No hybrid-energy capping; a walker with cos(theta) <= 0 gets weight
+    exactly 0 and keeps propagating (until a comb, R11, drops it).
 R8  The mixed estimator is normalised by sum_i w_i and uses Re E_loc.
 R9  Re-orthogonalisation: modified Gram-Schmidt per spin block with positive
     real R_ii; log<Psi_T|phi> decreases by sum log R_ii.
@@ -56,6 +57,13 @@ R12 Free projection (the fp-AFQMC section): fields from the plain Gaussian,
     r = max Re a_w over the walkers that count (w_w > 0, no singular or
     non-finite flag); E_T = E_HF only keeps the amplitudes of order one.  No
     walker is killed, capped or resampled.
+R13 Blocks (the simulation loop of Sec. 3.1 runs propagation, stabilisation,
+    population control and estimators and writes its output once per block):
+    a block is a fixed number of steps, each measuring the mixed estimator;
+    after the last step of a block one comb (R11) resamples the walkers and
+    E_T becomes the block's own estimate sum_k ENumer_k / sum_k EDenom_k (the
+    paper does not say how E_T is fed back; a global E_T only scales every
+    weight alike, so the estimator does not depend on it).
 """
 from __future__ import annotations
 
@@ -259,9 +267,10 @@ def overlap_ratio(ham: OracleHamiltonian, phi, logo0, y, taylor_order=6):
     return phi3, logo1, log_s, sing1
 
 
-def step_walker(ham: OracleHamiltonian, phi, weight, x, fb_cap=1.0, taylor_order=6):
+def step_walker(ham: OracleHamiltonian, phi, weight, x, fb_cap=1.0, taylor_order=6, e_shift=None):
     """One phaseless step for one walker: eqs. (propagate), (weight_update),
-    (fb), the hybrid importance function and (ovlp_ratio).
+    (fb), the hybrid importance function and (ovlp_ratio).  `e_shift` is E_T
+    (None: the trial energy, reading R6).
 
     Returns a dict with the new phi, weight, logO and flags, and the
     intermediate quantities (xbar, S, I, theta) for the pins."""
@@ -290,7 +299,8 @@ def step_walker(ham: OracleHamiltonian, phi, weight, x, fb_cap=1.0, taylor_order
     I = S * np.exp(np.sum(x * xbar) - 0.5 * np.sum(xbar * xbar))
     theta = float(np.angle(S))
     proj = max(0.0, np.cos(theta))
-    new_w = weight * abs(I) * proj * np.exp(-ham.dt * (ham.const - ham.e_trial))
+    e_t = ham.e_trial if e_shift is None else float(e_shift)
+    new_w = weight * abs(I) * proj * np.exp(-ham.dt * (ham.const - e_t))
     if proj == 0.0:
         flags |= W_DEAD
     if flags & W_NONFINITE:
@@ -299,7 +309,7 @@ def step_walker(ham: OracleHamiltonian, phi, weight, x, fb_cap=1.0, taylor_order
             "xbar": xbar, "S": S, "I": I, "theta": theta}
 
 
-def propagate(ham: OracleHamiltonian, phis, weights, logos, x, fb_cap=1.0, taylor_order=6):
+def propagate(ham: OracleHamiltonian, phis, weights, logos, x, fb_cap=1.0, taylor_order=6, e_shift=None):
     """One time step for every walker.  x: [W, G] real fields.
     Returns new (phis, weights, logos, flags)."""
     W = phis.shape[0]
@@ -308,7 +318,7 @@ def propagate(ham: OracleHamiltonian, phis, weights, logos, x, fb_cap=1.0, taylo
     out_l = np.empty(W, dtype=np.complex128)
     flags = np.zeros(W, dtype=np.uint32)
     for w in range(W):
-        r = step_walker(ham, phis[w], weights[w], x[w], fb_cap, taylor_order)
+        r = step_walker(ham, phis[w], weights[w], x[w], fb_cap, taylor_order, e_shift)
         out_phi[w], out_w[w], out_l[w], flags[w] = r["phi"], r["weight"], r["logo"], r["flags"]
     return out_phi, out_w, out_l, flags
 
@@ -461,3 +471,41 @@ def run(ham: OracleHamiltonian, phis, fields, nsteps, reortho_every=5, fb_cap=1.
         recs.append({"step": step, "weights": w.copy(), "energies": e, "logo": logo.copy(),
                      "flags": flags, "est": estimator(w, e)})
     return phis, w, logo, recs
+
+
+def run_blocks(ham: OracleHamiltonian, phis, fields, nblocks, block_steps, offsets=None, reortho_every=5,
+               fb_cap=1.0, taylor_order=6, feedback=True, e_shift=None, weights=None):
+    """Block loop (reading R13).  Step n = 1, 2, ... (counted over all blocks)
+    propagates with fields.next(), re-orthogonalises when n % reortho_every == 0
+    and records the estimator of the new walkers; after each block a comb with
+    offset offsets[b] (None: no comb) resamples the walkers and, with
+    `feedback`, E_T becomes sum ENumer / sum EDenom of the block.
+    Returns the final (phis, weights, logos) and per-block records
+    {"est": [per-step estimator dicts], "e_shift": E_T used in the block,
+     "parents": comb parents or None}."""
+    W = phis.shape[0]
+    w = np.ones(W) if weights is None else np.asarray(weights, float).copy()
+    logo = initial_logo(ham, phis)
+    e_t = ham.e_trial if e_shift is None else float(e_shift)
+    blocks = []
+    n = 0
+    for b in range(nblocks):
+        ests = []
+        used = e_t
+        for _ in range(block_steps):
+            n += 1
+            phis, w, logo, _ = propagate(ham, phis, w, logo, fields.next(), fb_cap, taylor_order, e_t)
+            if reortho_every and n % reortho_every == 0:
+                phis, logo = reorthogonalize(ham, phis, logo)
+            ests.append(estimator(w, local_energies(ham, phis)))
+        parents = None
+        if offsets is not None:
+            parents, w = comb(w, offsets[b])
+            phis, logo = phis[parents], logo[parents]
+        if feedback:
+            num = sum(e["ENumer"] for e in ests)
+            den = sum(e["EDenom"] for e in ests)
+            if den > 0.0:
+                e_t = num / den
+        blocks.append({"est": ests, "e_shift": used, "parents": parents})
+    return phis, w, logo, blocks

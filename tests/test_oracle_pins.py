@@ -516,3 +516,47 @@ def test_p19_force_bias_cap_rescales_the_modulus(phase_case):
     wref, S, I = _fock_weight(ref, phi, na, x, xc, 1.0)
     assert abs(r["S"] - S) < 1e-10 * abs(S) and abs(r["I"] - I) < 1e-10 * abs(I)
     assert abs(r["weight"] - wref) < 1e-10 * wref
+
+
+# P20: blocks, comb and E_T feedback ------------------------------------------------
+def test_p20_blocks_without_comb_or_feedback_repeat_the_step_loop(small_ham):
+    ham = small_ham
+    phis0 = gi.initial_walkers(ham.trial, 5, noise=0.05, seed=6)
+    ra = O.run(ham, phis0.copy(), gi.FieldStream(2, 5, ham.nchol), 9, reortho_every=5)
+    rb = O.run_blocks(ham, phis0.copy(), gi.FieldStream(2, 5, ham.nchol), 3, 3, offsets=None, feedback=False)
+    flat = [e for blk in rb[3] for e in blk["est"]]
+    assert len(flat) == 9
+    for a, b in zip(ra[3], flat):
+        assert a["est"] == b
+    assert all(blk["e_shift"] == ham.e_trial for blk in rb[3])
+
+
+def test_p20_feedback_scales_weights_only(small_ham):
+    """E_T enters the weight update as the factor exp(dt E_T), common to every
+    walker: with feedback the per-step mixed energies and the comb's choices are
+    those of the run without it, and the total weight differs by exactly
+    exp(dt sum_steps (E_T,step - E_HF)).  A wrong sign or a missing dt in the
+    E_T factor fails the last check; the block energy it feeds back is the
+    ratio of the block's summed records."""
+    ham = small_ham
+    W, nb, ns = 6, 4, 3
+    phis0 = gi.initial_walkers(ham.trial, W, noise=0.05, seed=7)
+    offs = np.random.default_rng(21).random(nb)
+    # a shifted starting E_T makes the first feedback step large
+    e0 = ham.e_trial + 0.7
+    fa = O.run_blocks(ham, phis0.copy(), gi.FieldStream(3, W, ham.nchol), nb, ns, offs, feedback=False, e_shift=e0)
+    fb = O.run_blocks(ham, phis0.copy(), gi.FieldStream(3, W, ham.nchol), nb, ns, offs, feedback=True, e_shift=e0)
+    log_ratio = 0.0
+    for ba, bb in zip(fa[3], fb[3]):
+        assert np.array_equal(ba["parents"], bb["parents"])
+        for ea, eb in zip(ba["est"], bb["est"]):
+            assert eb["ENumer"] / eb["EDenom"] == pytest.approx(ea["ENumer"] / ea["EDenom"], rel=1e-12)
+        log_ratio += ham.dt * ns * (bb["e_shift"] - e0)
+    assert fb[3][0]["e_shift"] == e0
+    for prev, nxt in zip(fb[3][:-1], fb[3][1:]):
+        num = sum(e["ENumer"] for e in prev["est"])
+        den = sum(e["EDenom"] for e in prev["est"])
+        assert nxt["e_shift"] == pytest.approx(num / den, rel=1e-14)
+        # the block estimate sits near the trial energy, far from the shifted start
+        assert abs(nxt["e_shift"] - ham.e_trial) < 0.1
+    assert np.sum(fb[1]) / np.sum(fa[1]) == pytest.approx(np.exp(log_ratio), rel=1e-11)
