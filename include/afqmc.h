@@ -19,8 +19,9 @@
  *   layout).
  * Ownership: the caller allocates and owns every walker, field and output
  *   buffer; the context owns everything derived from the Hamiltonian and its
- *   own workspaces, and frees them in afqmc_destroy.  No call keeps a caller
- *   pointer after it returns.
+ *   own workspaces, and frees them in afqmc_destroy.  No call dereferences a
+ *   caller pointer after it returns (afqmc_step and afqmc_run_block compare
+ *   walker addresses with the previous call's; see there).
  * Streams: every call except afqmc_setup_hamiltonian enqueues its kernels on
  *   `hip_stream` (a hipStream_t, NULL = the default stream) and returns
  *   without synchronising.  The returned status covers argument validation and
@@ -230,9 +231,14 @@ afqmc_status afqmc_reorthogonalize(afqmc_ctx *ctx, const afqmc_walkers *w, void 
  * step's local energy and the next step's force bias (Theta, hence vbias, is
  * unchanged when phi is re-orthogonalised, phi -> phi R^-1), so one overlap/LU
  * and one force-bias contraction are done per step instead of three and two.
- * The context keeps them for the walker buffers of its last afqmc_step; they
- * are recomputed when the buffers differ, after any other call on the context,
- * or when (flags & AFQMC_STEP_FRESH) says the walkers were changed elsewhere.
+ * The context keeps them for the walker buffers of its last afqmc_step (it
+ * remembers their addresses only, and never reads them after the call
+ * returns); they are recomputed when the addresses differ, after any other
+ * call on the context, or when (flags & AFQMC_STEP_FRESH) says the walkers
+ * were changed elsewhere.  A caller whose new walker buffers may reuse the
+ * previous step's addresses (a caching allocator), or who writes the walkers
+ * itself between steps, must pass AFQMC_STEP_FRESH; the Python binding does
+ * so whenever the walker sets differ from the previous step's.
  * When they are reused, log<Psi_T|phi> of the walkers is taken from
  * walkers.log_ovlp (which propagation and re-orthogonalisation keep current).
  * When they are recomputed, vbias is still taken as the trace of the exchange
@@ -336,9 +342,68 @@ afqmc_status afqmc_population_control(afqmc_ctx *ctx, const afqmc_walkers *w, co
                                       int32_t *const *parents_out, void *hip_stream);
 
 /* Sets E_T (the energy shift of the weight update, eq. weight_update) of
- * system `isys`, e.g. for feedback from the running estimate; drops recorded
- * step graphs (they hold the old factor).  Synchronises the device. */
-afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift);
+ * system `isys`.  E_T lives in device memory and the weight kernels read it
+ * there, so this only enqueues a one-thread write on `hip_stream` (no
+ * synchronisation; recorded graphs stay valid and see the new value).
+ * Errors: AFQMC_ERR_ARG (NULL context, bad index, non-finite value). */
+afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift, void *hip_stream);
+
+/*
+ * One block of the simulation loop of Sec. 3.1 (propagation, stabilisation,
+ * population control and estimators, with the outputs written once per block
+ * so that they can be reblocked as the run goes on):
+ *   for k = 0 .. nsteps-1: afqmc_step with the fields x[i] + k W G, with
+ *     AFQMC_STEP_REORTHO when reortho_every > 0 and (step0 + k + 1) is a
+ *     multiple of it (step0 = steps taken before this block), AFQMC_STEP_FRESH
+ *     on the first step when (flags & AFQMC_STEP_FRESH), and the estimator
+ *     record (ENumer, EDenom, E1Body, E2Body) of step k into est[i] + 4 k;
+ *   then, when u != NULL, afqmc_population_control with offset u[i];
+ *   then, when (flags & AFQMC_BLOCK_FEEDBACK), E_T <- sum_k ENumer_k /
+ *     sum_k EDenom_k of the block, on the device (kept when the sum of EDenom
+ *     is not positive).  The paper does not fix the feedback; a common E_T
+ *     scales every weight alike and leaves the mixed estimate unchanged.
+ * x: nsys device pointers, each [nsteps][W][G] standard-normal fields.
+ * e_out: nsys device pointers, double2 [W][3]: the last step's energies.
+ * est: nsys device pointers, double [nsteps][4].
+ * u: NULL or nsys device pointers to one double in [0, 1) each.
+ * With options.use_graph the whole block is recorded into a hipGraph the
+ * first time a combination of buffers, length, re-orthogonalisation phase and
+ * flags is seen, and replayed after that.  Enqueues and returns.
+ * Errors: AFQMC_ERR_ARG (NULL pointers, nsteps < 1, step0 < 0,
+ * reortho_every < 0, unknown flags); AFQMC_ERR_HIP on launch failure.
+ */
+enum { AFQMC_BLOCK_FEEDBACK = 4u };
+afqmc_status afqmc_run_block(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, int32_t nsteps,
+                             int64_t step0, int32_t reortho_every, void *const *e_out, double *const *est,
+                             const double *const *u, uint32_t flags, void *hip_stream);
+
+/*
+ * Reblocking analysis of a serially correlated series of n host doubles (the
+ * per-step or per-block estimates; the paper reblocks its block outputs as the
+ * run goes on, Sec. 3.1, after Flyvbjerg and Petersen, J. Chem. Phys. 91, 461
+ * (1989)).  Level 0 is the series itself; level l+1 averages consecutive pairs
+ * of level l, dropping an odd last sample; levels stop below two samples (at
+ * most AFQMC_REBLOCK_LEVELS).  At each level, with n_l samples of mean m_l and
+ * c0 = (1/n_l) sum (x - m_l)^2: std_err = sqrt(c0 / (n_l - 1)) and
+ * std_err_err = std_err / sqrt(2 (n_l - 1)).  `optimal` is the smallest level
+ * B with 2^(3B) > 2 n (std_err_B / std_err_0)^4 (Lee, Conduit, Nemec, Lopez
+ * Rios and Drummond, Phys. Rev. E 83, 066706 (2011)), or -1 when no level
+ * qualifies (the series is too short for its correlation time).  Host only:
+ * touches no device.  Errors: AFQMC_ERR_ARG (NULL pointers, n < 2, a
+ * non-finite sample).
+ */
+#define AFQMC_REBLOCK_LEVELS 64
+typedef struct {
+  int64_t n;          /* samples of the series                              */
+  double mean;        /* their mean                                         */
+  int32_t nlevels;    /* levels filled in below                             */
+  int32_t optimal;    /* chosen level, -1 if none qualifies                 */
+  int64_t count[AFQMC_REBLOCK_LEVELS];
+  double level_mean[AFQMC_REBLOCK_LEVELS];
+  double std_err[AFQMC_REBLOCK_LEVELS];
+  double std_err_err[AFQMC_REBLOCK_LEVELS];
+} afqmc_reblock_result;
+afqmc_status afqmc_reblock(const double *x, int64_t n, afqmc_reblock_result *out);
 
 /*
  * Free-projection AFQMC (the fp-AFQMC section): the walker step with the

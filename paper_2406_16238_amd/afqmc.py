@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import itertools
 import os
 from typing import Sequence
 
@@ -74,6 +75,15 @@ class Timings(ctypes.Structure):
 
 
 STEP_REORTHO, STEP_FRESH = 1, 2
+BLOCK_FEEDBACK = 4
+REBLOCK_LEVELS = 64
+
+
+class ReblockResult(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mean", ctypes.c_double), ("nlevels", ctypes.c_int32),
+                ("optimal", ctypes.c_int32), ("count", ctypes.c_int64 * REBLOCK_LEVELS),
+                ("level_mean", ctypes.c_double * REBLOCK_LEVELS), ("std_err", ctypes.c_double * REBLOCK_LEVELS),
+                ("std_err_err", ctypes.c_double * REBLOCK_LEVELS)]
 
 EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate",
            "afqmc_local_energy", "afqmc_reorthogonalize", "afqmc_step", "afqmc_overlap",
@@ -81,7 +91,8 @@ EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate"
            "afqmc_set_timing", "afqmc_get_timings", "afqmc_destroy", "afqmc_last_error",
            "afqmc_cv_collect", "afqmc_cv_train", "afqmc_cv_set_params", "afqmc_cv_get_params",
            "afqmc_cv_predict", "afqmc_cv_loss_grad", "afqmc_cv_state", "afqmc_population_control",
-           "afqmc_set_e_shift", "afqmc_free_propagate", "afqmc_free_estimator", "afqmc_free_step")
+           "afqmc_set_e_shift", "afqmc_free_propagate", "afqmc_free_estimator", "afqmc_free_step",
+           "afqmc_run_block", "afqmc_reblock")
 CV_NFEAT, CV_NPARAMS, CV_NNORM = 8, 17922, 20
 FREE_EST = 10
 
@@ -124,7 +135,10 @@ def load_library() -> ctypes.CDLL:
         "afqmc_cv_loss_grad": ([P, ctypes.c_int32, P, P, ctypes.c_int64, P, P, P], ctypes.c_int),
         "afqmc_cv_state": ([P, ctypes.c_int32, P, P, P, P], ctypes.c_int),
         "afqmc_population_control": ([P, ctypes.POINTER(CWalkers), pp, pp, P], ctypes.c_int),
-        "afqmc_set_e_shift": ([P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+        "afqmc_set_e_shift": ([P, ctypes.c_int32, ctypes.c_double, P], ctypes.c_int),
+        "afqmc_run_block": ([P, ctypes.POINTER(CWalkers), pp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, pp,
+                             pp, pp, ctypes.c_uint32, P], ctypes.c_int),
+        "afqmc_reblock": ([P, ctypes.c_int64, ctypes.POINTER(ReblockResult)], ctypes.c_int),
         "afqmc_free_propagate": ([P, ctypes.POINTER(CWalkers), pp, pp, P], ctypes.c_int),
         "afqmc_free_estimator": ([P, ctypes.POINTER(CWalkers), pp, pp, P, P], ctypes.c_int),
         "afqmc_free_step": ([P, ctypes.POINTER(CWalkers), pp, pp, pp, P, ctypes.c_uint32, P], ctypes.c_int),
@@ -195,14 +209,23 @@ class SystemInput:
         return self.chol.nchol if isinstance(self.chol, CholGen) else self.chol.shape[0]
 
 
+_walker_ids = itertools.count(1)
+
+
 @dataclasses.dataclass
 class Walkers:
-    """Caller-owned walker state of one system (torch tensors on the GPU)."""
+    """Caller-owned walker state of one system (torch tensors on the GPU).
+
+    `ident` tells walker sets apart: step() and run_block() ask the library to
+    recompute its cached Green's function (AFQMC_STEP_FRESH) whenever the sets
+    differ from those of the context's previous step, even when new tensors
+    happen to reuse the old ones' device addresses."""
 
     phi: "object"        # complex128 [W, M, Na+Nb]
     weight: "object"     # float64 [W]
     log_ovlp: "object"   # complex128 [W]
     flags: "object"      # int32 [W] (bit pattern of the library's uint32 flags)
+    ident: int = dataclasses.field(default_factory=lambda: next(_walker_ids), compare=False)
 
     def c_struct(self) -> CWalkers:
         import torch
@@ -230,6 +253,15 @@ class Context:
         self.handle = ctypes.c_void_p(handle)
         self.systems = list(systems)
         self.options = options
+        self.last_stepped = None   # idents of the walker sets of the previous step or block
+
+    def stepping(self, walkers) -> bool:
+        """Records the walker sets about to be stepped; True when they are the
+        previous step's (the library's cache may apply)."""
+        ids = tuple(w.ident for w in (walkers if isinstance(walkers, (list, tuple)) else [walkers]))
+        same = ids == self.last_stepped
+        self.last_stepped = ids
+        return same
 
     @property
     def nsys(self):
@@ -346,6 +378,7 @@ def step(ctx: Context, walkers, x, e_out, est_out=None, reortho=False, fresh=Fal
         if est_out.dtype != torch.float64 or not est_out.is_cuda or tuple(est_out.shape) != (ctx.nsys, 4):
             raise ValueError("est_out must be a float64 CUDA tensor of shape (nsys, 4)")
         est = est_out.data_ptr()
+    fresh = fresh or not ctx.stepping(walkers)
     flags = (STEP_REORTHO if reortho else 0) | (STEP_FRESH if fresh else 0)
     _check(load_library().afqmc_step(ctx.handle, w, xs, es, est, flags, _stream_handle(stream)))
 
@@ -410,9 +443,42 @@ def population_control(ctx: Context, walkers, u, parents_out=None, stream=None):
     _check(load_library().afqmc_population_control(ctx.handle, w, us, ps, _stream_handle(stream)))
 
 
-def set_e_shift(ctx: Context, e_shift: float, isys: int = 0):
-    """afqmc_set_e_shift: the energy shift E_T of the weight update."""
-    _check(load_library().afqmc_set_e_shift(ctx.handle, isys, float(e_shift)))
+def set_e_shift(ctx: Context, e_shift: float, isys: int = 0, stream=None):
+    """afqmc_set_e_shift: the energy shift E_T of the weight update (enqueued on the stream)."""
+    _check(load_library().afqmc_set_e_shift(ctx.handle, isys, float(e_shift), _stream_handle(stream)))
+
+
+def run_block(ctx: Context, walkers, x, e_out, est, u=None, step0: int = 0, reortho_every: int = 5,
+              feedback: bool = True, fresh: bool = False, stream=None):
+    """afqmc_run_block: nsteps walker steps with one estimator record each
+    (est float64 [nsteps, 4] per system), then a comb with offset u (float64 [1]
+    per system, or None for none) and, with `feedback`, E_T <- the block's
+    estimate.  x: float64 [nsteps, W, G] per system; e_out complex128 [W, 3]."""
+    import torch
+    xs_list = x if isinstance(x, (list, tuple)) else [x]
+    nsteps = int(xs_list[0].shape[0])
+    w = _walker_array(ctx, walkers)
+    xs = _ptr_array(ctx, xs_list, [(nsteps, s.nwalkers, s.nchol) for s in ctx.systems], torch.float64)
+    es = _ptr_array(ctx, e_out, [(s.nwalkers, 3) for s in ctx.systems], torch.complex128)
+    ests = _ptr_array(ctx, est, [(nsteps, 4)] * ctx.nsys, torch.float64)
+    us = None if u is None else _ptr_array(ctx, u, [(1,)] * ctx.nsys, torch.float64)
+    fresh = fresh or not ctx.stepping(walkers)
+    flags = (BLOCK_FEEDBACK if feedback else 0) | (STEP_FRESH if fresh else 0)
+    _check(load_library().afqmc_run_block(ctx.handle, w, xs, nsteps, int(step0), int(reortho_every), es, ests, us,
+                                          flags, _stream_handle(stream)))
+
+
+def reblock(series) -> dict:
+    """afqmc_reblock (host): mean, the error bar at the chosen level (None when
+    no level qualifies) and every level's (count, mean, std_err, std_err_err)."""
+    x = np.ascontiguousarray(np.asarray(series, dtype=np.float64).ravel())
+    r = ReblockResult()
+    _check(load_library().afqmc_reblock(x.ctypes.data, int(x.size), ctypes.byref(r)))
+    levels = [{"level": l, "n": int(r.count[l]), "mean": float(r.level_mean[l]), "std_err": float(r.std_err[l]),
+               "std_err_err": float(r.std_err_err[l])} for l in range(r.nlevels)]
+    opt = None if r.optimal < 0 else int(r.optimal)
+    return {"n": int(r.n), "mean": float(r.mean), "optimal": opt,
+            "std_err": levels[opt]["std_err"] if opt is not None else None, "levels": levels}
 
 
 # ---- free projection --------------------------------------------------------------------

@@ -2,8 +2,8 @@
 
     python -m paper_2406_16238_amd.build
 
-Every .hip file under csrc/ is compiled by hipcc into _build/, in parallel, and
-linked into paper_2406_16238_amd/libafqmc.so.
+Every .hip file under csrc/ is compiled by hipcc, every host-only .cpp file by
+g++, into _build/, in parallel, and linked into paper_2406_16238_amd/libafqmc.so.
 """
 from __future__ import annotations
 
@@ -22,6 +22,7 @@ LIB = os.path.join(HERE, "libafqmc.so")
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+GXX = shutil.which("g++") or "/usr/bin/g++"
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -54,11 +55,23 @@ def _check_defined(lib: str) -> None:
         raise RuntimeError("libafqmc.so leaves its own symbols undefined:\n  " + "\n  ".join(missing))
 
 
+def _compile_host(src: str) -> str:
+    """Host-only C++ (no device code) with the system compiler."""
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = [GXX, "-O2", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
+           "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed on {src}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    host = sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs) + len(host))) as ex:
+        objs = list(ex.map(_compile, srcs)) + list(ex.map(_compile_host, host))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

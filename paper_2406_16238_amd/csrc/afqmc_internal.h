@@ -18,6 +18,7 @@ constexpr int kCvFeatures = 8, kCvHidden = 128;
 constexpr int kCvParams = kCvHidden * kCvFeatures + kCvHidden + kCvHidden * kCvHidden + kCvHidden + 2 * kCvHidden + 2;
 constexpr int kCvNorm = 2 * kCvFeatures + 4;
 constexpr int kCvMaxWalkers = 4096;
+constexpr int kCvGradBlock = 16;  // samples per workgroup of the network's gradient kernel
 
 // Device buffers and scalars of one system.  Layouts (row-major):
 //   L      [G][M][M]     Cholesky vectors
@@ -51,6 +52,7 @@ struct System {
   double dt = 0, sqdt = 0, ecore = 0, e_hf = 0, e_shift = 0, const_c = 0;
   uint64_t bytes = 0;
 
+  double *eshift = nullptr;             // [1] E_T of the weight update, on the device
   double *L = nullptr, *LtT = nullptr, *htT = nullptr, *trial = nullptr, *B1 = nullptr, *lmf = nullptr;
   double *LtS[2] = {nullptr, nullptr};  // per spin [G][M][NR]: half-rotated, rows padded for the exchange
   double *Lp = nullptr;                 // [G][M(M+1)/2] packed upper triangles of the L^g
@@ -198,6 +200,9 @@ hipError_t launch_pad_half_rotated(const double *LtT, int G, int M, int Nt, int 
                                    hipStream_t st);
 hipError_t launch_energy_combine(const System &s, int W, double2 *e_out, hipStream_t st);
 hipError_t launch_estimator(const double *weight, const double2 *e_out, int W, double *est, hipStream_t st);
+// E_T: set to a value, or to the mixed estimate of a block of estimator records [nsteps][4]
+hipError_t launch_set_e_shift(const System &s, double e_shift, hipStream_t st);
+hipError_t launch_block_e_shift(const System &s, const double *est, int nsteps, hipStream_t st);
 
 // Set-up helpers.
 hipError_t launch_row_dot(const double *A, const double *v, long len, int rows, double *out, hipStream_t st);

@@ -34,6 +34,10 @@ afqmc_status fail(afqmc_status s, const std::string &msg) {
 
 }  // namespace
 
+namespace afqmc {
+afqmc_status record_error(afqmc_status s, const char *msg) { return fail(s, msg); }
+}  // namespace afqmc
+
 struct afqmc_ctx {
   std::vector<System> sys;
   Options opt;
@@ -448,11 +452,11 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   const Plan p = plan_for(s);
   const size_t M = s.M, Nt = s.Nt, G = s.G;
   const uint64_t setup_tmp = 8ull * (4 * M * M + M * M * 64 + M * M + G) + 16ull * (M * Nt + 3);
-  s.bytes = p.bytes();
+  s.bytes = p.bytes() + 8;
   if (limit && *bytes_used + s.bytes + setup_tmp > limit)
     return fail(AFQMC_ERR_OOM, "device memory needed (" + std::to_string(*bytes_used + s.bytes + setup_tmp) +
                                    " bytes) exceeds mem_limit_bytes");
-  bool ok = dalloc(c, &s.L, p.L) && dalloc(c, &s.LtT, p.LtT) && dalloc(c, &s.htT, p.htT) &&
+  bool ok = dalloc(c, &s.eshift, 1) && dalloc(c, &s.L, p.L) && dalloc(c, &s.LtT, p.LtT) && dalloc(c, &s.htT, p.htT) &&
             dalloc(c, &s.trial, p.trial) && dalloc(c, &s.B1, p.B1) && dalloc(c, &s.lmf, p.lmf) &&
             dalloc(c, &s.theta, p.theta) && dalloc(c, &s.fbpart, p.fbpart) && dalloc(c, &s.yp, p.yp) &&
             (p.vhs == 0 || dalloc(c, &s.vhs, p.vhs)) && dalloc(c, &s.tA, p.tbuf) && dalloc(c, &s.tB, p.tbuf) &&
@@ -868,6 +872,12 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
       return r;
     }
     sy.e_shift = std::isnan(o.e_shift) ? sy.e_hf : o.e_shift;
+    if (launch_set_e_shift(sy, sy.e_shift, st) != hipSuccess) {
+      (void)hipStreamSynchronize(st);
+      release(c);
+      delete c;
+      return fail(AFQMC_ERR_HIP, "energy-shift kernel");
+    }
   }
   afqmc_status r = make_lanes(c, o.streams == 0 ? 4 : o.streams);
   if (r == AFQMC_OK && c->use_graph) {
@@ -1022,70 +1032,105 @@ afqmc_status afqmc_propagate(afqmc_ctx *ctx, const afqmc_walkers *w, const doubl
 
 namespace {
 
+// One walker step of system i on stream ls (arguments already checked):
+// propagation, optional re-orthogonalisation, local energy and estimator
+// record (est may be NULL).
+afqmc_status step_one(afqmc_ctx *ctx, int i, const afqmc_walkers &wk, const double *x, void *e_out, double *est,
+                      uint32_t flags, hipStream_t ls) {
+  System &s = ctx->sys[i];
+  const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == wk.phi;
+  s.cache_phi = nullptr;
+  bool ready = false;
+  if (!reuse && s.ex_mfma && s.ex_mode == AFQMC_EX_FULL) {
+    // a fresh start takes vbias by the route every later step takes (the
+    // trace of the exchange matrices), so a run restarted from its walker
+    // state repeats the uninterrupted run bit for bit
+    {
+      Phase ph(ctx, AFQMC_PH_OVERLAP, ls);
+      AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(wk.phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
+                                  s.logo_now, s.stat_now, nullptr, ls, s.opart, s.ospart),
+                "overlap kernel");
+    }
+    afqmc_status r = exchange_sys(ctx, s, s.theta, s.W, s.fbpart, ls);
+    if (r != AFQMC_OK) return r;
+    s.fb_slices = 2;
+    ready = true;
+  }
+  afqmc_status r = propagate_sys(ctx, s, wk, x, reuse, true, ls, ready);
+  if (r != AFQMC_OK) return r;
+  if (flags & AFQMC_STEP_REORTHO) {
+    Phase ph(ctx, AFQMC_PH_REORTHO, ls);
+    AFQMC_HIP(launch_mgs(static_cast<double2 *>(wk.phi), s.M, s.Na, s.Nb, s.W, static_cast<double2 *>(wk.log_ovlp),
+                         ls, reinterpret_cast<double *>(s.opart)),
+              "Gram-Schmidt kernel");
+  }
+  r = local_energy_sys(ctx, s, static_cast<const double2 *>(wk.phi), s.W, static_cast<double2 *>(e_out), est,
+                       wk.weight, ls, true);
+  if (r != AFQMC_OK) return r;
+  s.cache_phi = wk.phi;
+  return AFQMC_OK;
+}
+
 // The body of afqmc_step (arguments already checked).
 afqmc_status step_body(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
                        double *est_out, uint32_t flags, hipStream_t st) {
   return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
+    return step_one(ctx, i, w[i], x[i], e_out[i], est_out ? est_out + 4 * i : nullptr, flags, ls);
+  });
+}
+
+// Arguments of one block of afqmc_run_block.
+struct BlockArgs {
+  const afqmc_walkers *w;
+  const double *const *x;
+  int nsteps;
+  int64_t step0;
+  int reortho_every;
+  void *const *e_out;
+  double *const *est;
+  const double *const *u;
+  uint32_t flags;
+};
+
+// The body of afqmc_run_block: every system runs its whole block on its lane.
+afqmc_status block_body(afqmc_ctx *ctx, const BlockArgs &b, hipStream_t st) {
+  return for_each_system(ctx, st, [&](int i, hipStream_t ls) {
     System &s = ctx->sys[i];
-    const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
-    s.cache_phi = nullptr;
-    bool ready = false;
-    if (!reuse && s.ex_mfma && s.ex_mode == AFQMC_EX_FULL) {
-      // a fresh start takes vbias by the route every later step takes (the
-      // trace of the exchange matrices), so a run restarted from its walker
-      // state repeats the uninterrupted run bit for bit
-      {
-        Phase ph(ctx, AFQMC_PH_OVERLAP, ls);
-        AFQMC_HIP(launch_ovlp_theta(static_cast<const double2 *>(w[i].phi), s.trial, s.M, s.Na, s.Nb, s.W, s.theta,
-                                    s.logo_now, s.stat_now, nullptr, ls, s.opart, s.ospart),
-                  "overlap kernel");
-      }
-      afqmc_status r = exchange_sys(ctx, s, s.theta, s.W, s.fbpart, ls);
+    const size_t per_step = (size_t)s.W * s.G;
+    for (int k = 0; k < b.nsteps; ++k) {
+      uint32_t f = (k == 0) ? (b.flags & AFQMC_STEP_FRESH) : 0u;
+      if (b.reortho_every > 0 && (b.step0 + k + 1) % b.reortho_every == 0) f |= AFQMC_STEP_REORTHO;
+      afqmc_status r = step_one(ctx, i, b.w[i], b.x[i] + (size_t)k * per_step, b.e_out[i],
+                                b.est[i] + (size_t)4 * k, f, ls);
       if (r != AFQMC_OK) return r;
-      s.fb_slices = 2;
-      ready = true;
     }
-    afqmc_status r = propagate_sys(ctx, s, w[i], x[i], reuse, true, ls, ready);
-    if (r != AFQMC_OK) return r;
-    if (flags & AFQMC_STEP_REORTHO) {
-      Phase ph(ctx, AFQMC_PH_REORTHO, ls);
-      AFQMC_HIP(launch_mgs(static_cast<double2 *>(w[i].phi), s.M, s.Na, s.Nb, s.W,
-                           static_cast<double2 *>(w[i].log_ovlp), ls, reinterpret_cast<double *>(s.opart)),
-                "Gram-Schmidt kernel");
+    if (b.u) {
+      s.cache_phi = nullptr;
+      AFQMC_HIP(launch_comb(s, b.w[i].weight, static_cast<double2 *>(b.w[i].phi),
+                            static_cast<double2 *>(b.w[i].log_ovlp), b.w[i].flags, b.u[i], nullptr, ls),
+                "population control kernels");
     }
-    r = local_energy_sys(ctx, s, static_cast<const double2 *>(w[i].phi), s.W, static_cast<double2 *>(e_out[i]),
-                         est_out ? est_out + 4 * i : nullptr, w[i].weight, ls, true);
-    if (r != AFQMC_OK) return r;
-    s.cache_phi = w[i].phi;
+    if (b.flags & AFQMC_BLOCK_FEEDBACK) AFQMC_HIP(launch_block_e_shift(s, b.est[i], b.nsteps, ls), "energy-shift kernel");
     return AFQMC_OK;
   });
 }
 
-// afqmc_step through a hipGraph: the step is recorded on the context's own
-// stream (never the caller's, which may be the legacy default stream) the first
-// time a combination of buffers, flags and cached state is seen, and replayed
-// after that.  Up to eight recorded steps are kept (a run alternates between a
-// few: the first step, plain steps and re-orthogonalising steps).
-afqmc_status step_graph(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
-                        double *est_out, uint32_t flags, hipStream_t st) {
-  std::vector<uintptr_t> key;
-  key.push_back(flags);
-  key.push_back(reinterpret_cast<uintptr_t>(est_out));
-  for (size_t i = 0; i < ctx->sys.size(); ++i) {
-    const System &s = ctx->sys[i];
-    const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
-    for (const void *p : {(const void *)w[i].phi, (const void *)w[i].weight, (const void *)w[i].log_ovlp,
-                          (const void *)w[i].flags, (const void *)x[i], (const void *)e_out[i]})
-      key.push_back(reinterpret_cast<uintptr_t>(p));
-    key.push_back(reuse ? 1u : 0u);
-  }
+// Records `body` into a hipGraph on the context's own stream (never the
+// caller's, which may be the legacy default stream) the first time `key` is
+// seen and replays it after that; `after_replay` restores the host-side state a
+// recorded call leaves behind.  Up to eight recordings are kept (a run
+// alternates between a few: the first step, plain and re-orthogonalising steps,
+// blocks).
+template <class Body, class After>
+afqmc_status run_graph(afqmc_ctx *ctx, const std::vector<uintptr_t> &key, hipStream_t st, Body body,
+                       After after_replay) {
   hipGraphExec_t exec = nullptr;
   for (auto &g : ctx->graphs)
     if (g.key == key) exec = g.exec;
   if (!exec) {
     AFQMC_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
     ctx->capturing = true;
-    afqmc_status r = step_body(ctx, w, x, e_out, est_out, flags, ctx->cap_stream);
+    afqmc_status r = body(ctx->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
     ctx->capturing = false;
@@ -1106,8 +1151,7 @@ afqmc_status step_graph(afqmc_ctx *ctx, const afqmc_walkers *w, const double *co
     ctx->graphs.push_back({key, exec});
     ++ctx->graph_captures;
   } else {
-    // the host-side state a recorded step leaves behind
-    for (size_t i = 0; i < ctx->sys.size(); ++i) ctx->sys[i].cache_phi = w[i].phi;
+    after_replay();
     ++ctx->graph_replays;
   }
   AFQMC_HIP(hipEventRecord(ctx->g_in, st), "event record");
@@ -1116,6 +1160,55 @@ afqmc_status step_graph(afqmc_ctx *ctx, const afqmc_walkers *w, const double *co
   AFQMC_HIP(hipEventRecord(ctx->g_out, ctx->cap_stream), "event record");
   AFQMC_HIP(hipStreamWaitEvent(st, ctx->g_out, 0), "stream wait");
   return AFQMC_OK;
+}
+
+// afqmc_step through a hipGraph, keyed by the flags, every buffer and whether
+// the cached Theta / vbias apply.
+afqmc_status step_graph(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, void *const *e_out,
+                        double *est_out, uint32_t flags, hipStream_t st) {
+  std::vector<uintptr_t> key;
+  key.push_back(0);  // afqmc_step
+  key.push_back(flags);
+  key.push_back(reinterpret_cast<uintptr_t>(est_out));
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    const System &s = ctx->sys[i];
+    const bool reuse = !(flags & AFQMC_STEP_FRESH) && s.cache_phi == w[i].phi;
+    for (const void *p : {(const void *)w[i].phi, (const void *)w[i].weight, (const void *)w[i].log_ovlp,
+                          (const void *)w[i].flags, (const void *)x[i], (const void *)e_out[i]})
+      key.push_back(reinterpret_cast<uintptr_t>(p));
+    key.push_back(reuse ? 1u : 0u);
+  }
+  return run_graph(
+      ctx, key, st, [&](hipStream_t cs) { return step_body(ctx, w, x, e_out, est_out, flags, cs); },
+      [&]() {
+        for (size_t i = 0; i < ctx->sys.size(); ++i) ctx->sys[i].cache_phi = w[i].phi;
+      });
+}
+
+// afqmc_run_block through a hipGraph; the key also holds the block length and
+// which of its steps re-orthogonalise.
+afqmc_status block_graph(afqmc_ctx *ctx, const BlockArgs &b, hipStream_t st) {
+  std::vector<uintptr_t> key;
+  key.push_back(1);  // afqmc_run_block
+  key.push_back(b.flags);
+  key.push_back((uintptr_t)b.nsteps);
+  key.push_back(b.reortho_every > 0 ? (uintptr_t)(b.step0 % b.reortho_every) : 0u);
+  key.push_back((uintptr_t)(b.reortho_every > 0 ? b.reortho_every : 0));
+  key.push_back(b.u ? 1u : 0u);
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    const System &s = ctx->sys[i];
+    const bool reuse = !(b.flags & AFQMC_STEP_FRESH) && s.cache_phi == b.w[i].phi;
+    for (const void *p : {(const void *)b.w[i].phi, (const void *)b.w[i].weight, (const void *)b.w[i].log_ovlp,
+                          (const void *)b.w[i].flags, (const void *)b.x[i], (const void *)b.e_out[i],
+                          (const void *)b.est[i], (const void *)(b.u ? b.u[i] : nullptr)})
+      key.push_back(reinterpret_cast<uintptr_t>(p));
+    key.push_back(reuse ? 1u : 0u);
+  }
+  return run_graph(
+      ctx, key, st, [&](hipStream_t cs) { return block_body(ctx, b, cs); },
+      [&]() {
+        for (size_t i = 0; i < ctx->sys.size(); ++i) ctx->sys[i].cache_phi = b.u ? nullptr : b.w[i].phi;
+      });
 }
 
 }  // namespace
@@ -1134,6 +1227,25 @@ afqmc_status afqmc_step(afqmc_ctx *ctx, const afqmc_walkers *w, const double *co
   }
   if (ctx->use_graph) return step_graph(ctx, w, x, e_out, est_out, flags, st);
   return step_body(ctx, w, x, e_out, est_out, flags, st);
+}
+
+afqmc_status afqmc_run_block(afqmc_ctx *ctx, const afqmc_walkers *w, const double *const *x, int32_t nsteps,
+                             int64_t step0, int32_t reortho_every, void *const *e_out, double *const *est,
+                             const double *const *u, uint32_t flags, void *hip_stream) {
+  if (!ctx || !w || !x || !e_out || !est) return fail(AFQMC_ERR_ARG, "NULL context, walkers, fields, e_out or est");
+  if (nsteps < 1 || step0 < 0 || reortho_every < 0)
+    return fail(AFQMC_ERR_ARG, "need nsteps >= 1, step0 >= 0 and reortho_every >= 0");
+  if (flags & ~(uint32_t)(AFQMC_STEP_FRESH | AFQMC_BLOCK_FEEDBACK)) return fail(AFQMC_ERR_ARG, "unknown block flags");
+  for (size_t i = 0; i < ctx->sys.size(); ++i) {
+    afqmc_status r = check_walkers(w[i], (int)i);
+    if (r != AFQMC_OK) return r;
+    if (!x[i] || !e_out[i] || !est[i] || (u && !u[i]))
+      return fail(AFQMC_ERR_ARG, "NULL fields, e_out, est or offset of system " + std::to_string(i));
+  }
+  const BlockArgs b{w, x, nsteps, step0, reortho_every, e_out, est, u, flags};
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (ctx->use_graph) return block_graph(ctx, b, st);
+  return block_body(ctx, b, st);
 }
 
 afqmc_status afqmc_local_energy(afqmc_ctx *ctx, const afqmc_walkers *w, void *const *e_out, double *est_out,
@@ -1422,14 +1534,11 @@ afqmc_status afqmc_population_control(afqmc_ctx *ctx, const afqmc_walkers *w, co
   });
 }
 
-afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift) {
+afqmc_status afqmc_set_e_shift(afqmc_ctx *ctx, int32_t isys, double e_shift, void *hip_stream) {
   if (!ctx || isys < 0 || isys >= (int)ctx->sys.size()) return fail(AFQMC_ERR_ARG, "NULL context or bad index");
   if (!std::isfinite(e_shift)) return fail(AFQMC_ERR_ARG, "e_shift must be finite");
-  ctx->sys[isys].e_shift = e_shift;
-  // recorded steps hold the old weight factor
-  (void)hipDeviceSynchronize();
-  for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
-  ctx->graphs.clear();
+  // the weight kernels read E_T from device memory: recorded steps stay valid
+  AFQMC_HIP(launch_set_e_shift(ctx->sys[isys], e_shift, static_cast<hipStream_t>(hip_stream)), "energy-shift kernel");
   return AFQMC_OK;
 }
 
@@ -1532,7 +1641,10 @@ afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out)
   if (isys < 0 || isys >= (int)ctx->sys.size()) return fail(AFQMC_ERR_ARG, "system index out of range");
   const System &s = ctx->sys[isys];
   out->e_hf = s.e_hf;
-  out->e_shift = s.e_shift;
+  double et = s.e_shift;
+  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(&et, s.eshift, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(AFQMC_ERR_HIP, "reading the energy shift");
+  out->e_shift = et;
   out->const_c = s.const_c;
   out->device_bytes = s.bytes;
   out->exchange_tile = s.ex_mfma ? s.ex_plan[s.Na > 0 ? 0 : 1].WX : 0;

@@ -31,7 +31,7 @@ constexpr int NF = kCvFeatures, NH = kCvHidden, NO = 2;
 constexpr int P_W1 = 0, P_B1 = NH * NF, P_W2 = P_B1 + NH, P_B2 = P_W2 + NH * NH, P_W3 = P_B2 + NH,
               P_B3 = P_W3 + NO * NH, NP = P_B3 + NO;
 static_assert(NP == kCvParams, "parameter layout");
-constexpr int CB = 16;          // samples per workgroup of the network kernels
+constexpr int CB = kCvGradBlock;  // samples per workgroup of the network kernels
 constexpr int S2 = NH + 1;      // LDS row stride of W2 (odd: conflict-free row and column walks)
 constexpr unsigned long long kGolden = 0x9E3779B97F4A7C15ull;
 

@@ -54,9 +54,11 @@ hipError_t launch_free_fields(const System &s, const double *x, int W, uint32_t 
 // log_ovlp as they were.
 __global__ void k_free_amplitude(double2 *__restrict__ logo, const double2 *__restrict__ logo_new,
                                  const uint32_t *__restrict__ stat_new, const double *__restrict__ wsc, double sqdt,
-                                 double dshift, int W, double2 *__restrict__ amp, uint32_t *__restrict__ flags) {
+                                 double dt, double const_c, const double *__restrict__ eshift, int W,
+                                 double2 *__restrict__ amp, uint32_t *__restrict__ flags) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
+  const double dshift = -dt * (const_c - eshift[0]);
   if (stat_new[w]) {
     flags[w] |= stat_new[w];
     return;
@@ -71,10 +73,9 @@ __global__ void k_free_amplitude(double2 *__restrict__ logo, const double2 *__re
 }
 
 hipError_t launch_free_amplitude(const System &s, const afqmc_walkers &wk, double2 *amp, int W, hipStream_t st) {
-  const double dshift = -s.dt * (s.const_c - s.e_shift);
   hipLaunchKernelGGL(k_free_amplitude, dim3((W + 255) / 256), dim3(256), 0, st,
-                     reinterpret_cast<double2 *>(wk.log_ovlp), s.logo_new, s.stat_new, s.wsc, s.sqdt, dshift, W, amp,
-                     wk.flags);
+                     reinterpret_cast<double2 *>(wk.log_ovlp), s.logo_new, s.stat_new, s.wsc, s.sqdt, s.dt,
+                     s.const_c, s.eshift, W, amp, wk.flags);
   return hipGetLastError();
 }
 

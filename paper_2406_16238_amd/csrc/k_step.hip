@@ -95,13 +95,16 @@ hipError_t launch_fb_energy_epilogue(const System &s, int W, double2 *vbias_out,
 // log S = log<Psi_T|phi'> - log<Psi_T|phi> + i sqrt(dt) sum_g y_g l_g,
 // theta = Im log S, |I| = exp(Re log S + Re(sum x.xbar - sum xbar^2 / 2)),
 // w <- w |I| max(0, cos theta) exp(-dt (C - E_T)).
+// E_T is read from device memory (eshift[0]) so that it can follow the running
+// estimate without the host and without invalidating recorded graphs.
 __global__ void k_weight_update(const double2 *__restrict__ logo_now, const double2 *__restrict__ logo_new,
                                 const uint32_t *__restrict__ stat_now, const uint32_t *__restrict__ stat_new,
-                                const double *__restrict__ wsc, double sqdt, double shift_factor, int W,
-                                double *__restrict__ weight, double2 *__restrict__ logo,
-                                uint32_t *__restrict__ flags) {
+                                const double *__restrict__ wsc, double sqdt, double dt, double const_c,
+                                const double *__restrict__ eshift, int W, double *__restrict__ weight,
+                                double2 *__restrict__ logo, uint32_t *__restrict__ flags) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
+  const double shift_factor = exp(-dt * (const_c - eshift[0]));
   uint32_t f = flags[w];
   const uint32_t sing = stat_now[w] | stat_new[w];
   if (sing) {
@@ -127,9 +130,8 @@ __global__ void k_weight_update(const double2 *__restrict__ logo_now, const doub
 }
 
 hipError_t launch_weight_update(const System &s, const afqmc_walkers &wk, int W, hipStream_t st) {
-  const double shift = exp(-s.dt * (s.const_c - s.e_shift));
   hipLaunchKernelGGL(k_weight_update, dim3((W + 255) / 256), dim3(256), 0, st, s.logo_now, s.logo_new,
-                     s.stat_now, s.stat_new, s.wsc, s.sqdt, shift, W, wk.weight,
+                     s.stat_now, s.stat_new, s.wsc, s.sqdt, s.dt, s.const_c, s.eshift, W, wk.weight,
                      reinterpret_cast<double2 *>(wk.log_ovlp), wk.flags);
   return hipGetLastError();
 }
@@ -216,6 +218,38 @@ __global__ __launch_bounds__(kThreads) void k_estimator(const double *__restrict
 
 hipError_t launch_estimator(const double *weight, const double2 *e_out, int W, double *est, hipStream_t st) {
   hipLaunchKernelGGL(k_estimator, dim3(1), dim3(kThreads), 0, st, weight, e_out, W, est);
+  return hipGetLastError();
+}
+
+// ---- energy shift ------------------------------------------------------------
+__global__ void k_set_scalar(double *__restrict__ p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+hipError_t launch_set_e_shift(const System &s, double e_shift, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, st, s.eshift, e_shift);
+  return hipGetLastError();
+}
+
+// Feedback of a block (the simulation loop of Sec. 3.1): E_T <- sum_k ENumer_k /
+// sum_k EDenom_k over the block's estimator records est[k][4], summed in step
+// order by one thread; kept when the denominator is not positive or the ratio
+// is not finite.
+__global__ void k_block_e_shift(const double *__restrict__ est, int nsteps, double *__restrict__ eshift) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double num = 0.0, den = 0.0;
+  for (int k = 0; k < nsteps; ++k) {
+    num += est[(size_t)k * 4 + 0];
+    den += est[(size_t)k * 4 + 1];
+  }
+  if (den > 0.0) {
+    const double e = num / den;
+    if (isfinite(e)) eshift[0] = e;
+  }
+}
+
+hipError_t launch_block_e_shift(const System &s, const double *est, int nsteps, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_e_shift, dim3(1), dim3(64), 0, st, est, nsteps, s.eshift);
   return hipGetLastError();
 }
 

@@ -133,7 +133,8 @@ def test_step_calls_reject_null_context(lib):
     assert lib.afqmc_cv_loss_grad(None, 0, None, None, 1, None, None, None) == A.ERR_ARG
     assert lib.afqmc_cv_state(None, 0, None, None, None, None) == A.ERR_ARG
     assert lib.afqmc_population_control(None, None, None, None, None) == A.ERR_ARG
-    assert lib.afqmc_set_e_shift(None, 0, 0.0) == A.ERR_ARG
+    assert lib.afqmc_set_e_shift(None, 0, 0.0, None) == A.ERR_ARG
+    assert lib.afqmc_run_block(None, ctypes.byref(w), None, 1, 0, 5, None, None, None, 0, None) == A.ERR_ARG
     assert lib.afqmc_free_propagate(None, ctypes.byref(w), None, None, None) == A.ERR_ARG
     assert lib.afqmc_free_estimator(None, ctypes.byref(w), None, None, None, None) == A.ERR_ARG
     assert lib.afqmc_free_step(None, ctypes.byref(w), None, None, None, None, 0, None) == A.ERR_ARG
@@ -152,7 +153,9 @@ def test_struct_layouts_match_header(tmp_path):
               "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
               "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "exchange_order", "lane",
                                       "graph_captures", "graph_replays", "cv_subset", "reserved_info"]),
-              "afqmc_timings": (A.Timings, ["ms", "count"])}
+              "afqmc_timings": (A.Timings, ["ms", "count"]),
+              "afqmc_reblock_result": (A.ReblockResult, ["n", "mean", "nlevels", "optimal", "count", "level_mean",
+                                                         "std_err", "std_err_err"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "afqmc.h"', "int main(void) {"]
     for cname, (_, fl) in fields.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
