@@ -10,6 +10,8 @@ import numpy as np
 import pytest
 
 import afqmc_inputs as gi
+from oracle import afqmc_oracle as O
+from pairs import cmp_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -98,6 +100,24 @@ def test_set_equals_separate_runs_bitwise(precision, graph):
             assert info.graph_replays >= nsteps - 3
     finally:
         ctx.close()
+    # walker 0 of every system against the oracle, which steps it alone on the
+    # same fields (walkers are independent without population control)
+    for k, (spec, W) in enumerate(specs):
+        sysin, trial = inputs[k]
+        ham = O.build(sysin.h1, sysin.chol, sysin.ecore, trial, spec.nalpha, spec.nbeta, sysin.dt)
+        phi = gi.initial_walkers(trial, W, seed=40 + k)[:1]
+        fs = gi.FieldStream(60 + k, W, sysin.nchol)
+        ow, ologo = np.ones(1), O.initial_logo(ham, phi)
+        for step in range(1, nsteps + 1):
+            phi, ow, ologo, _ = O.propagate(ham, phi, ow, ologo, fs.next()[:1])
+            if step % 5 == 0:
+                phi, ologo = O.reorthogonalize(ham, phi, ologo)
+        oe = np.array(O.local_energy(ham, phi[0]))
+        g = together[k]
+        tol = 1e-10 if precision == 0 else 1e-5
+        assert cmp_rel(g["e"][0], oe) < tol, k
+        assert cmp_rel(g["weight"][:1], ow) < tol, k
+        assert cmp_rel(g["phi"][0], phi[0], np.abs(phi[0]).max()) < tol, k
     for k in range(len(inputs)):
         one = A.setup_hamiltonian(inputs[k][0], A.default_options(precision=precision, streams=1))
         try:

@@ -135,6 +135,11 @@ def test_trajectory_strong_coupling_cap_active():
         assert np.sum(np.abs(r["xbar"]) > 0.03) >= 3  # the cap bites
         worst, g, o = run_both(p, 6, phis, fb_cap=0.03)
         assert worst["e"] < 1e-9 and worst["w"] < 1e-9 and worst["phi"] < 1e-9, worst
+        # the phaseless projection kills walkers here, on both sides alike
+        gflags, gw = g[3], g[1]
+        dead = (gflags & O.W_DEAD) != 0
+        assert dead.any()
+        assert np.all(gw[dead] == 0.0) and np.all(o[1][dead] == 0.0)
     finally:
         p.close()
 
@@ -334,3 +339,18 @@ def test_taylor_3m_equals_four_products():
     assert cmp_rel(a, b, np.abs(b).max()) < 1e-13
     assert cmp_rel(wa, wb) < 1e-13
     assert phase_diff(la, lb) < 1e-12
+
+
+def test_benzene_shape_sampled():
+    """The benzene-dimer-scale shape (M=1512 orbitals, N=42+42, counter recipe of
+    the Cholesky tensor) at a reduced G=96, 4 walkers, 3 steps with a
+    re-orthogonalisation after the second (the Gram-Schmidt kernel for M > 512
+    and the long contraction loops), against the oracle at 1e-10."""
+    import dataclasses
+    spec = dataclasses.replace(gi.BENZENE_SCALE.system, nchol=96)
+    p = Pair(spec, 4, gi.BENZENE_SCALE.dt)
+    try:
+        worst, g, o = run_both(p, 3, gi.initial_walkers(p.trial, 4, noise=0.01, seed=5), reortho_every=2)
+        assert worst["e"] < TOL and worst["w"] < TOL and worst["logo"] < TOL and worst["phi"] < TOL, worst
+    finally:
+        p.close()
