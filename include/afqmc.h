@@ -317,6 +317,25 @@ afqmc_status afqmc_cv_collect(afqmc_ctx *ctx, const afqmc_walkers *w, double *co
                               void *const *ek_out, void *hip_stream);
 afqmc_status afqmc_cv_train(afqmc_ctx *ctx, int32_t isys, const double *feat, const void *ek, int64_t n,
                             int32_t epochs, int32_t batch, double lr, double *loss_out, void *hip_stream);
+/*
+ * afqmc_cv_train for callers that cannot allocate device memory at call time
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * allocation): the same training, from the same kernels in the same order,
+ * with its workspace in a fixed device array of the library (under 8 MiB,
+ * one per GPU, held until the process ends) instead of allocations, and
+ * without synchronising: it enqueues on `hip_stream` and returns.
+ * loss_out: NULL or device double [epochs], zeroed and then accumulated in.
+ * Limits: n <= AFQMC_CV_NOALLOC_MAX_SAMPLES and min(batch, n) <=
+ * AFQMC_CV_NOALLOC_MAX_BATCH, else AFQMC_ERR_UNSUPPORTED (nothing launched).
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents (each call writes all it reads): calls that overlap in time on one
+ * GPU race, so issue them on one stream or synchronise between them.
+ * Other errors as afqmc_cv_train.
+ */
+#define AFQMC_CV_NOALLOC_MAX_SAMPLES 65536
+#define AFQMC_CV_NOALLOC_MAX_BATCH 512
+afqmc_status afqmc_cv_train_noalloc(afqmc_ctx *ctx, int32_t isys, const double *feat, const void *ek, int64_t n,
+                                    int32_t epochs, int32_t batch, double lr, double *loss_out, void *hip_stream);
 afqmc_status afqmc_cv_set_params(afqmc_ctx *ctx, int32_t isys, const float *params, const double *norm,
                                  void *hip_stream);
 afqmc_status afqmc_cv_get_params(afqmc_ctx *ctx, int32_t isys, float *params, double *norm, void *hip_stream);

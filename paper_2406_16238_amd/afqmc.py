@@ -92,8 +92,9 @@ EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate"
            "afqmc_cv_collect", "afqmc_cv_train", "afqmc_cv_set_params", "afqmc_cv_get_params",
            "afqmc_cv_predict", "afqmc_cv_loss_grad", "afqmc_cv_state", "afqmc_population_control",
            "afqmc_set_e_shift", "afqmc_free_propagate", "afqmc_free_estimator", "afqmc_free_step",
-           "afqmc_run_block", "afqmc_reblock")
+           "afqmc_run_block", "afqmc_reblock", "afqmc_cv_train_noalloc")
 CV_NFEAT, CV_NPARAMS, CV_NNORM = 8, 17922, 20
+CV_NOALLOC_MAX_SAMPLES, CV_NOALLOC_MAX_BATCH = 65536, 512
 FREE_EST = 10
 
 _lib = None
@@ -129,6 +130,8 @@ def load_library() -> ctypes.CDLL:
         "afqmc_cv_collect": ([P, ctypes.POINTER(CWalkers), pp, pp, P], ctypes.c_int),
         "afqmc_cv_train": ([P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                             ctypes.c_double, P, P], ctypes.c_int),
+        "afqmc_cv_train_noalloc": ([P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, P, P], ctypes.c_int),
         "afqmc_cv_set_params": ([P, ctypes.c_int32, P, P, P], ctypes.c_int),
         "afqmc_cv_get_params": ([P, ctypes.c_int32, P, P, P], ctypes.c_int),
         "afqmc_cv_predict": ([P, ctypes.c_int32, P, ctypes.c_int64, P, P], ctypes.c_int),
@@ -559,6 +562,20 @@ def cv_train(ctx: Context, feat, ek, epochs: int, batch: int, lr: float, isys: i
     _check(load_library().afqmc_cv_train(ctx.handle, isys, f, e, n, epochs, batch, lr, loss.data_ptr(),
                                          _stream_handle(stream)))
     return loss[:epochs]
+
+
+def cv_train_noalloc(ctx: Context, feat, ek, epochs: int, batch: int, lr: float, loss_out=None, isys: int = 0,
+                     stream=None):
+    """afqmc_cv_train_noalloc: the training of cv_train with the library's fixed
+    workspace (no allocation, no synchronisation); loss_out: None or float64
+    [epochs] on the GPU, filled with the mean loss of each pass."""
+    import torch
+    n = feat.shape[0]
+    f = _dev(feat, torch.float64, (n, CV_NFEAT), "feat")
+    e = _dev(ek, torch.complex128, (n,), "ek")
+    lo = _dev(loss_out, torch.float64, (epochs,), "loss_out") if loss_out is not None else None
+    _check(load_library().afqmc_cv_train_noalloc(ctx.handle, isys, f, e, n, epochs, batch, lr, lo,
+                                                 _stream_handle(stream)))
 
 
 def cv_set_params(ctx: Context, params=None, norm=None, isys: int = 0, stream=None):

@@ -38,6 +38,52 @@ namespace afqmc {
 afqmc_status record_error(afqmc_status s, const char *msg) { return fail(s, msg); }
 }  // namespace afqmc
 
+namespace {
+
+// Training workspace of afqmc_cv_train_noalloc: one fixed device array per GPU
+// (standardised samples and targets, per-workgroup gradient partials, the
+// gradient and the loss partials), so that the call allocates nothing.
+constexpr int64_t kNoAllocMaxSamples = AFQMC_CV_NOALLOC_MAX_SAMPLES;
+constexpr int kNoAllocMaxBatch = AFQMC_CV_NOALLOC_MAX_BATCH;
+constexpr int kNoAllocMaxWg = (kNoAllocMaxBatch + kCvGradBlock - 1) / kCvGradBlock;
+constexpr size_t pad256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNaX = 0;
+constexpr size_t kNaT = kNaX + pad256((size_t)kNoAllocMaxSamples * kCvFeatures * sizeof(float));
+constexpr size_t kNaPart = kNaT + pad256((size_t)kNoAllocMaxSamples * 2 * sizeof(float));
+constexpr size_t kNaGrad = kNaPart + pad256((size_t)kNoAllocMaxWg * kCvParams * sizeof(float));
+constexpr size_t kNaLpart = kNaGrad + pad256((size_t)kCvParams * sizeof(float));
+constexpr size_t kNoAllocBytes = kNaLpart + pad256((size_t)kNoAllocMaxWg * sizeof(double));
+static_assert(kNoAllocBytes <= 8u << 20, "the no-allocation workspace stays under 8 MiB");
+
+// In host code `scratch` names a host-side stand-in: its device address on
+// each GPU comes from hipGetSymbolAddress (scratch_address) and only that
+// address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_addr;  // device ordinal -> address of `scratch` there
+
+// Looks up (once per device, with that device current, at context set-up) the
+// device address of `scratch`.
+afqmc_status bind_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr.count(device)) return AFQMC_OK;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(AFQMC_ERR_HIP, std::string("address of the no-allocation workspace: ") + hipGetErrorString(e));
+  g_scratch_addr[device] = static_cast<unsigned char *>(p);
+  return AFQMC_OK;
+}
+
+unsigned char *scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  return it == g_scratch_addr.end() ? nullptr : it->second;
+}
+
+}  // namespace
+
 struct afqmc_ctx {
   std::vector<System> sys;
   Options opt;
@@ -843,6 +889,13 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->tune = o.tune != 0 && !c->ex_wx_forced;
   c->use_graph = o.use_graph != 0;
   (void)hipGetDevice(&c->device);
+  {
+    afqmc_status r = bind_scratch(c->device);
+    if (r != AFQMC_OK) {
+      delete c;
+      return r;
+    }
+  }
   c->sys.resize(nsys);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   uint64_t used = 0;
@@ -1445,6 +1498,44 @@ afqmc_status afqmc_cv_train(afqmc_ctx *ctx, int32_t isys, const double *feat, co
   if (loss_out && epochs > 0)
     AFQMC_HIP(hipMemcpyAsync(loss_out, loss, (size_t)epochs * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
   AFQMC_HIP(hipStreamSynchronize(st), "training");
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_cv_train_noalloc(afqmc_ctx *ctx, int32_t isys, const double *feat, const void *ek, int64_t n,
+                                    int32_t epochs, int32_t batch, double lr, double *loss_out, void *hip_stream) {
+  System *sp = cv_system(ctx, isys);
+  if (!sp || !feat || !ek) return fail(AFQMC_ERR_ARG, "NULL context, inputs or bad system index");
+  if (n < 2 || epochs < 0 || batch < 1 || !(lr > 0.0))
+    return fail(AFQMC_ERR_ARG, "need n >= 2, epochs >= 0, batch >= 1 and lr > 0");
+  if (n > kNoAllocMaxSamples || std::min<int64_t>(batch, n) > kNoAllocMaxBatch)
+    return fail(AFQMC_ERR_UNSUPPORTED, "afqmc_cv_train_noalloc takes at most " + std::to_string(kNoAllocMaxSamples) +
+                                           " samples and minibatches of at most " +
+                                           std::to_string(kNoAllocMaxBatch) + " (got n = " + std::to_string(n) +
+                                           ", batch = " + std::to_string(batch) + ")");
+  unsigned char *base = scratch_address(ctx->device);
+  if (!base) return fail(AFQMC_ERR_HIP, "the no-allocation workspace has no address on this device");
+  System &s = *sp;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  float *X = reinterpret_cast<float *>(base + kNaX), *T = reinterpret_cast<float *>(base + kNaT);
+  float *part = reinterpret_cast<float *>(base + kNaPart), *grad = reinterpret_cast<float *>(base + kNaGrad);
+  double *lpart = reinterpret_cast<double *>(base + kNaLpart);
+  // nothing in the workspace accumulates: every kernel below writes what it
+  // reads later in this call; the loss accumulates in the caller's buffer
+  AFQMC_HIP(launch_cv_stats(feat, static_cast<const double2 *>(ek), n, s.cv_norm, st), "statistics kernel");
+  AFQMC_HIP(launch_cv_standardise(feat, static_cast<const double2 *>(ek), n, s.cv_norm, X, T, st),
+            "standardise kernel");
+  AFQMC_HIP(launch_cv_zero(s.cv_m, kCvParams * sizeof(float), st), "zero fill");
+  AFQMC_HIP(launch_cv_zero(s.cv_v, kCvParams * sizeof(float), st), "zero fill");
+  if (loss_out && epochs > 0) AFQMC_HIP(launch_cv_zero(loss_out, (size_t)epochs * sizeof(double), st), "zero fill");
+  long t = 0;
+  for (int e = 0; e < epochs; ++e)
+    for (long b0 = 0; b0 < n; b0 += batch) {
+      const long nb = std::min<long>(batch, n - b0);
+      AFQMC_HIP(launch_cv_grad(s.cv_params, X, T, b0, nb, part, lpart, grad, (double)nb / (double)n,
+                               loss_out ? loss_out + e : nullptr, st),
+                "network gradient kernel");
+      AFQMC_HIP(launch_cv_adam(s.cv_params, grad, s.cv_m, s.cv_v, lr, ++t, st), "Adam kernel");
+    }
   return AFQMC_OK;
 }
 
