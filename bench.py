@@ -66,7 +66,8 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batching", "cv"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "medium", "small", "batching", "cv", "stat"],
                     help="batching: the sixteen-system set (aggregate walker-steps/s of separate contexts run "
                          "one after another, of one set context over internal streams, and of that context "
                          "replaying a hipGraph); cv: the learned control variate at the headline shape "
@@ -82,6 +83,9 @@ def parse_args(argv=None):
                     help="step: afqmc_step (one overlap/LU and one force bias per step); separate: "
                          "afqmc_propagate + afqmc_reorthogonalize + afqmc_local_energy")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="headline only: skip the other workloads' legs (medium FP64, reblocked energies of every "
+                         "form, the sixteen-system set, the control variate at headline and benzene scale)")
     ap.add_argument("--cv-train-steps", type=int, default=60, help="cv: trajectory steps whose walkers train the network")
     ap.add_argument("--cv-epochs", type=int, default=30, help="cv: training passes")
     ap.add_argument("--cv-draws", type=int, default=60, help="cv: subset draws at fixed walkers")
@@ -121,17 +125,44 @@ def step_flops(M, na, nb, G, free=False):
             + 2 * 4.0 * M * M * nt + 4.0 * G * M * nt + 2 * 16.0 * M * n2)
 
 
+def exchange_roofline(prec, phases, M, s, G, W, workload):
+    """Roofline object of the exchange kernel (the step's dominant one): the
+    algorithmic flops of one launch (one spin block of every walker) over its
+    average launch time from the library's HIP-event phase timers."""
+    ex_ms, ex_n = phases["exchange"]
+    blocks = [n for n in (s.nalpha, s.nbeta) if n > 0]
+    ex_flops = exchange_flops(M, s.nalpha, s.nbeta, G, W) / len(blocks)
+    avg_ms = ex_ms / max(ex_n, 1)
+    achieved = ex_flops / (avg_ms * 1e-3) / 1e12 if ex_n else 0.0
+    kernel = KERNEL_NAME[prec]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": measured_traffic(kernel, workload),
+            "kernel": f"{kernel} (one spin block of {W} walkers per launch)", "avg_launch_ms": round(avg_ms, 4),
+            "flops_per_launch": ex_flops, "executed_tflops": round(achieved * PRODUCTS[prec], 3)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(spec, n_walkers, n_steps, free=False):
     """The CPU oracle, as it stands, on a bounded sample of the same workload."""
     import numpy as np
     import afqmc_inputs as gi
     from oracle import afqmc_oracle as O
+    cores = len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_info
         blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
-        cores = int(blas[0]["num_threads"]) if blas else 1
+        blas_threads = int(blas[0]["num_threads"]) if blas else 1
     except Exception:
-        cores = len(os.sched_getaffinity(0))
+        blas_threads = None
     s = spec.system
     h1, chol, ecore, trial = gi.make_system(s)
     ham = O.build(h1, chol, ecore, trial, s.nalpha, s.nbeta, spec.dt)
@@ -170,7 +201,7 @@ def cpu_baseline(spec, n_walkers, n_steps, free=False):
     except ImportError:
         pass
     return {"value": n_walkers * n_steps / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
-            "single_thread": single,
+            "blas_threads": blas_threads, "cpu_model": cpu_model(), "single_thread": single,
             "sample": f"{n_walkers} walkers x {n_steps} {'free-projection ' if free else ''}steps "
                       f"(propagate + local energy, FP64) of {spec.name}, "
                       f"{dt:.1f} s on the host CPU, numpy complex128"}
@@ -244,6 +275,11 @@ def time_path(A, torch, ctx, spec, trial, xs, args):
 
 
 def bench_batching(args):
+    print(json.dumps(batching_leg(args)), flush=True)
+    return 0
+
+
+def batching_leg(args, precisions=(("fp64", 0), ("fp32", 1))):
     """Aggregate throughput of the sixteen-system set, FP64 and FP32."""
     import numpy as np
     import torch
@@ -292,7 +328,7 @@ def bench_batching(args):
         return fill
 
     out_modes = {}
-    for prec_name, prec in (("fp64", 0), ("fp32", 1)):
+    for prec_name, prec in precisions:
         modes = {}
         # separate contexts, one after another on one stream
         ctxs = [A.setup_hamiltonian(inputs[j][0], A.default_options(precision=prec, streams=1))
@@ -333,11 +369,115 @@ def bench_batching(args):
            "config": {"workload": "batching-16-systems-M60-360", "nbasis": [r.system.nbasis for r in runs],
                       "nwalkers": [r.nwalkers for r in runs], "nchol": "4M", "n_per_spin": "M/10"},
            "modes": out_modes}
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
+
+
+def train_cv_network(A, torch, ctx, trial, W, G, nsteps, epochs, seed0=5000):
+    """Features and exact exchange along the path's own trajectory (fields drawn
+    from seed0 on), then the network trained on them; returns the losses."""
+    import afqmc_inputs as gi
+    w = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
+    A.overlap(ctx, w)
+    gen = torch.Generator(device="cuda")
+    x = torch.empty((W, G), dtype=torch.float64, device="cuda")
+    e = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+    feats, eks = [], []
+    for k in range(nsteps):
+        gen.manual_seed(seed0 + k)
+        x.normal_(generator=gen)
+        A.step(ctx, w, x, e, reortho=(k + 1) % 5 == 0)
+        f = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+        q = torch.empty(W, dtype=torch.complex128, device="cuda")
+        A.cv_collect(ctx, w, f, q)
+        feats.append(f)
+        eks.append(q)
+    return A.cv_train(ctx, torch.cat(feats), torch.cat(eks), epochs, 256, 2e-3).cpu().numpy()
+
+
+def stat_error_leg(A, torch, spec, nblocks=20, block_steps=10, equil_blocks=4, cv_train_steps=40, cv_epochs=30):
+    """Mixed-estimator energies with stated statistical errors: the same
+    walkers, fields and comb offsets run in blocks (comb and E_T feedback after
+    each) through the FP64 path and each reduced or learned form; the per-step
+    mixed energies after the first `equil_blocks` blocks are reblocked by the
+    library (afqmc_reblock), and so is each form's per-step difference from
+    FP64."""
+    import numpy as np
+    import afqmc_inputs as gi
+    s = spec.system
+    W, G = spec.nwalkers, s.nchol
+    h1, chol, ecore, trial = gi.make_system(s)
+    sysin = A.SystemInput(h1, chol, ecore, trial, s.nalpha, s.nbeta, W, spec.dt)
+    del chol
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(spec.field_seed + 77)
+    xb = torch.randn((nblocks, block_steps, W, G), dtype=torch.float64, device="cuda", generator=gen)
+    offs = torch.rand((nblocks, 1), dtype=torch.float64, device="cuda", generator=gen)
+    forms = {"fp64": dict(precision=A.FP64), "bf16x2": dict(precision=A.BF16X2_CONTRACT),
+             "bf16x2+fp32prop": dict(precision=A.BF16X2_CONTRACT, prop_precision=A.FP32_CONTRACT),
+             "cv_fp64": dict(precision=A.FP64, ex_mode=A.EX_CV)}
+    series, rates, extra = {}, {}, {}
+    for name, kw in forms.items():
+        ctx = A.setup_hamiltonian(sysin, A.default_options(**kw))
+        try:
+            if kw.get("ex_mode") == A.EX_CV:
+                losses = train_cv_network(A, torch, ctx, trial, W, G, cv_train_steps, cv_epochs)
+                extra[name] = {"training_steps": cv_train_steps, "epochs": cv_epochs,
+                               "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+            w = A.Walkers.from_numpy(gi.initial_walkers(trial, W))
+            A.overlap(ctx, w)
+            e = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+            est = torch.empty((nblocks, block_steps, 4), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for b in range(nblocks):
+                A.run_block(ctx, w, xb[b], e, est[b], offs[b], step0=b * block_steps,
+                            reortho_every=spec.reortho_every, feedback=True)
+            ev1.record()
+            torch.cuda.synchronize()
+            rates[name] = W * nblocks * block_steps / (ev0.elapsed_time(ev1) * 1e-3)
+            h = est.cpu().numpy().reshape(-1, 4)
+            series[name] = h[:, 0] / h[:, 1]
+        finally:
+            ctx.close()
+        torch.cuda.empty_cache()
+    del xb
+    skip = equil_blocks * block_steps
+
+    def err(x):
+        r = A.reblock(x[skip:])
+        if r["optimal"] is not None:
+            return r["mean"], r["std_err"], True
+        # no level qualifies: the largest error of the levels with at least 8 blocks
+        cand = [lv["std_err"] for lv in r["levels"] if lv["n"] >= 8]
+        return r["mean"], max(cand) if cand else r["levels"][-1]["std_err"], False
+
+    e64, s64, ok64 = err(series["fp64"])
+    out = {"workload": spec.name, "nwalkers": W, "blocks": nblocks, "steps_per_block": block_steps,
+           "equilibration_steps_excluded": skip, "population_control": "comb after each block",
+           "e_shift_feedback": "block estimate", "error_analysis": "afqmc_reblock (Flyvbjerg-Petersen, "
+           "Lee et al. level); difference errors from the reblocked per-step difference series",
+           "fp64": {"energy_ha": e64, "err_ha": s64, "plateau": ok64, "walker_steps_per_s": round(rates["fp64"], 1)},
+           "forms": {}}
+    for name in forms:
+        if name == "fp64":
+            continue
+        ef, sf, okf = err(series[name])
+        dm, ds, okd = err(series[name] - series["fp64"])
+        out["forms"][name] = {"energy_ha": ef, "err_form_ha": sf, "err_fp64_ha": s64, "diff_ha": dm,
+                              "err_diff_ha": ds, "plateau": bool(okf and okd),
+                              "within_0.1mHa": bool(abs(dm) <= 1e-4),
+                              "walker_steps_per_s": round(rates[name], 1),
+                              "speedup_vs_fp64": round(rates[name] / rates["fp64"], 3), **extra.get(name, {})}
+    return out
 
 
 def bench_cv(args):
+    print(json.dumps(cv_leg(args, args.cv_system)), flush=True)
+    return 0
+
+
+def cv_leg(args, system):
     """Learned control variate: walker-steps/s with the exact exchange on a 1/8
     subset against full exchange, and the estimator's bias and spread at fixed
     walkers against plain subsampling (f = 0).  Headline shape, or the
@@ -347,7 +487,7 @@ def bench_cv(args):
     import afqmc_inputs as gi
     from paper_2406_16238_amd import afqmc as A
 
-    spec = gi.BENZENE_SCALE if args.cv_system == "benzene" else gi.HEADLINE
+    spec = gi.BENZENE_SCALE if system == "benzene" else gi.HEADLINE
     s = spec.system
     W, G = spec.nwalkers, s.nchol
     if s.recipe == "counter":
@@ -419,8 +559,13 @@ def bench_cv(args):
         return np.array(v)
     cvd = draws(args.cv_draws)
     params, norm = A.cv_get_params(ctx)
-    A.cv_set_params(ctx, torch.zeros(A.CV_NPARAMS, dtype=torch.float32, device="cuda"),
-                    torch.tensor([0.0] * 8 + [1.0] * 8 + [0.0, 0.0, 1.0, 1.0], dtype=torch.float64, device="cuda"))
+    zero = torch.zeros(A.CV_NPARAMS, dtype=torch.float32, device="cuda")
+    # the method without the network: f = the training mean of EK (zero weights
+    # keep only the target normalisation's mean), and plain subsampling (f = 0)
+    A.cv_set_params(ctx, zero, norm)
+    cmd = draws(args.cv_draws)
+    A.cv_set_params(ctx, zero, torch.tensor([0.0] * 8 + [1.0] * 8 + [0.0, 0.0, 1.0, 1.0], dtype=torch.float64,
+                                            device="cuda"))
     pld = draws(args.cv_draws)
     A.cv_set_params(ctx, params, norm)
     # throughput from the same walker state: control variate, then full exchange
@@ -448,10 +593,70 @@ def bench_cv(args):
             "draws": args.cv_draws, "exact_e2_ha": exact,
             "cv_bias_ha": float(cvd.mean() - exact), "cv_stderr_ha": float(cvd.std(ddof=1) / np.sqrt(len(cvd))),
             "cv_spread_ha": float(cvd.std(ddof=1)),
+            "constant_mean_bias_ha": float(cmd.mean() - exact), "constant_mean_spread_ha": float(cmd.std(ddof=1)),
             "plain_bias_ha": float(pld.mean() - exact), "plain_spread_ha": float(pld.std(ddof=1)),
+            "variance_ratio_cv_over_constant_mean": float(cvd.var(ddof=1) / cmd.var(ddof=1)),
             "variance_ratio_cv_over_plain": float(cvd.var(ddof=1) / pld.var(ddof=1))}})
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
+
+
+def medium_leg(args):
+    """The FP64 path at the medium shape (M=200, N=20+20, G=800, 512 walkers):
+    walker-steps/s and the FP64 exchange kernel's roofline."""
+    import argparse as ap_
+    import torch
+    import afqmc_inputs as gi
+    from paper_2406_16238_amd import afqmc as A
+    spec = gi.MEDIUM
+    s = spec.system
+    W, G, M = spec.nwalkers, s.nchol, s.nbasis
+    h1, chol, ecore, trial = gi.make_system(s)
+    ctx = A.setup_hamiltonian(A.SystemInput(h1, chol, ecore, trial, s.nalpha, s.nbeta, W, spec.dt))
+    del chol
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(spec.field_seed)
+    xs = torch.randn((args.warmup + args.steps, W, G), dtype=torch.float64, device="cuda", generator=gen)
+    a = ap_.Namespace(**vars(args))
+    a.api, a.projection, a.repeats = "step", "phaseless", 0
+    try:
+        r = time_path(A, torch, ctx, spec, trial, xs, a)
+    finally:
+        ctx.close()
+    return {"workload": spec.name, "dtype": "f64", "value": round(W * args.steps / (r["total_ms"] * 1e-3), 2),
+            "unit": "walker-steps/s", "ms_per_step": round(r["total_ms"] / args.steps, 4),
+            "mixed_energy": r["mixed_energy"], "roofline": exchange_roofline("fp64", r["phases"], M, s, G, W,
+                                                                              spec.name)}
+
+
+def run_legs(args):
+    """The other workloads, compactly, for the same JSON line: the FP64 medium
+    shape, reblocked energies of every form against FP64 (medium and headline),
+    the sixteen-system set, and the learned control variate (headline and
+    benzene scale)."""
+    import argparse as ap_
+    import torch
+    import afqmc_inputs as gi
+    from paper_2406_16238_amd import afqmc as A
+    legs = {}
+    a = ap_.Namespace(**vars(args))
+    a.cv_train_steps, a.cv_epochs, a.cv_draws = args.cv_train_steps, args.cv_epochs, 40
+    plan = [("medium_fp64", lambda: medium_leg(a)),
+            ("stat_error_medium", lambda: stat_error_leg(A, torch, gi.MEDIUM)),
+            ("stat_error_headline", lambda: stat_error_leg(A, torch, gi.HEADLINE)),
+            ("batching", lambda: batching_leg(a, precisions=(("fp64", 0),))),
+            ("cv_headline", lambda: cv_leg(a, "headline")),
+            ("cv_benzene", lambda: cv_leg(a, "benzene"))]
+    for name, fn in plan:
+        t0 = time.time()
+        print(f"leg {name} ...", file=sys.stderr, flush=True)
+        try:
+            legs[name] = fn()
+        except Exception as ex:   # a failing leg is reported, not fatal to the line
+            legs[name] = {"error": f"{type(ex).__name__}: {ex}"}
+        legs[name]["leg_seconds"] = round(time.time() - t0, 1)
+        print(f"leg {name} done in {legs[name]['leg_seconds']} s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return legs
 
 
 def main(argv=None):
@@ -466,6 +671,13 @@ def main(argv=None):
         return bench_batching(args)
     if args.workload == "cv":
         return bench_cv(args)
+    if args.workload == "stat":
+        import torch
+        import afqmc_inputs as gi
+        from paper_2406_16238_amd import afqmc as A
+        for spec in (gi.MEDIUM, gi.HEADLINE):
+            print(json.dumps(stat_error_leg(A, torch, spec)), flush=True)
+        return 0
 
     import numpy as np
     import torch
@@ -512,18 +724,7 @@ def main(argv=None):
     value = W * args.steps / (r["total_ms"] * 1e-3)
     # one exchange launch = one spin block of every walker (the phase timer
     # brackets each launch on the library's stream)
-    ex_ms, ex_n = r["phases"]["exchange"]
-    blocks = [n for n in (s.nalpha, s.nbeta) if n > 0]
-    ex_flops = exchange_flops(M, s.nalpha, s.nbeta, G, W) / len(blocks)
-    avg_ms = ex_ms / max(ex_n, 1)
-    achieved = ex_flops / (avg_ms * 1e-3) / 1e12 if ex_n else 0.0
-    kernel = KERNEL_NAME[rep]
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[rep], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[rep], 4),
-                "traffic": measured_traffic(kernel, spec.name),
-                "kernel": f"{kernel} (one spin block of {W} walkers per launch)", "avg_launch_ms": round(avg_ms, 4),
-                "flops_per_launch": ex_flops,
-                "executed_tflops": round(achieved * PRODUCTS[rep], 3)}
+    roofline = exchange_roofline(rep, r["phases"], M, s, G, W, spec.name)
     free = args.projection == "free"
     step_tf = step_flops(M, s.nalpha, s.nbeta, G, free) * W / (ms_per_step * 1e-3) / 1e12
 
@@ -566,6 +767,7 @@ def main(argv=None):
                                           "bar": 1e-4, "within_bar": bool(d.max() <= 1e-4)}
         # the same fields from the same walkers: the mixed estimators of the two trajectories
         out["mixed_energy_difference_vs_fp64_ha"] = abs(r["mixed_energy"] - f["mixed_energy"])
+        out["fp64_path"]["roofline"] = exchange_roofline("fp64", f["phases"], M, s, G, W, spec.name)
     if p32_key in runs and p32_key != rep_key:
         q = runs[p32_key]
         e_q = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
@@ -590,6 +792,8 @@ def main(argv=None):
         c.close()
     del xs, runs
     torch.cuda.empty_cache()
+    if not args.no_legs and args.workload == "headline" and args.projection == "phaseless":
+        out["legs"] = run_legs(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_walkers, args.cpu_steps, free)
     print(json.dumps(out), flush=True)
