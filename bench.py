@@ -30,15 +30,17 @@ if ROOT not in sys.path:
 METRIC = "walker-steps/s (propagate+energy) at M=400,N=40; speed-up vs FP64 at 0.1 mHa"
 METRIC_FREE = "free-projection walker-steps/s (propagate+energy) at M=400,N=40; speed-up vs FP64"
 # dense MI355X peaks per arithmetic type (TFLOP/s)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
-PRECISION_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
-PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0, "fp16t": 2500.0, "bf16t": 2500.0}
+PRECISION_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3, "fp16t": 4, "bf16t": 5}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6, "bf16x2": 3, "fp16t": 1, "bf16t": 1}
 
 
 KERNEL_NAME = {"fp64": "k_exchange_mfma", "fp32": "k_exchange_f32", "bf16x3": "k_exchange_bf16<40,3>",
-               "bf16x2": "k_exchange_bf16<40,2>"}
+               "bf16x2": "k_exchange_bf16<40,2>", "fp16t": "k_exchange_bf16<40,1,_Float16>",
+               "bf16t": "k_exchange_bf16<40,1,__bf16>"}
 KERNEL_SOURCE = {"k_exchange_mfma": "k_exchange.hip", "k_exchange_f32": "k_exchange_lp.hip",
-                 "k_exchange_bf16<40,3>": "k_exchange_lp.hip", "k_exchange_bf16<40,2>": "k_exchange_lp.hip"}
+                 "k_exchange_bf16<40,3>": "k_exchange_lp.hip", "k_exchange_bf16<40,2>": "k_exchange_lp.hip",
+                 "k_exchange_bf16<40,1,_Float16>": "k_exchange_lp.hip", "k_exchange_bf16<40,1,__bf16>": "k_exchange_lp.hip"}
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "exchange_hbm_traffic.md")
 
 
@@ -72,7 +74,7 @@ def parse_args(argv=None):
                          "one after another, of one set context over internal streams, and of that context "
                          "replaying a hipGraph); cv: the learned control variate at the headline shape "
                          "(training on the path's own trajectory, then full exchange vs the 1/8 subset)")
-    ap.add_argument("--precision", default="bf16x2", choices=["fp64", "fp32", "bf16x3", "bf16x2"],
+    ap.add_argument("--precision", default="bf16x2", choices=["fp64", "fp32", "bf16x3", "bf16x2", "fp16t", "bf16t"],
                     help="path reported in the JSON line (the FP64 path is timed too, for the speed-up)")
     ap.add_argument("--prop-precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the propagation (V_HS planes and Taylor terms) of the reported path")

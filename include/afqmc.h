@@ -52,8 +52,20 @@ typedef enum {
 } afqmc_status;
 
 /* Precision of the force-bias and exchange contractions (overlap LU,
- * determinant ratios, re-orthogonalisation and weights are always FP64). */
-enum { AFQMC_FP64 = 0, AFQMC_FP32_CONTRACT = 1, AFQMC_BF16X3_CONTRACT = 2, AFQMC_BF16X2_CONTRACT = 3 };
+ * determinant ratios, re-orthogonalisation and weights are always FP64):
+ * FP32; split BF16 with three or two bfloat16 terms per operand (six or three
+ * products); or the trial split, Theta = Psi + Q, T = Ltilde Psi (exact, set
+ * up once) + Ltilde Q with Ltilde and Q in one FP16 or BF16 term each (one
+ * product, scaled by powers of two per Cholesky vector and per walker).  All
+ * accumulate in FP32 on MFMA; spin blocks of at most 48 orbitals. */
+enum {
+  AFQMC_FP64 = 0,
+  AFQMC_FP32_CONTRACT = 1,
+  AFQMC_BF16X3_CONTRACT = 2,
+  AFQMC_BF16X2_CONTRACT = 3,
+  AFQMC_FP16_TSPLIT_CONTRACT = 4,
+  AFQMC_BF16_TSPLIT_CONTRACT = 5
+};
 
 /* Per-walker flag bits, OR-ed into afqmc_walkers.flags by the library. */
 enum {

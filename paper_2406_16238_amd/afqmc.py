@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafqmc.so")
 
 OK, ERR_ARG, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = 0, 1, 2, 3, 4
-FP64, FP32_CONTRACT, BF16X3_CONTRACT, BF16X2_CONTRACT = 0, 1, 2, 3
+FP64, FP32_CONTRACT, BF16X3_CONTRACT, BF16X2_CONTRACT, FP16_TSPLIT_CONTRACT, BF16_TSPLIT_CONTRACT = 0, 1, 2, 3, 4, 5
 W_SINGULAR, W_NONFINITE, W_DEAD = 1, 2, 4
 EX_FULL, EX_CV = 0, 1
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}

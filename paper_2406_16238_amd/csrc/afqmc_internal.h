@@ -102,8 +102,10 @@ struct System {
   int fb_slices = 0;           // slices of fbpart holding the current vbias
   // reduced-precision exchange (and force bias): per-spin operands
   int precision = AFQMC_FP64;
-  void *lp_lhs[2] = {nullptr, nullptr};  // Ltilde as FP32 [G][M][NR] or BF16 planes [3][G][NR][Kp]
-  void *lp_rhs[2] = {nullptr, nullptr};  // Theta as FP32 [W][M][CP] or BF16 planes [3][W][CP][Kp]
+  // Ltilde as FP32 [G][M][NR] or 16-bit planes [NT][G4][NR][Kp] (trial split: one plane, then T0 and scales)
+  void *lp_lhs[2] = {nullptr, nullptr};
+  // Theta as FP32 [W][M][CP] or 16-bit planes [NT][W][CP][Kp] (trial split: Q = Theta - Psi, then scales)
+  void *lp_rhs[2] = {nullptr, nullptr};
 };
 
 // Reduced-precision exchange (k_exchange_lp.hip).
@@ -111,6 +113,7 @@ bool lp_exchange_supported(int precision, int nr);
 // the split-BF16 kernels address their operand planes with 32-bit element offsets
 bool lp_operands_addressable(int precision, int G, int M, int W, int nr);
 size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs);
+size_t lp_operand_bytes(int precision, int G, int M, int W, int nr, bool lhs);
 hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st);
 hipError_t lp_enable_lds(const System &s);
 // Reduced-precision copy of one spin block of Theta (the right operand of the

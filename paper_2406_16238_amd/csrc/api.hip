@@ -296,11 +296,10 @@ Plan plan_for(const System &s) {
   p.ekpart = W * 2 * (size_t)s.ex_stride;
   p.LtS0 = s.ex_mfma && s.Na > 0 ? G * M * (size_t)s.ex_plan[0].NR : 0;
   p.LtS1 = s.ex_mfma && s.Nb > 0 ? G * M * (size_t)s.ex_plan[1].NR : 0;
-  const size_t esz = s.precision == AFQMC_FP32_CONTRACT ? 4 : 2;
   for (int sp = 0; sp < 2; ++sp) {
     const bool on = s.precision != AFQMC_FP64 && s.ex_plan[sp].N > 0;
-    p.lp_bytes[sp][0] = on ? esz * lp_operand_elems(s.precision, s.G, s.M, s.W, s.ex_plan[sp].NR, true) : 0;
-    p.lp_bytes[sp][1] = on ? esz * lp_operand_elems(s.precision, s.G, s.M, s.W, s.ex_plan[sp].NR, false) : 0;
+    p.lp_bytes[sp][0] = on ? lp_operand_bytes(s.precision, s.G, s.M, s.W, s.ex_plan[sp].NR, true) : 0;
+    p.lp_bytes[sp][1] = on ? lp_operand_bytes(s.precision, s.G, s.M, s.W, s.ex_plan[sp].NR, false) : 0;
   }
   p.stat = W;
   return p;
@@ -840,7 +839,8 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   if (opt) o = *opt;
   else afqmc_default_options(&o);
   if (o.precision != AFQMC_FP64 && o.precision != AFQMC_FP32_CONTRACT && o.precision != AFQMC_BF16X3_CONTRACT &&
-      o.precision != AFQMC_BF16X2_CONTRACT)
+      o.precision != AFQMC_BF16X2_CONTRACT && o.precision != AFQMC_FP16_TSPLIT_CONTRACT &&
+      o.precision != AFQMC_BF16_TSPLIT_CONTRACT)
     return fail(AFQMC_ERR_ARG, "unknown precision");
   if (o.taylor_order < 1 || o.taylor_order > 16) return fail(AFQMC_ERR_ARG, "taylor_order must be in 1..16");
   if (std::isnan(o.fb_cap) || std::isinf(o.fb_cap)) return fail(AFQMC_ERR_ARG, "fb_cap must be finite");

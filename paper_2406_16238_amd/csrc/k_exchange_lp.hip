@@ -11,9 +11,16 @@
 //           dropped ml + lm + ll are below FP32 rounding);
 //   BF16x2: the three terms hh + hm + mh (x is kept to about 2^-17 relative and
 //           the dropped mm is of order 2^-18 of the product).
-// In both forms T is kept in LDS as FP32; the FP32 form accumulates the traces in
-// FP64, the split forms each lane's partial traces (at most 100 products) in FP32
-// and the sums over lanes and Cholesky vectors in FP64.
+// Trial-split forms (FP16 or BF16, one product): Theta = Psi + Q with Psi^T Q = 0
+//   (Psi^T Theta = 1), so T = T0 + Ltilde Q with T0 = Ltilde Psi fixed at set-up
+//   (FP32) and only the walker's departure Q from the trial rounded: Ltilde^g and
+//   Q_w are scaled by powers of two (per Cholesky vector, per walker) into one
+//   16-bit term each, multiplied on v_mfma_f32_16x16x32_{f16,bf16} with FP32
+//   accumulation, and the epilogue undoes the scales and adds T0.  The rounding
+//   error is relative to Ltilde Q, not to T.
+// In all forms T is kept in LDS as FP32; the FP32 form accumulates the traces in
+// FP64, the 16-bit forms each lane's partial traces (at most 100 products) in
+// FP32 and the sums over lanes and Cholesky vectors in FP64.
 // Overlaps, LU, propagation, weights and re-orthogonalisation stay FP64.
 //
 // Work decomposition as in the FP64 kernel: one GEMM per spin block with rows
@@ -33,6 +40,18 @@ namespace afqmc {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+// 8-wide operand vector of a 16-bit element type, and the 16x16x32 MFMA on it
+template <typename E> struct Vec8;
+template <> struct Vec8<__bf16> { typedef bf8v type; };
+template <> struct Vec8<_Float16> { typedef h8v type; };
+__device__ __forceinline__ f4v mfma16x16x32(bf8v a, bf8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mfma16x16x32(h8v a, h8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 
 namespace {
 constexpr int LWX = 2;      // walkers per workgroup
@@ -133,6 +152,69 @@ __device__ __forceinline__ void lp_trace_u(const f4v (&acc)[RT][CT], const float
     const int i = l >> 1;
     dg[pass] += sU[(l & 1) * NR * CS + i * CS + i];
   }
+}
+
+// Trace epilogue of the 16-bit forms, one Cholesky vector (pass) of the wave at
+// a time, through LDS in natural order: S[i][j] = T_ij as two planes, Re and Im,
+// at row stride NR + 4, the Im plane 8 words past the Re plane (so the 64 lanes
+// of one store fall into distinct banks).  A lane stores its four accumulator
+// rows of column (j, re|im) as four words, and reads the partners T_ji of those
+// rows, T_{j, i0..i0+3}, as one 16-byte word per plane.  The waves use disjoint
+// LDS and exchange nothing, so no barrier is needed between store and read.
+template <int NR>
+__host__ __device__ constexpr int lp_s_plane() { return NR * (NR + 4) + 8; }
+
+template <int NR, int CT, int RT>
+__device__ __forceinline__ void lp_store_s(const f4v (&acc)[RT][CT], float *sS, int lane, int pass) {
+  constexpr int CS = NR + 4, PL = lp_s_plane<NR>();
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
+    if (glo == ghi && glo != pass) continue;
+    if ((rt * 16 + 4 * lk) / NR != pass) continue;   // the lane's four rows belong to one Cholesky vector
+    const int i0 = rt * 16 + 4 * lk - pass * NR;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      float *d = sS + (lr & 1) * PL + i0 * CS + ct * 8 + (lr >> 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) d[r * CS] = acc[rt][ct][r];
+    }
+  }
+}
+
+template <int NR, int CT, int RT>
+__device__ __forceinline__ void lp_trace_s(const f4v (&acc)[RT][CT], const float *sS, int lane, float &pre,
+                                           float &pim, float *dg, int pass) {
+  constexpr int CS = NR + 4, PL = lp_s_plane<NR>();
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool odd = lr & 1;
+  float a0 = 0.f, a1 = 0.f, d = 0.f;   // sum v Re T_ji, sum v Im T_ji, diagonal
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
+    if (glo == ghi && glo != pass) continue;
+    if ((rt * 16 + 4 * lk) / NR != pass) continue;
+    const int i0 = rt * 16 + 4 * lk - pass * NR;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int j = ct * 8 + (lr >> 1);
+      const f4v cre = *reinterpret_cast<const f4v *>(sS + j * CS + i0);
+      const f4v cim = *reinterpret_cast<const f4v *>(sS + PL + j * CS + i0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = acc[rt][ct][r];
+        a0 = fmaf(v, cre[r], a0);
+        a1 = fmaf(v, cim[r], a1);
+        if (i0 + r == j) d += v;
+      }
+    }
+  }
+  // the lane holds Re T_ij (even lr) or Im T_ij (odd lr); its diagonal share
+  // follows the parity convention of lp_finish
+  pre += odd ? -a1 : a0;
+  pim += odd ? a0 : a1;
+  dg[pass] += d;
 }
 
 template <int GC>
@@ -263,13 +345,40 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
 // LtB[p][g][NR][Kp] (g over lp_padded_g(G), the extra vectors zero),
 // ThB[p][w][CP][Kp] (bf16, p = h, m (, l) for NT = 2 (3) terms; contraction
 // index contiguous and zero-padded to Kp, a multiple of 32) for one spin block.
-template <int NR, int NT>
-__global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(const __bf16 *__restrict__ LtB,
-                                                             const __bf16 *__restrict__ ThB, int Kp, int N, int G,
+// NT = 3 or 2: split-BF16 terms of Ltilde and Theta; NT = 1: the trial split,
+// one E term of Ltilde and of Q, with T0 transposed [G4][NR][NR], the inverse scales of
+// the Cholesky vectors lsc [G4] and of the walkers qsc [W].
+#ifndef AFQMC_SPLIT_STAGES
+#define AFQMC_SPLIT_STAGES 2
+#endif
+#ifndef AFQMC_SPLIT_KSUB
+#define AFQMC_SPLIT_KSUB 2
+#endif
+// LDS stages of the one-product (trial-split) form; the split-BF16 forms keep two
+__host__ __device__ constexpr int lp16_stages(int nt) { return nt == 1 ? AFQMC_SPLIT_STAGES : 2; }
+// Staged planes per stage: the NT terms of the split-BF16 forms, or, for the
+// one-product form, KSUB consecutive runs of LKC contraction indices (a stage
+// then covers KSUB LKC indices: fewer barriers per contraction)
+__host__ __device__ constexpr int lp16_planes(int nt) { return nt == 1 ? AFQMC_SPLIT_KSUB : nt; }
+__host__ __device__ constexpr int lp16_kchunk(int nt) { return nt == 1 ? AFQMC_SPLIT_KSUB * LKC : LKC; }
+// contraction length of the staged operands: M rounded up to whole chunks
+__host__ __device__ constexpr int lp16_kp(int nt, int M) { return (M + lp16_kchunk(nt) - 1) / lp16_kchunk(nt) * lp16_kchunk(nt); }
+
+// s_waitcnt that waits until at most n vector-memory operations of the wave are
+// outstanding and leaves the LDS/scalar and export counters alone (gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+#define AFQMC_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (7 << 4) | (15 << 8) | ((((n) >> 4) & 3) << 14))
+
+template <int NR, int NT, typename E = __bf16>
+__global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(const E *__restrict__ LtB,
+                                                             const E *__restrict__ ThB, int Kp, int N, int G,
                                                              int W, int stride, int spin,
                                                              double2 *__restrict__ ekpart,
                                                              double2 *__restrict__ vbpart, int ngb, int nwb,
-                                                             int group) {
+                                                             int group, const float *__restrict__ T0,
+                                                             const float *__restrict__ lsc,
+                                                             const float *__restrict__ qsc) {
+  typedef typename Vec8<E>::type v8;
   constexpr int GC = (NR % 16 == 0) ? 1 : 2;
   constexpr int ROWW = GC * NR, RT = ROWW / 16;
   constexpr int CP = 2 * NR, CT = CP / 16;
@@ -280,18 +389,20 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   // read touches at one k group fall in distinct banks, and a row is still one
   // 64-byte run for the stores.
   constexpr int RS = LKC;                        // staged row stride (bf16)
-  constexpr int ASZ = NT * ROWS * RS, BSZ = NT * COLS * RS;   // bf16 per stage
-  constexpr int AV = NT * ROWS * (LKC / 8), BV = NT * COLS * (LKC / 8);  // 16-byte vectors per stage
+  constexpr int NP = lp16_planes(NT), KCH = lp16_kchunk(NT);
+  constexpr int ASZ = NP * ROWS * RS, BSZ = NP * COLS * RS;   // 16-bit elements per stage
+  constexpr int AV = NP * ROWS * (LKC / 8), BV = NP * COLS * (LKC / 8);  // 16-byte vectors per stage
   constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
   constexpr int TSF = CP + 2;
   static_assert(ROWW % 16 == 0 && CP % 16 == 0 && LKC == 32, "row bases keep the swizzle of the lane's row");
   // Two staging buffers (one barrier per chunk).  The two-term form fits two
   // workgroups per CU (80 KB of LDS, registers for two waves per SIMD) and does
   // the trace epilogue one Cholesky vector of each wave at a time.
-  constexpr int NBUF = 2;
+  constexpr int NBUF = lp16_stages(NT);
   auto swz = [](int r) { return ((r >> 1) ^ (r >> 2)) & 3; };
-  extern __shared__ __bf16 bsm[];
-  __bf16 *sA = bsm, *sB = bsm + NBUF * ASZ;
+  extern __shared__ __attribute__((aligned(16))) unsigned char bsm_raw[];
+  E *bsm = reinterpret_cast<E *>(bsm_raw);
+  E *sA = bsm, *sB = bsm + NBUF * ASZ;
   // With LDS DMA (global_load_lds_dwordx4: lane L's 16 bytes land at the wave's
   // LDS base + 16 L) a stage is filled straight from memory, 1 KB (16 staged
   // rows) per wave instruction (sources below).
@@ -304,7 +415,9 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: LDS stage addresses stay scalar
   const int wy = wv / LWX, wx = wv - (wv / LWX) * LWX;
   const int g0 = gb * LWY * GC, w0 = wb * LWX;
-  const size_t aplane = (size_t)lp_padded_g(G) * NR * Kp, bplane = (size_t)W * CP * Kp;
+  // plane offsets: the next term, or (one-product form) the next LKC contraction indices
+  const size_t aplane = NT == 1 ? (size_t)LKC : (size_t)lp_padded_g(G) * NR * Kp;
+  const size_t bplane = NT == 1 ? (size_t)LKC : (size_t)W * CP * Kp;
 
   uint4 ra[APT], rb[BPT];
   auto load = [&](int q0) {
@@ -330,8 +443,8 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     }
   };
   auto store = [&](int buf) {
-    __bf16 *a = sA + buf * ASZ;
-    __bf16 *b = sB + buf * BSZ;
+    E *a = sA + buf * ASZ;
+    E *b = sB + buf * BSZ;
 #pragma unroll
     for (int r = 0; r < APT; ++r) {
       const int v = tid + r * kThreads;
@@ -374,22 +487,26 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     }
   }
   auto issue = [&](int q0, int buf) {
-    __bf16 *a = sA + buf * ASZ;
-    __bf16 *b = sB + buf * BSZ;
-    const __bf16 *la = LtB + q0, *tb = ThB + q0;
+    E *a = sA + buf * ASZ;
+    E *b = sB + buf * BSZ;
+    const E *la = LtB + q0, *tb = ThB + q0;
 #pragma unroll
     for (int r = 0; r < NIA; ++r) {
       const int blk = wv + 4 * r;
       if ((AV / 64) % 4 != 0 && blk >= AV / 64) break;       // uniform in the wave
-      const __bf16 *src = la + offa[r];
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(a + blk * 512), 16, 0, 0);
+      const E *src = la + offa[r];
+      // non-dependent pointer types: the host pass drops a template kernel whose
+      // LDS-DMA builtin takes template-typed pointers
+      __builtin_amdgcn_global_load_lds((void *)src, (__attribute__((address_space(3))) void *)((void *)(a + blk * 512)),
+                                       16, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < NIB; ++r) {
       const int blk = wv + 4 * r;
       if ((BV / 64) % 4 != 0 && blk >= BV / 64) break;       // uniform in the wave
-      const __bf16 *src = tb + offb[r];
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(b + blk * 512), 16, 0, 0);
+      const E *src = tb + offb[r];
+      __builtin_amdgcn_global_load_lds((void *)src, (__attribute__((address_space(3))) void *)((void *)(b + blk * 512)),
+                                       16, 0, 0);
     }
   };
 
@@ -399,10 +516,16 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 
-  const int nchunk = Kp / LKC;
+  const int nchunk = Kp / KCH;
+  // LDS copies per chunk of the wave that issues fewest (the partial vmcnt
+  // waits below count in these; a wave that issues more waits a little longer)
+  constexpr int CMIN = (AV / 64) / 4 + (BV / 64) / 4;
   if constexpr (DMA) {
-    issue(0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
+    // chunks 0 .. NBUF-2 in flight, then wait for chunk 0
+    for (int c = 0; c < NBUF - 1; ++c)
+      if (c < nchunk) issue(c * KCH, c);
+    if (NBUF > 2 && nchunk >= NBUF - 1) AFQMC_WAIT_VMCNT((NBUF - 2) * CMIN);
+    else __builtin_amdgcn_s_waitcnt(0);
   } else {
     load(0);
     store(0);
@@ -410,39 +533,65 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
   for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = NBUF == 2 ? (ch & 1) : 0;
+    const int buf = ch % NBUF;
     if constexpr (DMA) {
-      if (ch + 1 < nchunk) issue((ch + 1) * LKC, buf ^ 1);
+      // into the buffer read in chunk ch - 1 (every wave has passed the barrier after it)
+      if (ch + NBUF - 1 < nchunk) issue((ch + NBUF - 1) * KCH, (ch + NBUF - 1) % NBUF);
     } else if (ch + 1 < nchunk) {
-      load((ch + 1) * LKC);
+      load((ch + 1) * KCH);
     }
-    const __bf16 *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * (lk ^ swz(lr));
-    const __bf16 *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * (lk ^ swz(lr));
-    bf8v ah[RT], am[RT], bh[CT], bm[CT];
+    const E *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * (lk ^ swz(lr));
+    const E *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * (lk ^ swz(lr));
+    if constexpr (NT == 1) {
+#pragma unroll
+      for (int sub = 0; sub < NP; ++sub) {
+        v8 ah[RT], bh[CT];
+#pragma unroll
+        for (int i = 0; i < (RT > CT ? RT : CT); ++i) {
+          if (i < RT) ah[i] = *reinterpret_cast<const v8 *>(a + (sub * ROWS + i * 16) * RS);
+          if (i < CT) bh[i] = *reinterpret_cast<const v8 *>(b + (sub * COLS + i * 16) * RS);
+        }
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < CT; ++j) acc[i][j] = mfma16x16x32(ah[i], bh[j], acc[i][j]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (DMA) {
+        // this wave's copies of chunk ch + 1 have landed (later chunks' may not)
+        if (NBUF > 2 && ch + NBUF - 1 < nchunk) AFQMC_WAIT_VMCNT((NBUF - 2) * CMIN);
+        else __builtin_amdgcn_s_waitcnt(0);
+      } else if (ch + 1 < nchunk) {
+        store((ch + 1) % NBUF);
+      }
+      __syncthreads();
+      continue;
+    }
+    v8 ah[RT], am[RT], bh[CT], bm[CT];
     // the fragments of the first sweep (am x bh) are read first; the other
     // RT + CT reads are spread over that sweep's MFMAs (the group barriers
     // below), so an MFMA waits only on the reads it uses
 #pragma unroll
     for (int i = 0; i < (RT > CT ? RT : CT); ++i) {
-      if (i < RT) am[i] = *reinterpret_cast<const bf8v *>(a + (1 * ROWS + i * 16) * RS);
-      if (i < CT) bh[i] = *reinterpret_cast<const bf8v *>(b + (0 * COLS + i * 16) * RS);
+      if (i < RT) am[i] = *reinterpret_cast<const v8 *>(a + (1 * ROWS + i * 16) * RS);
+      if (i < CT) bh[i] = *reinterpret_cast<const v8 *>(b + (0 * COLS + i * 16) * RS);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < CT; ++j) bm[j] = *reinterpret_cast<const bf8v *>(b + (1 * COLS + j * 16) * RS);
+    for (int j = 0; j < CT; ++j) bm[j] = *reinterpret_cast<const v8 *>(b + (1 * COLS + j * 16) * RS);
 #pragma unroll
-    for (int i = 0; i < RT; ++i) ah[i] = *reinterpret_cast<const bf8v *>(a + (0 * ROWS + i * 16) * RS);
+    for (int i = 0; i < RT; ++i) ah[i] = *reinterpret_cast<const v8 *>(a + (0 * ROWS + i * 16) * RS);
     // one sweep over all accumulators per term, so dependent MFMAs are far
     // apart; the smallest terms first
 #define AFQMC_SWEEP(X, Y)                                                                         \
   _Pragma("unroll") for (int i = 0; i < RT; ++i) _Pragma("unroll") for (int j = 0; j < CT; ++j) \
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(X[i], Y[j], acc[i][j], 0, 0, 0);
+      acc[i][j] = mfma16x16x32(X[i], Y[j], acc[i][j]);
     if constexpr (NT == 3) {
-      bf8v al[RT], bl[CT];
+      v8 al[RT], bl[CT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) al[i] = *reinterpret_cast<const bf8v *>(a + (2 * ROWS + i * 16) * RS);
+      for (int i = 0; i < RT; ++i) al[i] = *reinterpret_cast<const v8 *>(a + (2 * ROWS + i * 16) * RS);
 #pragma unroll
-      for (int j = 0; j < CT; ++j) bl[j] = *reinterpret_cast<const bf8v *>(b + (2 * COLS + j * 16) * RS);
+      for (int j = 0; j < CT; ++j) bl[j] = *reinterpret_cast<const v8 *>(b + (2 * COLS + j * 16) * RS);
       AFQMC_SWEEP(al, bh)
       AFQMC_SWEEP(ah, bl)
       AFQMC_SWEEP(am, bm)
@@ -466,23 +615,44 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_exchange_bf16(con
     if constexpr (DMA) {
       __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into the other buffer have landed
     } else if (ch + 1 < nchunk) {
-      store(buf ^ 1);
+      store((ch + 1) % NBUF);
     }
     __syncthreads();
   }
 
+  if constexpr (NT == 1) {
+    // T = T0 + (scaled product) / (scale of the Cholesky vector x scale of the
+    // walker); T0 is stored transposed, T0t[g][j][i], so the real part of the
+    // lane's four rows i0..i0+3 at column j is one 16-byte load
+    const int g0w = g0 + wy * GC;
+    const float qs = qsc[min(w0 + wx, W - 1)];
+    const bool re = !(lr & 1);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int row0 = rt * 16 + 4 * lk;
+      const int gl = row0 / NR, i0 = row0 - gl * NR;
+      const float f = lsc[g0w + gl] * qs;
+      const float *t0 = T0 + (size_t)(g0w + gl) * NR * NR + i0;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int j = (ct * 16 + lr) >> 1;
+        f4v add = f4v{0.f, 0.f, 0.f, 0.f};
+        if (re) add = *reinterpret_cast<const f4v *>(t0 + j * NR);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[rt][ct][r] = fmaf(acc[rt][ct][r], f, add[r]);
+      }
+    }
+  }
   // each lane's partial traces (at most ROWW CP / 64 products) in FP32, the
   // sums over lanes and Cholesky vectors in FP64
   float pre = 0.f, pim = 0.f, dg[2] = {0.f, 0.f};
-  if constexpr (NT == 2) {
-    // one Cholesky vector of the wave at a time: U (two NR x (NR + 4) planes) per wave in LDS
-    float *sU = reinterpret_cast<float *>(bsm) + (size_t)wv * NR * (NR + 4) * 2;
+  if constexpr (NT <= 2) {
+    // one Cholesky vector of the wave at a time: S (two planes) per wave in LDS
+    float *sS = reinterpret_cast<float *>(bsm) + (size_t)wv * 2 * lp_s_plane<NR>();
 #pragma unroll
     for (int pass = 0; pass < GC; ++pass) {
-      lp_store_u<NR, CT, RT>(acc, sU, lane, pass);
-      __syncthreads();
-      lp_trace_u<NR, CT, RT>(acc, sU, lane, pre, pim, dg, pass);
-      if (pass + 1 < GC) __syncthreads();
+      lp_store_s<NR, CT, RT>(acc, sS, lane, pass);
+      lp_trace_s<NR, CT, RT>(acc, sS, lane, pre, pim, dg, pass);
     }
   } else {
     float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * ROWW * TSF;
@@ -580,12 +750,113 @@ __global__ __launch_bounds__(kThreads) void k_theta_to_bf16(const double2 *__res
   }
 }
 
+// ---- trial-split operands ------------------------------------------------------
+// power of two that brings a maximum modulus into [2^13, 2^14) (1 for 0 or a
+// non-finite maximum): well inside the FP16 and BF16 ranges, exact to undo
+__device__ __forceinline__ float pow2_scale(float mx) {
+  if (!(mx > 0.f) || !isfinite(mx)) return 1.f;
+  int e;
+  (void)frexpf(mx, &e);  // mx = m 2^e, m in [0.5, 1)
+  return ldexpf(1.f, 14 - e);
+}
+
+__device__ __forceinline__ float block_max(float v, float *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  float m = red[0];
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmaxf(m, red[k]);
+  __syncthreads();
+  return m;
+}
+
+// One workgroup per Cholesky vector g < G4 (the padded count): the scaled
+// 16-bit plane LtB[g][i][q] (q < Kp, zero for q >= M, i >= N or g >= G), its
+// inverse scale lsc[g], and T0 transposed, T0t[g][j][i] = sum_q Ltilde[i][q]
+// Psi[q][off + j] (zero outside i, j < N), from LtS[g][q][i] (FP64, rows padded
+// to NR).
+template <typename E>
+__global__ __launch_bounds__(kThreads) void k_lt_split(const double *__restrict__ LtS, const double *__restrict__ trial,
+                                                      int G, int M, int Nt, int off, int N, int NR, int Kp,
+                                                      E *__restrict__ LtB, float *__restrict__ T0,
+                                                      float *__restrict__ lsc) {
+  __shared__ float red[kThreads / 64];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const double *L = LtS + (size_t)g * M * NR;
+  float mx = 0.f;
+  if (g < G)
+    for (int e = tid; e < M * NR; e += blockDim.x) mx = fmaxf(mx, fabsf((float)L[e]));
+  const float sc = pow2_scale(block_max(mx, red));
+  if (tid == 0) lsc[g] = 1.f / sc;
+  for (int e = tid; e < NR * Kp; e += blockDim.x) {
+    const int i = e / Kp, q = e - (e / Kp) * Kp;
+    const double x = (g < G && q < M && i < N) ? L[(size_t)q * NR + i] : 0.0;
+    LtB[(size_t)g * NR * Kp + e] = (E)(float)(x * (double)sc);
+  }
+  for (int e = tid; e < NR * NR; e += blockDim.x) {
+    const int j = e / NR, i = e - (e / NR) * NR;      // stored transposed: T0t[g][j][i]
+    double a = 0.0;
+    if (g < G && i < N && j < N)
+      for (int q = 0; q < M; ++q) a = fma(L[(size_t)q * NR + i], trial[(size_t)q * Nt + off + j], a);
+    T0[(size_t)g * NR * NR + e] = (float)a;
+  }
+}
+
+// Q = Theta - Psi of one spin block (re/im interleaved over CP = 2 NR columns,
+// zero past 2N), scaled by a power of two per walker and written K-contiguous,
+// ThB[w][c][q] (q < Kp, zero for q >= M).  First one workgroup per walker finds
+// max |Q| and stores the inverse scale in qsc[w]; then one workgroup per
+// (32 rows q, walker) transposes its rows through LDS.
+__global__ __launch_bounds__(kThreads) void k_q_max(const double2 *__restrict__ theta, const double *__restrict__ trial,
+                                                   int M, int Nt, int off, int N, float *__restrict__ qsc) {
+  __shared__ float red[kThreads / 64];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  const double2 *th = theta + (size_t)w * M * Nt + off;
+  float mx = 0.f;
+  for (int e = tid; e < M * N; e += blockDim.x) {
+    const int q = e / N, j = e - (e / N) * N;
+    const double2 z = th[(size_t)q * Nt + j];
+    mx = fmaxf(mx, fmaxf(fabsf((float)(z.x - trial[(size_t)q * Nt + off + j])), fabsf((float)z.y)));
+  }
+  const float sc = pow2_scale(block_max(mx, red));
+  if (tid == 0) qsc[w] = 1.f / sc;
+}
+
+template <typename E>
+__global__ __launch_bounds__(kThreads) void k_q_split(const double2 *__restrict__ theta,
+                                                     const double *__restrict__ trial, int M, int Nt, int off, int N,
+                                                     int CP, int Kp, const float *__restrict__ qsc,
+                                                     E *__restrict__ ThB) {
+  extern __shared__ float qsm[];  // [32][CP + 1]
+  const int w = blockIdx.y, q0 = blockIdx.x * 32, tid = threadIdx.x;
+  const double2 *th = theta + (size_t)w * M * Nt + off;
+  const double sc = 1.0 / (double)qsc[w];   // a power of two
+  for (int e = tid; e < 32 * CP; e += blockDim.x) {
+    const int qq = e / CP, c = e - (e / CP) * CP;
+    const int q = q0 + qq;
+    double v = 0.0;
+    if (q < M && c < 2 * N) {
+      const double2 z = th[(size_t)q * Nt + (c >> 1)];
+      v = (c & 1) ? z.y : z.x - trial[(size_t)q * Nt + off + (c >> 1)];
+    }
+    qsm[qq * (CP + 1) + c] = (float)(v * sc);
+  }
+  __syncthreads();
+  for (int e = tid; e < 32 * CP; e += blockDim.x) {
+    const int c = e / 32, qq = e - (e / 32) * 32;
+    ThB[((size_t)w * CP + c) * Kp + q0 + qq] = (E)qsm[qq * (CP + 1) + c];
+  }
+}
+
 // ---- dispatch -------------------------------------------------------------------
 namespace {
 using F32Kernel = void (*)(const float *, const float *, int, int, int, int, int, int, double2 *, double2 *, int,
                            int, int);
 using BFKernel = void (*)(const __bf16 *, const __bf16 *, int, int, int, int, int, int, double2 *, double2 *, int,
-                          int, int);
+                          int, int, const float *, const float *, const float *);
+using HKernel = void (*)(const _Float16 *, const _Float16 *, int, int, int, int, int, int, double2 *, double2 *, int,
+                         int, int, const float *, const float *, const float *);
 
 F32Kernel pick_f32(int nr) {
   switch (nr) {
@@ -610,11 +881,51 @@ BFKernel pick_bf_nt(int nr) {
     default: return nullptr;
   }
 }
-// bfloat16 terms per operand of a split-BF16 precision (0: not a split form)
-int bf_terms(int precision) {
-  return precision == AFQMC_BF16X3_CONTRACT ? 3 : precision == AFQMC_BF16X2_CONTRACT ? 2 : 0;
+HKernel pick_h1(int nr) {
+  switch (nr) {
+    case 8: return k_exchange_bf16<8, 1, _Float16>;
+    case 16: return k_exchange_bf16<16, 1, _Float16>;
+    case 24: return k_exchange_bf16<24, 1, _Float16>;
+    case 32: return k_exchange_bf16<32, 1, _Float16>;
+    case 40: return k_exchange_bf16<40, 1, _Float16>;
+    case 48: return k_exchange_bf16<48, 1, _Float16>;
+    default: return nullptr;
+  }
 }
-BFKernel pick_bf(int nr, int nt) { return nt == 3 ? pick_bf_nt<3>(nr) : nt == 2 ? pick_bf_nt<2>(nr) : nullptr; }
+// 16-bit terms per operand of a 16-bit precision (0: not one): the split-BF16
+// forms, or one term of the trial split
+int bf_terms(int precision) {
+  return precision == AFQMC_BF16X3_CONTRACT ? 3
+         : precision == AFQMC_BF16X2_CONTRACT ? 2
+         : (precision == AFQMC_FP16_TSPLIT_CONTRACT || precision == AFQMC_BF16_TSPLIT_CONTRACT) ? 1
+                                                                                                : 0;
+}
+bool tsplit(int precision) { return bf_terms(precision) == 1; }
+bool f16(int precision) { return precision == AFQMC_FP16_TSPLIT_CONTRACT; }
+BFKernel pick_bf(int nr, int nt) {
+  return nt == 3 ? pick_bf_nt<3>(nr) : nt == 2 ? pick_bf_nt<2>(nr) : nt == 1 ? pick_bf_nt<1>(nr) : nullptr;
+}
+const void *pick_lp16(int precision, int nr) {
+  return f16(precision) ? reinterpret_cast<const void *>(pick_h1(nr))
+                        : reinterpret_cast<const void *>(pick_bf(nr, bf_terms(precision)));
+}
+size_t pad256(size_t b) { return (b + 255) / 256 * 256; }
+// byte layout of the trial-split operands: lhs = plane | T0 | lsc, rhs = plane | qsc
+struct SplitLayout {
+  size_t lplane, t0, lsc, lhs, rplane, qsc, rhs;
+};
+SplitLayout split_layout(int G, int M, int W, int nr) {
+  const size_t kp = lp16_kp(1, M), g4 = lp_padded_g(G), cp = 2 * (size_t)nr;
+  SplitLayout l;
+  l.lplane = 0;
+  l.t0 = pad256(g4 * nr * kp * 2);
+  l.lsc = l.t0 + pad256(g4 * nr * nr * sizeof(float));
+  l.lhs = l.lsc + pad256(g4 * sizeof(float));
+  l.rplane = 0;
+  l.qsc = pad256((size_t)W * cp * kp * 2);
+  l.rhs = l.qsc + pad256((size_t)W * sizeof(float));
+  return l;
+}
 size_t lds_f32(int nr) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
   const size_t stage = 2ull * (LKC * LWY * roww + LWX * LKC * cp) * sizeof(float);
@@ -623,9 +934,9 @@ size_t lds_f32(int nr) {
 }
 size_t lds_bf(int nr, int nt) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
-  const size_t nbuf = 2;
-  const size_t stage = nbuf * nt * (LWY * roww + LWX * cp) * LKC * sizeof(__bf16);
-  const size_t epi = nt == 2 ? 4ull * nr * (nr + 4) * 2 * sizeof(float) : 4ull * roww * (cp + 2) * sizeof(float);
+  const size_t nbuf = lp16_stages(nt);
+  const size_t stage = nbuf * lp16_planes(nt) * (LWY * roww + LWX * cp) * LKC * sizeof(__bf16);
+  const size_t epi = nt <= 2 ? 4ull * 2 * (nr * (nr + 4) + 8) * sizeof(float) : 4ull * roww * (cp + 2) * sizeof(float);
   return stage > epi ? stage : epi;
 }
 }  // namespace
@@ -633,15 +944,24 @@ size_t lds_bf(int nr, int nt) {
 bool lp_exchange_supported(int precision, int nr) {
   if (precision == AFQMC_FP32_CONTRACT) return pick_f32(nr) && lds_f32(nr) <= 160 * 1024;
   const int nt = bf_terms(precision);
-  if (nt) return pick_bf(nr, nt) && lds_bf(nr, nt) <= 160 * 1024;
+  if (nt) return pick_lp16(precision, nr) && lds_bf(nr, nt) <= 160 * 1024;
   return false;
 }
 
 size_t lp_operand_elems(int precision, int G, int M, int W, int nr, bool lhs) {
-  const int kp = ((M + LKC - 1) / LKC) * LKC;
+  const int kp = lp16_kp(bf_terms(precision), M);
   if (precision == AFQMC_FP32_CONTRACT) return lhs ? (size_t)G * M * nr : (size_t)W * M * 2 * nr;
   const size_t nt = bf_terms(precision);
   return lhs ? nt * lp_padded_g(G) * nr * kp : nt * W * 2 * nr * kp;
+}
+
+size_t lp_operand_bytes(int precision, int G, int M, int W, int nr, bool lhs) {
+  if (tsplit(precision)) {
+    const SplitLayout l = split_layout(G, M, W, nr);
+    return lhs ? l.lhs : l.rhs;
+  }
+  const size_t esz = precision == AFQMC_FP32_CONTRACT ? 4 : 2;
+  return esz * lp_operand_elems(precision, G, M, W, nr, lhs);
 }
 
 bool lp_operands_addressable(int precision, int G, int M, int W, int nr) {
@@ -657,8 +977,20 @@ hipError_t lp_prepare_lhs(const System &s, int spin, hipStream_t st) {
     const long n = (long)s.G * s.M * p.NR;
     hipLaunchKernelGGL(k_lt_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtS[spin], n,
                        static_cast<float *>(s.lp_lhs[spin]));
+  } else if (tsplit(s.precision)) {
+    const int kp = lp16_kp(bf_terms(s.precision), s.M);
+    const SplitLayout l = split_layout(s.G, s.M, s.W, p.NR);
+    unsigned char *base = static_cast<unsigned char *>(s.lp_lhs[spin]);
+    float *T0 = reinterpret_cast<float *>(base + l.t0), *lsc = reinterpret_cast<float *>(base + l.lsc);
+    const int off = spin ? s.Na : 0;
+    if (f16(s.precision))
+      hipLaunchKernelGGL(k_lt_split<_Float16>, dim3(lp_padded_g(s.G)), dim3(kThreads), 0, st, s.LtS[spin], s.trial,
+                         s.G, s.M, s.Nt, off, p.N, p.NR, kp, reinterpret_cast<_Float16 *>(base), T0, lsc);
+    else
+      hipLaunchKernelGGL(k_lt_split<__bf16>, dim3(lp_padded_g(s.G)), dim3(kThreads), 0, st, s.LtS[spin], s.trial,
+                         s.G, s.M, s.Nt, off, p.N, p.NR, kp, reinterpret_cast<__bf16 *>(base), T0, lsc);
   } else {
-    const int kp = ((s.M + LKC - 1) / LKC) * LKC;
+    const int kp = lp16_kp(bf_terms(s.precision), s.M);
     const long n = (long)lp_padded_g(s.G) * p.NR * kp;
     hipLaunchKernelGGL(bf_terms(s.precision) == 3 ? k_lt_to_bf16<3> : k_lt_to_bf16<2>,
                        dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtS[spin], s.G, s.M, p.NR, kp,
@@ -676,8 +1008,8 @@ hipError_t lp_enable_lds(const System &s) {
       e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_f32(p.NR)),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_f32(p.NR));
     else
-      e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_bf(p.NR, bf_terms(s.precision))),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bf(p.NR, bf_terms(s.precision)));
+      e = hipFuncSetAttribute(pick_lp16(s.precision, p.NR), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_bf(p.NR, bf_terms(s.precision)));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -692,8 +1024,23 @@ hipError_t lp_prepare_rhs(const System &s, const double2 *theta, int W, int spin
     const long n = (long)W * s.M * CP;
     hipLaunchKernelGGL(k_theta_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, W, s.M, s.Nt,
                        off, p.N, CP, static_cast<float *>(s.lp_rhs[spin]));
+  } else if (tsplit(s.precision)) {
+    const int kp = lp16_kp(bf_terms(s.precision), s.M);
+    const SplitLayout l = split_layout(s.G, s.M, s.W, p.NR);
+    unsigned char *base = static_cast<unsigned char *>(s.lp_rhs[spin]);
+    float *qsc = reinterpret_cast<float *>(base + l.qsc);
+    const size_t lds = 32ull * (CP + 1) * sizeof(float);
+    hipLaunchKernelGGL(k_q_max, dim3(W), dim3(kThreads), 0, st, theta, s.trial, s.M, s.Nt, off, p.N, qsc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (f16(s.precision))
+      hipLaunchKernelGGL(k_q_split<_Float16>, dim3(kp / 32, W), dim3(kThreads), lds, st, theta, s.trial, s.M, s.Nt,
+                         off, p.N, CP, kp, qsc, reinterpret_cast<_Float16 *>(base));
+    else
+      hipLaunchKernelGGL(k_q_split<__bf16>, dim3(kp / 32, W), dim3(kThreads), lds, st, theta, s.trial, s.M, s.Nt,
+                         off, p.N, CP, kp, qsc, reinterpret_cast<__bf16 *>(base));
   } else {
-    const int kp = ((s.M + LKC - 1) / LKC) * LKC;
+    const int kp = lp16_kp(bf_terms(s.precision), s.M);
     hipLaunchKernelGGL(bf_terms(s.precision) == 3 ? k_theta_to_bf16<3> : k_theta_to_bf16<2>, dim3(kp / 32, W),
                        dim3(kThreads), 32 * (CP + 1) * sizeof(float), st, theta, W, s.M, s.Nt, off, p.N, CP, kp,
                        static_cast<__bf16 *>(s.lp_rhs[spin]));
@@ -712,11 +1059,25 @@ hipError_t launch_exchange_lp(const System &s, int W, int spin, hipStream_t st, 
                        static_cast<const float *>(s.lp_lhs[spin]), static_cast<const float *>(s.lp_rhs[spin]), s.M,
                        p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart, ngb, nwb, s.ex_group);
   } else {
-    const int kp = ((s.M + LKC - 1) / LKC) * LKC;
+    const int kp = lp16_kp(bf_terms(s.precision), s.M);
     const int nt = bf_terms(s.precision);
-    hipLaunchKernelGGL(pick_bf(p.NR, nt), grid, dim3(kThreads), lds_bf(p.NR, nt), st,
-                       static_cast<const __bf16 *>(s.lp_lhs[spin]), static_cast<const __bf16 *>(s.lp_rhs[spin]), kp,
-                       p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart, ngb, nwb, s.ex_group);
+    const float *T0 = nullptr, *lsc = nullptr, *qsc = nullptr;
+    if (tsplit(s.precision)) {
+      const SplitLayout l = split_layout(s.G, s.M, s.W, p.NR);
+      const unsigned char *lb = static_cast<const unsigned char *>(s.lp_lhs[spin]);
+      const unsigned char *rb = static_cast<const unsigned char *>(s.lp_rhs[spin]);
+      T0 = reinterpret_cast<const float *>(lb + l.t0);
+      lsc = reinterpret_cast<const float *>(lb + l.lsc);
+      qsc = reinterpret_cast<const float *>(rb + l.qsc);
+    }
+    if (f16(s.precision))
+      hipLaunchKernelGGL(pick_h1(p.NR), grid, dim3(kThreads), lds_bf(p.NR, nt), st,
+                         static_cast<const _Float16 *>(s.lp_lhs[spin]), static_cast<const _Float16 *>(s.lp_rhs[spin]),
+                         kp, p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart, ngb, nwb, s.ex_group, T0, lsc, qsc);
+    else
+      hipLaunchKernelGGL(pick_bf(p.NR, nt), grid, dim3(kThreads), lds_bf(p.NR, nt), st,
+                         static_cast<const __bf16 *>(s.lp_lhs[spin]), static_cast<const __bf16 *>(s.lp_rhs[spin]), kp,
+                         p.N, s.G, W, s.ex_stride, spin, s.ekpart, vbpart, ngb, nwb, s.ex_group, T0, lsc, qsc);
   }
   return hipGetLastError();
 }

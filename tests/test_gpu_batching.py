@@ -156,7 +156,7 @@ def test_graph_replays_match_eager_each_step():
         graph.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2, 3], ids=["fp64", "fp32", "bf16x3", "bf16x2"])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3, 4], ids=["fp64", "fp32", "bf16x3", "bf16x2", "fp16t"])
 def test_exchange_launch_shape_does_not_change_results(precision):
     """Walker tiling (FP64 kernel) and tile order (all exchange kernels) are
     speed knobs only: results are bitwise equal for every choice."""

@@ -1,7 +1,8 @@
-"""Precision form: exchange and force bias in FP32 or in split BF16 (three
-bfloat16 terms and six products, or two terms and three products; FP32
-accumulation); overlaps, LU, propagation, weights and re-orthogonalisation in
-FP64.
+"""Precision form: exchange and force bias in FP32, in split BF16 (three
+bfloat16 terms and six products, or two terms and three products), or in one
+FP16 / BF16 product of the walkers' departure from the trial with the trial's
+part exact (the trial split); FP32 accumulation; overlaps, LU, propagation,
+weights and re-orthogonalisation in FP64.
 
 Bar: per-walker local energies within 0.1 mHa of the FP64 path (and of the
 oracle) on identical walker states; the mixed estimator of a short trajectory
@@ -16,7 +17,7 @@ from pairs import Pair, cmp_rel
 
 pytestmark = pytest.mark.gpu
 MHA = 1e-3
-FORMS = {"fp32": 1, "bf16x3": 2, "bf16x2": 3}
+FORMS = {"fp32": 1, "bf16x3": 2, "bf16x2": 3, "fp16t": 4, "bf16t": 5}
 
 
 def ctx_for(p, precision):
@@ -53,8 +54,7 @@ def test_energy_error_on_identical_walkers(form, spec, W):
             oe = np.array(O.local_energy(p.ham, phis[k]))
             assert np.abs(elp[k] - oe).max() < 0.1 * MHA
         # the reduced form is not silently the FP64 path
-        if form == "fp32":
-            assert err[:, 2].max() > 0.0
+        assert err[:, 2].max() > 0.0
     finally:
         ctx.close()
         p.close()
@@ -113,6 +113,21 @@ def test_mixed_estimator_of_a_trajectory(form):
         d = np.abs(res[1] - res[0])
         print(f"{form}: mixed-estimator difference over 10 steps max {d.max():.2e} Ha")
         assert d.max() < 0.1 * MHA
+    finally:
+        ctx.close()
+        p.close()
+
+
+@pytest.mark.parametrize("form", ["fp16t", "bf16t"])
+def test_trial_split_at_the_trial_is_exact_to_fp32(form):
+    """Walkers equal to the trial (Q = 0): the split forms reduce to T = T0,
+    set up once in FP32, so the energies match FP64 to FP32 rounding."""
+    p = Pair(gi.SystemSpec(100, 10, 9, 200, tau=75.0, seed=11), 6, 0.005)
+    ctx = ctx_for(p, FORMS[form])
+    try:
+        phis = gi.initial_walkers(p.trial, 6)
+        err = np.abs(energies(p, ctx, phis) - energies(p, p.ctx, phis))
+        assert err.max() < 1e-6
     finally:
         ctx.close()
         p.close()
