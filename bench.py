@@ -7,12 +7,13 @@ re-orthogonalisation every 5th step, for every walker of the headline workload
 (M=400 orbitals, 40+40 electrons, 1600 Cholesky vectors, 256 walkers, dt=0.005;
 seeded synthetic Hamiltonian, trial and fields, resident in HBM before timing).
 
-By default the FP64 path and the precision form (exchange and force bias in
-split BF16 with two bfloat16 terms per operand and three products, everything
-else FP64) are both timed; the JSON line reports the
-precision form's walker-steps/s, its speed-up over FP64, and its per-walker
-energy error against the FP64 path on identical walker states (the bar is
-0.1 mHa).  The roofline object is the dominant kernel (exchange) of the reported
+By default the FP64 path and the precision form (exchange and force bias as
+the trial split: the trial's part of the Green's function exact, the walker's
+departure from it in one FP16 product with FP32 accumulation; everything else
+FP64) are both timed, with the split-BF16 form (two bfloat16 terms per operand,
+three products) beside them; the JSON line reports the precision form's
+walker-steps/s, its speed-up over FP64, and its per-walker energy error against
+the FP64 path on identical walker states (the bar is 0.1 mHa).  The roofline object is the dominant kernel (exchange) of the reported
 path, timed by the library's HIP-event phase timers inside the timed region.
 """
 from __future__ import annotations
@@ -74,7 +75,7 @@ def parse_args(argv=None):
                          "one after another, of one set context over internal streams, and of that context "
                          "replaying a hipGraph); cv: the learned control variate at the headline shape "
                          "(training on the path's own trajectory, then full exchange vs the 1/8 subset)")
-    ap.add_argument("--precision", default="bf16x2", choices=["fp64", "fp32", "bf16x3", "bf16x2", "fp16t", "bf16t"],
+    ap.add_argument("--precision", default="fp16t", choices=["fp64", "fp32", "bf16x3", "bf16x2", "fp16t", "bf16t"],
                     help="path reported in the JSON line (the FP64 path is timed too, for the speed-up)")
     ap.add_argument("--prop-precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the propagation (V_HS planes and Taylor terms) of the reported path")
@@ -415,7 +416,8 @@ def stat_error_leg(A, torch, spec, nblocks=20, block_steps=10, equil_blocks=4, c
     xb = torch.randn((nblocks, block_steps, W, G), dtype=torch.float64, device="cuda", generator=gen)
     offs = torch.rand((nblocks, 1), dtype=torch.float64, device="cuda", generator=gen)
     forms = {"fp64": dict(precision=A.FP64), "bf16x2": dict(precision=A.BF16X2_CONTRACT),
-             "bf16x2+fp32prop": dict(precision=A.BF16X2_CONTRACT, prop_precision=A.FP32_CONTRACT),
+             "fp16t": dict(precision=A.FP16_TSPLIT_CONTRACT),
+             "fp16t+fp32prop": dict(precision=A.FP16_TSPLIT_CONTRACT, prop_precision=A.FP32_CONTRACT),
              "cv_fp64": dict(precision=A.FP64, ex_mode=A.EX_CV)}
     series, rates, extra = {}, {}, {}
     for name, kw in forms.items():
@@ -711,10 +713,15 @@ def main(argv=None):
     p32_ok = s.nbasis % 4 == 0 and s.nalpha + s.nbeta <= 96
     if rep_key != "fp64" and not prop32 and not args.no_prop32_leg and p32_ok:
         forms.append(p32_key)
+    # the split-BF16 form beside a trial-split one (the robust form at three products)
+    alt_key = "bf16x2" if args.precision in ("fp16t", "bf16t") and not prop32 else None
+    if alt_key:
+        forms.append(alt_key)
     ctxs, runs = {}, {}
     for form in forms:
-        opt = A.default_options(precision=PRECISION_CODE[args.precision if form in (rep_key, p32_key) else "fp64"])
-        if form == p32_key:
+        prec_name = form.split("+")[0]
+        opt = A.default_options(precision=PRECISION_CODE[prec_name])
+        if form.endswith("+fp32prop"):
             opt.prop_precision = A.FP32_CONTRACT
         ctxs[form] = A.setup_hamiltonian(sysin, opt)
         runs[form] = time_path(A, torch, ctxs[form], spec, trial, xs, args)
@@ -733,7 +740,9 @@ def main(argv=None):
     out = {"metric": METRIC_FREE if free else METRIC, "value": round(value, 2), "unit": "walker-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": ("f64" if rep == "fp64" else f"{rep} (exchange, force bias)") +
+           "dtype": ("f64" if rep == "fp64" else
+                     ("f16 (trial-split exchange, force bias)" if rep == "fp16t" else
+                      f"{rep} (exchange, force bias)")) +
                     (" + f32 (V_HS, Taylor terms)" if prop32 else "") + ("" if rep_key == "fp64" else " + f64 (rest)"),
            "data": "synthetic (seeded generator: random symmetric h and Cholesky vectors scaled by "
                    "exp(-g/tau)/M, trial = lowest orbitals of a Fock-like matrix, N(0,1) fields)",
@@ -785,6 +794,23 @@ def main(argv=None):
             "energy_error_vs_fp64_ha": {"max": float(dq.max()), "bar": 1e-4, "within_bar": bool(dq.max() <= 1e-4)},
             "mixed_energy_difference_vs_fp64_ha": abs(q["mixed_energy"] - runs["fp64"]["mixed_energy"]),
             "note": "the reported form with V_HS and the Taylor terms in FP32 as well (the paper's mixed precision)"}
+    if alt_key:
+        q = runs[alt_key]
+        e_q = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        e_64 = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+        A.local_energy(ctxs[alt_key], q["walkers"], e_q)
+        A.local_energy(ctxs["fp64"], q["walkers"], e_64)
+        torch.cuda.synchronize()
+        dq = np.abs(e_q.cpu().numpy()[:, 0] - e_64.cpu().numpy()[:, 0])
+        qv = W * args.steps / (q["total_ms"] * 1e-3)
+        out[f"{alt_key}_path"] = {
+            "value": round(qv, 2), "ms_per_step": round(q["total_ms"] / args.steps, 4),
+            "speedup_vs_fp64": round(qv / (W * args.steps / (runs["fp64"]["total_ms"] * 1e-3)), 3),
+            "energy_error_vs_fp64_ha": {"max": float(dq.max()), "bar": 1e-4, "within_bar": bool(dq.max() <= 1e-4)},
+            "mixed_energy_difference_vs_fp64_ha": abs(q["mixed_energy"] - runs["fp64"]["mixed_energy"]),
+            "roofline": exchange_roofline(alt_key, q["phases"], M, s, G, W, spec.name),
+            "note": "split BF16, two terms per operand and three products: accurate whatever the walkers' "
+                    "distance from the trial"}
     if args.phases:
         for form in forms:
             print(f"-- {form}", file=sys.stderr)

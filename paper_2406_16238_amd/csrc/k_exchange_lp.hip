@@ -95,65 +95,6 @@ __device__ __forceinline__ void lp_trace(const f4v (&acc)[RT][CT], const float *
       }
 }
 
-// Trace epilogue of the two-term form, one Cholesky vector (pass) of the wave
-// at a time.  T^g goes to LDS as two planes, Re and Im, of U[j][i] = T^g_ij at
-// row stride NR + 4: a lane's four accumulator rows i0..i0+3 of column (j, re|im)
-// are one 16-byte store, and the partner T^g_ji of an entry is two 4-byte reads
-// at offsets fixed at compile time, so the epilogue is almost free of VALU work
-// (a wave64 VALU instruction costs four cycles of the SIMD).  Rows of one tile
-// belong to one Cholesky vector unless the tile straddles two (NR % 16 != 0);
-// in that tile each lane's four rows still share one.
-template <int NR, int CT, int RT>
-__device__ __forceinline__ void lp_store_u(const f4v (&acc)[RT][CT], float *sU, int lane, int pass) {
-  constexpr int CS = NR + 4;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int sidx = (lr & 1) * NR * CS + (lr >> 1) * CS + 4 * lk - pass * NR;
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
-    if (glo == ghi && glo != pass) continue;
-    const bool mine = glo == ghi || (rt * 16 + 4 * lk) / NR == pass;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-      if (mine) *reinterpret_cast<f4v *>(sU + sidx + ct * 8 * CS + rt * 16) = acc[rt][ct];
-  }
-}
-
-template <int NR, int CT, int RT>
-__device__ __forceinline__ void lp_trace_u(const f4v (&acc)[RT][CT], const float *sU, int lane, float &pre,
-                                           float &pim, float *dg, int pass) {
-  constexpr int CS = NR + 4;
-  const int lr = lane & 15, lk = lane >> 4;
-  const bool odd = lr & 1;
-  const int bidx = (4 * lk - pass * NR) * CS + (lr >> 1);   // + (rt 16 + r) CS + 8 ct: U[i][j], row i of the pass
-  float a0 = 0.f, a1 = 0.f;                                 // sum of v Re T_ji, sum of v Im T_ji
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
-    if (glo == ghi && glo != pass) continue;
-    const bool mine = glo == ghi || (rt * 16 + 4 * lk) / NR == pass;
-    if (!mine) continue;
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int off = bidx + (rt * 16 + r) * CS + ct * 8;
-        const float v = acc[rt][ct][r];
-        a0 = fmaf(v, sU[off], a0);
-        a1 = fmaf(v, sU[NR * CS + off], a1);
-      }
-  }
-  // the lane holds Re T_ij (even lr) or Im T_ij (odd lr)
-  pre += odd ? -a1 : a0;
-  pim += odd ? a0 : a1;
-  // diagonal, in the parity convention of lp_finish: lane l adds Re (l even)
-  // or Im (l odd) of T_ii, i = l / 2
-  for (int l = lane; l < 2 * NR; l += 64) {
-    const int i = l >> 1;
-    dg[pass] += sU[(l & 1) * NR * CS + i * CS + i];
-  }
-}
-
 // Trace epilogue of the 16-bit forms, one Cholesky vector (pass) of the wave at
 // a time, through LDS in natural order: S[i][j] = T_ij as two planes, Re and Im,
 // at row stride NR + 4, the Im plane 8 words past the Re plane (so the 64 lanes

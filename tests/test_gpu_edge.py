@@ -59,7 +59,7 @@ def test_fused_step_with_empty_beta_block():
         p.close()
 
 
-@pytest.mark.parametrize("precision", [1, 3], ids=["fp32", "bf16x2"])
+@pytest.mark.parametrize("precision", [1, 3, 4], ids=["fp32", "bf16x2", "fp16t"])
 def test_reduced_precision_with_empty_beta_block(precision):
     """The reduced-precision exchange skips the empty block (its vbias part is
     zero) and stays within 0.1 mHa of the FP64 energies."""
@@ -110,11 +110,12 @@ def test_free_projection_with_empty_beta_block():
         p.close()
 
 
-def test_split_bf16_rejects_blocks_wider_than_48():
+@pytest.mark.parametrize("precision", [3, 4, 5], ids=["bf16x2", "fp16t", "bf16t"])
+def test_16bit_forms_reject_blocks_wider_than_48(precision):
     from paper_2406_16238_amd import afqmc as A
     spec = gi.SystemSpec(64, 56, 56, 128, tau=50.0, seed=25)
     h1, chol, ecore, trial = gi.make_system(spec)
     with pytest.raises(A.AfqmcError) as err:
         A.setup_hamiltonian(A.SystemInput(h1, chol, ecore, trial, 56, 56, 2, 0.01),
-                            A.default_options(precision=A.BF16X2_CONTRACT))
+                            A.default_options(precision=precision))
     assert err.value.status == A.ERR_UNSUPPORTED
