@@ -389,7 +389,7 @@ def train_cv_network(A, torch, ctx, trial, W, G, nsteps, epochs, seed0=5000):
         gen.manual_seed(seed0 + k)
         x.normal_(generator=gen)
         A.step(ctx, w, x, e, reortho=(k + 1) % 5 == 0)
-        f = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+        f = torch.empty((W, A.CV_NFEAT), dtype=torch.float64, device="cuda")
         q = torch.empty(W, dtype=torch.complex128, device="cuda")
         A.cv_collect(ctx, w, f, q)
         feats.append(f)
@@ -534,7 +534,7 @@ def cv_leg(args, system):
     feats, eks = [], []
 
     def grab(k):
-        f = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+        f = torch.empty((W, A.CV_NFEAT), dtype=torch.float64, device="cuda")
         q = torch.empty(W, dtype=torch.complex128, device="cuda")
         A.cv_collect(ctx, w, f, q)
         feats.append(f)
@@ -550,7 +550,7 @@ def cv_leg(args, system):
     # estimator at fixed walkers: exact value from the full exchange, then R draws
     wt = w.weight.cpu().numpy()
     om = wt / wt.sum()
-    fx = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+    fx = torch.empty((W, A.CV_NFEAT), dtype=torch.float64, device="cuda")
     ex = torch.empty(W, dtype=torch.complex128, device="cuda")
     A.cv_collect(ctx, w, fx, ex)
     exact = float(np.sum(om * (fx[:, 0].cpu().numpy() + ex.cpu().numpy().real)))   # Re EJ + Re EK
@@ -568,7 +568,7 @@ def cv_leg(args, system):
     # keep only the target normalisation's mean), and plain subsampling (f = 0)
     A.cv_set_params(ctx, zero, norm)
     cmd = draws(args.cv_draws)
-    A.cv_set_params(ctx, zero, torch.tensor([0.0] * 8 + [1.0] * 8 + [0.0, 0.0, 1.0, 1.0], dtype=torch.float64,
+    A.cv_set_params(ctx, zero, torch.tensor([0.0] * A.CV_NFEAT + [1.0] * A.CV_NFEAT + [0.0, 0.0, 1.0, 1.0], dtype=torch.float64,
                                             device="cuda"))
     pld = draws(args.cv_draws)
     A.cv_set_params(ctx, params, norm)

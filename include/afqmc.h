@@ -290,20 +290,23 @@ afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w,
  * estimator is unbiased given the walkers (weights never depend on energies).
  * W <= 4096 in this mode (AFQMC_ERR_UNSUPPORTED otherwise).
  *
- * Features (double [W][8]): Re EJ, Im EJ, Re E1, Im E1, sum_g |vbias_g - l_g|^2,
- * Re sum_g (vbias_g - l_g)^2, cos and sin of arg <Psi_T|phi>.
+ * Features (double [W][10]): Re EJ, Im EJ, Re E1, Im E1, sum_g |vbias_g - l_g|^2,
+ * Re sum_g (vbias_g - l_g)^2, cos and sin of arg <Psi_T|phi>, and Re and Im of
+ * sum_s Tr(K_s Theta_s) with K_s = sum_g (Ltilde^{g s} Psi_s) Ltilde^{g s}: the
+ * exchange energy to first order in the walker's departure from the trial,
+ * EK(Psi) - sum_s Tr(K_s (Theta_s - Psi_s)), at the cost of a one-body energy.
  * Network (FP32): standardised features -> tanh(W1 x + b1) (128) ->
  * tanh(W2 h + b2) (128) -> W3 h + b3 = standardised (Re EK, Im EK).
- * Parameters: float [AFQMC_CV_NPARAMS] = W1 [128][8], b1 [128], W2 [128][128],
+ * Parameters: float [AFQMC_CV_NPARAMS] = W1 [128][10], b1 [128], W2 [128][128],
  * b2 [128], W3 [2][128], b3 [2] (row-major, (out, in)); normalisation:
- * double [AFQMC_CV_NNORM] = feature means [8], deviations [8], target means
+ * double [AFQMC_CV_NNORM] = feature means [10], deviations [10], target means
  * [2], deviations [2].  At set-up the weights are Glorot-uniform from a fixed
  * seed, the biases zero and the normalisation the identity.  Each system of a
  * context has its own network.
  *
  * afqmc_cv_collect: for every walker, features and the exact EK (full
  *   exchange in the context's precision), as training samples:
- *   feat_out[s] device double [W][8], ek_out[s] device double2 [W].
+ *   feat_out[s] device double [W][10], ek_out[s] device double2 [W].
  * afqmc_cv_train: sets the normalisation from the n samples (means and
  *   population deviations), then runs `epochs` passes of Adam (beta1 0.9,
  *   beta2 0.999, eps 1e-8, bias-corrected, moments reset at the start) over
@@ -313,18 +316,18 @@ afqmc_status afqmc_force_bias(afqmc_ctx *ctx, const afqmc_walkers *w,
  * afqmc_cv_set_params / afqmc_cv_get_params: device copies of the parameters
  *   and normalisation (either pointer may be NULL); set resets the Adam moments.
  * afqmc_cv_predict: f_out device double2 [n] = the network's EK for raw
- *   features feat device double [n][8].
+ *   features feat device double [n][10].
  * afqmc_cv_loss_grad: loss (device double [1]) and gradient (device float
  *   [AFQMC_CV_NPARAMS]) of the mean of 1/2 ||y - t||^2 over n standardised
- *   samples x device float [n][8], t device float [n][2].  Synchronous.
+ *   samples x device float [n][10], t device float [n][2].  Synchronous.
  * afqmc_cv_state: device copies of the last energy call's predictions
  *   (double2 [W]), subset (int32 [k], increasing) and call index (uint64 [1]).
  * Errors: AFQMC_ERR_ARG on NULL context, bad index or sizes; AFQMC_ERR_OOM;
  * AFQMC_ERR_HIP.
  */
-#define AFQMC_CV_NFEAT 8
-#define AFQMC_CV_NPARAMS 17922
-#define AFQMC_CV_NNORM 20
+#define AFQMC_CV_NFEAT 10
+#define AFQMC_CV_NPARAMS 18178
+#define AFQMC_CV_NNORM 24
 afqmc_status afqmc_cv_collect(afqmc_ctx *ctx, const afqmc_walkers *w, double *const *feat_out,
                               void *const *ek_out, void *hip_stream);
 afqmc_status afqmc_cv_train(afqmc_ctx *ctx, int32_t isys, const double *feat, const void *ek, int64_t n,

@@ -18,7 +18,14 @@ Conditional variance of sum_w omega_w g_w (omega = normalised weights, sampling
 without replacement): (1/pi - 1) * W/(W-1) * sum_w omega_w^2 d_w^2
 - (1/pi - 1)/(W-1) * (sum_w omega_w d_w)^2 with d = EK - f  (finite-population form).
 
-Network: x (8 features, standardised) -> tanh(W1 x + b1) (128) -> tanh(W2 h + b2)
+Features: besides the Coulomb energy, the one-body energy, the force-bias
+norms and the overlap phase, the first-order exchange: EK(Theta) expanded about
+the trial (Theta = Psi) is EK(Psi) - sum_s Tr(K_s (Theta_s - Psi_s)) with
+K_s = sum_g (Ltilde^{g s} Psi_s) Ltilde^{g s} (N x M), so Tr(K_s Theta_s) summed
+over spins carries the walker's exchange energy to first order at the cost of a
+one-body energy.
+
+Network: x (10 features, standardised) -> tanh(W1 x + b1) (128) -> tanh(W2 h + b2)
 (128) -> W3 h + b3 (2 outputs: Re and Im of the standardised EK).
 Training: mean squared error, Adam (Kingma & Ba 2015: beta1 = 0.9,
 beta2 = 0.999, eps = 1e-8, bias-corrected moments).
@@ -30,7 +37,7 @@ from __future__ import annotations
 
 import numpy as np
 
-NFEAT = 8
+NFEAT = 10
 HIDDEN = 128
 NOUT = 2
 MASK64 = (1 << 64) - 1
@@ -39,16 +46,30 @@ GOLDEN = 0x9E3779B97F4A7C15
 
 # ---- features --------------------------------------------------------------------
 
-def features(ham, phi, oracle) -> np.ndarray:
+def exchange_first_order_matrices(ham) -> list:
+    """K_s = sum_g (Ltilde^{g s} Psi_s) Ltilde^{g s} per spin block (N_s x M)."""
+    out = []
+    for s, sl in enumerate(ham.spins()):
+        lh = ham.lhalf[s]                        # [G, N_s, M]
+        t0 = np.matmul(lh, ham.trial[:, sl])     # Ltilde Psi, [G, N_s, N_s]
+        out.append(np.einsum("gij,gjq->iq", t0, lh))
+    return out
+
+
+def features(ham, phi, oracle, kmats=None) -> np.ndarray:
     """(Re EJ, Im EJ, Re E1, Im E1, sum|vbias - l|^2, Re sum (vbias - l)^2,
-    cos arg<Psi_T|phi>, sin arg<Psi_T|phi>) of one walker."""
+    cos arg<Psi_T|phi>, sin arg<Psi_T|phi>, Re sum_s Tr(K_s Theta_s),
+    Im sum_s Tr(K_s Theta_s)) of one walker.  `kmats`: the K_s of
+    exchange_first_order_matrices (computed when None)."""
     logo, thetas, _ = oracle.overlap_theta(ham, phi)
     _, e1, _ = oracle.local_energy(ham, phi)
     vb = oracle.force_bias(ham, thetas)
     ej = 0.5 * np.sum(vb * vb)
     d = vb - ham.lmf
+    ks = exchange_first_order_matrices(ham) if kmats is None else kmats
+    lin = sum(np.einsum("iq,qi->", k, th) for k, th in zip(ks, thetas))
     return np.array([ej.real, ej.imag, e1.real, e1.imag, np.sum(np.abs(d) ** 2), np.sum(d * d).real,
-                     np.cos(logo.imag), np.sin(logo.imag)])
+                     np.cos(logo.imag), np.sin(logo.imag), lin.real, lin.imag])
 
 
 def exchange_energy(ham, phi, oracle) -> complex:
@@ -93,7 +114,7 @@ def unflatten(v: np.ndarray) -> dict:
 
 
 def forward(p: dict, X: np.ndarray):
-    """X [n, 8] (standardised) -> (Y [n, 2], cache)."""
+    """X [n, NFEAT] (standardised) -> (Y [n, 2], cache)."""
     z1 = X @ p["W1"].T + p["b1"]
     h1 = np.tanh(z1)
     z2 = h1 @ p["W2"].T + p["b2"]

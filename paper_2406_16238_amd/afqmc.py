@@ -93,7 +93,7 @@ EXPORTS = ("afqmc_default_options", "afqmc_setup_hamiltonian", "afqmc_propagate"
            "afqmc_cv_predict", "afqmc_cv_loss_grad", "afqmc_cv_state", "afqmc_population_control",
            "afqmc_set_e_shift", "afqmc_free_propagate", "afqmc_free_estimator", "afqmc_free_step",
            "afqmc_run_block", "afqmc_reblock", "afqmc_cv_train_noalloc")
-CV_NFEAT, CV_NPARAMS, CV_NNORM = 8, 17922, 20
+CV_NFEAT, CV_NPARAMS, CV_NNORM = 10, 18178, 24
 CV_NOALLOC_MAX_SAMPLES, CV_NOALLOC_MAX_BATCH = 65536, 512
 FREE_EST = 10
 
@@ -544,7 +544,7 @@ def _dev(t, dtype, shape, what):
 
 
 def cv_collect(ctx: Context, walkers, feat_out, ek_out, stream=None):
-    """afqmc_cv_collect: features float64 [W, 8] and exact exchange complex128 [W] per system."""
+    """afqmc_cv_collect: features float64 [W, CV_NFEAT] and exact exchange complex128 [W] per system."""
     import torch
     w = _walker_array(ctx, walkers)
     fs = _ptr_array(ctx, feat_out, [(s.nwalkers, CV_NFEAT) for s in ctx.systems], torch.float64)
@@ -579,7 +579,7 @@ def cv_train_noalloc(ctx: Context, feat, ek, epochs: int, batch: int, lr: float,
 
 
 def cv_set_params(ctx: Context, params=None, norm=None, isys: int = 0, stream=None):
-    """afqmc_cv_set_params: params float32 [17922] and/or norm float64 [20] (device)."""
+    """afqmc_cv_set_params: params float32 [CV_NPARAMS] and/or norm float64 [CV_NNORM] (device)."""
     import torch
     p = _dev(params, torch.float32, (CV_NPARAMS,), "params") if params is not None else None
     q = _dev(norm, torch.float64, (CV_NNORM,), "norm") if norm is not None else None
@@ -587,7 +587,7 @@ def cv_set_params(ctx: Context, params=None, norm=None, isys: int = 0, stream=No
 
 
 def cv_get_params(ctx: Context, isys: int = 0, stream=None):
-    """afqmc_cv_get_params: (params float32 [17922], norm float64 [20]) on the GPU."""
+    """afqmc_cv_get_params: (params float32 [CV_NPARAMS], norm float64 [CV_NNORM]) on the GPU."""
     import torch
     params = torch.empty(CV_NPARAMS, dtype=torch.float32, device="cuda")
     norm = torch.empty(CV_NNORM, dtype=torch.float64, device="cuda")
@@ -597,7 +597,7 @@ def cv_get_params(ctx: Context, isys: int = 0, stream=None):
 
 
 def cv_predict(ctx: Context, feat, isys: int = 0, stream=None):
-    """afqmc_cv_predict: predicted exchange energies (complex128 [n]) for raw features float64 [n, 8]."""
+    """afqmc_cv_predict: predicted exchange energies (complex128 [n]) for raw features float64 [n, CV_NFEAT]."""
     import torch
     n = feat.shape[0]
     f = _dev(feat, torch.float64, (n, CV_NFEAT), "feat")
@@ -607,7 +607,7 @@ def cv_predict(ctx: Context, feat, isys: int = 0, stream=None):
 
 
 def cv_loss_grad(ctx: Context, x, t, isys: int = 0, stream=None):
-    """afqmc_cv_loss_grad (synchronous): (loss float64 [1], gradient float32 [17922]) on the GPU."""
+    """afqmc_cv_loss_grad (synchronous): (loss float64 [1], gradient float32 [CV_NPARAMS]) on the GPU."""
     import torch
     n = x.shape[0]
     xp = _dev(x, torch.float32, (n, CV_NFEAT), "x")

@@ -14,7 +14,7 @@ namespace afqmc {
 constexpr int kMaxSpinOrbitals = 56;  // widest spin block: N^2 complex fits the 64 KiB LDS budget
 constexpr int kThreads = 256;
 // learned control variate: network sizes and the largest walker count of its subset draw
-constexpr int kCvFeatures = 8, kCvHidden = 128;
+constexpr int kCvFeatures = 10, kCvHidden = 128;
 constexpr int kCvParams = kCvHidden * kCvFeatures + kCvHidden + kCvHidden * kCvHidden + kCvHidden + 2 * kCvHidden + 2;
 constexpr int kCvNorm = 2 * kCvFeatures + 4;
 constexpr int kCvMaxWalkers = 4096;
@@ -91,6 +91,8 @@ struct System {
   float *cv_params = nullptr, *cv_m = nullptr, *cv_v = nullptr;  // [kCvParams] each
   double *cv_norm = nullptr;             // [kCvNorm]
   double *cv_feat = nullptr;             // [W][kCvFeatures]
+  double *KtT = nullptr;                 // [M][Nt]: KtT[q][i'] = K_s[i][q], K_s = sum_g (Ltilde Psi_s) Ltilde
+  double2 *cv_lin = nullptr;             // [W] sum_s Tr(K_s Theta_s) (the first-order exchange feature)
   double2 *cv_f = nullptr;               // [W] predictions
   int *cv_sel = nullptr, *cv_pos = nullptr;  // [W]
   uint64_t *cv_counter = nullptr;        // [2]: next call, last call
@@ -192,6 +194,8 @@ hipError_t launch_weight_update(const System &s, const afqmc_walkers &w, int W, 
 
 // Energies.
 hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStream_t st);
+// out[w] = sum_{q,i'} mat[q][i'] theta[w][q][i'] (K = M Nt), complex
+hipError_t launch_trace_half(const double *mat, const double2 *theta, int W, long K, double2 *out, hipStream_t st);
 // With vbpart (MFMA path only) the kernel also writes this spin's trace of T,
 // sum_i T^{g s}_ii, to vbpart[s][w][g]: the spin parts of vbias_g.
 // spin = 0 or 1 launches that spin block only, -1 both.
@@ -245,6 +249,8 @@ hipError_t cv_enable_lds();
 hipError_t launch_cv_init(const System &s, uint64_t seed, hipStream_t st);
 hipError_t launch_cv_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_cv_features(const System &s, int W, double *feat, hipStream_t st);
+// K_s of the first-order exchange feature, from LtT and the trial (set-up; t0: [G][Nt][Nt] scratch)
+hipError_t launch_cv_kmat(System &s, double *t0, hipStream_t st);
 hipError_t launch_cv_predict(const System &s, const double *feat, long n, double2 *f, hipStream_t st);
 hipError_t launch_cv_subset(const System &s, int W, int k, uint64_t seed, hipStream_t st);
 hipError_t launch_cv_gather(const System &s, int k, hipStream_t st);

@@ -527,9 +527,11 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
     ok = ok && dalloc(c, &s.cv_params, kCvParams) && dalloc(c, &s.cv_m, kCvParams) &&
          dalloc(c, &s.cv_v, kCvParams) && dalloc(c, &s.cv_norm, kCvNorm) &&
          dalloc(c, &s.cv_feat, Wn * kCvFeatures) && dalloc(c, &s.cv_f, Wn) && dalloc(c, &s.cv_sel, Wn) &&
-         dalloc(c, &s.cv_pos, Wn) && dalloc(c, &s.cv_counter, 2);
+         dalloc(c, &s.cv_pos, Wn) && dalloc(c, &s.cv_counter, 2) && dalloc(c, &s.KtT, M * Nt) &&
+         dalloc(c, &s.cv_lin, Wn);
     if (ok && c->opt.ex_mode == AFQMC_EX_CV) ok = dalloc(c, &s.cv_theta, (size_t)s.cv_k * M * Nt);
     s.bytes += 4ull * 3 * kCvParams + 8ull * (kCvNorm + Wn * kCvFeatures) + 16ull * Wn + 8ull * Wn + 16 +
+               8ull * M * Nt + 16ull * Wn +
                (c->opt.ex_mode == AFQMC_EX_CV ? 16ull * s.cv_k * M * Nt : 0);
   }
   if (!ok) return fail(AFQMC_ERR_OOM, "device allocation failed");
@@ -629,6 +631,10 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
                   "padded half rotation");
     for (int sp = 0; sp < 2; ++sp)
       if (s.lp_lhs[sp]) AFQMC_HIP(lp_prepare_lhs(s, sp, st), "reduced-precision half rotation");
+    // K_s of the control variate's first-order exchange feature
+    double *t0 = nullptr;
+    if (!tmp.get(&t0, G * Nt * Nt)) return fail(AFQMC_ERR_OOM, "device allocation failed (first-order exchange)");
+    AFQMC_HIP(launch_cv_kmat(s, t0, st), "first-order exchange matrices");
   }
   // scalars and B1 = exp(-dt/2 H1)
   std::vector<double> hl(G), hH1(mm);

@@ -52,6 +52,7 @@ __global__ __launch_bounds__(kThreads) void k_cv_features(const double2 *__restr
                                                           const double2 *__restrict__ e1,
                                                           const double2 *__restrict__ ej,
                                                           const double2 *__restrict__ logo,
+                                                          const double2 *__restrict__ lin,
                                                           double *__restrict__ feat) {
   __shared__ double red[4 * 2];
   const int w = blockIdx.x, tid = threadIdx.x;
@@ -76,7 +77,43 @@ __global__ __launch_bounds__(kThreads) void k_cv_features(const double2 *__restr
     f[5] = acc[1];
     f[6] = cos(ph);
     f[7] = sin(ph);
+    f[8] = lin[w].x;
+    f[9] = lin[w].y;
   }
+}
+
+// K_s[i][q] = sum_g sum_j T0_g[i][j] Ltilde^{g s}[j][q] for i, j of one spin
+// block, T0_g = Ltilde^{g s} Psi_s (in t0 [G][Nt][Nt], the cross-spin blocks
+// unused); written as KtT[q][i'] (the layout of the half-rotated h).  One
+// thread per (q, i'), the sum over g and j in a fixed order.
+__global__ void k_cv_kmat(const double *__restrict__ LtT, const double *__restrict__ t0, int G, int M, int Nt, int Na,
+                          double *__restrict__ KtT) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)M * Nt) return;
+  const int q = (int)(e / Nt), ip = (int)(e - (e / Nt) * Nt);
+  const int j0 = ip < Na ? 0 : Na, j1 = ip < Na ? Na : Nt;
+  double a = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const double *t = t0 + ((size_t)g * Nt + ip) * Nt;
+    const double *l = LtT + ((size_t)g * M + q) * Nt;
+    for (int j = j0; j < j1; ++j) a = fma(t[j], l[j], a);
+  }
+  KtT[e] = a;
+}
+
+hipError_t launch_cv_kmat(System &s, double *t0, hipStream_t st) {
+  // t0[g] = LtT[g]^T trial (Nt x Nt per Cholesky vector)
+  GemmArgs g;
+  g.m = s.Nt; g.n = s.Nt; g.k = s.M; g.batch = s.G;
+  g.A = s.LtT; g.sai = 1; g.sak = s.Nt; g.sab = (long)s.M * s.Nt;
+  g.B = s.trial; g.sbk = s.Nt; g.sbj = 1; g.sbb = 0;
+  g.C = t0; g.sci = s.Nt; g.scj = 1; g.scb = (long)s.Nt * s.Nt;
+  hipError_t e = gemm_f64(g, st);
+  if (e != hipSuccess) return e;
+  const long n = (long)s.M * s.Nt;
+  hipLaunchKernelGGL(k_cv_kmat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.LtT, t0, s.G, s.M, s.Nt, s.Na,
+                     s.KtT);
+  return hipGetLastError();
 }
 
 // ---- subset draw ------------------------------------------------------------------
@@ -469,8 +506,11 @@ hipError_t cv_enable_lds() {
 }
 
 hipError_t launch_cv_features(const System &s, int W, double *feat, hipStream_t st) {
+  // sum_s Tr(K_s Theta_s), a trace of the same form as the one-body energy
+  hipError_t e = launch_trace_half(s.KtT, s.theta, W, (long)s.M * s.Nt, s.cv_lin, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cv_features, dim3(W), dim3(kThreads), 0, st, s.fbpart, s.fb_slices, s.G, W, s.lmf, s.e1,
-                     s.ej, s.logo_new, feat);
+                     s.ej, s.logo_new, s.cv_lin, feat);
   return hipGetLastError();
 }
 

@@ -160,6 +160,11 @@ hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStr
   return hipGetLastError();
 }
 
+hipError_t launch_trace_half(const double *mat, const double2 *theta, int W, long K, double2 *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_e1, dim3(W), dim3(kThreads), 0, st, mat, theta, K, 0.0, out);
+  return hipGetLastError();
+}
+
 // ---- combine: E2 = EJ + sum of exchange partials (fixed order), E = E1 + E2 ---
 __global__ __launch_bounds__(kThreads) void k_energy_combine(const double2 *__restrict__ e1,
                                                             const double2 *__restrict__ ej,

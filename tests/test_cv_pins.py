@@ -90,6 +90,35 @@ def test_features_at_the_trial():
     assert abs(f[6] - 1.0) < 1e-15 and abs(f[7]) < 1e-15     # <Psi|Psi> = 1
     ek = CV.exchange_energy(ham, trial.astype(complex), O)
     assert abs(ham.e_trial - (f[2] + f[0] + ek.real)) < 1e-12
+    # at the trial sum_s Tr(K_s Psi_s) = sum_g sum_s Tr(T0 T0) = -2 EK
+    assert abs(f[8] + 2.0 * ek.real) < 1e-12 * max(1.0, abs(ek)) and abs(f[9]) < 1e-14
+
+
+@pytest.mark.parametrize("uhf", [False, True])
+def test_first_order_exchange_feature_is_the_derivative_of_ek(uhf):
+    """The tenth and ninth features carry the exchange energy to first order
+    about the trial: along any walker path phi(e) through the trial, with Theta
+    the Green's-function factor, d EK / de = -d Tr(K Theta) / de.  Central
+    differences of the oracle's exchange energy (pinned to the 4-index ERI) and
+    of the feature must agree; a wrong sign, a missing factor, the transposed
+    K or the other spin's trial fail this."""
+    m, na, nb = 6, 3, 2
+    spec = gi.SystemSpec(m, na, nb, 9, tau=3.0, scale="literal", seed=5)
+    h1, chol, _, trial = gi.make_system(spec)
+    if uhf:
+        q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((m, nb)))
+        trial = np.hstack([trial[:, :na], q])
+    ham = O.build(h1, chol, 0.2, trial, na, nb, 0.01)
+    ks = CV.exchange_first_order_matrices(ham)
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal((m, na + nb)) + 1j * rng.standard_normal((m, na + nb))
+    eps = 1e-4
+    plus, minus = trial + eps * d, trial - eps * d
+    dek = CV.exchange_energy(ham, plus, O) - CV.exchange_energy(ham, minus, O)
+    fp, fm = CV.features(ham, plus, O, ks), CV.features(ham, minus, O, ks)
+    dlin = complex(fp[8] - fm[8], fp[9] - fm[9])
+    assert abs(dek) > 1e-6
+    assert abs(dek + dlin) < 1e-7 * abs(dek)
 
 
 def test_adam_first_two_updates_in_closed_form():

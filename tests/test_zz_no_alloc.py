@@ -22,7 +22,7 @@ def samples(p, ctx, nsteps, seed):
     feats, eks = [], []
     for k in range(nsteps):
         A.step(ctx, w, torch.as_tensor(fs.next(), device="cuda"), e, reortho=(k + 1) % 5 == 0)
-        f = torch.empty((W, 8), dtype=torch.float64, device="cuda")
+        f = torch.empty((W, A.CV_NFEAT), dtype=torch.float64, device="cuda")
         q = torch.empty(W, dtype=torch.complex128, device="cuda")
         A.cv_collect(ctx, w, f, q)
         feats.append(f)
@@ -65,7 +65,7 @@ def test_noalloc_limits():
     A, torch = p.A, p.torch
     try:
         n = A.CV_NOALLOC_MAX_SAMPLES + 1
-        feat = torch.zeros((n, 8), dtype=torch.float64, device="cuda")
+        feat = torch.zeros((n, A.CV_NFEAT), dtype=torch.float64, device="cuda")
         ek = torch.zeros(n, dtype=torch.complex128, device="cuda")
         with pytest.raises(A.AfqmcError) as ei:
             A.cv_train_noalloc(p.ctx, feat, ek, 1, 64, 1e-3)
