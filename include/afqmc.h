@@ -119,9 +119,12 @@ typedef struct {
                                into a hipGraph the first time it sees a set of
                                buffers and flags, and replays it when they repeat
                                (default 0).  Phase timers do not see replays.     */
-  int32_t tune;             /* time the exchange kernel's walker tiling (1, 2 or 4
-                               walkers per workgroup) at set-up and keep the
-                               fastest; default 1.  Results do not depend on it.  */
+  int32_t tune;             /* time launch shapes at set-up and keep the fastest
+                               per problem shape: the exchange kernels' walker
+                               tiling (1, 2 or 4 walkers per workgroup) and tile
+                               order, the V_HS product's tiles and the Taylor
+                               kernel's row tiles; default 1.  Results do not
+                               depend on it.                                      */
   int32_t ex_mode;          /* AFQMC_EX_FULL (default) or AFQMC_EX_CV              */
   double cv_fraction;       /* AFQMC_EX_CV: share of walkers whose exact exchange
                                is computed per call, k = ceil(cv_fraction W);
@@ -133,24 +136,27 @@ typedef struct {
                                stay FP64; the mixed precision the paper mentions
                                in Sec. 6).  Needs M a multiple of 4, Nt <= 96.    */
   int32_t reserved_opt;
+  const char *tune_cache;   /* with tune: path of a file of JSON lines, one per
+                               problem shape, that the tuner reads before timing
+                               and appends its choices to (NULL, the default:
+                               choices are kept for the process only).  A file
+                               that cannot be written is AFQMC_ERR_ARG.  The
+                               library reads the string during set-up only.      */
   int32_t reserved[8];      /* reserved[0] bit 0: VALU (non-MFMA) exchange kernel;
                                bit 1: VALU kernels for the force bias, V_HS, B1
                                and Taylor products; bit 2: the generic MFMA GEMM
                                for the Taylor terms; bit 3: V_HS from the full
                                (unpacked) L^g; bit 4: free projection through
-                               both V_HS planes; bit 5: four real products per
-                               Taylor term instead of three (all for comparison
-                               runs);
+                               both V_HS planes (all for comparison runs);
                                reserved[1]: walkers per exchange workgroup (1, 2
                                or 4); reserved[2]: exchange tile order (1 = Cholesky
                                block fastest, g > 1 = groups of g walker blocks);
-                               either one fixes the launch shape (no tuning);
-                               reserved[3]: tile shape of the V_HS product (0 =
-                               default, 1..8 alternatives for comparison runs);
-                               reserved[4]: tile shape of the Taylor-term kernels
-                               (0 = default, 1..8 four-product alternatives,
-                               9..10 three-product alternatives);
-                               other entries: zero                                */
+                               either one fixes the exchange launch shape;
+                               reserved[3]: k = 1..4 fixes the V_HS tile shape
+                               k - 1; reserved[4]: k = 1..3 fixes the Taylor
+                               kernel's row tile k - 1 (48, 32 or 64 rows; 64
+                               for FP32 propagation only); 0 leaves each to the
+                               tuner; other entries: zero                         */
 } afqmc_options;
 
 /* Walker state of one system; every pointer is device memory owned by the caller. */
@@ -174,6 +180,9 @@ typedef struct {
   int64_t graph_captures; /* afqmc_step graphs recorded so far (whole context)  */
   int64_t graph_replays;  /* afqmc_step graph replays so far (whole context)    */
   int32_t cv_subset;      /* walkers with exact exchange per energy call (EX_CV), else 0 */
+  int32_t vhs_tile;       /* V_HS tile shape in use (0..3; -1: another route)        */
+  int32_t taylor_tile;    /* Taylor row tile in use (0 = 48, 1 = 32, 2 = 64 rows; -1:
+                             the generic GEMM route)                                 */
   int32_t reserved_info;
 } afqmc_info;
 

@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
                 ("mem_limit_bytes", ctypes.c_uint64), ("streams", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("tune", ctypes.c_int32), ("ex_mode", ctypes.c_int32), ("cv_fraction", ctypes.c_double),
                 ("cv_seed", ctypes.c_uint64), ("prop_precision", ctypes.c_int32), ("reserved_opt", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("tune_cache", ctypes.c_char_p), ("reserved", ctypes.c_int32 * 8)]
 
 
 class CWalkers(ctypes.Structure):
@@ -63,7 +63,8 @@ class Info(ctypes.Structure):
                 ("const_c", ctypes.c_double), ("device_bytes", ctypes.c_uint64),
                 ("exchange_tile", ctypes.c_int32), ("exchange_order", ctypes.c_int32), ("lane", ctypes.c_int32),
                 ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
-                ("cv_subset", ctypes.c_int32), ("reserved_info", ctypes.c_int32)]
+                ("cv_subset", ctypes.c_int32), ("vhs_tile", ctypes.c_int32), ("taylor_tile", ctypes.c_int32),
+                ("reserved_info", ctypes.c_int32)]
 
 
 PHASES = ("overlap", "force_bias", "fb_epilogue", "vhs", "one_body", "taylor", "weight",

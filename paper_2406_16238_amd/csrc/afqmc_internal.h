@@ -69,6 +69,11 @@ struct System {
   uint32_t *stat_now = nullptr, *stat_new = nullptr;
   double2 *opart = nullptr;    // per-spin-block scratch of the overlap and Gram-Schmidt kernels, [W][2]
   uint32_t *ospart = nullptr;   // [W][2]
+  // second stream of the Taylor terms (the walkers' second half), forked from
+  // and joined into the system's stream, so that one half's launch tail
+  // overlaps the other half's work
+  hipStream_t half_stream = nullptr;
+  hipEvent_t half_fork = nullptr, half_join = nullptr;
 
   int fb_ksplit = 1;  // split-K slices of the force-bias contraction
   int ex_gb = 1;      // Cholesky vectors per workgroup of the VALU exchange kernel
@@ -76,11 +81,10 @@ struct System {
   size_t ex_lds = 0;  // its dynamic LDS
   bool use_mfma_gemm = true;   // MFMA kernels for force bias, V_HS, B1 and Taylor terms
   bool taylor_kernel = true;   // the dedicated Taylor-term kernel (else the generic MFMA GEMM)
-  int vhs_variant = 0;         // tile shape of the V_HS GEMM
-  int taylor_variant = 0;      // tile shape of the Taylor-term kernel
+  int vhs_shape = 0;           // tile shape of the V_HS GEMM (kVhsShapes candidates)
+  int taylor_shape = 0;        // tile shape of the Taylor-term kernel (taylor_shapes(s) candidates)
   bool pack_chol = true;       // V_HS from the packed upper triangles of the L^g
   bool free_full = false;      // free projection through both V_HS planes (comparison runs)
-  bool taylor4 = false;        // four real products per Taylor term (comparison runs)
   bool ex_mfma = false;        // MFMA exchange kernel in use (both spin blocks)
   ExchangePlan ex_plan[2];     // its per-spin plans
   int ex_group = 0;            // tile order of the MFMA exchange launches (see tile_of)
@@ -153,7 +157,8 @@ struct GemmArgs {
   int cplx_rows = 0;
 };
 hipError_t gemm_f64(const GemmArgs &a, hipStream_t st);
-hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st, int variant);
+hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st, int shape);
+constexpr int kVhsShapes = 4;   // tile shapes of the V_HS GEMM the tuner tries
 hipError_t gemm_b1_mfma(const GemmArgs &a, hipStream_t st);
 hipError_t gemm_taylor_mfma(const GemmArgs &a, hipStream_t st);
 hipError_t gemm_fb_mfma(const GemmArgs &a, hipStream_t st);
@@ -242,7 +247,12 @@ hipError_t launch_gen_chol(const System &s, uint64_t seed, const double *fac, do
 // dedicated Taylor-term kernel (k_taylor.hip)
 bool taylor_mfma_supported(int M, int Nt);
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st, int kbeg = 0);
+                              hipStream_t st, int kbeg = 0, int w0 = 0);
+// the Taylor terms of walkers [w0, w0 + W) can run as a launch of their own
+// (the dedicated three-product kernel)
+bool taylor_walker_split(const System &s);
+// tile shapes of the dedicated Taylor kernel in use (FP64 or FP32 propagation)
+int taylor_shapes(const System &s);
 
 // learned control variate (k_cv.hip)
 hipError_t cv_enable_lds();

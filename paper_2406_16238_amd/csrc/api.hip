@@ -92,8 +92,9 @@ struct afqmc_ctx {
   bool force_valu_exchange = false;  // reserved[0] & 1: use the VALU exchange kernel
   bool force_valu_gemm = false;      // reserved[0] & 2: VALU kernels for the other contractions
   int debug_bits = 0;                // reserved[0]
-  int vhs_variant = 0;               // reserved[3]: tile shape of the V_HS GEMM (0 = default, 1..8 others)
-  int taylor_variant = 0;            // reserved[4]: tile shape of the Taylor kernels (0 = default, others 1..8)
+  int vhs_fixed = -1;                // reserved[3] - 1: V_HS tile shape fixed by the caller (-1: tuned)
+  int taylor_fixed = -1;             // reserved[4] - 1: Taylor tile shape fixed by the caller (-1: tuned)
+  std::string tune_cache;            // options.tune_cache ("" = none)
   int ex_wx = 2;                     // walkers per exchange workgroup (reserved[1]: 1, 2 or 4)
   int ex_group = 8;                  // exchange tile order (reserved[2]: 1 = plain, g > 1 = groups of g)
   bool ex_wx_forced = false;         // launch shape fixed by the caller: no tuning
@@ -191,6 +192,13 @@ void release(afqmc_ctx *c) {
   c->graphs.clear();
   for (hipStream_t l : c->lanes) (void)hipStreamDestroy(l);
   c->lanes.clear();
+  for (System &sy : c->sys) {
+    if (sy.half_stream) (void)hipStreamDestroy(sy.half_stream);
+    for (hipEvent_t e : {sy.half_fork, sy.half_join})
+      if (e) (void)hipEventDestroy(e);
+    sy.half_stream = nullptr;
+    sy.half_fork = sy.half_join = nullptr;
+  }
   for (hipEvent_t e : c->join_ev) (void)hipEventDestroy(e);
   c->join_ev.clear();
   for (hipEvent_t e : {c->fork_ev, c->g_in, c->g_out})
@@ -462,11 +470,10 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
                                            " orbitals is not supported");
   s.use_mfma_gemm = !c->force_valu_gemm;
   s.taylor_kernel = !(c->debug_bits & 4);
-  s.vhs_variant = c->vhs_variant;
-  s.taylor_variant = c->taylor_variant;
+  s.vhs_shape = std::max(c->vhs_fixed, 0);
+  s.taylor_shape = std::max(c->taylor_fixed, 0);
   s.pack_chol = s.use_mfma_gemm && !(c->debug_bits & 8);
   s.free_full = (c->debug_bits & 16) != 0;
-  s.taylor4 = (c->debug_bits & 32) != 0;
   s.prop32 = c->opt.prop_precision == AFQMC_FP32_CONTRACT;
   if (s.prop32 && !(s.pack_chol && prop32_supported(s.M, s.Nt)))
     return fail(AFQMC_ERR_UNSUPPORTED, "FP32 propagation needs the MFMA path, M a multiple of 4 and at most 96 "
@@ -677,79 +684,226 @@ afqmc_status setup_one(afqmc_ctx *c, const afqmc_system_desc &d, System &s, hipS
   return AFQMC_OK;
 }
 
-// Launch shape of the exchange kernels, timed on the system's own sizes with
-// Theta filled by a fixed pattern: the walker tiling of the FP64 kernel (1, 2
-// or 4 walkers per workgroup; the four waves then split 4, 2 or 1 ways over
-// Cholesky vectors) and the tile order (tile_of: Cholesky block fastest, or
-// groups of 4, 8 or 16 walker blocks).  Every wave sums the same Cholesky
-// vectors of one walker in the same order whatever the shape, so the choice
-// changes speed only.  It is kept per shape for the rest of the process, so
-// every context of one shape launches alike.
-afqmc_status tune_exchange(System &s, hipStream_t st) {
+// Set-up tuner.  Launch shapes are timed on the system's own sizes, with the
+// operands filled by a fixed pattern:
+//  * the exchange kernels: the walker tiling of the FP64 kernel (1, 2 or 4
+//    walkers per workgroup; the four waves then split 4, 2 or 1 ways over
+//    Cholesky vectors) and the tile order (tile_of: Cholesky block fastest, or
+//    groups of 4, 8 or 16 walker blocks);
+//  * the V_HS product: kVhsShapes workgroup tiles;
+//  * the Taylor-term kernel: its row tiles (48 or 32 rows; 48, 32 or 64 for
+//    FP32 propagation).
+// Every choice changes speed only: each kernel sums the same terms in the same
+// order whatever the shape.  Choices are kept per problem shape (M, N_alpha,
+// N_beta, G, W, precision, propagation precision) for the rest of the process,
+// so every context of one shape launches alike, and, with options.tune_cache,
+// in a file of JSON lines that later processes read instead of timing.
+struct TuneKey {
+  std::array<int, 7> k;
+  bool operator<(const TuneKey &o) const { return k < o.k; }
+};
+struct TuneChoice {
+  int ex_tile = -1, ex_order = -1, vhs = -1, taylor = -1;   // -1: not tuned
+};
+const char *const kTuneNames[7] = {"M", "Na", "Nb", "G", "W", "precision", "prop32"};
+
+// integer value of "name": in one JSON line (false if absent or malformed)
+bool json_int(const std::string &line, const char *name, int *out) {
+  const std::string pat = std::string("\"") + name + "\"";
+  size_t p = line.find(pat);
+  if (p == std::string::npos) return false;
+  p = line.find(':', p + pat.size());
+  if (p == std::string::npos) return false;
+  ++p;
+  while (p < line.size() && (line[p] == ' ' || line[p] == '\t')) ++p;
+  char *end = nullptr;
+  const long v = strtol(line.c_str() + p, &end, 10);
+  if (end == line.c_str() + p) return false;
+  *out = (int)v;
+  return true;
+}
+
+// the last line of the cache file for `key` (parts absent in it stay -1)
+void cache_read(const std::string &path, const TuneKey &key, TuneChoice *ch) {
+  FILE *f = fopen(path.c_str(), "r");
+  if (!f) return;
+  char buf[1024];
+  while (fgets(buf, sizeof buf, f)) {
+    const std::string line(buf);
+    bool match = true;
+    for (int i = 0; i < 7 && match; ++i) {
+      int v;
+      match = json_int(line, kTuneNames[i], &v) && v == key.k[i];
+    }
+    if (!match) continue;
+    TuneChoice c;
+    (void)json_int(line, "ex_tile", &c.ex_tile);
+    (void)json_int(line, "ex_order", &c.ex_order);
+    (void)json_int(line, "vhs_tile", &c.vhs);
+    (void)json_int(line, "taylor_tile", &c.taylor);
+    *ch = c;
+  }
+  fclose(f);
+}
+
+bool cache_append(const std::string &path, const TuneKey &key, const TuneChoice &c) {
+  FILE *f = fopen(path.c_str(), "a");
+  if (!f) return false;
+  std::string line = "{";
+  for (int i = 0; i < 7; ++i) line += std::string("\"") + kTuneNames[i] + "\": " + std::to_string(key.k[i]) + ", ";
+  line += "\"ex_tile\": " + std::to_string(c.ex_tile) + ", \"ex_order\": " + std::to_string(c.ex_order) +
+          ", \"vhs_tile\": " + std::to_string(c.vhs) + ", \"taylor_tile\": " + std::to_string(c.taylor) + "}\n";
+  const bool ok = fputs(line.c_str(), f) >= 0;
+  return fclose(f) == 0 && ok;
+}
+
+// median-free timing: one warm-up call, then two timed calls between events
+template <class F>
+hipError_t time_ms(F run, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float *ms) {
+  hipError_t e = run();
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+  for (int r = 0; r < 2; ++r)
+    if ((e = run()) != hipSuccess) return e;
+  if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
+  if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+  return hipEventElapsedTime(ms, e0, e1);
+}
+
+hipError_t tune_exchange_shape(System &s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, TuneChoice *ch) {
+  const bool lp = s.precision != AFQMC_FP64;
+  hipError_t err = launch_fill_pattern2(s.theta, (long)s.W * s.M * s.Nt, st);
+  if (lp)
+    for (int sp = 0; sp < 2 && err == hipSuccess; ++sp) err = lp_prepare_rhs(s, s.theta, s.W, sp, st);
+  if (err != hipSuccess) return err;
+  auto run = [&]() -> hipError_t {
+    for (int sp = 0; sp < 2; ++sp) {
+      hipError_t e = lp ? launch_exchange_lp(s, s.W, sp, st, s.fbpart) : launch_exchange(s, s.theta, s.W, st, s.fbpart, sp);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  float best_ms = 0.0f;
+  for (int wx : {1, 2, 4}) {
+    if (lp && wx != 2) continue;  // the reduced-precision kernels have a fixed walker tiling
+    const ExchangePlan p0 = exchange_plan(s.Na, s.G, wx), p1 = exchange_plan(s.Nb, s.G, wx);
+    if ((s.Na > 0 && !p0.mfma) || (s.Nb > 0 && !p1.mfma)) continue;
+    s.ex_plan[0] = p0;
+    s.ex_plan[1] = p1;
+    if ((err = exchange_enable_lds(s)) != hipSuccess) return err;
+    for (int group : {0, 4, 8, 16}) {
+      s.ex_group = group;
+      float ms = 0.0f;
+      if ((err = time_ms(run, st, e0, e1, &ms)) != hipSuccess) return err;
+      if (ch->ex_tile < 0 || ms < best_ms) {
+        ch->ex_tile = wx;
+        ch->ex_order = group;
+        best_ms = ms;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t tune_vhs_shape(System &s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, TuneChoice *ch) {
+  hipError_t err = launch_fill_pattern2(reinterpret_cast<double2 *>(s.yp), (long)s.W * s.G, st);
+  if (err != hipSuccess) return err;
+  float best_ms = 0.0f;
+  for (int v = 0; v < kVhsShapes; ++v) {
+    s.vhs_shape = v;
+    float ms = 0.0f;
+    if ((err = time_ms([&]() { return launch_vhs(s, s.W, st, false); }, st, e0, e1, &ms)) != hipSuccess) return err;
+    if (ch->vhs < 0 || ms < best_ms) {
+      ch->vhs = v;
+      best_ms = ms;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t tune_taylor_shape(System &s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, TuneChoice *ch) {
+  // V_HS from pattern fields, then one term from a pattern walker slab
+  hipError_t err = launch_fill_pattern2(reinterpret_cast<double2 *>(s.yp), (long)s.W * s.G, st);
+  if (err == hipSuccess) err = launch_vhs(s, s.W, st, false);
+  if (err == hipSuccess) err = launch_fill_pattern2(s.tA, (long)s.W * s.M * s.Nt, st);
+  if (err == hipSuccess && s.prop32) err = launch_c128_to_c64(s.tA, (long)s.W * s.M * s.Nt, s.tA32, st);
+  if (err != hipSuccess) return err;
+  float best_ms = 0.0f;
+  for (int v = 0; v < taylor_shapes(s); ++v) {
+    s.taylor_shape = v;
+    auto run = [&]() {
+      return s.prop32 ? launch_taylor_f32(s, s.tA32, s.tB32, 1.0, s.W, st, 0)
+                      : launch_taylor_term(s, s.tA, s.tB, 1.0, s.W, st, 0);
+    };
+    float ms = 0.0f;
+    if ((err = time_ms(run, st, e0, e1, &ms)) != hipSuccess) return err;
+    if (ch->taylor < 0 || ms < best_ms) {
+      ch->taylor = v;
+      best_ms = ms;
+    }
+  }
+  return hipSuccess;
+}
+
+afqmc_status tune_system(afqmc_ctx *c, System &s, hipStream_t st) {
   static std::mutex mu;
-  static std::map<std::array<int, 6>, std::pair<int, int>> chosen;
-  const std::array<int, 6> key{s.M, s.Na, s.Nb, s.G, s.W, s.precision};
-  std::pair<int, int> best{0, 0};
+  static std::map<TuneKey, TuneChoice> chosen;
+  const TuneKey key{{s.M, s.Na, s.Nb, s.G, s.W, s.precision, s.prop32 ? 1 : 0}};
+  if (c->taylor_fixed >= taylor_shapes(s)) return fail(AFQMC_ERR_ARG, "reserved[4]: no such Taylor tile shape");
+  // which parts this context leaves to the tuner
+  const bool want_ex = c->tune && !c->ex_wx_forced && s.ex_mfma;
+  const bool want_vhs = c->tune && c->vhs_fixed < 0 && s.use_mfma_gemm && s.Lp && !s.prop32;
+  const bool want_taylor = c->tune && c->taylor_fixed < 0 && (s.prop32 || taylor_walker_split(s));
+  TuneChoice ch;
   {
     std::lock_guard<std::mutex> lock(mu);
     auto it = chosen.find(key);
-    if (it != chosen.end()) best = it->second;
+    if (it != chosen.end()) ch = it->second;
   }
-  const bool lp = s.precision != AFQMC_FP64;
-  if (best.first == 0) {
-    AFQMC_HIP(launch_fill_pattern2(s.theta, (long)s.W * s.M * s.Nt, st), "pattern fill");
-    if (lp)
-      for (int sp = 0; sp < 2; ++sp) AFQMC_HIP(lp_prepare_rhs(s, s.theta, s.W, sp, st), "operand kernel");
+  const bool from_file = !c->tune_cache.empty() &&
+                         ((want_ex && ch.ex_tile < 0) || (want_vhs && ch.vhs < 0) || (want_taylor && ch.taylor < 0));
+  if (from_file) {
+    TuneChoice f;
+    cache_read(c->tune_cache, key, &f);
+    if (ch.ex_tile < 0) { ch.ex_tile = f.ex_tile; ch.ex_order = f.ex_order; }
+    if (ch.vhs < 0) ch.vhs = f.vhs;
+    if (ch.taylor < 0) ch.taylor = f.taylor;
+  }
+  const bool time_ex = want_ex && ch.ex_tile < 0, time_vhs = want_vhs && ch.vhs < 0,
+             time_taylor = want_taylor && ch.taylor < 0;
+  if (time_ex || time_vhs || time_taylor) {
     hipEvent_t e0, e1;
     AFQMC_HIP(hipEventCreate(&e0), "event create");
     if (hipEventCreate(&e1) != hipSuccess) {
       (void)hipEventDestroy(e0);
       return fail(AFQMC_ERR_HIP, "event create");
     }
-    float best_ms = 0.0f;
     hipError_t err = hipSuccess;
-    auto run = [&]() -> hipError_t {
-      for (int sp = 0; sp < 2; ++sp) {
-        hipError_t e = lp ? launch_exchange_lp(s, s.W, sp, st, s.fbpart)
-                          : launch_exchange(s, s.theta, s.W, st, s.fbpart, sp);
-        if (e != hipSuccess) return e;
-      }
-      return hipSuccess;
-    };
-    for (int wx : {1, 2, 4}) {
-      if (lp && wx != 2) continue;  // the reduced-precision kernels have a fixed walker tiling
-      const ExchangePlan p0 = exchange_plan(s.Na, s.G, wx), p1 = exchange_plan(s.Nb, s.G, wx);
-      if ((s.Na > 0 && !p0.mfma) || (s.Nb > 0 && !p1.mfma)) continue;
-      s.ex_plan[0] = p0;
-      s.ex_plan[1] = p1;
-      if ((err = exchange_enable_lds(s)) != hipSuccess) break;
-      for (int group : {0, 4, 8, 16}) {
-        s.ex_group = group;
-        if ((err = run()) != hipSuccess) break;
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < 2 && err == hipSuccess; ++r) err = run();
-        (void)hipEventRecord(e1, st);
-        if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (best.first == 0 || ms < best_ms) {
-          best = {wx, group};
-          best_ms = ms;
-        }
-      }
-      if (err != hipSuccess) break;
-    }
+    if (time_ex) err = tune_exchange_shape(s, st, e0, e1, &ch);
+    if (err == hipSuccess && time_vhs) err = tune_vhs_shape(s, st, e0, e1, &ch);
+    if (err == hipSuccess && time_taylor) err = tune_taylor_shape(s, st, e0, e1, &ch);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (err != hipSuccess) return fail(AFQMC_ERR_HIP, std::string("exchange tuning: ") + hipGetErrorString(err));
-    if (best.first == 0) return AFQMC_OK;
-    std::lock_guard<std::mutex> lock(mu);
-    chosen.emplace(key, best);
+    if (err != hipSuccess) return fail(AFQMC_ERR_HIP, std::string("launch-shape tuning: ") + hipGetErrorString(err));
+    s.cache_phi = nullptr;  // Theta and the walker slabs hold tuning patterns
+    if (!c->tune_cache.empty() && !cache_append(c->tune_cache, key, ch))
+      return fail(AFQMC_ERR_ARG, "cannot write the tuning cache " + c->tune_cache);
   }
-  s.ex_plan[0] = exchange_plan(s.Na, s.G, best.first);
-  s.ex_plan[1] = exchange_plan(s.Nb, s.G, best.first);
-  s.ex_group = best.second;
-  AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    TuneChoice &kept = chosen[key];
+    if (ch.ex_tile >= 0) { kept.ex_tile = ch.ex_tile; kept.ex_order = ch.ex_order; }
+    if (ch.vhs >= 0) kept.vhs = ch.vhs;
+    if (ch.taylor >= 0) kept.taylor = ch.taylor;
+  }
+  if (want_ex && ch.ex_tile > 0) {
+    s.ex_plan[0] = exchange_plan(s.Na, s.G, ch.ex_tile);
+    s.ex_plan[1] = exchange_plan(s.Nb, s.G, ch.ex_tile);
+    s.ex_group = ch.ex_order;
+  }
+  if (s.ex_mfma) AFQMC_HIP(exchange_enable_lds(s), "exchange kernel LDS attribute");
+  s.vhs_shape = c->vhs_fixed >= 0 ? c->vhs_fixed : (want_vhs && ch.vhs >= 0 ? ch.vhs : 0);
+  s.taylor_shape = c->taylor_fixed >= 0 ? c->taylor_fixed : (want_taylor && ch.taylor >= 0 ? ch.taylor : 0);
   return AFQMC_OK;
 }
 
@@ -882,8 +1036,9 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   c->force_valu_exchange = (o.reserved[0] & 1) != 0;
   c->force_valu_gemm = (o.reserved[0] & 2) != 0;
   c->debug_bits = o.reserved[0];
-  if (o.reserved[3] >= 0 && o.reserved[3] <= 8) c->vhs_variant = o.reserved[3];
-  if (o.reserved[4] >= 0 && o.reserved[4] <= 10) c->taylor_variant = o.reserved[4];
+  if (o.reserved[3] >= 1 && o.reserved[3] <= kVhsShapes) c->vhs_fixed = o.reserved[3] - 1;
+  if (o.reserved[4] >= 1 && o.reserved[4] <= 3) c->taylor_fixed = o.reserved[4] - 1;
+  if (o.tune_cache) c->tune_cache = o.tune_cache;
   if (o.reserved[1] == 1 || o.reserved[1] == 2 || o.reserved[1] == 4) {
     c->ex_wx = o.reserved[1];
     c->ex_wx_forced = true;
@@ -892,7 +1047,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     c->ex_group = o.reserved[2] == 1 ? 0 : o.reserved[2];
     c->ex_wx_forced = true;
   }
-  c->tune = o.tune != 0 && !c->ex_wx_forced;
+  c->tune = o.tune != 0;
   c->use_graph = o.use_graph != 0;
   (void)hipGetDevice(&c->device);
   {
@@ -908,7 +1063,7 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
   for (int i = 0; i < nsys; ++i) {
     afqmc_status r = setup_one(c, sys[i], c->sys[i], st, &used, o.mem_limit_bytes);
     System &sy = c->sys[i];
-    if (r == AFQMC_OK && c->tune && sy.ex_mfma) r = tune_exchange(sy, st);
+    if (r == AFQMC_OK) r = tune_system(c, sy, st);
     if (r == AFQMC_OK && sy.Lp && sy.L) {
       // after set-up only the packed triangles are read: give the full tensor back
       if (hipStreamSynchronize(st) != hipSuccess) r = fail(AFQMC_ERR_HIP, "set-up failed on the device");
@@ -939,6 +1094,13 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     }
   }
   afqmc_status r = make_lanes(c, o.streams == 0 ? 4 : o.streams);
+  for (System &sy : c->sys) {
+    if (r != AFQMC_OK || !taylor_walker_split(sy) || sy.W < 2) continue;
+    if (hipStreamCreateWithFlags(&sy.half_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sy.half_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sy.half_join, hipEventDisableTiming) != hipSuccess)
+      r = fail(AFQMC_ERR_HIP, "Taylor stream or event create");
+  }
   if (r == AFQMC_OK && c->use_graph) {
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->g_in, hipEventDisableTiming) != hipSuccess ||
@@ -987,11 +1149,31 @@ static afqmc_status apply_propagator(afqmc_ctx *ctx, System &s, double2 *phi, bo
         std::swap(tin, tout);
       }
     } else {
+      // with a second stream, walkers [W1, W) take their terms there: the
+      // launch tail of each term of one half overlaps the other half's work
+      // (not while a graph is being recorded: recording it crashed the host runtime)
+      const bool split = s.half_stream != nullptr && W >= 2 && !ctx->capturing;
+      const int W1 = split ? (W + 1) / 2 : W;
+      if (split) {
+        AFQMC_HIP(hipEventRecord(s.half_fork, st), "event record");
+        AFQMC_HIP(hipStreamWaitEvent(s.half_stream, s.half_fork, 0), "stream wait");
+      }
       double2 *tin = s.tA, *tout = s.tB;
-      for (int n = 1; n <= ctx->opt.taylor_order; ++n) {
-        AFQMC_HIP(launch_taylor_term(s, tin, tout, 1.0 / n, W, st, kbeg), "Taylor kernel");
+      hipError_t e = hipSuccess;
+      for (int n = 1; n <= ctx->opt.taylor_order && e == hipSuccess; ++n) {
+        if (split) {
+          e = launch_taylor_mfma(s, tin, tout, 1.0 / n, W1, st, kbeg, 0);
+          if (e == hipSuccess) e = launch_taylor_mfma(s, tin, tout, 1.0 / n, W - W1, s.half_stream, kbeg, W1);
+        } else {
+          e = launch_taylor_term(s, tin, tout, 1.0 / n, W, st, kbeg);
+        }
         std::swap(tin, tout);
       }
+      if (split) {  // joined also after a failure, so that the second stream never runs ahead of `st`
+        AFQMC_HIP(hipEventRecord(s.half_join, s.half_stream), "event record");
+        AFQMC_HIP(hipStreamWaitEvent(st, s.half_join, 0), "stream wait");
+      }
+      AFQMC_HIP(e, "Taylor kernel");
     }
   }
   {
@@ -1750,6 +1932,8 @@ afqmc_status afqmc_get_info(const afqmc_ctx *ctx, int32_t isys, afqmc_info *out)
   out->graph_captures = ctx->graph_captures;
   out->graph_replays = ctx->graph_replays;
   out->cv_subset = s.ex_mode == AFQMC_EX_CV ? s.cv_k : 0;
+  out->vhs_tile = s.use_mfma_gemm && !s.prop32 ? s.vhs_shape : -1;
+  out->taylor_tile = s.prop32 || taylor_walker_split(s) ? s.taylor_shape : -1;
   out->reserved_info = 0;
   return AFQMC_OK;
 }

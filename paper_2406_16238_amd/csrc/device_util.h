@@ -131,4 +131,9 @@ __device__ __forceinline__ double wrap_phase(double a) {
   return r;
 }
 
+// s_waitcnt that waits until at most n vector-memory operations of the wave are
+// outstanding and leaves the LDS/scalar and export counters alone (gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+#define AFQMC_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (7 << 4) | (15 << 8) | ((((n) >> 4) & 3) << 14))
+
 }  // namespace afqmc

@@ -57,10 +57,6 @@ namespace {
 constexpr int LWX = 2;      // walkers per workgroup
 constexpr int LWY = 2;      // Cholesky-vector groups per workgroup
 constexpr int LKC = 32;     // contraction rows per LDS stage
-#ifndef AFQMC_EXCHANGE_DMA
-#define AFQMC_EXCHANGE_DMA 1
-#endif
-constexpr bool kExchangeDma = AFQMC_EXCHANGE_DMA;  // stage the split-BF16 operands by LDS DMA
 // Cholesky vectors per plane of the split-BF16 half rotation: G rounded up to
 // whole workgroup rows (LWY groups of at most two vectors), the extra vectors
 // zero, so every staged row a workgroup reads lies inside the planes.
@@ -289,26 +285,18 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
 // NT = 3 or 2: split-BF16 terms of Ltilde and Theta; NT = 1: the trial split,
 // one E term of Ltilde and of Q, with T0 transposed [G4][NR][NR], the inverse scales of
 // the Cholesky vectors lsc [G4] and of the walkers qsc [W].
-#ifndef AFQMC_SPLIT_STAGES
-#define AFQMC_SPLIT_STAGES 2
-#endif
-#ifndef AFQMC_SPLIT_KSUB
-#define AFQMC_SPLIT_KSUB 2
-#endif
-// LDS stages of the one-product (trial-split) form; the split-BF16 forms keep two
-__host__ __device__ constexpr int lp16_stages(int nt) { return nt == 1 ? AFQMC_SPLIT_STAGES : 2; }
+constexpr int kSplitKsub = 2;   // contraction runs per stage of the one-product form
+// LDS stages of the 16-bit forms (two at two workgroups per CU; deeper ones,
+// at one workgroup per CU, measured slower)
+__host__ __device__ constexpr int lp16_stages(int) { return 2; }
 // Staged planes per stage: the NT terms of the split-BF16 forms, or, for the
 // one-product form, KSUB consecutive runs of LKC contraction indices (a stage
 // then covers KSUB LKC indices: fewer barriers per contraction)
-__host__ __device__ constexpr int lp16_planes(int nt) { return nt == 1 ? AFQMC_SPLIT_KSUB : nt; }
-__host__ __device__ constexpr int lp16_kchunk(int nt) { return nt == 1 ? AFQMC_SPLIT_KSUB * LKC : LKC; }
+__host__ __device__ constexpr int lp16_planes(int nt) { return nt == 1 ? kSplitKsub : nt; }
+__host__ __device__ constexpr int lp16_kchunk(int nt) { return nt == 1 ? kSplitKsub * LKC : LKC; }
 // contraction length of the staged operands: M rounded up to whole chunks
 __host__ __device__ constexpr int lp16_kp(int nt, int M) { return (M + lp16_kchunk(nt) - 1) / lp16_kchunk(nt) * lp16_kchunk(nt); }
 
-// s_waitcnt that waits until at most n vector-memory operations of the wave are
-// outstanding and leaves the LDS/scalar and export counters alone (gfx9
-// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
-#define AFQMC_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (7 << 4) | (15 << 8) | ((((n) >> 4) & 3) << 14))
 
 template <int NR, int NT, typename E = __bf16>
 __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(const E *__restrict__ LtB,
@@ -333,7 +321,6 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
   constexpr int NP = lp16_planes(NT), KCH = lp16_kchunk(NT);
   constexpr int ASZ = NP * ROWS * RS, BSZ = NP * COLS * RS;   // 16-bit elements per stage
   constexpr int AV = NP * ROWS * (LKC / 8), BV = NP * COLS * (LKC / 8);  // 16-byte vectors per stage
-  constexpr int APT = (AV + kThreads - 1) / kThreads, BPT = (BV + kThreads - 1) / kThreads;
   constexpr int TSF = CP + 2;
   static_assert(ROWW % 16 == 0 && CP % 16 == 0 && LKC == 32, "row bases keep the swizzle of the lane's row");
   // Two staging buffers (one barrier per chunk).  The two-term form fits two
@@ -347,7 +334,6 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
   // With LDS DMA (global_load_lds_dwordx4: lane L's 16 bytes land at the wave's
   // LDS base + 16 L) a stage is filled straight from memory, 1 KB (16 staged
   // rows) per wave instruction (sources below).
-  constexpr bool DMA = kExchangeDma;
   static_assert(AV % 64 == 0 && BV % 64 == 0, "whole 1 KB blocks");
 
   int gb, wb;
@@ -359,50 +345,6 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
   // plane offsets: the next term, or (one-product form) the next LKC contraction indices
   const size_t aplane = NT == 1 ? (size_t)LKC : (size_t)lp_padded_g(G) * NR * Kp;
   const size_t bplane = NT == 1 ? (size_t)LKC : (size_t)W * CP * Kp;
-
-  uint4 ra[APT], rb[BPT];
-  auto load = [&](int q0) {
-#pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      const int v = tid + r * kThreads;                  // (p, row, k8)
-      const int k8 = v % (LKC / 8), t = v / (LKC / 8);
-      const int row = t % ROWS, p = t / ROWS;
-      const int gl = row / NR, i = row - gl * NR, g = g0 + gl;
-      ra[r] = (v < AV && g < G)
-                  ? *reinterpret_cast<const uint4 *>(LtB + p * aplane + ((size_t)g * NR + i) * Kp + q0 + 8 * k8)
-                  : make_uint4(0u, 0u, 0u, 0u);
-    }
-#pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int v = tid + r * kThreads;                  // (p, col, k8)
-      const int k8 = v % (LKC / 8), t = v / (LKC / 8);
-      const int col = t % COLS, p = t / COLS;
-      const int wl = col / CP, c = col - wl * CP, w = w0 + wl;
-      rb[r] = (v < BV && w < W)
-                  ? *reinterpret_cast<const uint4 *>(ThB + p * bplane + ((size_t)w * CP + c) * Kp + q0 + 8 * k8)
-                  : make_uint4(0u, 0u, 0u, 0u);
-    }
-  };
-  auto store = [&](int buf) {
-    E *a = sA + buf * ASZ;
-    E *b = sB + buf * BSZ;
-#pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      const int v = tid + r * kThreads;
-      if (v < AV) {
-        const int k8 = v % (LKC / 8), t = v / (LKC / 8);
-        *reinterpret_cast<uint4 *>(a + t * RS + 8 * (k8 ^ swz(t))) = ra[r];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int v = tid + r * kThreads;
-      if (v < BV) {
-        const int k8 = v % (LKC / 8), t = v / (LKC / 8);
-        *reinterpret_cast<uint4 *>(b + t * RS + 8 * (k8 ^ swz(t))) = rb[r];
-      }
-    }
-  };
 
   // LDS DMA sources: this lane's 16 bytes of every staged row it fills, as
   // element offsets at k = 0 (loop-invariant; a chunk adds q0 to the uniform
@@ -461,26 +403,17 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
   // LDS copies per chunk of the wave that issues fewest (the partial vmcnt
   // waits below count in these; a wave that issues more waits a little longer)
   constexpr int CMIN = (AV / 64) / 4 + (BV / 64) / 4;
-  if constexpr (DMA) {
-    // chunks 0 .. NBUF-2 in flight, then wait for chunk 0
-    for (int c = 0; c < NBUF - 1; ++c)
-      if (c < nchunk) issue(c * KCH, c);
-    if (NBUF > 2 && nchunk >= NBUF - 1) AFQMC_WAIT_VMCNT((NBUF - 2) * CMIN);
-    else __builtin_amdgcn_s_waitcnt(0);
-  } else {
-    load(0);
-    store(0);
-  }
+  // chunks 0 .. NBUF-2 in flight, then wait for chunk 0
+  for (int c = 0; c < NBUF - 1; ++c)
+    if (c < nchunk) issue(c * KCH, c);
+  if (NBUF > 2 && nchunk >= NBUF - 1) AFQMC_WAIT_VMCNT((NBUF - 2) * CMIN);
+  else __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch % NBUF;
-    if constexpr (DMA) {
-      // into the buffer read in chunk ch - 1 (every wave has passed the barrier after it)
-      if (ch + NBUF - 1 < nchunk) issue((ch + NBUF - 1) * KCH, (ch + NBUF - 1) % NBUF);
-    } else if (ch + 1 < nchunk) {
-      load((ch + 1) * KCH);
-    }
+    // into the buffer read in chunk ch - 1 (every wave has passed the barrier after it)
+    if (ch + NBUF - 1 < nchunk) issue((ch + NBUF - 1) * KCH, (ch + NBUF - 1) % NBUF);
     const E *a = sA + buf * ASZ + (wy * ROWW + lr) * RS + 8 * (lk ^ swz(lr));
     const E *b = sB + buf * BSZ + (wx * CP + lr) * RS + 8 * (lk ^ swz(lr));
     if constexpr (NT == 1) {
@@ -498,13 +431,9 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
           for (int j = 0; j < CT; ++j) acc[i][j] = mfma16x16x32(ah[i], bh[j], acc[i][j]);
       }
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (DMA) {
-        // this wave's copies of chunk ch + 1 have landed (later chunks' may not)
-        if (NBUF > 2 && ch + NBUF - 1 < nchunk) AFQMC_WAIT_VMCNT((NBUF - 2) * CMIN);
-        else __builtin_amdgcn_s_waitcnt(0);
-      } else if (ch + 1 < nchunk) {
-        store((ch + 1) % NBUF);
-      }
+      // this wave's copies of chunk ch + 1 have landed (later chunks' may not)
+      if (NBUF > 2 && ch + NBUF - 1 < nchunk) AFQMC_WAIT_VMCNT((NBUF - 2) * CMIN);
+      else __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       continue;
     }
@@ -553,11 +482,7 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
     // scheduler would otherwise sink most of them below the barrier, leaving
     // the copies a fraction of the chunk to land in)
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (DMA) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into the other buffer have landed
-    } else if (ch + 1 < nchunk) {
-      store((ch + 1) % NBUF);
-    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into the other buffer have landed
     __syncthreads();
   }
 

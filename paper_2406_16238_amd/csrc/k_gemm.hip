@@ -219,7 +219,7 @@ hipError_t launch_vhs(const System &s, int W, hipStream_t st, bool imag_only) {
     a.n = (int)Mp;
     a.B = s.Lp; a.sbk = Mp; a.sbj = 1;
     a.C = s.vhsp + (size_t)roff * Mp; a.sci = rstride * Mp; a.scj = 1;
-    hipError_t e = gemm_vhs_mfma(a, st, s.vhs_variant);
+    hipError_t e = gemm_vhs_mfma(a, st, s.vhs_shape);
     if (e != hipSuccess) return e;
     if (s.prop32) return launch_unpack_f32(s, W, st, imag_only);
     const int nt = (s.M + 31) / 32;
@@ -230,7 +230,7 @@ hipError_t launch_vhs(const System &s, int W, hipStream_t st, bool imag_only) {
   a.n = (int)MM;
   a.B = s.L; a.sbk = MM; a.sbj = 1;
   a.C = s.vhs + (size_t)roff * MM; a.sci = rstride * MM; a.scj = 1;
-  return s.use_mfma_gemm ? gemm_vhs_mfma(a, st, s.vhs_variant) : gemm_f64(a, st);
+  return s.use_mfma_gemm ? gemm_vhs_mfma(a, st, s.vhs_shape) : gemm_f64(a, st);
 }
 
 // ---- one-body half step: out_w = B1 in_w (complex columns as real pairs) -----

@@ -273,21 +273,18 @@ hipError_t run(const GemmArgs &a, hipStream_t st) {
 
 }  // namespace
 
-// V_HS planes: rows (w, c) = 2W, columns M^2, contraction over G.
-// Default: 128 x 128 tiles, 64 x 64 per wave, two waves per SIMD (245
-// registers since the operand loads became affine; measured 7 % faster at the
-// headline shape than 128 x 96 tiles, which led while the loads needed more
-// registers); the other shapes are kept for comparison runs.
-hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st, int variant) {
-  switch (variant) {
-    case 1: return run<2, 2, 4, 4, 0, 0, 1>(a, st);
-    case 2: return run<2, 2, 4, 3, 0, 0, 2>(a, st);
-    case 3: return run<2, 2, 2, 4, 0, 0, 2>(a, st);
-    case 4: return run<1, 4, 8, 2, 0, 0, 1>(a, st);
-    case 5: return run<4, 1, 2, 6, 0, 0, 2>(a, st);
-    case 6: return run<4, 1, 2, 5, 0, 0, 2>(a, st);
-    case 7: return run<4, 1, 2, 4, 0, 0, 2>(a, st);
-    case 8: return run<4, 1, 1, 8, 0, 0, 2>(a, st);
+// V_HS planes: rows (w, c) = 2W, columns M^2 (or the packed M(M+1)/2),
+// contraction over G.  Default: 128 x 128 tiles, 64 x 64 per wave, two waves
+// per SIMD (245 registers since the operand loads became affine; measured 7 %
+// faster at the headline shape than 128 x 96 tiles).
+hipError_t gemm_vhs_mfma(const GemmArgs &a, hipStream_t st, int shape) {
+  // rows x columns of a workgroup tile: 128 x 128 (default), 128 x 96,
+  // 64 x 128 and 128 x 64, all at two waves per SIMD; the set-up tuner times
+  // them per problem shape
+  switch (shape) {
+    case 1: return run<2, 2, 4, 3, 0, 0, 2>(a, st);
+    case 2: return run<2, 2, 2, 4, 0, 0, 2>(a, st);
+    case 3: return run<4, 1, 2, 4, 0, 0, 2>(a, st);
     default: return run<2, 2, 4, 4, 0, 0, 2>(a, st);
   }
 }

@@ -2,332 +2,240 @@
 // walker slabs (Sec. 2, eq. Bprop, exp(sqrt(dt) V_HS) phi by its series):
 //   T_out = alpha * A_w T_in,   tacc += T_out,
 // with A_w = sqrt(dt) V_HS of walker w held as real and imaginary M x M planes
-// and T complex M x Nt.  As one real product per walker: rows i, columns
-// c = (j, re/im) interleaved, contraction over the two planes times q,
-//   [Re A | Im A] (M x 2M)  x  [T ; iT] (2M x 2Nt),   iT = (-Im T, Re T).
+// and T complex M x Nt, in three real products instead of four (the 3M form of
+// a complex product): with A = Ar + i Ai and T = Tr + i Ti,
+//   P1 = Ar Tr,  P2 = Ai Ti,  P3 = (Ar + Ai)(Tr + Ti),
+//   A T = (P1 - P2) + i (P3 - P1 - P2),
+// each an M x M by M x Nt real product, so a term costs 6 M^2 Nt flops instead
+// of 8.  IMAG: A = i Ai (free projection, a real-field V_HS): A T = -Ai Ti +
+// i Ai Tr, two products, and only the Ai plane is read.
 //
-// A workgroup owns BM = 4 WM TR rows and all BN = 16 WN TN >= 2 Nt columns of
-// one walker, on a WM x WN grid of waves (4 TR rows x 16 TN columns each), so the
-// walker's A rows are read from memory exactly once and its T (M x Nt, 16 M Nt
-// bytes) is shared by the M / BM row tiles, which the launch order places on
-// one XCD.  Each wave issues TR x TN v_mfma_f64_4x4x4_4b_f64 per 4 contraction
-// indices (lane 16k+4b+i supplies A_b[i][k], lane 16k+4b+j supplies B_b[k][j],
-// lane 16i+4b+j receives D_b[i][j]; the four blocks are the four 4-column
-// groups of one 16-column group).  The contraction is staged 16 indices at a
-// time in LDS (k-major, padded rows) with 16-byte global loads, double-buffered
-// through registers.  M must be even (16-byte loads of A never straddle the two
-// planes) and Nt at most 96; other shapes use the generic GEMM.  The contraction
-// starts at kbeg: 0, or M to skip a real plane that is zero (free projection,
-// where V_HS is purely imaginary).
+// A workgroup owns BM = 4 TR NCW rows and all 16 TN >= Nt complex columns of
+// one walker: compute wave w holds rows 4 TR w .. 4 TR (w + 1) - 1 and the
+// three products of its rows, so the combination happens in registers and
+// each lane writes whole complex entries.  The walker's A rows are read from
+// memory once and its T (16 M Nt bytes) is shared by the M / BM row tiles,
+// which the launch order places on one XCD.  Each wave issues TR x TN
+// v_mfma_f64_4x4x4_4b_f64 per product and 4 contraction indices (lane
+// 16k+4b+i supplies A_b[i][k], lane 16k+4b+j supplies B_b[k][j], lane
+// 16i+4b+j receives D_b[i][j]; the four blocks are the four 4-column groups of
+// one 16-column group, so A is the same for the four blocks).  M must be even
+// and Nt at most 96; other shapes use the generic GEMM.
+#include <type_traits>
+
 #include "afqmc_internal.h"
 #include "device_util.h"
 
 namespace afqmc {
 
-namespace {
-constexpr int TKC = 16;  // contraction indices per LDS stage
+// The three-product term with both operands staged in LDS by DMA
+// (buffer_load ... lds: lane L's 16 bytes land at the wave's LDS base + 16 L)
+// through NBUF stages of TKC contraction indices.  One extra wave only copies:
+// it issues the copies of chunk ch + NBUF - 1 while the NCW compute waves work
+// on chunk ch, waits for chunk ch + 1, and meets them at the barrier that ends
+// the chunk.  The compute waves issue no copies, so their LDS reads never wait
+// on one (the compiler makes any LDS read of a wave with copies in flight wait
+// for all of them).
+// A stage holds the workgroup's rows of both V_HS planes ([plane][row][TKC],
+// the 16-byte slots of row r swizzled by sw(r)) and TKC rows of T as they lie
+// in memory (Nt interleaved complex entries a row).  In MFMA step s of a
+// chunk, lane group g = lane >> 4 contracts index k0 + KS g + s
+// (KS = TKC / 4), so a lane's A values of a chunk are consecutive in k and
+// come in 16-byte reads.  Rows past M read row M - 1 (dropped at the store);
+// contraction indices past M read zeros or finite values of the same walker
+// against T rows that are zero: the copies' buffer resources end at the
+// walker's data, and a buffer load whose offset (the VGPR part, which carries
+// the whole offset here) lies past the end returns zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+// one 16-byte LDS copy per lane (non-template: the host pass drops a kernel
+// template that names this builtin itself)
+__device__ __forceinline__ void lds_copy16(__amdgpu_buffer_rsrc_t r, void *lds, int voff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds, 16, voff, 0, 0, 0);
 }
 
-template <int WM, int WN, int TR, int TN>
-__global__ __launch_bounds__(64 * WM * WN) void k_taylor_mfma(const double *__restrict__ vhs,
-                                                             const double2 *__restrict__ tin,
-                                                             double2 *__restrict__ tout, double2 *__restrict__ tacc,
-                                                             int M, int Nt, int W, int nrt, double alpha,
-                                                             int kbeg) {
-  constexpr int NTH = 64 * WM * WN;
-  constexpr int BM = WM * 4 * TR, BN = WN * 16 * TN;
-  constexpr int LDA = BM + 1, LDB = BN + 1;
-  constexpr int AV = BM * TKC / 2;                 // double2 of A per stage
-  constexpr int BV = TKC * BN / 2;                 // double2 of B per stage
-  constexpr int APT = (AV + NTH - 1) / NTH, BPT = (BV + NTH - 1) / NTH;
-  extern __shared__ double tsm[];
-  double *sA = tsm;                    // [2][TKC][LDA]
-  double *sB = tsm + 2 * TKC * LDA;    // [2][TKC][LDB]
-
-  // contiguous stretch of (walker, row tile) per XCD (workgroups are dealt to
-  // the 8 XCDs round-robin), row tile fastest
-  const int ntiles = W * nrt;
-  const int per = ntiles >> 3, rem = ntiles & 7;
-  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
-  const int t = x * per + min(x, rem) + jx;
-  const int w = t / nrt, i0 = (t - w * nrt) * BM;
-
-  const size_t MM = (size_t)M * M;
-  const double *Aw = vhs + (size_t)w * 2 * MM;
-  const double2 *Tw = tin + (size_t)w * M * Nt;
-  const int K = 2 * M, cols = 2 * Nt;
-
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv / WN, wn = wv - (wv / WN) * WN;
-  const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
-
-  double2 ra[APT], rb[BPT];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * NTH;                 // (row, k pair)
-      const int row = e / (TKC / 2), kp = e - row * (TKC / 2);
-      const int gi = i0 + row, gk = k0 + 2 * kp;
-      ra[r] = (e < AV && gi < M && gk < K)
-                  ? *reinterpret_cast<const double2 *>(Aw + (gk >= M ? MM : 0) + (size_t)gi * M + (gk >= M ? gk - M : gk))
-                  : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * NTH;                 // (k, complex column j)
-      const int kk = e / (BN / 2), j = e - kk * (BN / 2);
-      const int gk = k0 + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (e < BV && j < Nt && gk < K) {
-        const double2 z = Tw[(size_t)(gk >= M ? gk - M : gk) * Nt + j];
-        v = gk >= M ? make_double2(-z.y, z.x) : z;
-      }
-      rb[r] = v;
-    }
-  };
-  auto store = [&](int buf) {
-    double *a = sA + buf * TKC * LDA;
-    double *b = sB + buf * TKC * LDB;
-#pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * NTH;
-      if (e < AV) {
-        const int row = e / (TKC / 2), kp = e - row * (TKC / 2);
-        a[(2 * kp) * LDA + row] = ra[r].x;
-        a[(2 * kp + 1) * LDA + row] = ra[r].y;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * NTH;
-      if (e < BV) {
-        const int kk = e / (BN / 2), j = e - kk * (BN / 2);
-        b[kk * LDB + 2 * j] = rb[r].x;
-        b[kk * LDB + 2 * j + 1] = rb[r].y;
-      }
-    }
-  };
-
-  constexpr int TRW = TR;  // 4-row slabs per wave
-  double acc[TRW][TN];
-#pragma unroll
-  for (int i = 0; i < TRW; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
-
-  const int nchunk = (K - kbeg + TKC - 1) / TKC;
-  load(kbeg);
-  store(0);
-  __syncthreads();
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nchunk) load(kbeg + (ch + 1) * TKC);
-    const double *a = sA + buf * TKC * LDA + wm * 4 * TR + l4;
-    const double *b = sB + buf * TKC * LDB + wn * 16 * TN + lr;
-#pragma unroll
-    for (int ks = 0; ks < TKC / 4; ++ks) {
-      double av[TRW], bv[TN];
-#pragma unroll
-      for (int i = 0; i < TRW; ++i) av[i] = a[(ks * 4 + lk) * LDA + i * 4];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bv[j] = b[(ks * 4 + lk) * LDB + j * 16];
-#pragma unroll
-      for (int i = 0; i < TRW; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    if (ch + 1 < nchunk) store(buf ^ 1);
-    __syncthreads();
-  }
-
-  double *to = reinterpret_cast<double *>(tout + (size_t)w * M * Nt);
-  double *ta = reinterpret_cast<double *>(tacc + (size_t)w * M * Nt);
-#pragma unroll
-  for (int i = 0; i < TRW; ++i) {
-    const int gi = i0 + wm * 4 * TR + 4 * i + lk;
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int c = wn * 16 * TN + 16 * j + lr;
-      if (gi < M && c < cols) {
-        const size_t off = (size_t)gi * cols + c;
-        const double v = alpha * acc[i][j];
-        to[off] = v;
-        ta[off] += v;
-      }
-    }
-  }
-}
-
-// The same term with three real products instead of four (the 3M form of a
-// complex product): with A = Ar + i Ai and T = Tr + i Ti,
-//   P1 = Ar Tr,  P2 = Ai Ti,  P3 = (Ar + Ai)(Tr + Ti),
-//   A T = (P1 - P2) + i (P3 - P1 - P2),
-// each an M x M by M x Nt real product, so a term costs 6 M^2 Nt flops instead
-// of 8.  A workgroup owns BM = 4 WM TR rows and BNC = 16 WN TN >= Nt complex
-// columns of one walker; wave (wm, wn) holds the three products of its
-// 4 TR x 16 TN block, so the combination happens in registers and each lane
-// writes whole complex entries.  Ar + Ai and Tr + Ti are formed from the
-// staged operands in registers.  LDS per stage: the Ar and Ai rows (k-major)
-// and the Tr and Ti planes of 16 contraction indices.
-// IMAG: A = i Ai (free projection, a real-field V_HS): A T = -Ai Ti + i Ai Tr,
-// two products P1 = Ai Tr, P2 = Ai Ti and only the Ai rows staged.
-template <int WM, int WN, int TR, int TN, bool IMAG = false>
-__global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__restrict__ vhs,
-                                                             const double2 *__restrict__ tin,
-                                                             double2 *__restrict__ tout,
-                                                             double2 *__restrict__ tacc, int M, int Nt, int W,
-                                                             int nrt, double alpha) {
-  constexpr int NTH = 64 * WM * WN;
-  constexpr int BM = WM * 4 * TR, BNC = WN * 16 * TN;
-  constexpr int LDA = BM + 1, LDB = BNC + 1;
-  constexpr int NPL = IMAG ? 1 : 2;                 // staged planes of A
-  constexpr int AV = NPL * BM * TKC / 2;            // double2 (k pairs) of A per stage
-  constexpr int BV = TKC * BNC;                     // complex entries of T per stage
-  constexpr int APT = (AV + NTH - 1) / NTH, BPT = (BV + NTH - 1) / NTH;
-  extern __shared__ double tsm[];
-  double *sA = tsm;                          // [2 buf][NPL plane][TKC][LDA]
-  double *sB = tsm + 2 * NPL * TKC * LDA;    // [2 buf][2 plane][TKC][LDB]
+template <int TR, int TN, bool IMAG, int TKC_, int NBUF, int NCW>
+__global__ __launch_bounds__(64 * (NCW + 1)) __attribute__((amdgpu_waves_per_eu(3))) void k_taylor3s(const double *__restrict__ vhs,
+                                                                 const double2 *__restrict__ tin,
+                                                                 double2 *__restrict__ tout,
+                                                                 double2 *__restrict__ tacc, int M, int Nt, int W,
+                                                                 int nrt, double alpha) {
+  constexpr int BM = 4 * TR * NCW, KS = TKC_ / 4, SLOTS = TKC_ / 2;   // 16-byte slots per staged A row
+  constexpr int NPL = IMAG ? 1 : 2;
+  constexpr int AROWS = NPL * BM, AI = (AROWS * SLOTS + 63) / 64;    // copy instructions of an A stage
+  constexpr int TI = (TKC_ * 16 * TN + 63) / 64;                    // of a T stage (Nt <= 16 TN entries a row)
+  constexpr int NI = AI + TI, D = NBUF - 1;                         // D chunks in flight
+  static_assert((D - 1) * NI < 64, "vmcnt range");
+  static_assert(NCW % 4 == 0, "compute waves spread evenly over the SIMDs");
+  auto sw = [](int r) { return TKC_ == 16 ? (r >> 1) & 1 : 0; };
+  extern __shared__ __attribute__((aligned(16))) double2 ssh[];
+  double2 *sA = ssh;                                               // [NBUF][AI * 64]
+  double2 *sT = ssh + NBUF * AI * 64;                              // [NBUF][TI * 64]
 
   const int ntiles = W * nrt;
   const int per = ntiles >> 3, rem = ntiles & 7;
   const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
   const int t = x * per + min(x, rem) + jx;
   const int w = t / nrt, i0 = (t - w * nrt) * BM;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wm = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nchunk = (M + TKC_ - 1) / TKC_;
+  const int rbase = i0 + wm * 4 * TR;
+  const bool live = rbase < M;   // a compute wave whose rows all lie past M issues no MFMA
 
-  const size_t MM = (size_t)M * M;
-  const double *Aw = vhs + (size_t)w * 2 * MM;
-  const double2 *Tw = tin + (size_t)w * M * Nt;
-
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv / WN, wn = wv - (wv / WN) * WN;
-  const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
-
-  // Loop-invariant addressing: A element (plane, row, k pair) e = tid + NTH r
-  // keeps its source offset at k = 0 and its LDS slot; T is loaded as columns
-  // t%16 + 16c of contraction row t/16.  Interior chunks skip the bounds tests.
-  static_assert(BPT * NTH == BV && NTH == 16 * TKC, "T staged as t%16 + 16c, row t/16");
-  const int tq = tid >> 4, tl = tid & 15;
-  size_t offa[APT];
-  int sla[APT];
-  bool rowa[APT];
+  if (wm == NCW) {
+    // the copy wave: instruction q of a stage is A block q (q < AI) or T block
+    // q - AI; the lane's byte offset at chunk 0 (a chunk adds k0 * 8 for A,
+    // k0 * Nt * 16 for T)
+    const int MM = M * M;
+    const __amdgpu_buffer_rsrc_t ares =
+        buffer_rsrc(vhs + (size_t)w * 2 * MM + (IMAG ? MM : 0), (uint32_t)NPL * MM * 8u);
+    const __amdgpu_buffer_rsrc_t tres = buffer_rsrc(tin + (size_t)w * M * Nt, (uint32_t)M * Nt * 16u);
+    int qoff[NI];
 #pragma unroll
-  for (int r = 0; r < APT; ++r) {
-    const int e = tid + r * NTH;                   // (plane, row, k pair)
-    const int pr = e / (TKC / 2), kp = e - pr * (TKC / 2);
-    const int pl = pr / BM, row = pr - pl * BM;
-    offa[r] = (IMAG ? 1 : pl) * MM + (size_t)(i0 + row) * M + 2 * kp;
-    sla[r] = (pl * TKC + 2 * kp) * LDA + row;
-    rowa[r] = e < AV && i0 + row < M;
-  }
-  const bool rows_in = i0 + BM <= M && AV % NTH == 0, cols_in = BNC <= Nt;
-  const int kpl = 2 * ((tid % (TKC / 2)));         // the k pair of every A element of this thread
-
-  double2 ra[APT], rb[BPT];
-  auto load = [&](int k0) {
-    const double2 *pb = Tw + (size_t)(k0 + tq) * Nt + tl;
-    if (rows_in && cols_in && k0 + TKC <= M) {
-#pragma unroll
-      for (int r = 0; r < APT; ++r) ra[r] = *reinterpret_cast<const double2 *>(Aw + offa[r] + k0);
-#pragma unroll
-      for (int c = 0; c < BPT; ++c) rb[c] = pb[16 * c];
-    } else {
-      const bool ka = k0 + kpl < M, kb = k0 + tq < M;
-#pragma unroll
-      for (int r = 0; r < APT; ++r)
-        ra[r] = (rowa[r] && ka) ? *reinterpret_cast<const double2 *>(Aw + offa[r] + k0) : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int c = 0; c < BPT; ++c) rb[c] = (kb && tl + 16 * c < Nt) ? pb[16 * c] : make_double2(0.0, 0.0);
-    }
-  };
-  auto store = [&](int buf) {
-    double *a = sA + buf * NPL * TKC * LDA;
-    double *b = sB + buf * 2 * TKC * LDB;
-#pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      if (AV % NTH == 0 || tid + r * NTH < AV) {
-        a[sla[r]] = ra[r].x;
-        a[sla[r] + LDA] = ra[r].y;
+    for (int q = 0; q < NI; ++q) {
+      if (q < AI) {
+        const int e = q * 64 + lane, row = e / SLOTS, slot = e - row * SLOTS;
+        const int p = row / BM, r = row - p * BM;
+        qoff[q] = (p * MM + min(i0 + r, M - 1) * M + 2 * (slot ^ sw(r))) * 8;
+      } else {
+        qoff[q] = ((q - AI) * 64 + lane) * 16;
       }
     }
+    auto issue = [&](int ch) {
+      const int buf = ch % NBUF, k0 = ch * TKC_;
 #pragma unroll
-    for (int c = 0; c < BPT; ++c) {
-      b[tq * LDB + tl + 16 * c] = rb[c].x;
-      b[(TKC + tq) * LDB + tl + 16 * c] = rb[c].y;
+      for (int q = 0; q < NI; ++q) {
+        if (q < AI)
+          lds_copy16(ares, sA + (buf * AI + q) * 64, qoff[q] + k0 * 8);
+        else
+          lds_copy16(tres, sT + (buf * TI + q - AI) * 64, qoff[q] + k0 * Nt * 16);
+      }
+    };
+#pragma unroll
+    for (int c = 0; c < D; ++c) issue(c);
+    // the copies complete in order: with those of the D - 1 later chunks at
+    // most outstanding, the next chunk has landed.  Copies past the last chunk
+    // read zeros or unused values into stages no one reads, which keeps every
+    // wait's count the same.  Bare barriers: a fence would wait for every copy.
+    AFQMC_WAIT_VMCNT((D - 1) * NI);
+    __builtin_amdgcn_s_barrier();
+    for (int c = 0; c < nchunk; ++c) {
+      issue(c + D);
+      AFQMC_WAIT_VMCNT((D - 1) * NI);
+      __builtin_amdgcn_s_barrier();
     }
-  };
+    AFQMC_WAIT_VMCNT(0);   // no copy may outlive the workgroup's LDS
+    return;
+  }
 
+  const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
   double p1[TR][TN], p2[TR][TN], p3[TR][TN];
 #pragma unroll
   for (int i = 0; i < TR; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = 0.0;
 
-  const int nchunk = (M + TKC - 1) / TKC;
-  // a wave of the last row tile whose rows all lie past M stages operands with
-  // the others but issues no MFMA
-  const bool live = i0 + wm * 4 * TR < M;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nchunk) load((ch + 1) * TKC);
-    const double *ar = sA + buf * NPL * TKC * LDA + wm * 4 * TR + l4;
-    const double *ai = IMAG ? ar : ar + TKC * LDA;
-    const double *br = sB + buf * 2 * TKC * LDB + wn * 16 * TN + lr;
-    const double *bi = br + TKC * LDB;
+  // operands of one MFMA step: the lane's A pair of steps 2h, 2h + 1 (slab i,
+  // plane p) and its B entries (Re, Im); those of the next step are read
+  // before the MFMAs of this one.
+  auto read_a = [&](int stage, int h, double2 (&dst)[NPL][TR]) {
+    const double2 *a = sA + stage * AI * 64;
 #pragma unroll
-    for (int ks = 0; ks < (live ? TKC / 4 : 0); ++ks) {
-      const int kr = ks * 4 + lk;
-      double xr[TR], xi[TR], yr[TN], yi[TN];
+    for (int p = 0; p < NPL; ++p)
 #pragma unroll
       for (int i = 0; i < TR; ++i) {
-        xi[i] = ai[kr * LDA + i * 4];
-        xr[i] = IMAG ? 0.0 : ar[kr * LDA + i * 4];
+        const int r = wm * 4 * TR + 4 * i + l4;
+        dst[p][i] = a[(p * BM + r) * SLOTS + (((KS / 2) * lk + h) ^ sw(r))];
       }
+  };
+  auto read_b = [&](int stage, int s, double2 (&dst)[TN]) {
+    const double2 *b = sT + stage * TI * 64 + (KS * lk + s) * Nt + lr;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) dst[j] = b[16 * j];
+  };
+  double2 av[NPL][TR], bv[TN];
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    if (!live) {
+      __syncthreads();
+      continue;
+    }
+    const int stage = ch % NBUF;
+    read_a(stage, 0, av);
+    read_b(stage, 0, bv);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      double2 an[NPL][TR], bn[TN];
+      const bool last = s + 1 == KS;
+      if (!last) {
+        read_b(stage, s + 1, bn);
+        if ((s + 1) % 2 == 0) read_a(stage, (s + 1) / 2, an);
+      }
+      double yr[TN], yi[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        yr[j] = br[kr * LDB + j * 16];
-        yi[j] = bi[kr * LDB + j * 16];
+        yr[j] = bv[j].x;
+        yi[j] = bv[j].y;
       }
+      auto aval = [&](int p, int i) { return (s & 1) ? av[p][i].y : av[p][i].x; };
       if constexpr (IMAG) {
+#pragma unroll
+        for (int i = 0; i < TR; ++i) {
+          const double xi = aval(0, i);
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi, yr[j], p1[i][j], 0, 0, 0);
+            p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi, yi[j], p2[i][j], 0, 0, 0);
+          }
+        }
+      } else {
+        double xr[TR], xi[TR];
+#pragma unroll
+        for (int i = 0; i < TR; ++i) {
+          xr[i] = aval(0, i);
+          xi[i] = aval(1, i);
+        }
 #pragma unroll
         for (int i = 0; i < TR; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j) {
-            p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi[i], yr[j], p1[i][j], 0, 0, 0);
+            p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p1[i][j], 0, 0, 0);
             p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
           }
-        continue;
+#pragma unroll
+        for (int i = 0; i < TR; ++i) xr[i] += xi[i];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) yr[j] += yi[j];
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            p3[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p3[i][j], 0, 0, 0);
       }
+      if (!last) {
 #pragma unroll
-      for (int i = 0; i < TR; ++i)
+        for (int j = 0; j < TN; ++j) bv[j] = bn[j];
+        if ((s + 1) % 2 == 0)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p1[i][j], 0, 0, 0);
-          p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
-        }
+          for (int p = 0; p < NPL; ++p)
 #pragma unroll
-      for (int i = 0; i < TR; ++i) xr[i] += xi[i];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) yr[j] += yi[j];
-#pragma unroll
-      for (int i = 0; i < TR; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) p3[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p3[i][j], 0, 0, 0);
+            for (int i = 0; i < TR; ++i) av[p][i] = an[p][i];
+      }
     }
-    if (ch + 1 < nchunk) store(buf ^ 1);
     __syncthreads();
   }
+  if (!live) return;
 
   double2 *to = tout + (size_t)w * M * Nt;
   double2 *ta = tacc + (size_t)w * M * Nt;
 #pragma unroll
   for (int i = 0; i < TR; ++i) {
-    const int gi = i0 + wm * 4 * TR + 4 * i + lk;
+    const int gi = rbase + 4 * i + lk;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      const int c = wn * 16 * TN + 16 * j + lr;
+      const int c = 16 * j + lr;
       if (gi < M && c < Nt) {
         const size_t off = (size_t)gi * Nt + c;
         const double re = IMAG ? -p2[i][j] : p1[i][j] - p2[i][j];
@@ -342,99 +250,64 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_taylor3m(const double *__re
 }
 
 namespace {
-template <int WM, int WN, int TR, int TN>
-hipError_t run_taylor(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
-                      int kbeg) {
-  constexpr int BM = WM * 4 * TR, BN = WN * 16 * TN;
-  static_assert(BN >= 2, "columns");
-  const size_t lds = 2ull * TKC * ((BM + 1) + (BN + 1)) * sizeof(double);
-  auto k = k_taylor_mfma<WM, WN, TR, TN>;
+constexpr int kTaylorKc = 8;     // contraction indices per stage
+constexpr int kTaylorStages = 4;
+
+template <int TR, int NCW, int TN, bool IMAG>
+hipError_t run_taylor3s(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
+                        int w0) {
+  constexpr int BM = 4 * TR * NCW, TK = kTaylorKc, NB = kTaylorStages;
+  const int ai = ((IMAG ? 1 : 2) * BM * (TK / 2) + 63) / 64, ti = (TK * 16 * TN + 63) / 64;
+  const size_t lds = (size_t)NB * (ai + ti) * 64 * sizeof(double2);
+  auto k = k_taylor3s<TR, TN, IMAG, TK, NB, NCW>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+                                       80 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
+  if (lds > 80 * 1024) return hipErrorInvalidValue;
   const int nrt = (s.M + BM - 1) / BM;
-  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * WM * WN), lds, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt,
-                     W, nrt, alpha, kbeg);
-  return hipGetLastError();
-}
-}  // namespace
-
-namespace {
-template <int WM, int WN, int TR, int TN, bool IMAG = false>
-hipError_t run_taylor3m(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
-  constexpr int BM = WM * 4 * TR, BNC = WN * 16 * TN;
-  const size_t lds = 2ull * TKC * ((IMAG ? 1 : 2) * (BM + 1) + 2 * (BNC + 1)) * sizeof(double);
-  auto k = k_taylor3m<WM, WN, TR, TN, IMAG>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  const int nrt = (s.M + BM - 1) / BM;
-  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * WM * WN), lds, st, s.vhs, tin, tout, s.tacc, s.M, s.Nt,
-                     W, nrt, alpha);
+  const size_t wt = (size_t)w0 * s.M * s.Nt;
+  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * (NCW + 1)), lds, st, s.vhs + (size_t)w0 * 2 * s.M * s.M,
+                     tin + wt, tout + wt, s.tacc + wt, s.M, s.Nt, W, nrt, alpha);
   return hipGetLastError();
 }
 
-template <int TR, bool IMAG = false>
-hipError_t run_taylor3m_tn(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st) {
+template <int TR, bool IMAG>
+hipError_t run_taylor3s_tn(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
+                           int w0) {
   switch ((s.Nt + 15) / 16) {
-    case 1: return run_taylor3m<4, 1, TR, 1, IMAG>(s, tin, tout, alpha, W, st);
-    case 2: return run_taylor3m<4, 1, TR, 2, IMAG>(s, tin, tout, alpha, W, st);
-    case 3: return run_taylor3m<4, 1, TR, 3, IMAG>(s, tin, tout, alpha, W, st);
-    case 4: return run_taylor3m<4, 1, TR, 4, IMAG>(s, tin, tout, alpha, W, st);
-    case 5: return run_taylor3m<4, 1, TR, 5, IMAG>(s, tin, tout, alpha, W, st);
+    case 1: return run_taylor3s<TR, 4, 1, IMAG>(s, tin, tout, alpha, W, st, w0);
+    case 2: return run_taylor3s<TR, 4, 2, IMAG>(s, tin, tout, alpha, W, st, w0);
+    case 3: return run_taylor3s<TR, 4, 3, IMAG>(s, tin, tout, alpha, W, st, w0);
+    case 4: return run_taylor3s<TR, 4, 4, IMAG>(s, tin, tout, alpha, W, st, w0);
+    case 5: return run_taylor3s<TR, 4, 5, IMAG>(s, tin, tout, alpha, W, st, w0);
     // 96 columns: 32-row tiles keep the three accumulator sets in registers
-    default: return run_taylor3m<4, 1, 2, 6, IMAG>(s, tin, tout, alpha, W, st);
+    default: return run_taylor3s<2, 4, 6, IMAG>(s, tin, tout, alpha, W, st, w0);
   }
 }
 }  // namespace
 
 bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <= 96; }
 
+bool taylor_walker_split(const System &s) {
+  return s.use_mfma_gemm && s.taylor_kernel && taylor_mfma_supported(s.M, s.Nt);
+}
+
+int taylor_shapes(const System &s) { return s.prop32 ? 3 : 2; }
+
+// shape 0: 48-row tiles, 1: 32-row tiles
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st, int kbeg) {
-  // a complex V_HS: three real products per term (taylor4, or variants 1..8,
-  // keep the four-product kernel for comparison runs; 9..10 other 3M row tiles)
-  if (!s.taylor4 && (s.taylor_variant == 0 || s.taylor_variant >= 9)) {
-    if (kbeg != 0) {
-      // purely imaginary V_HS (its real plane is not formed): two products
-      if (kbeg != s.M) return hipErrorInvalidValue;
-      return s.taylor_variant == 10 ? run_taylor3m_tn<4, true>(s, tin, tout, alpha, W, st)
-                                    : run_taylor3m_tn<3, true>(s, tin, tout, alpha, W, st);
-    }
-    switch (s.taylor_variant) {
-      case 9: return run_taylor3m_tn<2>(s, tin, tout, alpha, W, st);
-      case 10: return run_taylor3m_tn<4>(s, tin, tout, alpha, W, st);
-      default: return run_taylor3m_tn<3>(s, tin, tout, alpha, W, st);
-    }
-  }
-  if (s.Nt <= 16) return run_taylor<2, 2, 16, 1>(s, tin, tout, alpha, W, st, kbeg);
-  if (s.Nt <= 32) return run_taylor<2, 2, 16, 2>(s, tin, tout, alpha, W, st, kbeg);
-  if (s.Nt <= 48) return run_taylor<2, 2, 12, 3>(s, tin, tout, alpha, W, st, kbeg);
-  if (s.Nt <= 64) return run_taylor<2, 2, 12, 4>(s, tin, tout, alpha, W, st, kbeg);
-  if (s.Nt <= 80) {
-    switch (s.taylor_variant) {
-      case 1: return run_taylor<2, 1, 10, 10>(s, tin, tout, alpha, W, st, kbeg);
-      case 2: return run_taylor<1, 2, 20, 5>(s, tin, tout, alpha, W, st, kbeg);
-      case 3: return run_taylor<2, 2, 20, 5>(s, tin, tout, alpha, W, st, kbeg);
-      case 4: return run_taylor<4, 1, 5, 10>(s, tin, tout, alpha, W, st, kbeg);
-      case 5: return run_taylor<2, 2, 10, 5>(s, tin, tout, alpha, W, st, kbeg);
-      case 6: return run_taylor<2, 2, 4, 5>(s, tin, tout, alpha, W, st, kbeg);
-      case 7: return run_taylor<2, 2, 7, 5>(s, tin, tout, alpha, W, st, kbeg);
-      case 8: return run_taylor<2, 2, 8, 5>(s, tin, tout, alpha, W, st, kbeg);
-      // default 48-row tiles: at the headline shape 0.82 ms per term against
-      // 0.93 for 80 rows (a shorter grid tail at three waves per SIMD)
-      default: return run_taylor<2, 2, 6, 5>(s, tin, tout, alpha, W, st, kbeg);
-    }
-  }
-  return run_taylor<2, 2, 8, 6>(s, tin, tout, alpha, W, st, kbeg);
+                              hipStream_t st, int kbeg, int w0) {
+  const bool imag = kbeg != 0;
+  if (imag && kbeg != s.M) return hipErrorInvalidValue;
+  if (s.taylor_shape == 1)
+    return imag ? run_taylor3s_tn<2, true>(s, tin, tout, alpha, W, st, w0)
+                : run_taylor3s_tn<2, false>(s, tin, tout, alpha, W, st, w0);
+  return imag ? run_taylor3s_tn<3, true>(s, tin, tout, alpha, W, st, w0)
+              : run_taylor3s_tn<3, false>(s, tin, tout, alpha, W, st, w0);
 }
 
 }  // namespace afqmc

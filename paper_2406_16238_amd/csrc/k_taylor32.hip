@@ -4,16 +4,11 @@
 // v_mfma_f32_16x16x4f32, while the series is accumulated, B1 applied and
 // everything else computed in FP64.
 //
-// Term: T_out = alpha A_w T_in (FP32), tacc += T_out (FP64), with the same real
-// form as the FP64 kernel: [Re A | Im A] (M x 2M) x [T ; iT] (2M x 2Nt).  A
-// workgroup owns 16 QRT rows and all 32 CT >= 2 Nt real columns of one walker on
-// two waves (16 QRT rows x 16 CT columns each: QRT x CT accumulator tiles of 16 x 16);
 // f32 16x16x4 lane layout: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16], accumulator item r of lane l is D[4 (l / 16) + r][l % 16].
 // The contraction is staged 16 indices at a time in LDS (k-major) with 16-byte
 // global loads, double-buffered through registers.  M must be a multiple of 4
-// (16-byte loads of A never straddle the planes); Nt at most 96.  The
-// contraction starts at kbeg (0, or M when the real plane is zero).
+// (16-byte loads of A never straddle the planes); Nt at most 96.
 #include "afqmc_internal.h"
 #include "device_util.h"
 
@@ -23,136 +18,7 @@ typedef float f4t __attribute__((ext_vector_type(4)));
 
 namespace {
 constexpr int QKC = 16;   // contraction indices per LDS stage
-constexpr int QTH = 128;  // two waves
 }  // namespace
-
-// QRT 16-row tiles per wave (16 QRT rows per workgroup)
-template <int QRT, int CT>
-__global__ __launch_bounds__(QTH) void k_taylor_f32(const float *__restrict__ A32, const float2 *__restrict__ tin,
-                                                    float2 *__restrict__ tout, double2 *__restrict__ tacc, int M,
-                                                    int Nt, int W, int nrt, float alpha, int kbeg) {
-  constexpr int BM = 16 * QRT, BN = 32 * CT;
-  constexpr int LDA = BM + 4, LDB = BN + 16;  // LDB = 16 mod 32 banks: conflict-free B reads
-  constexpr int AV = BM * QKC / 4;   // float4 of A per stage
-  constexpr int BV = QKC * BN / 4;   // float4 of B per stage (two complex each)
-  constexpr int APT = (AV + QTH - 1) / QTH, BPT = (BV + QTH - 1) / QTH;
-  extern __shared__ float qsm[];
-  float *sA = qsm;                     // [2][QKC][LDA]
-  float *sB = qsm + 2 * QKC * LDA;     // [2][QKC][LDB]
-
-  // contiguous stretch of (walker, row tile) per XCD, row tile fastest
-  const int ntiles = W * nrt;
-  const int per = ntiles >> 3, rem = ntiles & 7;
-  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
-  const int t = x * per + min(x, rem) + jx;
-  const int w = t / nrt, i0 = (t - w * nrt) * BM;
-
-  const size_t MM = (size_t)M * M;
-  const float *Aw = A32 + (size_t)w * 2 * MM;
-  const float2 *Tw = tin + (size_t)w * M * Nt;
-  const int K = 2 * M, cols = 2 * Nt;
-  const int tid = threadIdx.x, lane = tid & 63, wn = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-
-  float4 ra[APT], rb[BPT];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * QTH;               // (row, k quad)
-      const int row = e / (QKC / 4), kq = e - row * (QKC / 4);
-      const int gi = i0 + row, gk = k0 + 4 * kq;
-      ra[r] = (e < AV && gi < M && gk < K)
-                  ? *reinterpret_cast<const float4 *>(Aw + (gk >= M ? MM : 0) + (size_t)gi * M + (gk >= M ? gk - M : gk))
-                  : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-#pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * QTH;               // (k, complex column pair)
-      const int kk = e / (BN / 4), jp = e - kk * (BN / 4);
-      const int gk = k0 + kk, j = 2 * jp;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (e < BV && gk < K && j < Nt) {
-        const float2 *src = Tw + (size_t)(gk >= M ? gk - M : gk) * Nt + j;
-        const float2 z0 = src[0];
-        const float2 z1 = (j + 1 < Nt) ? src[1] : make_float2(0.f, 0.f);
-        v = gk >= M ? make_float4(-z0.y, z0.x, -z1.y, z1.x) : make_float4(z0.x, z0.y, z1.x, z1.y);
-      }
-      rb[r] = v;
-    }
-  };
-  auto store = [&](int buf) {
-    float *a = sA + buf * QKC * LDA;
-    float *b = sB + buf * QKC * LDB;
-#pragma unroll
-    for (int r = 0; r < APT; ++r) {
-      const int e = tid + r * QTH;
-      if (e < AV) {
-        const int row = e / (QKC / 4), kq = e - row * (QKC / 4);
-        a[(4 * kq + 0) * LDA + row] = ra[r].x;
-        a[(4 * kq + 1) * LDA + row] = ra[r].y;
-        a[(4 * kq + 2) * LDA + row] = ra[r].z;
-        a[(4 * kq + 3) * LDA + row] = ra[r].w;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < BPT; ++r) {
-      const int e = tid + r * QTH;
-      if (e < BV) {
-        const int kk = e / (BN / 4), jp = e - kk * (BN / 4);
-        *reinterpret_cast<float4 *>(b + kk * LDB + 4 * jp) = rb[r];
-      }
-    }
-  };
-
-  f4t acc[QRT][CT];
-#pragma unroll
-  for (int i = 0; i < QRT; ++i)
-#pragma unroll
-    for (int j = 0; j < CT; ++j) acc[i][j] = f4t{0.f, 0.f, 0.f, 0.f};
-
-  const int nchunk = (K - kbeg + QKC - 1) / QKC;
-  load(kbeg);
-  store(0);
-  __syncthreads();
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nchunk) load(kbeg + (ch + 1) * QKC);
-    const float *a = sA + buf * QKC * LDA + lr;
-    const float *b = sB + buf * QKC * LDB + wn * 16 * CT + lr;
-#pragma unroll
-    for (int ks = 0; ks < QKC / 4; ++ks) {
-      float av[QRT], bv[CT];
-#pragma unroll
-      for (int i = 0; i < QRT; ++i) av[i] = a[(ks * 4 + lk) * LDA + i * 16];
-#pragma unroll
-      for (int j = 0; j < CT; ++j) bv[j] = b[(ks * 4 + lk) * LDB + j * 16];
-#pragma unroll
-      for (int i = 0; i < QRT; ++i)
-#pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    if (ch + 1 < nchunk) store(buf ^ 1);
-    __syncthreads();
-  }
-
-  float *to = reinterpret_cast<float *>(tout + (size_t)w * M * Nt);
-  double *ta = reinterpret_cast<double *>(tacc + (size_t)w * M * Nt);
-#pragma unroll
-  for (int i = 0; i < QRT; ++i)
-#pragma unroll
-    for (int j = 0; j < CT; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gi = i0 + i * 16 + 4 * lk + r;
-        const int c = wn * 16 * CT + j * 16 + lr;
-        if (gi < M && c < cols) {
-          const size_t off = (size_t)gi * cols + c;
-          const float v = alpha * acc[i][j][r];
-          to[off] = v;
-          ta[off] += (double)v;
-        }
-      }
-}
 
 // The FP32 term with three real products (the 3M form of the complex product,
 // as in the FP64 kernel): P1 = Ar Tr, P2 = Ai Ti, P3 = (Ar + Ai)(Tr + Ti),
@@ -483,32 +349,6 @@ hipError_t launch_vhs_f32(const System &s, int W, hipStream_t st, bool imag_only
 }
 
 namespace {
-template <int QRT, int CT>
-hipError_t run_taylor32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
-                        int kbeg) {
-  constexpr int BM = 16 * QRT, BN = 32 * CT;
-  const size_t lds = 2ull * QKC * ((BM + 4) + (BN + 16)) * sizeof(float);
-  const int nrt = (s.M + BM - 1) / BM;
-  hipLaunchKernelGGL((k_taylor_f32<QRT, CT>), dim3((unsigned)(W * nrt)), dim3(QTH), lds, st, s.vhs32, tin, tout,
-                     s.tacc, s.M, s.Nt, W, nrt, (float)alpha, kbeg);
-  return hipGetLastError();
-}
-
-template <int QRT>
-hipError_t run_taylor32_ct(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
-                           int kbeg) {
-  switch ((2 * s.Nt + 31) / 32) {
-    case 1: return run_taylor32<QRT, 1>(s, tin, tout, alpha, W, st, kbeg);
-    case 2: return run_taylor32<QRT, 2>(s, tin, tout, alpha, W, st, kbeg);
-    case 3: return run_taylor32<QRT, 3>(s, tin, tout, alpha, W, st, kbeg);
-    case 4: return run_taylor32<QRT, 4>(s, tin, tout, alpha, W, st, kbeg);
-    case 5: return run_taylor32<QRT, 5>(s, tin, tout, alpha, W, st, kbeg);
-    default: return run_taylor32<QRT, 6>(s, tin, tout, alpha, W, st, kbeg);
-  }
-}
-}  // namespace
-
-namespace {
 template <int WM, int TNC, bool IMAG>
 hipError_t run_taylor3m_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st) {
   constexpr int BM = 16 * WM, BNC = 16 * TNC;
@@ -535,31 +375,21 @@ hipError_t run_taylor3m_f32_tn(const System &s, const float2 *tin, float2 *tout,
 
 bool prop32_supported(int M, int Nt) { return M % 4 == 0 && Nt >= 1 && Nt <= 96; }
 
+// shape 0: 48-row tiles, 1: 32 rows, 2: 64 rows (measured at the headline
+// shape: 48 rows fastest, the smaller grid tail outweighing the extra re-reads
+// of T)
 hipError_t launch_taylor_f32(const System &s, const float2 *tin, float2 *tout, double alpha, int W, hipStream_t st,
                              int kbeg) {
-  // three real products (two for a purely imaginary V_HS, kbeg = M); taylor4 or
-  // variants 1..3 keep the four-product kernel for comparison runs, 9 and 10
-  // are other row tiles
-  if (!s.taylor4 && (s.taylor_variant == 0 || s.taylor_variant >= 9)) {
-    if (kbeg != 0 && kbeg != s.M) return hipErrorInvalidValue;
-    const bool imag = kbeg != 0;
-    switch (s.taylor_variant) {
-      case 9: return imag ? run_taylor3m_f32_tn<2, true>(s, tin, tout, alpha, W, st)
-                          : run_taylor3m_f32_tn<2, false>(s, tin, tout, alpha, W, st);
-      case 10: return imag ? run_taylor3m_f32_tn<4, true>(s, tin, tout, alpha, W, st)
-                           : run_taylor3m_f32_tn<4, false>(s, tin, tout, alpha, W, st);
-      default: return imag ? run_taylor3m_f32_tn<3, true>(s, tin, tout, alpha, W, st)
-                           : run_taylor3m_f32_tn<3, false>(s, tin, tout, alpha, W, st);
-    }
-  }
-  // default 48-row tiles (measured at the headline shape: 3.51 ms per step
-  // against 4.14 for 80 rows, 4.02 for 32 and 3.60 for 64: the smaller grid
-  // tail outweighs the extra re-reads of T)
-  switch (s.taylor_variant) {
-    case 1: return run_taylor32_ct<2>(s, tin, tout, alpha, W, st, kbeg);
-    case 2: return run_taylor32_ct<5>(s, tin, tout, alpha, W, st, kbeg);
-    case 3: return run_taylor32_ct<4>(s, tin, tout, alpha, W, st, kbeg);
-    default: return run_taylor32_ct<3>(s, tin, tout, alpha, W, st, kbeg);
+  // three real products (two for a purely imaginary V_HS, kbeg = M)
+  if (kbeg != 0 && kbeg != s.M) return hipErrorInvalidValue;
+  const bool imag = kbeg != 0;
+  switch (s.taylor_shape) {
+    case 1: return imag ? run_taylor3m_f32_tn<2, true>(s, tin, tout, alpha, W, st)
+                        : run_taylor3m_f32_tn<2, false>(s, tin, tout, alpha, W, st);
+    case 2: return imag ? run_taylor3m_f32_tn<4, true>(s, tin, tout, alpha, W, st)
+                        : run_taylor3m_f32_tn<4, false>(s, tin, tout, alpha, W, st);
+    default: return imag ? run_taylor3m_f32_tn<3, true>(s, tin, tout, alpha, W, st)
+                         : run_taylor3m_f32_tn<3, false>(s, tin, tout, alpha, W, st);
   }
 }
 

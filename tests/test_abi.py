@@ -54,7 +54,8 @@ def test_default_options(lib):
     assert o.precision == A.FP64 and o.taylor_order == 6 and o.fb_cap == 1.0
     assert math.isnan(o.e_shift) and o.mem_limit_bytes == 0
     assert o.streams == 0 and o.use_graph == 0 and o.tune == 1 and o.ex_mode == A.EX_FULL
-    assert o.cv_fraction == 0.125 and o.cv_seed == 7
+    assert o.cv_fraction == 0.125 and o.cv_seed == 7 and o.tune_cache is None
+    assert list(o.reserved) == [0] * 8
     assert lib.afqmc_default_options(None) == A.ERR_ARG
 
 
@@ -149,10 +150,11 @@ def test_struct_layouts_match_header(tmp_path):
                                                    "gen_tau", "gen_scale"]),
               "afqmc_options": (A.Options, ["precision", "taylor_order", "fb_cap", "e_shift", "mem_limit_bytes",
                                             "streams", "use_graph", "tune", "ex_mode", "cv_fraction", "cv_seed",
-                                            "prop_precision", "reserved_opt", "reserved"]),
+                                            "prop_precision", "reserved_opt", "tune_cache", "reserved"]),
               "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
               "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "exchange_order", "lane",
-                                      "graph_captures", "graph_replays", "cv_subset", "reserved_info"]),
+                                      "graph_captures", "graph_replays", "cv_subset", "vhs_tile", "taylor_tile",
+                                      "reserved_info"]),
               "afqmc_timings": (A.Timings, ["ms", "count"]),
               "afqmc_reblock_result": (A.ReblockResult, ["n", "mean", "nlevels", "optimal", "count", "level_mean",
                                                          "std_err", "std_err_err"])}

@@ -247,8 +247,8 @@ def test_full_size_sampled(spec):
         p.close()
 
 
-@pytest.mark.parametrize("bits", [1, 2, 3, 4, 8, 32], ids=["valu-exchange", "valu-gemm", "valu-all", "generic-taylor",
-                                                           "unpacked-vhs", "four-product-taylor"])
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 8], ids=["valu-exchange", "valu-gemm", "valu-all", "generic-taylor",
+                                                       "unpacked-vhs"])
 @pytest.mark.parametrize("spec,W", [(RAGGED, 7), (TILED, 70)], ids=["ragged", "tiled"])
 def test_valu_kernels_match_oracle(spec, W, bits):
     """The VALU kernels (kept for comparison runs and as the exchange fallback
@@ -301,32 +301,37 @@ def test_fused_step_matches_oracle(which, small):
             p.close()
 
 
-@pytest.mark.parametrize("variant", [9, 10])
+@pytest.mark.parametrize("shape", [1, 2])
 @pytest.mark.parametrize("spec,W", [(TILED, 70), (WIDE, 9)], ids=["tiled", "wide"])
-def test_taylor_3m_tiles_match_oracle(spec, W, variant):
-    """The three-product Taylor kernel's other row tiles (reserved[4] = 9: 32
-    rows, 10: 64 rows; at 96 columns always 32 rows) at parity too."""
+def test_taylor_tiles_match_oracle(spec, W, shape):
+    """The Taylor kernel's row tiles (reserved[4] = 1: 48 rows, 2: 32 rows; at
+    96 columns always 32 rows) at parity too."""
     from paper_2406_16238_amd import afqmc as A
     o = A.default_options()
-    o.reserved[4] = variant
+    o.reserved[4] = shape
     p = Pair(spec, W, 0.01, options=o)
     try:
+        assert A.get_info(p.ctx).taylor_tile == shape - 1
         worst, g, _ = run_both(p, 2, gi.initial_walkers(p.trial, W, noise=0.05, seed=21), reortho_every=0)
         assert worst["e"] < TOL and worst["w"] < TOL and worst["phi"] < TOL, worst
     finally:
         p.close()
 
 
-def test_taylor_3m_equals_four_products():
-    """Three real products per Taylor term against four (reserved[0] bit 5) on
-    the same fields: the same walkers to rounding."""
+def test_taylor_row_tiles_agree_bitwise_and_with_four_products():
+    """The row tiles change only which workgroup computes a row: every entry
+    sums the same terms in the same order, so the walkers agree bit for bit.
+    Against four real products per term (the generic GEMM, reserved[0] bit 2)
+    on the same fields: the same walkers to rounding."""
     from paper_2406_16238_amd import afqmc as A
-    o = A.default_options()
-    o.reserved[0] = 32
     outs = []
-    for opts in (None, o):
-        p = Pair(TILED, 40, 0.01, options=opts)
+    for bits, shape in ((0, 1), (0, 2), (4, 0)):
+        o = A.default_options()
+        o.reserved[0] = bits
+        o.reserved[4] = shape
+        p = Pair(TILED, 40, 0.01, options=o)
         try:
+            assert A.get_info(p.ctx).taylor_tile == (shape - 1 if bits == 0 else -1)
             phis = gi.initial_walkers(p.trial, 40, noise=0.05, seed=4)
             w = p.walkers(phis)
             fields = gi.FieldStream(6, 40, p.ham.nchol)
@@ -335,7 +340,9 @@ def test_taylor_3m_equals_four_products():
             outs.append(p.to_host(w))
         finally:
             p.close()
-    (a, wa, la, _), (b, wb, lb, _) = outs
+    for x, y in zip(outs[0], outs[1]):
+        assert x.tobytes() == y.tobytes()
+    (a, wa, la, _), (b, wb, lb, _) = outs[0], outs[2]
     assert cmp_rel(a, b, np.abs(b).max()) < 1e-13
     assert cmp_rel(wa, wb) < 1e-13
     assert phase_diff(la, lb) < 1e-12

@@ -1,0 +1,89 @@
+"""Set-up tuner: the launch shapes it picks per problem shape, kept in a file
+of JSON lines (options.tune_cache) that later set-ups read instead of timing.
+Results never depend on the shapes (bitwise checks of the row tiles and the
+exchange launch shapes live with the parity and batching tests)."""
+import json
+
+import pytest
+
+import afqmc_inputs as gi
+
+pytestmark = pytest.mark.gpu
+KEYS = ("M", "Na", "Nb", "G", "W", "precision", "prop32")
+
+
+def _setup(spec, W, **opts):
+    from paper_2406_16238_amd import afqmc as A
+    h1, chol, ecore, trial = gi.make_system(spec)
+    reserved = opts.pop("reserved", {})
+    o = A.default_options(**opts)
+    for k, v in reserved.items():
+        o.reserved[k] = v
+    return A, A.setup_hamiltonian(A.SystemInput(h1, chol, ecore, trial, spec.nalpha, spec.nbeta, W, 0.005), o)
+
+
+def _lines(path):
+    return [json.loads(x) for x in path.read_text().splitlines() if x.strip()]
+
+
+def test_choices_are_written_then_read(tmp_path):
+    cache = tmp_path / "tune.jsonl"
+    # a shape no other test of this process tunes, so the file is written
+    spec, W = gi.SystemSpec(56, 6, 5, 112, tau=40.0, seed=3), 19
+    A, ctx = _setup(spec, W, tune_cache=str(cache).encode())
+    try:
+        info = A.get_info(ctx)
+    finally:
+        ctx.close()
+    (line,) = _lines(cache)
+    assert [line[k] for k in KEYS] == [56, 6, 5, 112, 19, 0, 0]
+    assert line["ex_tile"] == info.exchange_tile and line["ex_order"] == info.exchange_order
+    assert line["vhs_tile"] == info.vhs_tile and line["taylor_tile"] == info.taylor_tile
+    assert 0 <= line["vhs_tile"] < 4 and line["taylor_tile"] in (0, 1)
+
+    # a line written by hand for another shape is taken as it stands: no timing,
+    # nothing appended
+    spec2, W2 = gi.SystemSpec(58, 6, 6, 116, tau=40.0, seed=4), 21
+    hand = {"M": 58, "Na": 6, "Nb": 6, "G": 116, "W": 21, "precision": 0, "prop32": 0,
+            "ex_tile": 1, "ex_order": 4, "vhs_tile": 2, "taylor_tile": 1}
+    with open(cache, "a") as f:
+        f.write(json.dumps(hand) + "\n")
+    A, ctx = _setup(spec2, W2, tune_cache=str(cache).encode())
+    try:
+        info = A.get_info(ctx)
+        assert (info.exchange_tile, info.exchange_order, info.vhs_tile, info.taylor_tile) == (1, 4, 2, 1)
+    finally:
+        ctx.close()
+    assert len(_lines(cache)) == 2
+    # a fixed row tile wins over the cached one
+    A, ctx = _setup(spec2, W2, tune_cache=str(cache).encode(), reserved={4: 1})
+    try:
+        assert A.get_info(ctx).taylor_tile == 0
+    finally:
+        ctx.close()
+
+
+def test_unwritable_cache_is_an_argument_error(tmp_path):
+    from paper_2406_16238_amd import afqmc as A
+    spec, W = gi.SystemSpec(60, 6, 6, 120, tau=40.0, seed=5), 23
+    with pytest.raises(A.AfqmcError) as err:
+        _setup(spec, W, tune_cache=str(tmp_path / "no" / "such" / "dir" / "t.jsonl").encode())
+    assert err.value.status == A.ERR_ARG
+
+
+def test_no_tuning_keeps_the_defaults():
+    spec, W = gi.SystemSpec(62, 6, 6, 124, tau=40.0, seed=6), 25
+    A, ctx = _setup(spec, W, tune=0)
+    try:
+        info = A.get_info(ctx)
+        assert (info.exchange_tile, info.exchange_order, info.vhs_tile, info.taylor_tile) == (2, 8, 0, 0)
+    finally:
+        ctx.close()
+
+
+def test_bad_row_tile_is_rejected():
+    from paper_2406_16238_amd import afqmc as A
+    spec, W = gi.SystemSpec(56, 6, 6, 112, tau=40.0, seed=7), 8
+    with pytest.raises(A.AfqmcError) as err:
+        _setup(spec, W, reserved={4: 3})   # 64-row tiles exist for FP32 propagation only
+    assert err.value.status == A.ERR_ARG
