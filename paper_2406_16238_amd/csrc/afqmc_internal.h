@@ -246,8 +246,9 @@ hipError_t launch_comb(const System &s, double *weight, double2 *phi, double2 *l
 hipError_t launch_gen_chol(const System &s, uint64_t seed, const double *fac, double root3, hipStream_t st);
 // dedicated Taylor-term kernel (k_taylor.hip)
 bool taylor_mfma_supported(int M, int Nt);
+// acc: 1 tacc += tout; 0 tacc untouched (tin may be tacc); 2 tacc += tin + tout
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st, int kbeg = 0, int w0 = 0);
+                              hipStream_t st, int kbeg = 0, int w0 = 0, int acc = 1);
 // the Taylor terms of walkers [w0, w0 + W) can run as a launch of their own
 // (the dedicated three-product kernel)
 bool taylor_walker_split(const System &s);

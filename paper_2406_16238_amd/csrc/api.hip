@@ -1131,10 +1131,14 @@ static afqmc_status apply_propagator(afqmc_ctx *ctx, System &s, double2 *phi, bo
     Phase ph(ctx, AFQMC_PH_VHS, st);
     AFQMC_HIP(launch_vhs(s, W, st, half), "V_HS kernel");
   }
+  // The dedicated FP64 kernel takes the first term straight from tacc = B1 phi
+  // without adding to it, and the second term adds its input and output, so
+  // the series needs no copy of B1 phi.
+  const bool fold = !s.prop32 && taylor_walker_split(s) && ctx->opt.taylor_order >= 2;
   {
     Phase ph(ctx, AFQMC_PH_ONE_BODY, st);
     AFQMC_HIP(launch_b1(s, phi, s.tacc, W, st), "one-body kernel");
-    if (!s.prop32)
+    if (!s.prop32 && !fold)
       AFQMC_HIP(hipMemcpyAsync(s.tA, s.tacc, (size_t)W * s.M * s.Nt * sizeof(double2), hipMemcpyDeviceToDevice, st),
                 "copy");
   }
@@ -1158,16 +1162,24 @@ static afqmc_status apply_propagator(afqmc_ctx *ctx, System &s, double2 *phi, bo
         AFQMC_HIP(hipEventRecord(s.half_fork, st), "event record");
         AFQMC_HIP(hipStreamWaitEvent(s.half_stream, s.half_fork, 0), "stream wait");
       }
-      double2 *tin = s.tA, *tout = s.tB;
+      double2 *tin = fold ? s.tacc : s.tA, *tout = fold ? s.tA : s.tB;
       hipError_t e = hipSuccess;
       for (int n = 1; n <= ctx->opt.taylor_order && e == hipSuccess; ++n) {
+        const int acc = !fold ? 1 : n == 1 ? 0 : n == 2 ? 2 : 1;
         if (split) {
-          e = launch_taylor_mfma(s, tin, tout, 1.0 / n, W1, st, kbeg, 0);
-          if (e == hipSuccess) e = launch_taylor_mfma(s, tin, tout, 1.0 / n, W - W1, s.half_stream, kbeg, W1);
+          e = launch_taylor_mfma(s, tin, tout, 1.0 / n, W1, st, kbeg, 0, acc);
+          if (e == hipSuccess) e = launch_taylor_mfma(s, tin, tout, 1.0 / n, W - W1, s.half_stream, kbeg, W1, acc);
+        } else if (fold) {
+          e = launch_taylor_mfma(s, tin, tout, 1.0 / n, W, st, kbeg, 0, acc);
         } else {
           e = launch_taylor_term(s, tin, tout, 1.0 / n, W, st, kbeg);
         }
-        std::swap(tin, tout);
+        if (fold && n == 1) {
+          tin = s.tA;
+          tout = s.tB;
+        } else {
+          std::swap(tin, tout);
+        }
       }
       if (split) {  // joined also after a failure, so that the second stream never runs ahead of `st`
         AFQMC_HIP(hipEventRecord(s.half_join, s.half_stream), "event record");

@@ -1,6 +1,8 @@
 // One term of the Taylor series of the two-body exponential applied to the
 // walker slabs (Sec. 2, eq. Bprop, exp(sqrt(dt) V_HS) phi by its series):
-//   T_out = alpha * A_w T_in,   tacc += T_out,
+//   T_out = alpha * A_w T_in,   tacc += T_out   (acc = 1; acc = 0 leaves tacc
+// alone, so T_in may be tacc itself; acc = 2 adds T_in + T_out, which folds in
+// the term before),
 // with A_w = sqrt(dt) V_HS of walker w held as real and imaginary M x M planes
 // and T complex M x Nt, in three real products instead of four (the 3M form of
 // a complex product): with A = Ar + i Ai and T = Tr + i Ti,
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(64 * (NCW + 1)) __attribute__((amdgpu_waves_per_eu(
                                                                  const double2 *__restrict__ tin,
                                                                  double2 *__restrict__ tout,
                                                                  double2 *__restrict__ tacc, int M, int Nt, int W,
-                                                                 int nrt, double alpha) {
+                                                                 int nrt, double alpha, int acc) {
   constexpr int BM = 4 * TR * NCW, KS = TKC_ / 4, SLOTS = TKC_ / 2;   // 16-byte slots per staged A row
   constexpr int NPL = IMAG ? 1 : 2;
   constexpr int AROWS = NPL * BM, AI = (AROWS * SLOTS + 63) / 64;    // copy instructions of an A stage
@@ -230,6 +232,7 @@ __global__ __launch_bounds__(64 * (NCW + 1)) __attribute__((amdgpu_waves_per_eu(
 
   double2 *to = tout + (size_t)w * M * Nt;
   double2 *ta = tacc + (size_t)w * M * Nt;
+  const double2 *tw = tin + (size_t)w * M * Nt;
 #pragma unroll
   for (int i = 0; i < TR; ++i) {
     const int gi = rbase + 4 * i + lk;
@@ -242,8 +245,15 @@ __global__ __launch_bounds__(64 * (NCW + 1)) __attribute__((amdgpu_waves_per_eu(
         const double im = IMAG ? p1[i][j] : (p3[i][j] - p1[i][j]) - p2[i][j];
         const double2 v = make_double2(alpha * re, alpha * im);
         to[off] = v;
-        const double2 o = ta[off];
-        ta[off] = make_double2(o.x + v.x, o.y + v.y);
+        if (acc) {
+          const double2 o = ta[off];
+          double2 u = v;
+          if (acc == 2) {
+            const double2 x = tw[off];
+            u = make_double2(x.x + v.x, x.y + v.y);
+          }
+          ta[off] = make_double2(o.x + u.x, o.y + u.y);
+        }
       }
     }
   }
@@ -255,7 +265,7 @@ constexpr int kTaylorStages = 4;
 
 template <int TR, int NCW, int TN, bool IMAG>
 hipError_t run_taylor3s(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
-                        int w0) {
+                        int w0, int acc) {
   constexpr int BM = 4 * TR * NCW, TK = kTaylorKc, NB = kTaylorStages;
   const int ai = ((IMAG ? 1 : 2) * BM * (TK / 2) + 63) / 64, ti = (TK * 16 * TN + 63) / 64;
   const size_t lds = (size_t)NB * (ai + ti) * 64 * sizeof(double2);
@@ -271,21 +281,21 @@ hipError_t run_taylor3s(const System &s, const double2 *tin, double2 *tout, doub
   const int nrt = (s.M + BM - 1) / BM;
   const size_t wt = (size_t)w0 * s.M * s.Nt;
   hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * (NCW + 1)), lds, st, s.vhs + (size_t)w0 * 2 * s.M * s.M,
-                     tin + wt, tout + wt, s.tacc + wt, s.M, s.Nt, W, nrt, alpha);
+                     tin + wt, tout + wt, s.tacc + wt, s.M, s.Nt, W, nrt, alpha, acc);
   return hipGetLastError();
 }
 
 template <int TR, bool IMAG>
 hipError_t run_taylor3s_tn(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
-                           int w0) {
+                           int w0, int acc) {
   switch ((s.Nt + 15) / 16) {
-    case 1: return run_taylor3s<TR, 4, 1, IMAG>(s, tin, tout, alpha, W, st, w0);
-    case 2: return run_taylor3s<TR, 4, 2, IMAG>(s, tin, tout, alpha, W, st, w0);
-    case 3: return run_taylor3s<TR, 4, 3, IMAG>(s, tin, tout, alpha, W, st, w0);
-    case 4: return run_taylor3s<TR, 4, 4, IMAG>(s, tin, tout, alpha, W, st, w0);
-    case 5: return run_taylor3s<TR, 4, 5, IMAG>(s, tin, tout, alpha, W, st, w0);
+    case 1: return run_taylor3s<TR, 4, 1, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 2: return run_taylor3s<TR, 4, 2, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 3: return run_taylor3s<TR, 4, 3, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 4: return run_taylor3s<TR, 4, 4, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 5: return run_taylor3s<TR, 4, 5, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
     // 96 columns: 32-row tiles keep the three accumulator sets in registers
-    default: return run_taylor3s<2, 4, 6, IMAG>(s, tin, tout, alpha, W, st, w0);
+    default: return run_taylor3s<2, 4, 6, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
   }
 }
 }  // namespace
@@ -300,14 +310,14 @@ int taylor_shapes(const System &s) { return s.prop32 ? 3 : 2; }
 
 // shape 0: 48-row tiles, 1: 32-row tiles
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
-                              hipStream_t st, int kbeg, int w0) {
+                              hipStream_t st, int kbeg, int w0, int acc) {
   const bool imag = kbeg != 0;
   if (imag && kbeg != s.M) return hipErrorInvalidValue;
   if (s.taylor_shape == 1)
-    return imag ? run_taylor3s_tn<2, true>(s, tin, tout, alpha, W, st, w0)
-                : run_taylor3s_tn<2, false>(s, tin, tout, alpha, W, st, w0);
-  return imag ? run_taylor3s_tn<3, true>(s, tin, tout, alpha, W, st, w0)
-              : run_taylor3s_tn<3, false>(s, tin, tout, alpha, W, st, w0);
+    return imag ? run_taylor3s_tn<2, true>(s, tin, tout, alpha, W, st, w0, acc)
+                : run_taylor3s_tn<2, false>(s, tin, tout, alpha, W, st, w0, acc);
+  return imag ? run_taylor3s_tn<3, true>(s, tin, tout, alpha, W, st, w0, acc)
+              : run_taylor3s_tn<3, false>(s, tin, tout, alpha, W, st, w0, acc);
 }
 
 }  // namespace afqmc
