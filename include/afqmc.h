@@ -135,7 +135,12 @@ typedef struct {
                                FP32 (the series sum, B1, overlaps and energies
                                stay FP64; the mixed precision the paper mentions
                                in Sec. 6).  Needs M a multiple of 4, Nt <= 96.    */
-  int32_t reserved_opt;
+  int32_t deterministic;    /* 1 (default): every reduction (split-K partials, the
+                               sums over Cholesky vectors, lanes and walkers, the
+                               estimator) runs in a fixed order, so a run replays
+                               bitwise and a set of systems equals separate runs;
+                               0 (unordered atomic reductions) is not provided and
+                               is AFQMC_ERR_ARG                                   */
   const char *tune_cache;   /* with tune: path of a file of JSON lines, one per
                                problem shape, that the tuner reads before timing
                                and appends its choices to (NULL, the default:

@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("fb_cap", ctypes.c_double), ("e_shift", ctypes.c_double),
                 ("mem_limit_bytes", ctypes.c_uint64), ("streams", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("tune", ctypes.c_int32), ("ex_mode", ctypes.c_int32), ("cv_fraction", ctypes.c_double),
-                ("cv_seed", ctypes.c_uint64), ("prop_precision", ctypes.c_int32), ("reserved_opt", ctypes.c_int32),
+                ("cv_seed", ctypes.c_uint64), ("prop_precision", ctypes.c_int32), ("deterministic", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p), ("reserved", ctypes.c_int32 * 8)]
 
 

@@ -985,6 +985,7 @@ afqmc_status afqmc_default_options(afqmc_options *opt) {
   opt->ex_mode = AFQMC_EX_FULL;
   opt->cv_fraction = 0.125;
   opt->cv_seed = 7;
+  opt->deterministic = 1;
   return AFQMC_OK;
 }
 
@@ -1009,6 +1010,8 @@ afqmc_status afqmc_setup_hamiltonian(const afqmc_system_desc *sys, int32_t nsys,
     return fail(AFQMC_ERR_ARG, "prop_precision must be AFQMC_FP64 or AFQMC_FP32_CONTRACT");
   if (o.ex_mode != AFQMC_EX_FULL && o.ex_mode != AFQMC_EX_CV) return fail(AFQMC_ERR_ARG, "unknown ex_mode");
   if (!(o.cv_fraction > 0.0 && o.cv_fraction <= 1.0)) return fail(AFQMC_ERR_ARG, "cv_fraction must be in (0, 1]");
+  if (o.deterministic != 1)
+    return fail(AFQMC_ERR_ARG, "deterministic must be 1: only fixed-order reductions are provided");
   if (o.ex_mode == AFQMC_EX_CV)
     for (int i = 0; i < nsys; ++i)
       if (sys[i].nwalkers > kCvMaxWalkers)

@@ -54,7 +54,7 @@ def test_default_options(lib):
     assert o.precision == A.FP64 and o.taylor_order == 6 and o.fb_cap == 1.0
     assert math.isnan(o.e_shift) and o.mem_limit_bytes == 0
     assert o.streams == 0 and o.use_graph == 0 and o.tune == 1 and o.ex_mode == A.EX_FULL
-    assert o.cv_fraction == 0.125 and o.cv_seed == 7 and o.tune_cache is None
+    assert o.cv_fraction == 0.125 and o.cv_seed == 7 and o.tune_cache is None and o.deterministic == 1
     assert list(o.reserved) == [0] * 8
     assert lib.afqmc_default_options(None) == A.ERR_ARG
 
@@ -103,7 +103,8 @@ def test_setup_rejects_bad_options(lib):
     out = ctypes.c_void_p()
     for field, value in (("taylor_order", 0), ("taylor_order", 17), ("precision", 9), ("fb_cap", float("nan")),
                          ("streams", -1), ("ex_mode", 2), ("cv_fraction", 0.0), ("cv_fraction", 1.5),
-                         ("cv_fraction", float("nan")), ("prop_precision", 2)):
+                         ("cv_fraction", float("nan")), ("prop_precision", 2), ("deterministic", 0),
+                         ("deterministic", 2)):
         o = A.default_options()
         setattr(o, field, value)
         assert lib.afqmc_setup_hamiltonian(ctypes.byref(d), 1, ctypes.byref(o), None, ctypes.byref(out)) \
@@ -150,7 +151,7 @@ def test_struct_layouts_match_header(tmp_path):
                                                    "gen_tau", "gen_scale"]),
               "afqmc_options": (A.Options, ["precision", "taylor_order", "fb_cap", "e_shift", "mem_limit_bytes",
                                             "streams", "use_graph", "tune", "ex_mode", "cv_fraction", "cv_seed",
-                                            "prop_precision", "reserved_opt", "tune_cache", "reserved"]),
+                                            "prop_precision", "deterministic", "tune_cache", "reserved"]),
               "afqmc_walkers": (A.CWalkers, ["phi", "weight", "log_ovlp", "flags"]),
               "afqmc_info": (A.Info, ["e_hf", "e_shift", "const_c", "device_bytes", "exchange_tile", "exchange_order", "lane",
                                       "graph_captures", "graph_replays", "cv_subset", "vhs_tile", "taylor_tile",
