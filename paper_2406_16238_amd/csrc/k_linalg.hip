@@ -4,27 +4,42 @@
 // Overlap (Sec. 2, eq. ovlp_ratio and the walker expansion): for each spin block
 // O_s = Psi_s^T phi_s (N_s x N_s), <Psi_T|phi> = prod_s det O_s, and the mixed
 // Green's function G^s_pq = <a+_p a_q> = sum_i Psi_pi Theta_qi with
-// Theta_s = phi_s O_s^-1.  One workgroup per walker holds O_s in LDS and inverts
-// it in place by Gauss-Jordan elimination with partial (row) pivoting; the
-// pivots give the determinant.  The two spin blocks of a walker run in separate
+// Theta_s = phi_s O_s^-1.  One workgroup per walker and spin block forms O_s on
+// the matrix cores, holds it in LDS and inverts it in place by Gauss-Jordan
+// elimination with partial (row) pivoting (the pivots give the determinant),
+// then forms Theta_s on the matrix cores.  The two spin blocks of a walker run in separate
 // workgroups; a second small kernel adds their log-determinants.
 #include "afqmc_internal.h"
 #include "device_util.h"
 
 namespace afqmc {
 
-namespace {
-constexpr int OKQ = 32;                                   // rows of phi / Psi staged per pass
-constexpr int OBI = 2, OBJ = 4;                           // O entries per thread block: rows x columns
-constexpr int OBLK = ((kMaxSpinOrbitals + OBI - 1) / OBI * ((kMaxSpinOrbitals + OBJ - 1) / OBJ) + kThreads - 1) /
-                     kThreads;                             // O blocks per thread
-constexpr int TBQ = 2, TBJ = 4;                           // Theta entries per thread block: rows x columns
-}  // namespace
+// Both products run on v_mfma_f64_4x4x4_4b_f64 (four 4x4x4 blocks that share
+// one 4-row slab of A; lane 16k+4b+i supplies A[i][k], lane 16k+4b+j supplies
+// B[k][4b+j], lane 16i+4b+j receives D[i][4b+j]), with operands read straight
+// from memory: a slab r and a 16-column group c of C give C[4r + lane/16]
+// [16c + lane%16].  Complex matrices enter as real ones with interleaved
+// (re, im) columns.  The kernels are instantiated for NB = ceil(max N / 8):
+// O has 2 NB slabs and NB column groups.
+// Operands are read through buffer resources: a byte offset past the end of the
+// buffer (kOutside) reads zero, so entries outside the matrices need no select
+// or branch and a load can be issued steps before its use.
+constexpr int kOutside = 0x7ffffff0;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double ld_f64(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ double mfma_f64(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
 
 // One workgroup per (walker, spin block).  LDS: O (N x N complex, inverted in
-// place), plus staging for OKQ rows of Psi_s (real) and phi_s (complex).
+// place).
 // part[w][s] = (log |det O_s|, sum of pivot phases, not reduced), spart[w][s] = 1
 // when O_s is singular (then Theta_s is not written).
+template <int NB>
 __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restrict__ phi,
                                                         const double *__restrict__ trial, int M, int Na,
                                                         int Nb, double2 *__restrict__ theta,
@@ -32,19 +47,25 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
                                                         uint32_t *__restrict__ spart) {
   extern __shared__ double2 sdyn[];
   __shared__ double2 scol[kMaxSpinOrbitals];
-  __shared__ int spiv[kMaxSpinOrbitals];
-  __shared__ double2 spivval;
+  __shared__ double2 spv[kMaxSpinOrbitals];   // pivots, in elimination order
+  __shared__ int spiv[kMaxSpinOrbitals];      // pivot rows
+  __shared__ int scolof[kMaxSpinOrbitals];    // column order that undoes the interchanges
   __shared__ int ssing;
+  __shared__ double2 szero;
+  constexpr int NW = kThreads / 64;
+  static_assert(kMaxSpinOrbitals <= 64 && kMaxSpinOrbitals <= 8 * 7, "one lane per column; NB <= 7");
+  // O in column passes of at most 4 groups (registers); Theta in batches of TS slabs
+  constexpr int RS = 2 * NB, CPASS = NB <= 5 ? NB : (NB + 1) / 2, TS = NB <= 4 ? 8 : 28 / NB;
+  constexpr int PD = NB <= 3 ? 4 : NB == 4 ? 3 : 2;   // contraction steps whose operands are in flight
 
   const int w = blockIdx.x, s = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: loop bounds stay scalar
+  const int l4 = lane & 3, lk = lane >> 4, l16 = lane & 15;
   const int Nt = Na + Nb;
-  const int nmax = Na > Nb ? Na : Nb;
   double2 *sA = sdyn;                                        // [N][N]
-  double2 *sPh = sdyn + nmax * nmax;                         // [OKQ][N]
-  double *sPs = reinterpret_cast<double *>(sPh + OKQ * nmax);  // [OKQ][N]
   const double2 *ph = phi + (size_t)w * M * Nt;
-  double lre = 0.0, lim = 0.0;  // log det accumulated by thread 0
+  double lre = 0.0, lim = 0.0;  // log det, summed by thread 0
 
   {
     const int N = s ? Nb : Na;
@@ -56,68 +77,80 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       }
       return;
     }
-    const int NN = N * N;
-    // O = Psi_s^T phi_s, OKQ rows at a time through LDS.  Each thread owns
-    // blocks of OBI x OBJ entries, so a staged row costs OBI + OBJ LDS reads
-    // for OBI OBJ complex updates (indices past N are clamped on read and
-    // dropped on write); every entry sums over q in the same order.
-    const int nbj = (N + OBJ - 1) / OBJ, nob = ((N + OBI - 1) / OBI) * nbj;
-    int oi0[OBLK], oj0[OBLK];
+    // O = Psi_s^T phi_s as a real N x 2N product over q: wave v takes the
+    // 4-row contraction steps v, v + NW, ..., and the waves' partial sums are
+    // added in LDS in wave order (a fixed order).  A[i][q] = Psi[q][i],
+    // B[q][2j + t] = (re, im) of phi[q][j]; rows past N and columns past 2N
+    // read zero and are dropped.
+    // trial [M][Nt] and this walker's phi [M][Nt] (complex) as buffers
+    const __amdgpu_buffer_rsrc_t rpsi = rsrc_of(trial, (uint32_t)(M * Nt) * 8u);
+    const __amdgpu_buffer_rsrc_t rphi = rsrc_of(ph, (uint32_t)(M * Nt) * 16u);
+    const int nsteps = (M + 3) / 4;
+    for (int c0 = 0; c0 < NB; c0 += CPASS) {
+      double acc[RS][CPASS];
 #pragma unroll
-    for (int b = 0; b < OBLK; ++b) {
-      const int bid = tid + b * kThreads;
-      oi0[b] = (bid / nbj) * OBI;
-      oj0[b] = (bid - (bid / nbj) * nbj) * OBJ;
-    }
-    double2 o[OBLK][OBI][OBJ];
+      for (int r = 0; r < RS; ++r)
 #pragma unroll
-    for (int b = 0; b < OBLK; ++b)
+        for (int c = 0; c < CPASS; ++c) acc[r][c] = 0.0;
+      double av[RS], bv[CPASS];
+      // byte offsets within a row (kOutside for rows past N, columns past 2N)
+      int aoff[RS], boff[CPASS];
 #pragma unroll
-      for (int r = 0; r < OBI; ++r)
-#pragma unroll
-        for (int c = 0; c < OBJ; ++c) o[b][r][c] = make_double2(0.0, 0.0);
-    for (int q0 = 0; q0 < M; q0 += OKQ) {
-      const int nq = min(OKQ, M - q0);
-      for (int e = tid; e < nq * N; e += blockDim.x) {
-        const int qq = e / N, j = e - (e / N) * N;
-        sPh[qq * N + j] = ph[(size_t)(q0 + qq) * Nt + off + j];
-        sPs[qq * N + j] = trial[(size_t)(q0 + qq) * Nt + off + j];
+      for (int r = 0; r < RS; ++r) {
+        const int i = 4 * r + l4;
+        aoff[r] = i < N ? 8 * (off + i) : kOutside;
       }
-      __syncthreads();
 #pragma unroll
-      for (int b = 0; b < OBLK; ++b) {
-        if (tid + b * kThreads >= nob) continue;
-        int ic[OBI], jc[OBJ];
+      for (int c = 0; c < CPASS; ++c) {
+        const int col = 16 * (c0 + c) + l16;
+        boff[c] = (c0 + c < NB && col < 2 * N) ? 8 * (2 * off + col) : kOutside;
+      }
+      auto load = [&](int st, double (&aa)[RS], double (&bb)[CPASS]) {
+        const int q = 4 * st + lk;
+        const bool ok = q < M;
+        const int ra = q * Nt * 8, rb = q * Nt * 16;
 #pragma unroll
-        for (int r = 0; r < OBI; ++r) ic[r] = min(oi0[b] + r, N - 1);
+        for (int r = 0; r < RS; ++r) aa[r] = ld_f64(rpsi, (ok && aoff[r] != kOutside) ? ra + aoff[r] : kOutside);
 #pragma unroll
-        for (int c = 0; c < OBJ; ++c) jc[c] = min(oj0[b] + c, N - 1);
-        for (int qq = 0; qq < nq; ++qq) {
-          double t[OBI];
-          double2 pv[OBJ];
+        for (int c = 0; c < CPASS; ++c) bb[c] = ld_f64(rphi, (ok && boff[c] != kOutside) ? rb + boff[c] : kOutside);
+      };
+      // operands of the wave's next PD steps in flight (a rotating set of
+      // buffers, indexed statically in the unrolled loop; zero past the end)
+      double ab[PD][RS], bb[PD][CPASS];
 #pragma unroll
-          for (int r = 0; r < OBI; ++r) t[r] = sPs[qq * N + ic[r]];
+      for (int u = 0; u < PD; ++u) load(wv + NW * u, ab[u], bb[u]);
+      const int nst = (nsteps - wv + NW - 1) / NW;
+      for (int n0 = 0; n0 < nst; n0 += PD) {
 #pragma unroll
-          for (int c = 0; c < OBJ; ++c) pv[c] = sPh[qq * N + jc[c]];
+        for (int u = 0; u < PD; ++u) {
+          if (n0 + u < nst) {
 #pragma unroll
-          for (int r = 0; r < OBI; ++r)
+            for (int r = 0; r < RS; ++r) av[r] = ab[u][r];
 #pragma unroll
-            for (int c = 0; c < OBJ; ++c)
-              o[b][r][c] = make_double2(fma(t[r], pv[c].x, o[b][r][c].x), fma(t[r], pv[c].y, o[b][r][c].y));
+            for (int c = 0; c < CPASS; ++c) bv[c] = bb[u][c];
+            load(wv + NW * (n0 + u + PD), ab[u], bb[u]);
+#pragma unroll
+            for (int r = 0; r < RS; ++r)
+#pragma unroll
+              for (int c = 0; c < CPASS; ++c) acc[r][c] = mfma_f64(av[r], bv[c], acc[r][c]);
+          }
         }
       }
-      __syncthreads();
-    }
+      for (int v = 0; v < NW; ++v) {
+        if (wv == v) {
 #pragma unroll
-    for (int b = 0; b < OBLK; ++b) {
-      if (tid + b * kThreads >= nob) continue;
+          for (int r = 0; r < RS; ++r)
 #pragma unroll
-      for (int r = 0; r < OBI; ++r)
-#pragma unroll
-        for (int c = 0; c < OBJ; ++c) {
-          const int i = oi0[b] + r, j = oj0[b] + c;
-          if (i < N && j < N) sA[i * N + j] = o[b][r][c];
+            for (int c = 0; c < CPASS; ++c) {
+              const int i = 4 * r + lk, col = 16 * (c0 + c) + l16;
+              if (i < N && c0 + c < NB && col < 2 * N) {
+                double *d = reinterpret_cast<double *>(sA + i * N + (col >> 1)) + (col & 1);
+                *d = v == 0 ? acc[r][c] : *d + acc[r][c];
+              }
+            }
         }
+        __syncthreads();
+      }
     }
     if (tid == 0) ssing = 0;
     __syncthreads();
@@ -136,42 +169,39 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
         if (tid == 63) {
           spiv[k] = bi;
           const double2 pv = sA[bi * N + k];
-          spivval = pv;
+          spv[k] = pv;
           if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) ssing = 1;
         }
       }
       __syncthreads();
       if (ssing) break;
       const int p = spiv[k];
-      const double2 pv = spivval;
-      if (p != k) {
-        for (int j = tid; j < N; j += blockDim.x) {
-          const double2 a = sA[k * N + j];
-          sA[k * N + j] = sA[p * N + j];
-          sA[p * N + j] = a;
-        }
-      }
-      if (tid == 0) {
-        lre += 0.5 * log(cabs2(pv));
-        lim += atan2(pv.y, pv.x) + (p != k ? 3.14159265358979323846 : 0.0);
-      }
-      __syncthreads();
-      // save column k of the other rows, then scale the pivot row (the pivot
-      // position becomes 1 / pivot); the two touch disjoint entries
-      const double2 inv = cdiv(make_double2(1.0, 0.0), pv);
-      for (int i = tid; i < N; i += blockDim.x)
-        if (i != k) scol[i] = sA[i * N + k];
+      const double2 inv = cdiv(make_double2(1.0, 0.0), spv[k]);
+      // one pass over rows k and p and column k: row k becomes old row p scaled
+      // by 1 / pivot (the pivot position 1 / pivot), row p becomes old row k,
+      // and scol keeps column k of every other row after the interchange
+      // (thread j owns entry j of rows k and p, thread i entry i of column k)
       for (int j = tid; j < N; j += blockDim.x) {
-        const double2 a = (j == k) ? make_double2(1.0, 0.0) : sA[k * N + j];
-        sA[k * N + j] = cmul(a, inv);
+        const double2 ak = sA[k * N + j], ap = sA[p * N + j];
+        if (p != k) sA[p * N + j] = ak;
+        sA[k * N + j] = cmul((j == k) ? make_double2(1.0, 0.0) : ap, inv);
+        if (j == k && p != k) scol[p] = ak;
       }
+      for (int i = tid; i < N; i += blockDim.x)
+        if (i != k && i != p) scol[i] = sA[i * N + k];
       __syncthreads();
-      // eliminate column k from every other row
-      for (int e = tid; e < NN; e += blockDim.x) {
-        const int i = e / N, j = e - (e / N) * N;
-        if (i == k) continue;
-        const double2 a = (j == k) ? make_double2(0.0, 0.0) : sA[e];
-        sA[e] = csub(a, cmul(scol[i], sA[k * N + j]));
+      // eliminate column k from every other row: lane j of wave v updates
+      // column j of rows v, v + NW, ... (the multiplier scol[i] is one address
+      // for the whole wave)
+      if (lane < N) {
+        const int j = lane;
+        const double2 rk = sA[k * N + j];
+#pragma unroll 4
+        for (int i = wv; i < N; i += NW) {
+          if (i == k) continue;
+          const double2 a = (j == k) ? make_double2(0.0, 0.0) : sA[i * N + j];
+          sA[i * N + j] = csub(a, cmul(scol[i], rk));
+        }
       }
       __syncthreads();
     }
@@ -182,65 +212,113 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       }
       return;
     }
-    // undo the row interchanges as column interchanges, last first
-    for (int k = N - 1; k >= 0; --k) {
-      const int p = spiv[k];
-      if (p != k) {
-        for (int i = tid; i < N; i += blockDim.x) {
-          const double2 a = sA[i * N + k];
-          sA[i * N + k] = sA[i * N + p];
-          sA[i * N + p] = a;
-        }
-      }
-      __syncthreads();
+    // log det O_s from the pivots: thread i takes log |pivot i| and its phase
+    // (plus pi for an interchange), thread 0 sums them in elimination order
+    if (tid < N) {
+      const double2 pv = spv[tid];
+      scol[tid] = make_double2(0.5 * log(cabs2(pv)), atan2(pv.y, pv.x) + (spiv[tid] != tid ? 3.14159265358979323846 : 0.0));
     }
-    // Theta_s = phi_s O_s^-1, OKQ rows of phi_s at a time through LDS; each
-    // thread owns TBQ rows x TBJ columns, every entry summed over k in order
+    for (int c = tid; c < N; c += blockDim.x) scolof[c] = c;
+    __syncthreads();
+    if (tid == 0) {
+      for (int k = 0; k < N; ++k) {
+        lre += scol[k].x;
+        lim += scol[k].y;
+      }
+      // the row interchanges undone as column interchanges, last first, composed
+      // into one order: column c of O_s^-1 is column scolof[c] of sA (the
+      // product below reads it so)
+      for (int k = N - 1; k >= 0; --k) {
+        const int p = spiv[k], t = scolof[k];
+        scolof[k] = scolof[p];
+        scolof[p] = t;
+      }
+    }
+    __syncthreads();
+    // Theta_s = phi_s O_s^-1 as a real M x 2N product over 2N: A = [Re phi |
+    // Im phi] (row q), B[k][2j + t] = (Re X, Im X)[k][j] for k < N and
+    // (-Im X, Re X)[k - N][j] for k >= N, X = O_s^-1 read through the column
+    // order.  Wave v takes 4-row slabs v, v + NW, ... in batches of TS.
     if (theta) {
-      double2 *th = theta + (size_t)w * M * Nt;
-      const int tnbj = (N + TBJ - 1) / TBJ;
-      for (int q0 = 0; q0 < M; q0 += OKQ) {
-        const int nq = min(OKQ, M - q0);
-        for (int e = tid; e < nq * N; e += blockDim.x) {
-          const int qq = e / N, j = e - (e / N) * N;
-          sPh[qq * N + j] = ph[(size_t)(q0 + qq) * Nt + off + j];
+      double *thr = reinterpret_cast<double *>(theta + (size_t)w * M * Nt + off);
+      if (tid == 0) szero = make_double2(0.0, 0.0);
+      __syncthreads();
+      const int nslab = (M + 3) / 4, ksteps = (2 * N + 3) / 4;
+      // this lane's B entries: column 16c + l16 -> X column scolof[j], part t
+      int xcol[NB];
+      bool xok[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const int col = 16 * c + l16;
+        xok[c] = col < 2 * N;
+        xcol[c] = scolof[min(col, 2 * N - 1) >> 1];
+      }
+      const bool im = l16 & 1;
+      for (int sb = wv; sb < nslab; sb += NW * TS) {
+        double acc[TS][NB];
+#pragma unroll
+        for (int r = 0; r < TS; ++r)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) acc[r][c] = 0.0;
+        double av[TS];
+        // A entries: row q of slab sb + NW r, contraction index k = 4 ks + lk
+        // (Re phi[q][k] for k < N, Im phi[q][k - N] after)
+        int qoff[TS];
+#pragma unroll
+        for (int r = 0; r < TS; ++r) {
+          const int q = 4 * (sb + NW * r) + l4;
+          qoff[r] = q < M ? 16 * (q * Nt + off) : -1;
         }
-        __syncthreads();
-        const int tnb = ((nq + TBQ - 1) / TBQ) * tnbj;
-        for (int bid = tid; bid < tnb; bid += blockDim.x) {
-          const int qb = (bid / tnbj) * TBQ, jb = (bid - (bid / tnbj) * tnbj) * TBJ;
-          int qc[TBQ], jc[TBJ];
+        auto load = [&](int ks, double (&aa)[TS]) {
+          const int k = 4 * ks + lk;
+          const int ko = k < N ? 16 * k : 16 * (k - N) + 8;
 #pragma unroll
-          for (int r = 0; r < TBQ; ++r) qc[r] = min(qb + r, nq - 1);
+          for (int r = 0; r < TS; ++r) aa[r] = ld_f64(rphi, (k < 2 * N && qoff[r] >= 0) ? qoff[r] + ko : kOutside);
+        };
+        // B entries of contraction step ks for this lane (zero past 2N)
+        auto loadb = [&](int ks, double (&bv)[NB]) {
+          const int k = 4 * ks + lk;
+          const bool kok = k < 2 * N, lo = k < N;
+          const int kr = (lo ? k : k - N) * N;
 #pragma unroll
-          for (int c = 0; c < TBJ; ++c) jc[c] = min(jb + c, N - 1);
-          double re[TBQ][TBJ], im[TBQ][TBJ];
-#pragma unroll
-          for (int r = 0; r < TBQ; ++r)
-#pragma unroll
-            for (int c = 0; c < TBJ; ++c) re[r][c] = im[r][c] = 0.0;
-          for (int k = 0; k < N; ++k) {
-            double2 pv[TBQ], xv[TBJ];
-#pragma unroll
-            for (int r = 0; r < TBQ; ++r) pv[r] = sPh[qc[r] * N + k];
-#pragma unroll
-            for (int c = 0; c < TBJ; ++c) xv[c] = sA[k * N + jc[c]];
-#pragma unroll
-            for (int r = 0; r < TBQ; ++r)
-#pragma unroll
-              for (int c = 0; c < TBJ; ++c) {
-                re[r][c] += pv[r].x * xv[c].x - pv[r].y * xv[c].y;
-                im[r][c] += pv[r].x * xv[c].y + pv[r].y * xv[c].x;
-              }
+          for (int c = 0; c < NB; ++c) {
+            const double2 *src = (kok && xok[c]) ? sA + kr + xcol[c] : &szero;   // szero holds 0
+            const double2 x = *src;
+            bv[c] = lo ? (im ? x.y : x.x) : (im ? x.x : -x.y);
           }
+        };
+        // A operands of the next PD steps in flight, B one step ahead
+        double ab[PD][TS], bcur[NB], bnxt[NB];
 #pragma unroll
-          for (int r = 0; r < TBQ; ++r)
+        for (int u = 0; u < PD; ++u) load(u, ab[u]);
+        loadb(0, bcur);
+        for (int k0 = 0; k0 < ksteps; k0 += PD) {
 #pragma unroll
-            for (int c = 0; c < TBJ; ++c)
-              if (qb + r < nq && jb + c < N)
-                th[(size_t)(q0 + qb + r) * Nt + off + jb + c] = make_double2(re[r][c], im[r][c]);
+          for (int u = 0; u < PD; ++u) {
+            const int ks = k0 + u;
+            if (ks < ksteps) {
+#pragma unroll
+              for (int r = 0; r < TS; ++r) av[r] = ab[u][r];
+              load(ks + PD, ab[u]);
+              loadb(ks + 1, bnxt);
+#pragma unroll
+              for (int r = 0; r < TS; ++r)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) acc[r][c] = mfma_f64(av[r], bcur[c], acc[r][c]);
+#pragma unroll
+              for (int c = 0; c < NB; ++c) bcur[c] = bnxt[c];
+            }
+          }
         }
-        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < TS; ++r) {
+          const int q = 4 * (sb + NW * r) + lk;
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            const int col = 16 * c + l16;
+            if (q < M && col < 2 * N) thr[2 * (size_t)q * Nt + col] = acc[r][c];
+          }
+        }
       }
     }
   }
@@ -274,21 +352,39 @@ __global__ __launch_bounds__(kThreads) void k_theta_zero_singular(const uint32_t
   for (long e = threadIdx.x; e < per; e += blockDim.x) th[e] = make_double2(0.0, 0.0);
 }
 
-size_t ovlp_lds_bytes(int nmax) {
-  return (size_t)nmax * nmax * sizeof(double2) + (size_t)OKQ * nmax * (sizeof(double2) + sizeof(double));
-}
+size_t ovlp_lds_bytes(int nmax) { return (size_t)nmax * nmax * sizeof(double2); }
 
-hipError_t ovlp_enable_lds(int nmax) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(k_ovlp_theta), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)ovlp_lds_bytes(kMaxSpinOrbitals));
+namespace {
+using OvlpKernel = void (*)(const double2 *, const double *, int, int, int, double2 *, double2 *, uint32_t *);
+OvlpKernel pick_ovlp(int nmax) {
+  switch ((nmax + 7) / 8) {
+    case 1: return k_ovlp_theta<1>;
+    case 2: return k_ovlp_theta<2>;
+    case 3: return k_ovlp_theta<3>;
+    case 4: return k_ovlp_theta<4>;
+    case 5: return k_ovlp_theta<5>;
+    case 6: return k_ovlp_theta<6>;
+    default: return k_ovlp_theta<7>;
+  }
+}
+}  // namespace
+
+hipError_t ovlp_enable_lds(int) {
+  for (int nb = 1; nb <= 7; ++nb) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(pick_ovlp(8 * nb)),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)ovlp_lds_bytes(8 * nb));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_ovlp_theta(const double2 *phi, const double *trial, int M, int Na, int Nb, int W,
                              double2 *theta, double2 *logo, uint32_t *stat, uint32_t *flags_or, hipStream_t st,
                              double2 *part, uint32_t *spart) {
   const int nmax = Na > Nb ? Na : Nb;
-  hipLaunchKernelGGL(k_ovlp_theta, dim3(W, 2), dim3(kThreads), ovlp_lds_bytes(nmax), st, phi, trial, M, Na, Nb, theta,
-                     part, spart);
+  if (nmax > kMaxSpinOrbitals) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pick_ovlp(nmax), dim3(W, 2), dim3(kThreads), ovlp_lds_bytes(nmax), st, phi, trial, M, Na, Nb,
+                     theta, part, spart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ovlp_finish, dim3((W + 255) / 256), dim3(256), 0, st, part, spart, W, logo, stat, flags_or);
