@@ -152,48 +152,82 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
         __syncthreads();
       }
     }
-    if (tid == 0) ssing = 0;
-    __syncthreads();
-
-    for (int k = 0; k < N; ++k) {
-      // pivot: largest |A_ik| for i >= k (first index on ties), found by wave 0
-      // (the arg-max over its lanes by DPP steps lands in lane 63)
-      if (tid < 64) {
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + tid; i < N; i += 64) {
-          const double a = cabs2(sA[i * N + k]);
-          if (a > best) { best = a; bi = i; }
-        }
-        wave_argmax_dpp(best, bi);
-        if (tid == 63) {
-          spiv[k] = bi;
-          const double2 pv = sA[bi * N + k];
-          spv[k] = pv;
-          if (!(cabs2(pv) > 0.0) || !isfinite(pv.x) || !isfinite(pv.y)) ssing = 1;
-        }
+    // Gauss-Jordan with partial pivoting.  The pivot of column k is the
+    // largest |A_ik| over rows i >= k (first index on ties), found by wave 0
+    // (DPP arg-max, result in lane 63).  Each step takes two passes: (1) row k
+    // becomes old row p scaled by 1 / pivot (the pivot position 1 / pivot), row
+    // p becomes old row k, and scol keeps column k of every other row after
+    // the interchange; (2) column k is eliminated from every other row, and
+    // wave 0 first updates column k + 1 of all rows and finds the next pivot
+    // from those values (the others leave column k + 1 to it).
+    auto bad = [](double2 v) { return !(cabs2(v) > 0.0) || !isfinite(v.x) || !isfinite(v.y); };
+    auto lane_value = [](double2 v, int src) {   // v of lane src (uniform)
+      const long long x = __double_as_longlong(v.x), y = __double_as_longlong(v.y);
+      const int xl = __builtin_amdgcn_readlane((int)x, src), xh = __builtin_amdgcn_readlane((int)(x >> 32), src);
+      const int yl = __builtin_amdgcn_readlane((int)y, src), yh = __builtin_amdgcn_readlane((int)(y >> 32), src);
+      return make_double2(__longlong_as_double(((long long)xh << 32) | (unsigned int)xl),
+                          __longlong_as_double(((long long)yh << 32) | (unsigned int)yl));
+    };
+    if (wv == 0) {
+      double best = -1.0;
+      int bi = 0;
+      double2 a0 = make_double2(0.0, 0.0);
+      if (lane < N) {
+        a0 = sA[lane * N];
+        best = cabs2(a0);
+        bi = lane;
       }
-      __syncthreads();
+      wave_argmax_dpp(best, bi);
+      const int p0 = __builtin_amdgcn_readlane(bi, 63);
+      const double2 pv0 = lane_value(a0, p0);
+      if (lane == 0) {
+        spiv[0] = p0;
+        spv[0] = pv0;
+        ssing = bad(pv0) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
       if (ssing) break;
       const int p = spiv[k];
-      const double2 inv = cdiv(make_double2(1.0, 0.0), spv[k]);
-      // one pass over rows k and p and column k: row k becomes old row p scaled
-      // by 1 / pivot (the pivot position 1 / pivot), row p becomes old row k,
-      // and scol keeps column k of every other row after the interchange
-      // (thread j owns entry j of rows k and p, thread i entry i of column k)
-      for (int j = tid; j < N; j += blockDim.x) {
+      // pass 1: wave 0 lane j owns entry j of rows k and p, wave 1 lane i entry i of column k
+      if (wv == 0 && lane < N) {
+        const int j = lane;
+        const double2 inv = cdiv(make_double2(1.0, 0.0), spv[k]);
         const double2 ak = sA[k * N + j], ap = sA[p * N + j];
         if (p != k) sA[p * N + j] = ak;
         sA[k * N + j] = cmul((j == k) ? make_double2(1.0, 0.0) : ap, inv);
         if (j == k && p != k) scol[p] = ak;
       }
-      for (int i = tid; i < N; i += blockDim.x)
-        if (i != k && i != p) scol[i] = sA[i * N + k];
+      if (wv == 1 && lane < N && lane != k && lane != p) scol[lane] = sA[lane * N + k];
       __syncthreads();
-      // eliminate column k from every other row: lane j of wave v updates
-      // column j of rows v, v + NW, ... (the multiplier scol[i] is one address
-      // for the whole wave)
-      if (lane < N) {
+      // pass 2
+      const int k1 = k + 1;
+      if (wv == 0 && k1 < N) {
+        const double2 r1 = sA[k * N + k1];
+        double best = -1.0;
+        int bi = k1;
+        double2 a1 = make_double2(0.0, 0.0);
+        if (lane < N && lane != k) {
+          a1 = csub(sA[lane * N + k1], cmul(scol[lane], r1));
+          sA[lane * N + k1] = a1;
+          if (lane >= k1) {
+            best = cabs2(a1);
+            bi = lane;
+          }
+        }
+        wave_argmax_dpp(best, bi);
+        const int p1 = __builtin_amdgcn_readlane(bi, 63);
+        const double2 pv1 = lane_value(a1, p1);
+        if (lane == 0) {
+          spiv[k1] = p1;
+          spv[k1] = pv1;
+          if (bad(pv1)) ssing = 1;
+        }
+      }
+      // lane j of wave v: column j (not k + 1) of rows v, v + NW, ...; the
+      // multiplier scol[i] is one address for the whole wave
+      if (lane < N && lane != k1) {
         const int j = lane;
         const double2 rk = sA[k * N + j];
 #pragma unroll 4
