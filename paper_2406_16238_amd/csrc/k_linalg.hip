@@ -52,11 +52,13 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
   __shared__ int scolof[kMaxSpinOrbitals];    // column order that undoes the interchanges
   __shared__ int ssing;
   __shared__ double2 szero;
+  __shared__ double2 sdump[64];   // sink for results of elimination slots past the matrix
   constexpr int NW = kThreads / 64;
   static_assert(kMaxSpinOrbitals <= 64 && kMaxSpinOrbitals <= 8 * 7, "one lane per column; NB <= 7");
   // O in column passes of at most 4 groups (registers); Theta in batches of TS slabs
   constexpr int RS = 2 * NB, CPASS = NB <= 5 ? NB : (NB + 1) / 2, TS = NB <= 4 ? 8 : 28 / NB;
   constexpr int PD = NB <= 3 ? 4 : NB == 4 ? 3 : 2;   // contraction steps whose operands are in flight
+  constexpr int RW = (8 * NB + NW - 1) / NW;           // rows of O per wave in the elimination
 
   const int w = blockIdx.x, s = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -227,14 +229,24 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
       }
       // lane j of wave v: column j (not k + 1) of rows v, v + NW, ...; the
       // multiplier scol[i] is one address for the whole wave
+      // (all the wave's reads first, from clamped rows; a result that belongs
+      // to no entry goes to this lane's slot of sdump)
       if (lane < N && lane != k1) {
         const int j = lane;
         const double2 rk = sA[k * N + j];
-#pragma unroll 4
-        for (int i = wv; i < N; i += NW) {
-          if (i == k) continue;
-          const double2 a = (j == k) ? make_double2(0.0, 0.0) : sA[i * N + j];
-          sA[i * N + j] = csub(a, cmul(scol[i], rk));
+        double2 av[RW], cv[RW];
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+          const int i = min(wv + NW * t, N - 1);
+          av[t] = sA[i * N + j];
+          cv[t] = scol[i];
+        }
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+          const int i = wv + NW * t;
+          const double2 a = (j == k) ? make_double2(0.0, 0.0) : av[t];
+          double2 *dst = (i < N && i != k) ? sA + i * N + j : sdump + lane;
+          *dst = csub(a, cmul(cv[t], rk));
         }
       }
       __syncthreads();
