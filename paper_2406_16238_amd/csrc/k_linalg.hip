@@ -24,7 +24,7 @@ namespace afqmc {
 // Operands are read through buffer resources: a byte offset past the end of the
 // buffer (kOutside) reads zero, so entries outside the matrices need no select
 // or branch and a load can be issued steps before its use.
-constexpr int kOutside = 0x7ffffff0;
+constexpr int kOutside = 0x40000000;   // above every buffer here, and room to add a row offset
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
 }
@@ -36,7 +36,7 @@ __device__ __forceinline__ double mfma_f64(double a, double b, double c) {
 }
 
 // One workgroup per (walker, spin block).  LDS: O (N x N complex, inverted in
-// place).
+// place), then B of the Theta product.
 // part[w][s] = (log |det O_s|, sum of pivot phases, not reduced), spart[w][s] = 1
 // when O_s is singular (then Theta_s is not written).
 template <int NB>
@@ -51,7 +51,6 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
   __shared__ int spiv[kMaxSpinOrbitals];      // pivot rows
   __shared__ int scolof[kMaxSpinOrbitals];    // column order that undoes the interchanges
   __shared__ int ssing;
-  __shared__ double2 szero;
   __shared__ double2 sdump[64];   // sink for results of elimination slots past the matrix
   constexpr int NW = kThreads / 64;
   static_assert(kMaxSpinOrbitals <= 64 && kMaxSpinOrbitals <= 8 * 7, "one lane per column; NB <= 7");
@@ -65,7 +64,10 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: loop bounds stay scalar
   const int l4 = lane & 3, lk = lane >> 4, l16 = lane & 15;
   const int Nt = Na + Nb;
+  const int nmax = Na > Nb ? Na : Nb;
   double2 *sA = sdyn;                                        // [N][N]
+  constexpr int LDB = 16 * NB + 1;                           // row stride of sBx (doubles)
+  double *sBx = reinterpret_cast<double *>(sdyn + nmax * nmax);   // [8 ceil(N/4)][LDB]
   const double2 *ph = phi + (size_t)w * M * Nt;
   double lre = 0.0, lim = 0.0;  // log det, summed by thread 0
 
@@ -107,14 +109,14 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
         const int col = 16 * (c0 + c) + l16;
         boff[c] = (c0 + c < NB && col < 2 * N) ? 8 * (2 * off + col) : kOutside;
       }
+      // (rows q >= M lie past the end of both buffers)
       auto load = [&](int st, double (&aa)[RS], double (&bb)[CPASS]) {
         const int q = 4 * st + lk;
-        const bool ok = q < M;
         const int ra = q * Nt * 8, rb = q * Nt * 16;
 #pragma unroll
-        for (int r = 0; r < RS; ++r) aa[r] = ld_f64(rpsi, (ok && aoff[r] != kOutside) ? ra + aoff[r] : kOutside);
+        for (int r = 0; r < RS; ++r) aa[r] = ld_f64(rpsi, ra + aoff[r]);
 #pragma unroll
-        for (int c = 0; c < CPASS; ++c) bb[c] = ld_f64(rphi, (ok && boff[c] != kOutside) ? rb + boff[c] : kOutside);
+        for (int c = 0; c < CPASS; ++c) bb[c] = ld_f64(rphi, rb + boff[c]);
       };
       // operands of the wave's next PD steps in flight (a rotating set of
       // buffers, indexed statically in the unrolled loop; zero past the end)
@@ -287,19 +289,27 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
     // order.  Wave v takes 4-row slabs v, v + NW, ... in batches of TS.
     if (theta) {
       double *thr = reinterpret_cast<double *>(theta + (size_t)w * M * Nt + off);
-      if (tid == 0) szero = make_double2(0.0, 0.0);
-      __syncthreads();
-      const int nslab = (M + 3) / 4, ksteps = (2 * N + 3) / 4;
-      // this lane's B entries: column 16c + l16 -> X column scolof[j], part t
-      int xcol[NB];
-      bool xok[NB];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const int col = 16 * c + l16;
-        xok[c] = col < 2 * N;
-        xcol[c] = scolof[min(col, 2 * N - 1) >> 1];
+      // contraction steps: the Re half (k < N) then the Im half, ceil(N / 4)
+      // each, so which half a step is in is the same for the whole wave
+      const int nslab = (M + 3) / 4, khalf = (N + 3) / 4, ksteps = 2 * khalf;
+      // B as a real matrix in LDS, rows 4 khalf (Re half) + 4 khalf (Im half),
+      // columns 16 NB at stride LDB: B[k][2j + t] = (Re X, Im X)[k][j] and
+      // B[4 khalf + k][2j + t] = (-Im X, Re X)[k][j] for k < N, X[k][j] =
+      // sA[k][scolof[j]]; zero elsewhere, so the A entries of rows k >= N
+      // (finite values of the walker, or past the buffer) add nothing
+      const int KR = 8 * khalf;
+      for (int e = tid; e < KR * 16 * NB; e += kThreads) {
+        const int kk = e / (16 * NB), col = e - kk * (16 * NB);
+        const bool hi = kk >= 4 * khalf;
+        const int k = hi ? kk - 4 * khalf : kk;
+        double v = 0.0;
+        if (k < N && col < 2 * N) {
+          const double2 x = sA[k * N + scolof[col >> 1]];
+          v = hi ? ((col & 1) ? x.x : -x.y) : ((col & 1) ? x.y : x.x);
+        }
+        sBx[kk * LDB + col] = v;
       }
-      const bool im = l16 & 1;
+      __syncthreads();
       for (int sb = wv; sb < nslab; sb += NW * TS) {
         double acc[TS][NB];
 #pragma unroll
@@ -313,25 +323,18 @@ __global__ __launch_bounds__(kThreads) void k_ovlp_theta(const double2 *__restri
 #pragma unroll
         for (int r = 0; r < TS; ++r) {
           const int q = 4 * (sb + NW * r) + l4;
-          qoff[r] = q < M ? 16 * (q * Nt + off) : -1;
+          qoff[r] = q < M ? 16 * (q * Nt + off) : kOutside;
         }
         auto load = [&](int ks, double (&aa)[TS]) {
-          const int k = 4 * ks + lk;
-          const int ko = k < N ? 16 * k : 16 * (k - N) + 8;
+          const bool hi = ks >= khalf;
+          const int ko = 16 * (4 * (hi ? ks - khalf : ks) + lk) + (hi ? 8 : 0);
 #pragma unroll
-          for (int r = 0; r < TS; ++r) aa[r] = ld_f64(rphi, (k < 2 * N && qoff[r] >= 0) ? qoff[r] + ko : kOutside);
+          for (int r = 0; r < TS; ++r) aa[r] = ld_f64(rphi, qoff[r] + ko);
         };
-        // B entries of contraction step ks for this lane (zero past 2N)
         auto loadb = [&](int ks, double (&bv)[NB]) {
-          const int k = 4 * ks + lk;
-          const bool kok = k < 2 * N, lo = k < N;
-          const int kr = (lo ? k : k - N) * N;
+          const double *b = sBx + min(4 * ks + lk, KR - 1) * LDB + l16;
 #pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            const double2 *src = (kok && xok[c]) ? sA + kr + xcol[c] : &szero;   // szero holds 0
-            const double2 x = *src;
-            bv[c] = lo ? (im ? x.y : x.x) : (im ? x.x : -x.y);
-          }
+          for (int c = 0; c < NB; ++c) bv[c] = b[16 * c];
         };
         // A operands of the next PD steps in flight, B one step ahead
         double ab[PD][TS], bcur[NB], bnxt[NB];
@@ -398,7 +401,11 @@ __global__ __launch_bounds__(kThreads) void k_theta_zero_singular(const uint32_t
   for (long e = threadIdx.x; e < per; e += blockDim.x) th[e] = make_double2(0.0, 0.0);
 }
 
-size_t ovlp_lds_bytes(int nmax) { return (size_t)nmax * nmax * sizeof(double2); }
+// O, then the real B matrix of the Theta product
+size_t ovlp_lds_bytes(int nmax) {
+  const size_t nb = (nmax + 7) / 8, khalf = (nmax + 3) / 4;
+  return (size_t)nmax * nmax * sizeof(double2) + 8 * khalf * (16 * nb + 1) * sizeof(double);
+}
 
 namespace {
 using OvlpKernel = void (*)(const double2 *, const double *, int, int, int, double2 *, double2 *, uint32_t *);
