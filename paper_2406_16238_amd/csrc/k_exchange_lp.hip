@@ -16,8 +16,9 @@
 //   (FP32) and only the walker's departure Q from the trial rounded: Ltilde^g and
 //   Q_w are scaled by powers of two (per Cholesky vector, per walker) into one
 //   16-bit term each, multiplied on v_mfma_f32_16x16x32_{f16,bf16} with FP32
-//   accumulation, and the epilogue undoes the scales and adds T0.  The rounding
-//   error is relative to Ltilde Q, not to T.
+//   accumulation; the accumulators start at T0 divided by the two scales and
+//   the epilogue multiplies them back.  The rounding error of the 16-bit terms
+//   is relative to Ltilde Q, not to T.
 // In all forms T is kept in LDS as FP32; the FP32 form accumulates the traces in
 // FP64, the 16-bit forms each lane's partial traces (at most 100 products) in
 // FP32 and the sums over lanes and Cholesky vectors in FP64.
@@ -406,10 +407,36 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
   // chunks 0 .. NBUF-2 in flight, then wait for chunk 0
   for (int c = 0; c < NBUF - 1; ++c)
     if (c < nchunk) issue(c * KCH, c);
+  const int lr = lane & 15, lk = lane >> 4;
+  // One-product form: T = T0 + f P with f = (scale of the Cholesky vector) x
+  // (scale of the walker), a power of two, so the accumulators start at T0 / f
+  // (exact) and end as T / f.  T0 is stored transposed, T0t[g][j][i], so the
+  // real part of the lane's four rows i0..i0+3 at column j is one 16-byte load;
+  // these loads run while the first stages are copied.
+  float tsc[RT];   // f of each row block
+  if constexpr (NT == 1) {
+    const int g0w = g0 + wy * GC;
+    const float qs = qsc[min(w0 + wx, W - 1)];
+    const float re = (lr & 1) ? 0.f : 1.f;   // odd lanes hold imaginary parts: T0 adds nothing
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int row0 = rt * 16 + 4 * lk;
+      const int gl = row0 / NR, i0 = row0 - gl * NR;
+      tsc[rt] = lsc[g0w + gl] * qs;
+      const float m = re / tsc[rt];
+      const float *t0 = T0 + (size_t)(g0w + gl) * NR * NR + i0;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int j = (ct * 16 + lr) >> 1;
+        const f4v t = *reinterpret_cast<const f4v *>(t0 + j * NR);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[rt][ct][r] = t[r] * m;
+      }
+    }
+  }
   if (NBUF > 2 && nchunk >= NBUF - 1) AFQMC_WAIT_VMCNT((NBUF - 2) * CMIN);
   else __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const int lr = lane & 15, lk = lane >> 4;
   for (int ch = 0; ch < nchunk; ++ch) {
     const int buf = ch % NBUF;
     // into the buffer read in chunk ch - 1 (every wave has passed the barrier after it)
@@ -486,28 +513,13 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
     __syncthreads();
   }
 
-  if constexpr (NT == 1) {
-    // T = T0 + (scaled product) / (scale of the Cholesky vector x scale of the
-    // walker); T0 is stored transposed, T0t[g][j][i], so the real part of the
-    // lane's four rows i0..i0+3 at column j is one 16-byte load
-    const int g0w = g0 + wy * GC;
-    const float qs = qsc[min(w0 + wx, W - 1)];
-    const bool re = !(lr & 1);
+  if constexpr (NT == 1) {   // T = f (T0 / f + P)
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int row0 = rt * 16 + 4 * lk;
-      const int gl = row0 / NR, i0 = row0 - gl * NR;
-      const float f = lsc[g0w + gl] * qs;
-      const float *t0 = T0 + (size_t)(g0w + gl) * NR * NR + i0;
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int j = (ct * 16 + lr) >> 1;
-        f4v add = f4v{0.f, 0.f, 0.f, 0.f};
-        if (re) add = *reinterpret_cast<const f4v *>(t0 + j * NR);
+      for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[rt][ct][r] = fmaf(acc[rt][ct][r], f, add[r]);
-      }
-    }
+        for (int r = 0; r < 4; ++r) acc[rt][ct][r] *= tsc[rt];
   }
   // each lane's partial traces (at most ROWW CP / 64 products) in FP32, the
   // sums over lanes and Cholesky vectors in FP64
