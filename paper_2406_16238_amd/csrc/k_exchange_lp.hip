@@ -155,6 +155,56 @@ __device__ __forceinline__ void lp_trace_s(const f4v (&acc)[RT][CT], const float
   dg[pass] += d;
 }
 
+// The same trace with one plane of S in LDS at a time (half the LDS): the
+// lanes holding Re T_ij (part 0, even lr) or Im T_ij (part 1) store their
+// entries, then every lane reads the partners from that plane.
+template <int NR, int CT, int RT>
+__device__ __forceinline__ void lp_store_s1(const f4v (&acc)[RT][CT], float *sS, int lane, int pass, int part) {
+  constexpr int CS = NR + 4;
+  const int lr = lane & 15, lk = lane >> 4;
+  if ((lr & 1) != part) return;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
+    if (glo == ghi && glo != pass) continue;
+    if ((rt * 16 + 4 * lk) / NR != pass) continue;   // the lane's four rows belong to one Cholesky vector
+    const int i0 = rt * 16 + 4 * lk - pass * NR;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      float *d = sS + i0 * CS + ct * 8 + (lr >> 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) d[r * CS] = acc[rt][ct][r];
+    }
+  }
+}
+
+// a += sum v * (plane entry of the partner T_ji); with diag, d += the lane's
+// diagonal entries
+template <int NR, int CT, int RT>
+__device__ __forceinline__ void lp_trace_s1(const f4v (&acc)[RT][CT], const float *sS, int lane, float &a, float &d,
+                                            int pass, bool diag) {
+  constexpr int CS = NR + 4;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
+    if (glo == ghi && glo != pass) continue;
+    if ((rt * 16 + 4 * lk) / NR != pass) continue;
+    const int i0 = rt * 16 + 4 * lk - pass * NR;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int j = ct * 8 + (lr >> 1);
+      const f4v c = *reinterpret_cast<const f4v *>(sS + j * CS + i0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = acc[rt][ct][r];
+        a = fmaf(v, c[r], a);
+        if (diag && i0 + r == j) d += v;
+      }
+    }
+  }
+}
+
 template <int GC>
 __device__ __forceinline__ void lp_finish(double pre, double pim, const double *dg, int lane, int w, int W, int g0w,
                                           int G, int spin, int stride, int part, double2 *ekpart,
@@ -286,9 +336,15 @@ __global__ __launch_bounds__(kThreads) void k_exchange_f32(const float *__restri
 // NT = 3 or 2: split-BF16 terms of Ltilde and Theta; NT = 1: the trial split,
 // one E term of Ltilde and of Q, with T0 transposed [G4][NR][NR], the inverse scales of
 // the Cholesky vectors lsc [G4] and of the walkers qsc [W].
-constexpr int kSplitKsub = 2;   // contraction runs per stage of the one-product form
-// LDS stages of the 16-bit forms (two at two workgroups per CU; deeper ones,
-// at one workgroup per CU, measured slower)
+// Contraction runs per stage of the one-product form: one, so that a stage is
+// 20 KB and, with the one-plane trace epilogue (28 KB), a workgroup needs 40 KB
+// of LDS and three fit on a CU (two 32-deep runs per stage at two workgroups
+// per CU measured 9 % slower)
+constexpr int kSplitKsub = 1;
+// workgroups per CU the one-product kernels are compiled for (registers)
+constexpr int kLp16Occupancy1 = 3;
+// LDS stages of the 16-bit forms (two; deeper ones, at fewer workgroups per CU,
+// measured slower)
 __host__ __device__ constexpr int lp16_stages(int) { return 2; }
 // Staged planes per stage: the NT terms of the split-BF16 forms, or, for the
 // one-product form, KSUB consecutive runs of LKC contraction indices (a stage
@@ -300,7 +356,7 @@ __host__ __device__ constexpr int lp16_kp(int nt, int M) { return (M + lp16_kchu
 
 
 template <int NR, int NT, typename E = __bf16>
-__global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(const E *__restrict__ LtB,
+__global__ __launch_bounds__(kThreads, NT == 1 ? kLp16Occupancy1 : NT <= 2 ? 2 : 1) void k_exchange_bf16(const E *__restrict__ LtB,
                                                              const E *__restrict__ ThB, int Kp, int N, int G,
                                                              int W, int stride, int spin,
                                                              double2 *__restrict__ ekpart,
@@ -325,8 +381,9 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
   constexpr int TSF = CP + 2;
   static_assert(ROWW % 16 == 0 && CP % 16 == 0 && LKC == 32, "row bases keep the swizzle of the lane's row");
   // Two staging buffers (one barrier per chunk).  The two-term form fits two
-  // workgroups per CU (80 KB of LDS, registers for two waves per SIMD) and does
-  // the trace epilogue one Cholesky vector of each wave at a time.
+  // workgroups per CU (80 KB of LDS, registers for two waves per SIMD), the
+  // one-product form three (40 KB, three waves per SIMD); both do the trace
+  // epilogue one Cholesky vector of each wave at a time.
   constexpr int NBUF = lp16_stages(NT);
   auto swz = [](int r) { return ((r >> 1) ^ (r >> 2)) & 3; };
   extern __shared__ __attribute__((aligned(16))) unsigned char bsm_raw[];
@@ -524,7 +581,28 @@ __global__ __launch_bounds__(kThreads, NT <= 2 ? 2 : 1) void k_exchange_bf16(con
   // each lane's partial traces (at most ROWW CP / 64 products) in FP32, the
   // sums over lanes and Cholesky vectors in FP64
   float pre = 0.f, pim = 0.f, dg[2] = {0.f, 0.f};
-  if constexpr (NT <= 2) {
+  if constexpr (NT == 1) {
+    // one Cholesky vector of the wave at a time, one plane of S per wave in
+    // LDS (the empty asm statements keep the compiler from moving LDS accesses
+    // across the phases; the wave's LDS accesses run in order)
+    float *sS = reinterpret_cast<float *>(bsm) + (size_t)wv * lp_s_plane<NR>();
+    const bool odd = lr & 1;
+#pragma unroll
+    for (int pass = 0; pass < GC; ++pass) {
+      float a0 = 0.f, a1 = 0.f, d = 0.f;   // sum v Re T_ji, sum v Im T_ji, diagonal
+      lp_store_s1<NR, CT, RT>(acc, sS, lane, pass, 0);
+      asm volatile("" ::: "memory");
+      lp_trace_s1<NR, CT, RT>(acc, sS, lane, a0, d, pass, true);
+      asm volatile("" ::: "memory");
+      lp_store_s1<NR, CT, RT>(acc, sS, lane, pass, 1);
+      asm volatile("" ::: "memory");
+      lp_trace_s1<NR, CT, RT>(acc, sS, lane, a1, d, pass, false);
+      asm volatile("" ::: "memory");
+      pre += odd ? -a1 : a0;
+      pim += odd ? a0 : a1;
+      dg[pass] += d;
+    }
+  } else if constexpr (NT == 2) {
     // one Cholesky vector of the wave at a time: S (two planes) per wave in LDS
     float *sS = reinterpret_cast<float *>(bsm) + (size_t)wv * 2 * lp_s_plane<NR>();
 #pragma unroll
@@ -814,7 +892,8 @@ size_t lds_bf(int nr, int nt) {
   const int gc = (nr % 16 == 0) ? 1 : 2, roww = gc * nr, cp = 2 * nr;
   const size_t nbuf = lp16_stages(nt);
   const size_t stage = nbuf * lp16_planes(nt) * (LWY * roww + LWX * cp) * LKC * sizeof(__bf16);
-  const size_t epi = nt <= 2 ? 4ull * 2 * (nr * (nr + 4) + 8) * sizeof(float) : 4ull * roww * (cp + 2) * sizeof(float);
+  const size_t epi = nt == 1 ? 4ull * (nr * (nr + 4) + 8) * sizeof(float)
+                     : nt == 2 ? 4ull * 2 * (nr * (nr + 4) + 8) * sizeof(float) : 4ull * roww * (cp + 2) * sizeof(float);
   return stage > epi ? stage : epi;
 }
 }  // namespace
