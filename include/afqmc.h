@@ -158,10 +158,12 @@ typedef struct {
                                block fastest, g > 1 = groups of g walker blocks);
                                either one fixes the exchange launch shape;
                                reserved[3]: k = 1..4 fixes the V_HS tile shape
-                               k - 1; reserved[4]: k = 1..3 fixes the Taylor
-                               kernel's row tile k - 1 (48, 32 or 64 rows; 64
-                               for FP32 propagation only); 0 leaves each to the
-                               tuner; other entries: zero                         */
+                               k - 1; reserved[4]: k fixes the Taylor kernel's
+                               shape k - 1: with FP64 propagation k = 1..4 (48-
+                               or 32-row tiles with a copy wave, the same
+                               without one at three workgroups per CU), with
+                               FP32 propagation k = 1..3 (48, 32 or 64 rows);
+                               0 leaves each to the tuner; other entries: zero   */
 } afqmc_options;
 
 /* Walker state of one system; every pointer is device memory owned by the caller. */

@@ -259,6 +259,209 @@ __global__ __launch_bounds__(64 * (NCW + 1)) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
+// The same term without a copy wave, for three workgroups per CU: each of the
+// NCW waves issues its share of every stage's copies (instructions q = wave +
+// NCW n) at the top of a chunk, NBUF - 1 chunks ahead, waits for its share of
+// the next chunk and meets the others at a bare barrier.  Its LDS reads go
+// through native vector types, which the compiler does not make wait for the
+// wave's own copies in flight.
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bare_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int TR, int TN, bool IMAG, int TKC_, int NBUF, int NCW, int OCC>
+__global__ __launch_bounds__(64 * NCW, OCC) void k_taylor3w(const double *__restrict__ vhs,
+                                                             const double2 *__restrict__ tin,
+                                                             double2 *__restrict__ tout,
+                                                             double2 *__restrict__ tacc, int M, int Nt, int W,
+                                                             int nrt, double alpha, int acc) {
+  constexpr int BM = 4 * TR * NCW, KS = TKC_ / 4, SLOTS = TKC_ / 2;
+  constexpr int NPL = IMAG ? 1 : 2;
+  constexpr int AROWS = NPL * BM, AI = (AROWS * SLOTS + 63) / 64;
+  constexpr int TI = (TKC_ * 16 * TN + 63) / 64;
+  constexpr int NI = AI + TI, D = NBUF - 1;
+  constexpr int NQ = (NI + NCW - 1) / NCW, CMIN = NI / NCW;   // copies per wave and stage: at most, at least
+  static_assert((D - 1) * NQ < 64, "vmcnt range");
+  auto sw = [](int r) { return TKC_ == 16 ? (r >> 1) & 1 : 0; };
+  extern __shared__ __attribute__((aligned(16))) double2 ssh[];
+  double2 *sA = ssh;
+  double2 *sT = ssh + NBUF * AI * 64;
+
+  const int ntiles = W * nrt;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int t = x * per + min(x, rem) + jx;
+  const int w = t / nrt, i0 = (t - w * nrt) * BM;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wm = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nchunk = (M + TKC_ - 1) / TKC_;
+  const int rbase = i0 + wm * 4 * TR;
+  const bool live = rbase < M;
+
+  const int MM = M * M;
+  const __amdgpu_buffer_rsrc_t ares = buffer_rsrc(vhs + (size_t)w * 2 * MM + (IMAG ? MM : 0), (uint32_t)NPL * MM * 8u);
+  const __amdgpu_buffer_rsrc_t tres = buffer_rsrc(tin + (size_t)w * M * Nt, (uint32_t)M * Nt * 16u);
+  int qoff[NQ];
+#pragma unroll
+  for (int n = 0; n < NQ; ++n) {
+    const int q = wm + NCW * n;
+    int off;
+    if (q < AI) {
+      const int e = q * 64 + lane, row = e / SLOTS, slot = e - row * SLOTS;
+      const int p = row / BM, r = row - p * BM;
+      off = (p * MM + min(i0 + r, M - 1) * M + 2 * (slot ^ sw(r))) * 8;
+    } else {
+      off = ((q - AI) * 64 + lane) * 16;
+    }
+    qoff[n] = off;
+  }
+  auto issue = [&](int ch) {
+    const int buf = ch % NBUF, k0 = ch * TKC_;
+#pragma unroll
+    for (int n = 0; n < NQ; ++n) {
+      const int q = wm + NCW * n;
+      if (NI % NCW != 0 && q >= NI) break;   // uniform in the wave
+      if (q < AI)
+        lds_copy16(ares, sA + (buf * AI + q) * 64, qoff[n] + k0 * 8);
+      else
+        lds_copy16(tres, sT + (buf * TI + q - AI) * 64, qoff[n] + k0 * Nt * 16);
+    }
+  };
+
+  const int lr = lane & 15, lk = lane >> 4, l4 = lane & 3;
+  double p1[TR][TN], p2[TR][TN], p3[TR][TN];
+#pragma unroll
+  for (int i = 0; i < TR; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) p1[i][j] = p2[i][j] = p3[i][j] = 0.0;
+  auto read_a = [&](int stage, int h, v2d (&dst)[NPL][TR]) {
+    const v2d *a = reinterpret_cast<const v2d *>(sA + stage * AI * 64);
+#pragma unroll
+    for (int p = 0; p < NPL; ++p)
+#pragma unroll
+      for (int i = 0; i < TR; ++i) {
+        const int r = wm * 4 * TR + 4 * i + l4;
+        dst[p][i] = a[(p * BM + r) * SLOTS + (((KS / 2) * lk + h) ^ sw(r))];
+      }
+  };
+  auto read_b = [&](int stage, int s, v2d (&dst)[TN]) {
+    const v2d *b = reinterpret_cast<const v2d *>(sT + stage * TI * 64 + (KS * lk + s) * Nt + lr);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) dst[j] = b[16 * j];
+  };
+
+  // chunks 0 .. D-1 in flight; copies past the last chunk read zeros or unused
+  // values into stages no one reads, which keeps every wait's count the same
+#pragma unroll
+  for (int c = 0; c < D; ++c) issue(c);
+  AFQMC_WAIT_VMCNT((D - 1) * CMIN);   // this wave's copies of chunk 0 (a wave with more waits a little longer)
+  bare_barrier();
+  v2d av[NPL][TR], bv[TN];
+  for (int ch = 0; ch < nchunk; ++ch) {
+    issue(ch + D);   // into the stage read in chunk ch - 1
+    if (live) {
+      const int stage = ch % NBUF;
+      read_a(stage, 0, av);
+      read_b(stage, 0, bv);
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        v2d an[NPL][TR], bn[TN];
+        const bool last = s + 1 == KS;
+        if (!last) {
+          read_b(stage, s + 1, bn);
+          if ((s + 1) % 2 == 0) read_a(stage, (s + 1) / 2, an);
+        }
+        double yr[TN], yi[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          yr[j] = bv[j].x;
+          yi[j] = bv[j].y;
+        }
+        auto aval = [&](int p, int i) { return (s & 1) ? av[p][i].y : av[p][i].x; };
+        if constexpr (IMAG) {
+#pragma unroll
+          for (int i = 0; i < TR; ++i) {
+            const double xi = aval(0, i);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi, yr[j], p1[i][j], 0, 0, 0);
+              p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi, yi[j], p2[i][j], 0, 0, 0);
+            }
+          }
+        } else {
+          double xr[TR], xi[TR];
+#pragma unroll
+          for (int i = 0; i < TR; ++i) {
+            xr[i] = aval(0, i);
+            xi[i] = aval(1, i);
+          }
+#pragma unroll
+          for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              p1[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p1[i][j], 0, 0, 0);
+              p2[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xi[i], yi[j], p2[i][j], 0, 0, 0);
+            }
+#pragma unroll
+          for (int i = 0; i < TR; ++i) xr[i] += xi[i];
+#pragma unroll
+          for (int j = 0; j < TN; ++j) yr[j] += yi[j];
+#pragma unroll
+          for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              p3[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(xr[i], yr[j], p3[i][j], 0, 0, 0);
+        }
+        if (!last) {
+#pragma unroll
+          for (int j = 0; j < TN; ++j) bv[j] = bn[j];
+          if ((s + 1) % 2 == 0)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p)
+#pragma unroll
+              for (int i = 0; i < TR; ++i) av[p][i] = an[p][i];
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    AFQMC_WAIT_VMCNT((D - 1) * CMIN);   // this wave's copies of chunk ch + 1
+    bare_barrier();
+  }
+  AFQMC_WAIT_VMCNT(0);   // no copy may outlive the workgroup's LDS
+  if (!live) return;
+
+  double2 *to = tout + (size_t)w * M * Nt;
+  double2 *ta = tacc + (size_t)w * M * Nt;
+  const double2 *tw = tin + (size_t)w * M * Nt;
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    const int gi = rbase + 4 * i + lk;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = 16 * j + lr;
+      if (gi < M && c < Nt) {
+        const size_t off = (size_t)gi * Nt + c;
+        const double re = IMAG ? -p2[i][j] : p1[i][j] - p2[i][j];
+        const double im = IMAG ? p1[i][j] : (p3[i][j] - p1[i][j]) - p2[i][j];
+        const double2 v = make_double2(alpha * re, alpha * im);
+        to[off] = v;
+        if (acc) {
+          const double2 o = ta[off];
+          double2 u = v;
+          if (acc == 2) {
+            const double2 x = tw[off];
+            u = make_double2(x.x + v.x, x.y + v.y);
+          }
+          ta[off] = make_double2(o.x + u.x, o.y + u.y);
+        }
+      }
+    }
+  }
+}
+
 namespace {
 constexpr int kTaylorKc = 8;     // contraction indices per stage
 constexpr int kTaylorStages = 4;
@@ -298,6 +501,40 @@ hipError_t run_taylor3s_tn(const System &s, const double2 *tin, double2 *tout, d
     default: return run_taylor3s<2, 4, 6, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
   }
 }
+template <int TR, int TN, bool IMAG>
+hipError_t run_taylor3w(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
+                        int w0, int acc) {
+  constexpr int NCW = 4, BM = 4 * TR * NCW, TK = kTaylorKc, NB = 3;
+  const int ai = ((IMAG ? 1 : 2) * BM * (TK / 2) + 63) / 64, ti = (TK * 16 * TN + 63) / 64;
+  const size_t lds = (size_t)NB * (ai + ti) * 64 * sizeof(double2);
+  auto k = k_taylor3w<TR, TN, IMAG, TK, NB, NCW, 3>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       80 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  if (lds > 80 * 1024) return hipErrorInvalidValue;
+  const int nrt = (s.M + BM - 1) / BM;
+  const size_t wt = (size_t)w0 * s.M * s.Nt;
+  hipLaunchKernelGGL(k, dim3((unsigned)(W * nrt)), dim3(64 * NCW), lds, st, s.vhs + (size_t)w0 * 2 * s.M * s.M,
+                     tin + wt, tout + wt, s.tacc + wt, s.M, s.Nt, W, nrt, alpha, acc);
+  return hipGetLastError();
+}
+
+template <int TR, bool IMAG>
+hipError_t run_taylor3w_tn(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
+                           int w0, int acc) {
+  switch ((s.Nt + 15) / 16) {
+    case 1: return run_taylor3w<TR, 1, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 2: return run_taylor3w<TR, 2, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 3: return run_taylor3w<TR, 3, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 4: return run_taylor3w<TR, 4, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 5: return run_taylor3w<TR, 5, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    default: return run_taylor3w<2, 6, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+  }
+}
 }  // namespace
 
 bool taylor_mfma_supported(int M, int Nt) { return M % 2 == 0 && Nt >= 1 && Nt <= 96; }
@@ -306,13 +543,20 @@ bool taylor_walker_split(const System &s) {
   return s.use_mfma_gemm && s.taylor_kernel && taylor_mfma_supported(s.M, s.Nt);
 }
 
-int taylor_shapes(const System &s) { return s.prop32 ? 3 : 2; }
+int taylor_shapes(const System &s) { return s.prop32 ? 3 : 4; }
 
-// shape 0: 48-row tiles, 1: 32-row tiles
+// shape 0: 48-row tiles, 1: 32-row tiles (copy wave, two workgroups per CU);
+// 2: 48-row tiles, 3: 32-row tiles (no copy wave, three workgroups per CU)
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
                               hipStream_t st, int kbeg, int w0, int acc) {
   const bool imag = kbeg != 0;
   if (imag && kbeg != s.M) return hipErrorInvalidValue;
+  if (s.taylor_shape == 2)
+    return imag ? run_taylor3w_tn<3, true>(s, tin, tout, alpha, W, st, w0, acc)
+                : run_taylor3w_tn<3, false>(s, tin, tout, alpha, W, st, w0, acc);
+  if (s.taylor_shape == 3)
+    return imag ? run_taylor3w_tn<2, true>(s, tin, tout, alpha, W, st, w0, acc)
+                : run_taylor3w_tn<2, false>(s, tin, tout, alpha, W, st, w0, acc);
   if (s.taylor_shape == 1)
     return imag ? run_taylor3s_tn<2, true>(s, tin, tout, alpha, W, st, w0, acc)
                 : run_taylor3s_tn<2, false>(s, tin, tout, alpha, W, st, w0, acc);

@@ -301,7 +301,7 @@ def test_fused_step_matches_oracle(which, small):
             p.close()
 
 
-@pytest.mark.parametrize("shape", [1, 2])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
 @pytest.mark.parametrize("spec,W", [(TILED, 70), (WIDE, 9)], ids=["tiled", "wide"])
 def test_taylor_tiles_match_oracle(spec, W, shape):
     """The Taylor kernel's row tiles (reserved[4] = 1: 48 rows, 2: 32 rows; at
@@ -325,7 +325,7 @@ def test_taylor_row_tiles_agree_bitwise_and_with_four_products():
     on the same fields: the same walkers to rounding."""
     from paper_2406_16238_amd import afqmc as A
     outs = []
-    for bits, shape in ((0, 1), (0, 2), (4, 0)):
+    for bits, shape in ((0, 1), (0, 2), (0, 3), (0, 4), (4, 0)):
         o = A.default_options()
         o.reserved[0] = bits
         o.reserved[4] = shape
@@ -340,9 +340,10 @@ def test_taylor_row_tiles_agree_bitwise_and_with_four_products():
             outs.append(p.to_host(w))
         finally:
             p.close()
-    for x, y in zip(outs[0], outs[1]):
-        assert x.tobytes() == y.tobytes()
-    (a, wa, la, _), (b, wb, lb, _) = outs[0], outs[2]
+    for other in outs[1:-1]:
+        for x, y in zip(outs[0], other):
+            assert x.tobytes() == y.tobytes()
+    (a, wa, la, _), (b, wb, lb, _) = outs[0], outs[-1]
     assert cmp_rel(a, b, np.abs(b).max()) < 1e-13
     assert cmp_rel(wa, wb) < 1e-13
     assert phase_diff(la, lb) < 1e-12

@@ -85,5 +85,5 @@ def test_bad_row_tile_is_rejected():
     from paper_2406_16238_amd import afqmc as A
     spec, W = gi.SystemSpec(56, 6, 6, 112, tau=40.0, seed=7), 8
     with pytest.raises(A.AfqmcError) as err:
-        _setup(spec, W, reserved={4: 3})   # 64-row tiles exist for FP32 propagation only
+        _setup(spec, W, prop_precision=A.FP32_CONTRACT, reserved={4: 4})   # FP32 propagation has three shapes
     assert err.value.status == A.ERR_ARG
