@@ -161,7 +161,8 @@ typedef struct {
                                k - 1; reserved[4]: k fixes the Taylor kernel's
                                shape k - 1: with FP64 propagation k = 1..4 (48-
                                or 32-row tiles with a copy wave, the same
-                               without one at three workgroups per CU), with
+                               without one at three or four workgroups per
+                               CU), with
                                FP32 propagation k = 1..3 (48, 32 or 64 rows);
                                0 leaves each to the tuner; other entries: zero   */
 } afqmc_options;

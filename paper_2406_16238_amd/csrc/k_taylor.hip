@@ -259,7 +259,7 @@ __global__ __launch_bounds__(64 * (NCW + 1)) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
-// The same term without a copy wave, for three workgroups per CU: each of the
+// The same term without a copy wave, for three or four workgroups per CU: each of the
 // NCW waves issues its share of every stage's copies (instructions q = wave +
 // NCW n) at the top of a chunk, NBUF - 1 chunks ahead, waits for its share of
 // the next chunk and meets the others at a bare barrier.  Its LDS reads go
@@ -501,13 +501,14 @@ hipError_t run_taylor3s_tn(const System &s, const double2 *tin, double2 *tout, d
     default: return run_taylor3s<2, 4, 6, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
   }
 }
-template <int TR, int TN, bool IMAG>
+// NB stages, OCC workgroups per CU (LDS and registers permitting)
+template <int TR, int TN, bool IMAG, int NB, int OCC>
 hipError_t run_taylor3w(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
                         int w0, int acc) {
-  constexpr int NCW = 4, BM = 4 * TR * NCW, TK = kTaylorKc, NB = 3;
+  constexpr int NCW = 4, BM = 4 * TR * NCW, TK = kTaylorKc;
   const int ai = ((IMAG ? 1 : 2) * BM * (TK / 2) + 63) / 64, ti = (TK * 16 * TN + 63) / 64;
   const size_t lds = (size_t)NB * (ai + ti) * 64 * sizeof(double2);
-  auto k = k_taylor3w<TR, TN, IMAG, TK, NB, NCW, 3>;
+  auto k = k_taylor3w<TR, TN, IMAG, TK, NB, NCW, OCC>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -523,16 +524,21 @@ hipError_t run_taylor3w(const System &s, const double2 *tin, double2 *tout, doub
   return hipGetLastError();
 }
 
+// 48-row tiles: three stages (48 KB), three workgroups per CU; 32-row tiles:
+// two stages (28 KB), four workgroups per CU (measured faster than three
+// stages at three: more workgroups cover one's barrier wait better than a
+// deeper pipeline); 96 columns: 32-row tiles, three stages at three
 template <int TR, bool IMAG>
 hipError_t run_taylor3w_tn(const System &s, const double2 *tin, double2 *tout, double alpha, int W, hipStream_t st,
                            int w0, int acc) {
+  constexpr int NB = TR == 2 ? 2 : 3, OCC = TR == 2 ? 4 : 3;
   switch ((s.Nt + 15) / 16) {
-    case 1: return run_taylor3w<TR, 1, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
-    case 2: return run_taylor3w<TR, 2, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
-    case 3: return run_taylor3w<TR, 3, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
-    case 4: return run_taylor3w<TR, 4, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
-    case 5: return run_taylor3w<TR, 5, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
-    default: return run_taylor3w<2, 6, IMAG>(s, tin, tout, alpha, W, st, w0, acc);
+    case 1: return run_taylor3w<TR, 1, IMAG, NB, OCC>(s, tin, tout, alpha, W, st, w0, acc);
+    case 2: return run_taylor3w<TR, 2, IMAG, NB, OCC>(s, tin, tout, alpha, W, st, w0, acc);
+    case 3: return run_taylor3w<TR, 3, IMAG, NB, OCC>(s, tin, tout, alpha, W, st, w0, acc);
+    case 4: return run_taylor3w<TR, 4, IMAG, NB, OCC>(s, tin, tout, alpha, W, st, w0, acc);
+    case 5: return run_taylor3w<TR, 5, IMAG, NB, OCC>(s, tin, tout, alpha, W, st, w0, acc);
+    default: return run_taylor3w<2, 6, IMAG, 3, 3>(s, tin, tout, alpha, W, st, w0, acc);
   }
 }
 }  // namespace
@@ -546,7 +552,7 @@ bool taylor_walker_split(const System &s) {
 int taylor_shapes(const System &s) { return s.prop32 ? 3 : 4; }
 
 // shape 0: 48-row tiles, 1: 32-row tiles (copy wave, two workgroups per CU);
-// 2: 48-row tiles, 3: 32-row tiles (no copy wave, three workgroups per CU)
+// 2: 48-row tiles, 3: 32-row tiles (no copy wave; three and four workgroups per CU)
 hipError_t launch_taylor_mfma(const System &s, const double2 *tin, double2 *tout, double alpha, int W,
                               hipStream_t st, int kbeg, int w0, int acc) {
   const bool imag = kbeg != 0;
