@@ -102,6 +102,23 @@ def test_free_projection_medium_tiled():
         p.close()
 
 
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
+def test_free_projection_taylor_shapes(shape):
+    """Each shape of the Taylor kernel (with and without the copy wave, 48- and
+    32-row tiles) in its two-product form (purely imaginary V_HS) against the
+    oracle, on a system that spans several row tiles."""
+    from paper_2406_16238_amd import afqmc as A
+    o = A.default_options()
+    o.reserved[4] = shape
+    p = Pair(gi.MEDIUM.system, 70, 0.005, options=o)
+    try:
+        assert A.get_info(p.ctx).taylor_tile == shape - 1
+        worst, _ = _free_run(p, 70, 3, 3)
+        assert max(worst.values()) < TOL, worst
+    finally:
+        p.close()
+
+
 def test_imaginary_plane_path_equals_both_planes():
     """Free projection contracts only the imaginary plane of V_HS; reserved[0]
     bit 4 forces both planes (the real one zero).  Same walkers either way, to
