@@ -123,11 +123,11 @@ __device__ __forceinline__ void lp_store_s(const f4v (&acc)[RT][CT], float *sS, 
 
 template <int NR, int CT, int RT>
 __device__ __forceinline__ void lp_trace_s(const f4v (&acc)[RT][CT], const float *sS, int lane, float &pre,
-                                           float &pim, float *dg, int pass) {
+                                           float &pim, int pass) {
   constexpr int CS = NR + 4, PL = lp_s_plane<NR>();
   const int lr = lane & 15, lk = lane >> 4;
   const bool odd = lr & 1;
-  float a0 = 0.f, a1 = 0.f, d = 0.f;   // sum v Re T_ji, sum v Im T_ji, diagonal
+  float a0 = 0.f, a1 = 0.f;   // sum v Re T_ji, sum v Im T_ji
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int glo = rt * 16 / NR, ghi = (rt * 16 + 15) / NR;
@@ -144,15 +144,12 @@ __device__ __forceinline__ void lp_trace_s(const f4v (&acc)[RT][CT], const float
         const float v = acc[rt][ct][r];
         a0 = fmaf(v, cre[r], a0);
         a1 = fmaf(v, cim[r], a1);
-        if (i0 + r == j) d += v;
       }
     }
   }
-  // the lane holds Re T_ij (even lr) or Im T_ij (odd lr); its diagonal share
-  // follows the parity convention of lp_finish
+  // the lane holds Re T_ij (even lr) or Im T_ij (odd lr)
   pre += odd ? -a1 : a0;
   pim += odd ? a0 : a1;
-  dg[pass] += d;
 }
 
 // The same trace with one plane of S in LDS at a time (half the LDS): the
@@ -178,11 +175,9 @@ __device__ __forceinline__ void lp_store_s1(const f4v (&acc)[RT][CT], float *sS,
   }
 }
 
-// a += sum v * (plane entry of the partner T_ji); with diag, d += the lane's
-// diagonal entries
+// a += sum v * (plane entry of the partner T_ji)
 template <int NR, int CT, int RT>
-__device__ __forceinline__ void lp_trace_s1(const f4v (&acc)[RT][CT], const float *sS, int lane, float &a, float &d,
-                                            int pass, bool diag) {
+__device__ __forceinline__ void lp_trace_s1(const f4v (&acc)[RT][CT], const float *sS, int lane, float &a, int pass) {
   constexpr int CS = NR + 4;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
@@ -196,11 +191,7 @@ __device__ __forceinline__ void lp_trace_s1(const f4v (&acc)[RT][CT], const floa
       const int j = ct * 8 + (lr >> 1);
       const f4v c = *reinterpret_cast<const f4v *>(sS + j * CS + i0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float v = acc[rt][ct][r];
-        a = fmaf(v, c[r], a);
-        if (diag && i0 + r == j) d += v;
-      }
+      for (int r = 0; r < 4; ++r) a = fmaf(acc[rt][ct][r], c[r], a);
     }
   }
 }
@@ -222,6 +213,25 @@ __device__ __forceinline__ void lp_finish(double pre, double pim, const double *
       dim = wave_sum_dpp(dim);
       const int g = g0w + gl;
       if (lane == 63 && w < W && g < G) vbpart[((size_t)spin * W + w) * G + g] = make_double2(dre, dim);
+    }
+  }
+}
+
+// The same, each lane holding its share of both parts of every diagonal sum.
+template <int GC>
+__device__ __forceinline__ void lp_finish_ri(double pre, double pim, const double *dre, const double *dim, int lane,
+                                             int w, int W, int g0w, int G, int spin, int stride, int part,
+                                             double2 *ekpart, double2 *vbpart) {
+  pre = wave_sum_dpp(pre);
+  pim = wave_sum_dpp(pim);
+  if (lane == 63 && w < W && g0w < G)
+    ekpart[((size_t)w * 2 + spin) * stride + part] = make_double2(-0.5 * pre, -0.5 * pim);
+  if (vbpart) {
+#pragma unroll
+    for (int gl = 0; gl < GC; ++gl) {
+      const double sre = wave_sum_dpp(dre[gl]), sim = wave_sum_dpp(dim[gl]);
+      const int g = g0w + gl;
+      if (lane == 63 && w < W && g < G) vbpart[((size_t)spin * W + w) * G + g] = make_double2(sre, sim);
     }
   }
 }
@@ -585,31 +595,55 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? kLp16Occupancy1 : NT <= 2 ? 2 :
     // one Cholesky vector of the wave at a time, one plane of S per wave in
     // LDS (the empty asm statements keep the compiler from moving LDS accesses
     // across the phases; the wave's LDS accesses run in order)
+    // The diagonal T_ii is read back from the plane by lane i (i < NR) once
+    // the plane is in LDS, rather than picked out of the accumulators.
     float *sS = reinterpret_cast<float *>(bsm) + (size_t)wv * lp_s_plane<NR>();
     const bool odd = lr & 1;
+    const float *sdiag = sS + min(lane, NR - 1) * (NR + 5);   // S[i][i], row stride NR + 4
+    double dre[GC], dim[GC];
 #pragma unroll
     for (int pass = 0; pass < GC; ++pass) {
-      float a0 = 0.f, a1 = 0.f, d = 0.f;   // sum v Re T_ji, sum v Im T_ji, diagonal
+      float a0 = 0.f, a1 = 0.f;   // sum v Re T_ji, sum v Im T_ji
       lp_store_s1<NR, CT, RT>(acc, sS, lane, pass, 0);
       asm volatile("" ::: "memory");
-      lp_trace_s1<NR, CT, RT>(acc, sS, lane, a0, d, pass, true);
+      lp_trace_s1<NR, CT, RT>(acc, sS, lane, a0, pass);
+      const float xre = *sdiag;
       asm volatile("" ::: "memory");
       lp_store_s1<NR, CT, RT>(acc, sS, lane, pass, 1);
       asm volatile("" ::: "memory");
-      lp_trace_s1<NR, CT, RT>(acc, sS, lane, a1, d, pass, false);
+      lp_trace_s1<NR, CT, RT>(acc, sS, lane, a1, pass);
+      const float xim = *sdiag;
       asm volatile("" ::: "memory");
       pre += odd ? -a1 : a0;
       pim += odd ? a0 : a1;
-      dg[pass] += d;
+      dre[pass] = lane < NR ? (double)xre : 0.0;
+      dim[pass] = lane < NR ? (double)xim : 0.0;
     }
+    lp_finish_ri<GC>((double)pre, (double)pim, dre, dim, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride,
+                     gb * LWY + wy, ekpart, vbpart);
+    return;
   } else if constexpr (NT == 2) {
-    // one Cholesky vector of the wave at a time: S (two planes) per wave in LDS
+    // one Cholesky vector of the wave at a time: S (two planes) per wave in
+    // LDS, its diagonal read back by lane i (i < NR).  Lanes read entries
+    // other lanes stored: the empty asm statements keep the compiler from
+    // moving LDS accesses across the phases or reusing a value loaded in the
+    // previous pass (the wave's LDS accesses run in order).
     float *sS = reinterpret_cast<float *>(bsm) + (size_t)wv * 2 * lp_s_plane<NR>();
+    const float *sdiag = sS + min(lane, NR - 1) * (NR + 5);   // S[i][i], row stride NR + 4
+    double dre[GC], dim[GC];
 #pragma unroll
     for (int pass = 0; pass < GC; ++pass) {
       lp_store_s<NR, CT, RT>(acc, sS, lane, pass);
-      lp_trace_s<NR, CT, RT>(acc, sS, lane, pre, pim, dg, pass);
+      asm volatile("" ::: "memory");
+      lp_trace_s<NR, CT, RT>(acc, sS, lane, pre, pim, pass);
+      const float xre = sdiag[0], xim = sdiag[lp_s_plane<NR>()];
+      asm volatile("" ::: "memory");
+      dre[pass] = lane < NR ? (double)xre : 0.0;
+      dim[pass] = lane < NR ? (double)xim : 0.0;
     }
+    lp_finish_ri<GC>((double)pre, (double)pim, dre, dim, lane, w0 + wx, W, g0 + wy * GC, G, spin, stride,
+                     gb * LWY + wy, ekpart, vbpart);
+    return;
   } else {
     float *sT = reinterpret_cast<float *>(bsm) + (size_t)wv * ROWW * TSF;
 #pragma unroll
