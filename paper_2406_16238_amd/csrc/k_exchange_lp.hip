@@ -796,11 +796,15 @@ __global__ __launch_bounds__(kThreads) void k_lt_split(const double *__restrict_
 // Q = Theta - Psi of one spin block (re/im interleaved over CP = 2 NR columns,
 // zero past 2N), scaled by a power of two per walker and written K-contiguous,
 // ThB[w][c][q] (q < Kp, zero for q >= M).  First one workgroup per walker finds
-// max |Q| and stores the inverse scale in qsc[w]; then one workgroup per
-// (32 rows q, walker) transposes its rows through LDS.
-__global__ __launch_bounds__(kThreads) void k_q_max(const double2 *__restrict__ theta, const double *__restrict__ trial,
-                                                   int M, int Nt, int off, int N, float *__restrict__ qsc) {
-  __shared__ float red[kThreads / 64];
+// max |Q| and stores the inverse scale in qsc[w] (sixteen waves, so that one
+// workgroup per CU keeps enough loads in flight; a maximum does not depend on
+// the order); then one workgroup per (32 rows q, walker) transposes its rows
+// through LDS.
+constexpr int kQmaxThreads = 1024;
+__global__ __launch_bounds__(kQmaxThreads) void k_q_max(const double2 *__restrict__ theta,
+                                                       const double *__restrict__ trial, int M, int Nt, int off,
+                                                       int N, float *__restrict__ qsc) {
+  __shared__ float red[kQmaxThreads / 64];
   const int w = blockIdx.x, tid = threadIdx.x;
   const double2 *th = theta + (size_t)w * M * Nt + off;
   float mx = 0.f;
@@ -1021,7 +1025,7 @@ hipError_t lp_prepare_rhs(const System &s, const double2 *theta, int W, int spin
     unsigned char *base = static_cast<unsigned char *>(s.lp_rhs[spin]);
     float *qsc = reinterpret_cast<float *>(base + l.qsc);
     const size_t lds = 32ull * (CP + 1) * sizeof(float);
-    hipLaunchKernelGGL(k_q_max, dim3(W), dim3(kThreads), 0, st, theta, s.trial, s.M, s.Nt, off, p.N, qsc);
+    hipLaunchKernelGGL(k_q_max, dim3(W), dim3(kQmaxThreads), 0, st, theta, s.trial, s.M, s.Nt, off, p.N, qsc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (f16(s.precision))

@@ -137,10 +137,13 @@ hipError_t launch_weight_update(const System &s, const afqmc_walkers &wk, int W,
 }
 
 // ---- one-body energy: E1 = ecore + sum_{q,i'} htT[q][i'] Theta[w][q][i'] ------
-__global__ __launch_bounds__(kThreads) void k_energy_e1(const double *__restrict__ htT,
-                                                       const double2 *__restrict__ theta, long K,
-                                                       double ecore, double2 *__restrict__ e1) {
-  __shared__ double red[4 * 2];
+// One workgroup of sixteen waves per walker: with one workgroup per CU, four
+// waves left the loads of a walker's Theta too few in flight.
+constexpr int kE1Threads = 1024;
+__global__ __launch_bounds__(kE1Threads) void k_energy_e1(const double *__restrict__ htT,
+                                                         const double2 *__restrict__ theta, long K,
+                                                         double ecore, double2 *__restrict__ e1) {
+  __shared__ double red[kE1Threads / 64 * 2];
   const int w = blockIdx.x;
   const double2 *th = theta + (size_t)w * K;
   double acc[2] = {0.0, 0.0};
@@ -155,13 +158,13 @@ __global__ __launch_bounds__(kThreads) void k_energy_e1(const double *__restrict
 }
 
 hipError_t launch_energy_e1(const System &s, const double2 *theta, int W, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_e1, dim3(W), dim3(kThreads), 0, st, s.htT, theta, (long)s.M * s.Nt, s.ecore,
+  hipLaunchKernelGGL(k_energy_e1, dim3(W), dim3(kE1Threads), 0, st, s.htT, theta, (long)s.M * s.Nt, s.ecore,
                      s.e1);
   return hipGetLastError();
 }
 
 hipError_t launch_trace_half(const double *mat, const double2 *theta, int W, long K, double2 *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy_e1, dim3(W), dim3(kThreads), 0, st, mat, theta, K, 0.0, out);
+  hipLaunchKernelGGL(k_energy_e1, dim3(W), dim3(kE1Threads), 0, st, mat, theta, K, 0.0, out);
   return hipGetLastError();
 }
 
