@@ -131,3 +131,41 @@ def test_trial_split_at_the_trial_is_exact_to_fp32(form):
     finally:
         ctx.close()
         p.close()
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("spec,W", [(gi.SystemSpec(37, 5, 3, 70, tau=30.0, seed=7), 11),
+                                    (gi.SystemSpec(18, 3, 2, 1, tau=5.0, seed=24), 7),
+                                    (gi.SystemSpec(30, 4, 4, 6, tau=10.0, seed=27), 5)],
+                         ids=["g70-open-shell", "one-vector", "g6"])
+def test_cholesky_counts_off_the_workgroup_tile(form, spec, W):
+    """Cholesky-vector counts that are no multiple of the four vectors a 16-bit
+    exchange workgroup covers (so that the second vector of a wave can be a
+    padded one), and odd walker counts: the padded vectors and walkers must add
+    nothing.  Per-walker energies on identical walkers against the oracle, and
+    a short trajectory (weights move by the force bias, i.e. vbias from the
+    trace of the exchange) against the FP64 path on the same fields."""
+    p = Pair(spec, W, 0.005)
+    ctx = ctx_for(p, FORMS[form])
+    try:
+        A, torch = p.A, p.torch
+        phis = gi.initial_walkers(p.trial, W, noise=0.02, seed=41)
+        ref = O.local_energies(p.ham, phis)
+        elp = energies(p, ctx, phis)
+        assert np.abs(elp - ref).max() < 0.1 * MHA
+        outs = []
+        for c in (p.ctx, ctx):
+            w = A.Walkers.from_numpy(phis)
+            A.overlap(c, w)
+            e = torch.empty((W, 3), dtype=torch.complex128, device="cuda")
+            fl = gi.FieldStream(3, W, spec.nchol)
+            for step in range(3):
+                A.step(c, w, torch.as_tensor(fl.next(), device="cuda"), e)
+            torch.cuda.synchronize()
+            outs.append((e.cpu().numpy(), w.weight.cpu().numpy()))
+        (e64, w64), (e2, w2) = outs
+        assert np.abs(e2 - e64).max() < 0.1 * MHA
+        assert cmp_rel(w2, w64) < 1e-4
+    finally:
+        ctx.close()
+        p.close()
